@@ -1,0 +1,171 @@
+"""CPU oracle for the sigma_min(zI - A) hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the GPU library (its own C source, its own grid and band handling); the two
+meet only through the seeded inputs of the ``workloads`` package.
+
+Contents (each function names the passage of the paper it follows):
+  * ``sigma_min``      -- dense one-sided Jacobi SVD per shift (``jacobi.c``), Sec. 2.1 and
+                          the third form of the pseudospectrum definition (Sec. 2).
+  * ``grid_points``    -- the shift grid G of Sec. 2.1.
+  * ``compact_mask``   -- the restricted set R of Sec. 4 as an index list.
+  * ``sensitive``      -- the sensitive zone S_eps, Sec. 2.1 eq. (sensitive_zone).
+  * ``adjoint``        -- gradients of sigma_min from the singular pair (first-order
+                          perturbation of a simple singular value; the paper is silent).
+  * ``newton_step``    -- one Newton step on ln(sigma/eps) toward the eps-level curve
+                          (the level curve of Sec. 2.1; the paper is silent on refinement).
+Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
+closed forms, invariants, brute force and the paper's Jordan example.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jacobi.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (OpenMP, no LAPACK)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC,
+                               "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.oracle_sigma_min.argtypes = [i64, i64, i64, P, i64, i64, P, P, P, P, P, P,
+                                         ctypes.c_int, ctypes.c_int]
+        lib.oracle_sigma_min.restype = ctypes.c_int
+        lib.oracle_svd_dense.argtypes = [i64, P, P, P, P, P]
+        lib.oracle_svd_dense.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def sigma_min(band, z, want_vectors: bool = False, all_sv: bool = False, nthreads: int | None = None,
+              parallel_pairs: bool | None = None):
+    """sigma_min(zI - A) at each shift in ``z`` (Sec. 2.1: sigma_min(z) = s_n of the SVD).
+
+    ``band`` has attributes ab (GB, shape (n, kl+ku+1)), n, kl, ku.  Returns a dict with
+    ``sigma`` [npts]; ``sall`` [npts, n] (unsorted) if ``all_sv``; ``u``, ``v`` [npts, n]
+    (phase: first max-modulus entry of v real positive) if ``want_vectors``; ``sweeps``.
+    """
+    lib = _load()
+    z = np.ascontiguousarray(np.atleast_1d(np.asarray(z, dtype=np.complex128)))
+    ab = np.ascontiguousarray(band.ab, dtype=np.complex128)
+    n, kl, ku = int(band.n), int(band.kl), int(band.ku)
+    npts = z.size
+    nthreads = nthreads or default_threads()
+    if parallel_pairs is None:
+        parallel_pairs = n >= 512 and npts < nthreads
+    sigma = np.empty(npts)
+    sall = np.empty((npts, n)) if all_sv else None
+    u = np.empty((npts, n), dtype=np.complex128) if want_vectors else None
+    v = np.empty((npts, n), dtype=np.complex128) if want_vectors else None
+    sweeps = np.empty(npts, dtype=np.int32)
+    st = lib.oracle_sigma_min(n, kl, ku, _ptr(ab), kl + ku + 1, npts, _ptr(z), _ptr(sigma), _ptr(sall),
+                              _ptr(u), _ptr(v), _ptr(sweeps), int(nthreads), int(bool(parallel_pairs)))
+    if st != 0:
+        raise RuntimeError("oracle Jacobi failed (status %d)" % st)
+    out = dict(sigma=sigma, sweeps=sweeps)
+    if all_sv:
+        out["sall"] = sall
+    if want_vectors:
+        out["u"], out["v"] = u, v
+    return out
+
+
+def svd_dense(M):
+    """All singular values (unsorted, column order) and U, V of a dense complex matrix."""
+    lib = _load()
+    M = np.asarray(M, dtype=np.complex128)
+    n = M.shape[0]
+    Mf = np.asfortranarray(M)
+    s = np.empty(n)
+    U = np.empty((n, n), dtype=np.complex128, order="F")
+    V = np.empty((n, n), dtype=np.complex128, order="F")
+    sw = np.empty(1, dtype=np.int32)
+    st = lib.oracle_svd_dense(n, _ptr(Mf), _ptr(s), _ptr(U), _ptr(V), _ptr(sw))
+    if st != 0:
+        raise RuntimeError("oracle Jacobi failed (status %d)" % st)
+    return s, U, V
+
+
+def grid_points(grid) -> np.ndarray:
+    """Sec. 2.1: z_ij = x_j + i*y_i, x_j in [a, b] (N_x points), y_i in [c, d] (N_y points).
+
+    Inclusive end points (x_j = a + (b - a) j/(N_x - 1); a single point sits at a);
+    flattened row-major, row index <-> y.
+    """
+    xs = np.array([grid.a + (grid.b - grid.a) * j / (grid.nx - 1) if grid.nx > 1 else grid.a
+                   for j in range(grid.nx)], dtype=np.float64)
+    ys = np.array([grid.c + (grid.d - grid.c) * i / (grid.ny - 1) if grid.ny > 1 else grid.c
+                   for i in range(grid.ny)], dtype=np.float64)
+    return (xs[None, :] + 1j * ys[:, None]).ravel()
+
+
+def compact_mask(mask) -> np.ndarray:
+    """Sec. 4: the restricted set R as the ascending flat indices of the nonzero mask entries."""
+    return np.flatnonzero(np.asarray(mask).ravel()).astype(np.int64)
+
+
+def sensitive(sigma, eps) -> np.ndarray:
+    """Sec. 2.1 eq. (sensitive_zone): z is sensitive iff sigma_min(z) <= eps (inclusive)."""
+    return (np.asarray(sigma) <= eps).astype(np.uint8)
+
+
+def adjoint(band, u, v, grad_sigma):
+    """Gradients of L = sum_p g_p sigma_p for sigma_p = sigma_min(z_p I - A), from the singular pairs.
+
+    For a simple singular value, d sigma = Re(u^H dM v) with dM = dz I - dA.  In the
+    conjugate-Wirtinger convention (d/dRe + i d/dIm):
+        grad_z[p]   = g_p * conj(u_p^H v_p)
+        grad_A[i,j] = -sum_p g_p * u_p[i] * conj(v_p[j])   (only on the band)
+    Returns grad_z [npts] and grad_band in GB layout (shape of band.ab).
+    """
+    u = np.asarray(u, dtype=np.complex128)
+    v = np.asarray(v, dtype=np.complex128)
+    g = np.asarray(grad_sigma, dtype=np.float64)
+    c = np.sum(np.conj(u) * v, axis=1)
+    grad_z = g * np.conj(c)
+    n, kl, ku = band.n, band.kl, band.ku
+    gb = np.zeros_like(band.ab)
+    for j in range(n):
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            gb[j, ku + i - j] = -np.sum(g * u[:, i] * np.conj(v[:, j]))
+    return grad_z, gb
+
+
+def newton_step(z, sigma, grad_z, eps):
+    """One Newton step on phi(z) = ln(sigma_min(z)/eps) along its gradient:
+    z <- z - phi * (grad sigma / sigma) / |grad sigma / sigma|^2 = z - sigma ln(sigma/eps) g/|g|^2,
+    with g = grad_z (conjugate-Wirtinger gradient of sigma_min)."""
+    z = np.asarray(z, dtype=np.complex128)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    g = np.asarray(grad_z, dtype=np.complex128)
+    return z - sigma * np.log(sigma / eps) * g / np.abs(g) ** 2
