@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark: shifts/s of sigma_min(zI - A) in FP64 on one MI355X.
+
+Workload (the measured configuration): non-normal tridiagonal Toeplitz A, n = 2000
+(sub 0.25, diag 0, super 1.0), complex128; 256 x 256 grid on [-2, 2] x [-2, 2].  One step =
+the whole hot path over that grid: the full grid through ps_eval_grid (the plain method,
+every grid point, with the sensitive-zone epilogue at eps = 1e-2) plus the restricted set of
+~25 % of the grid points (an annulus around |z| = 1, seeded) through the mask path of
+ps_eval_grid.  value = shifts evaluated per second over the timed steps (65536 + 16280
+shifts per step), inputs resident in HBM before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints ONE JSON line.  The roofline object prices the dominant kernel (the persistent
+LU + inverse-Lanczos kernel, full-grid launch) by its algorithmic bytes: per shift
+  B_LU   = (w_L + w_U) 16 n + n                 (L, U, pivots written once)
+  B_step = (2 (w_L + w_U) + 10) 16 n + 2 n      (factors read twice, ten vector passes,
+                                                  pivots read twice) per Lanczos step
+  B_out  = 16
+plus the band of A (kl + ku + 1) 16 n once per launch, with w_L = kl, w_U = kl + ku + 1 and
+the Lanczos step count of each shift as returned by the kernel.  Duration: HIP events on
+the stream the kernel runs on.  Peak: 8 TB/s (MI355X HBM3E).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+EPS_ZONE = 1e-2
+
+
+def algorithmic_bytes(n, kl, ku, iters):
+    wl, wu = kl, kl + ku + 1
+    b_lu = (wl + wu) * 16 * n + n
+    b_step = (2 * (wl + wu) + 10) * 16 * n + 2 * n
+    iters = np.asarray(iters, dtype=np.float64)
+    return float((kl + ku + 1) * 16 * n + np.sum(b_lu + iters * b_step + 16))
+
+
+def cpu_baseline(band, z_sample, threads):
+    import oracle
+    oracle.build(force=False)
+    t = time.time()
+    oracle.sigma_min(band, z_sample, nthreads=threads, parallel_pairs=True)
+    dt = time.time() - t
+    return dict(value=len(z_sample) / dt, unit="shifts/s", cores=threads, kind="oracle",
+                sample="%d grid point(s) of the same workload (n=2000), dense one-sided Jacobi to convergence, "
+                       "round-robin pairs over %d threads; %.1f s" % (len(z_sample), threads, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-points", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(shifts are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2605_04550_amd import api
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = W.workload("toeplitz2000")
+    band, grid = w["band"], w["grid"]
+    mat = api.BandedMatrix.from_band(band)
+    mask = torch.tensor(w["mask"], dtype=torch.uint8, device=dev)
+    npts_full = grid.npts
+    npts_mask = int(w["mask"].sum())
+
+    # workspaces allocated once, outside the timed region
+    from paper_2605_04550_amd import ps_workspace_size
+    o = api.make_opts()
+    ws = torch.empty(ps_workspace_size(mat.handle, npts_full, o), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        rf = api.eval_grid(mat, grid, eps=EPS_ZONE, workspace=ws, device=dev)
+        ev[1].record(stream)
+        ev[2].record(stream)
+        rm = api.eval_grid(mat, grid, mask, eps=EPS_ZONE, workspace=ws)
+        ev[3].record(stream)
+        return rf, rm, ev
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_step = 1000.0 * elapsed / args.steps
+    value = (npts_full + npts_mask) * args.steps / elapsed
+
+    # roofline of the dominant kernel: the full-grid launch of the persistent kernel
+    dur_full = np.mean([r[2][0].elapsed_time(r[2][1]) for r in runs]) / 1000.0
+    dur_mask = np.mean([r[2][2].elapsed_time(r[2][3]) for r in runs]) / 1000.0
+    rf, rm, _ = runs[-1]
+    it_full = rf["iters"].cpu().numpy()
+    info_full = rf["info"].cpu().numpy()
+    cnt_mask = int(rm["count"].item())
+    it_mask = rm["iters"][:cnt_mask].cpu().numpy()
+    bytes_full = algorithmic_bytes(band.n, band.kl, band.ku, it_full)
+    achieved = bytes_full / dur_full / 1e9
+
+    traffic = None
+    prof = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
+    if os.path.exists(prof):
+        try:
+            traffic = json.load(open(prof)).get("traffic_bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": "shifts/sec sigma_min(zI-A) FP64 (|dsigma|<=1e-10||A||_F+1e-8 sigma)",
+        "value": value,
+        "unit": "shifts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "toeplitz2000: tridiagonal Toeplitz n=2000 (0.25, 0, 1), 256x256 grid on [-2,2]^2, "
+                        "full grid + 25% annulus mask per step",
+            "n": band.n, "kl": band.kl, "ku": band.ku,
+            "shifts_per_step": npts_full + npts_mask,
+            "full_grid_ms": dur_full * 1000.0, "mask_ms": dur_mask * 1000.0,
+            "iters_mean_full": float(it_full.mean()), "iters_max_full": int(it_full.max()),
+            "iters_mean_mask": float(it_mask.mean()) if cnt_mask else 0.0,
+            "maxiter_points_full": int(np.sum((info_full & 2) != 0)),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "ps::k_eval<1,1,false> (full-grid launch)",
+            "algorithmic_bytes_per_launch": bytes_full,
+        },
+    }
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(2605_04550)
+        import oracle
+        zs = oracle.grid_points(grid)[rng.choice(npts_full, size=args.cpu_points, replace=False)]
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        out["cpu_baseline"] = cpu_baseline(band, zs, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

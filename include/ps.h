@@ -1,0 +1,192 @@
+/*
+ * ps.h -- C ABI of the MI355X (gfx950) library for sigma_min(zI - A) of a banded
+ * non-normal matrix A at many complex shifts z.
+ *
+ * What is computed.  Sec. 2 (definition of the pseudospectrum, third form) and
+ * Sec. 2.1 (Singular Value Decomposition): for each shift z, sigma_min(z) is the
+ * smallest singular value s_n of zI - A; z lies in the eps-pseudospectrum iff
+ * sigma_min(z) <= eps, and the sensitive zone is S_eps = {z in G : sigma_min(z) <= eps}
+ * (Sec. 2.1, eq. (sensitive_zone)).  The shifts are either the full grid
+ * G = {x_j + i y_i} of Sec. 2.1 (plain method) or a subset R of it (Sec. 4: the
+ * restricted region; values on R are exact, errors are only omissions).
+ *
+ * How it is computed (not the paper's dense SVD): per shift a complex banded LU with
+ * partial pivoting of zI - A, then Golub-Kahan (inverse Lanczos) bidiagonalisation of
+ * (zI - A)^{-1} through banded triangular solves; sigma_min = 1 / sigma_max of the
+ * bidiagonal.  Solves are overflow-safe (per-row binary exponents), so sigma_min far
+ * below the double range is reported as 0 with PS_PT_UNDERFLOW.
+ *
+ * Conventions shared by every call:
+ *  - Complex numbers are ps_c128 = {re, im} doubles (same bytes as
+ *    hipDoubleComplex and torch.complex128).
+ *  - Pointers named *_dev or documented "device" must be device (HBM) pointers on the
+ *    current HIP device; all other pointers are host pointers.
+ *  - "stream" is a hipStream_t (NULL = the default stream).  Calls that take a stream
+ *    only enqueue work on it and return; results are valid after the stream is
+ *    synchronised.  Calls without a stream argument are synchronous.
+ *  - Ownership: ps_create_banded copies the band into library-owned device memory
+ *    (freed by ps_destroy).  Everything else (shifts, masks, outputs, workspace) is
+ *    owned by the caller; the library keeps no pointer after a call returns.
+ *  - Errors: every call validates its arguments before launching anything and returns
+ *    a ps_status; no exception or process exit crosses the ABI.  ps_last_error()
+ *    returns a thread-local message describing the last failure on this thread.
+ *    Per-shift outcomes are reported in the optional info[] output (PS_PT_* bits).
+ */
+#ifndef PS_H_
+#define PS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double re, im;
+} ps_c128;
+
+typedef struct ps_matrix_s *ps_matrix;
+
+typedef enum {
+    PS_OK = 0,
+    PS_ERR_INVALID = 1,     /* bad argument (sizes, NULL where required, ...)            */
+    PS_ERR_NONFINITE = 2,   /* NaN or Inf in the band or in the grid parameters          */
+    PS_ERR_WORKSPACE = 3,   /* workspace NULL or smaller than the minimum for the call   */
+    PS_ERR_HIP = 4,         /* a HIP runtime call failed (message in ps_last_error)      */
+    PS_ERR_UNSUPPORTED = 5  /* bandwidths outside the compiled range, ...                */
+} ps_status;
+
+/* Per-shift info bits (info[p]).  0 means converged to the requested tolerance. */
+enum {
+    PS_PT_CONVERGED = 0,
+    PS_PT_SINGULAR = 1,   /* the LU met an exactly zero (or negligible) pivot: sigma_min = 0 */
+    PS_PT_MAXITER = 2,    /* iteration cap reached: sigma is the best (upper) estimate        */
+    PS_PT_UNDERFLOW = 4   /* sigma_min below the smallest double: reported as 0               */
+};
+
+/* Flags of ps_create_banded. */
+enum {
+    PS_DEVICE_PTR = 1,    /* ab is a device pointer (default: host pointer)                  */
+    PS_REAL_A = 2         /* A is real: ps_backward returns the real part of the band gradient */
+};
+
+/* Grid of Sec. 2.1: x_j = a + (b - a) j / (nx - 1), y_i = c + (d - c) i / (ny - 1)
+ * (inclusive ends; a single point sits at a, resp. c); z_ij = x_j + i y_i; flat index
+ * i * nx + j (row index <-> y).  Requires nx, ny >= 1 and finite a, b, c, d. */
+typedef struct {
+    double a, b, c, d;
+    int64_t nx, ny;
+} ps_grid;
+
+/* Options.  tol_norm and tol_rel set the stopping target
+ * |sigma - sigma_min| <= tol_norm * ||A||_F + tol_rel * sigma_min.
+ * max_iter caps the Lanczos steps per shift (1 .. 4096).  slots: number of shifts
+ * processed concurrently (0 = library default; rounded down to a multiple of 256). */
+typedef struct {
+    double tol_norm;      /* default 1e-10 */
+    double tol_rel;       /* default 1e-8  */
+    int32_t max_iter;     /* default 3000  */
+    int32_t want_vectors; /* 1: also return u, v (sizes [npts][n])          */
+    int32_t slots;        /* 0: default                                       */
+    int32_t reserved;
+} ps_opts;
+
+/* Fills *o with the defaults listed above. */
+void ps_opts_default(ps_opts *o);
+
+/*
+ * ps_create_banded -- register a banded matrix A (n x n, kl sub- and ku superdiagonals).
+ * Passage: the problem input A in C^{n x n} (Sec. 2; banded class of Sec. 3.2, eq. (matrix)).
+ *   ab    LAPACK general-band storage, column-major: A[i][j] = ab[(ku + i - j) + j * ldab]
+ *         for max(0, j - ku) <= i <= min(n - 1, j + kl); other entries are ignored.
+ *         Host pointer unless flags has PS_DEVICE_PTR.
+ *   ldab  >= kl + ku + 1.   n >= 1.   0 <= kl, ku <= n - 1; kl, ku <= 4 are supported.
+ *   flags PS_DEVICE_PTR | PS_REAL_A.   stream: used for the upload (the call waits for it).
+ *   out   receives a handle that owns a device copy of the band (plus ||A||_F).
+ * Errors: PS_ERR_INVALID (sizes, NULL), PS_ERR_NONFINITE (NaN/Inf in the band),
+ *         PS_ERR_UNSUPPORTED (kl or ku > 4), PS_ERR_HIP.
+ */
+ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t kl, int32_t ku,
+                           uint32_t flags, void *stream, ps_matrix *out);
+
+/* ps_destroy -- free the handle and its device memory (NULL is accepted). */
+ps_status ps_destroy(ps_matrix m);
+
+/* ps_matrix_info -- n, kl, ku and ||A||_F of a handle (any output may be NULL). */
+ps_status ps_matrix_info(ps_matrix m, int64_t *n, int32_t *kl, int32_t *ku, double *fro);
+
+/*
+ * ps_workspace_size -- bytes of device workspace needed by ps_eval_points / ps_eval_grid
+ * for npts shifts with options o (NULL = defaults).  The result depends on n, kl, ku, the
+ * number of slots and whether vectors are wanted, not on the shift values.
+ */
+ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes);
+
+/*
+ * ps_eval_points -- sigma_min(z_p I - A) for an explicit list of shifts (the restricted
+ * set R of Sec. 4 given as a list, or any points).
+ *   z_dev      device ps_c128[npts].   npts >= 0 (0: nothing is launched).
+ *   ws_dev     device workspace of ws_bytes >= ps_workspace_size(m, npts, o).
+ *   sigma_dev  device double[npts] (required).
+ *   u_dev, v_dev  device ps_c128[npts][n] or NULL; required when o->want_vectors.
+ *              Unit singular vectors with (zI - A) v = sigma u; the joint phase makes the
+ *              first entry of v of largest modulus real and positive.
+ *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL.
+ * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const ps_opts *o, void *ws_dev,
+                         size_t ws_bytes, double *sigma_dev, ps_c128 *u_dev, ps_c128 *v_dev, int32_t *info_dev,
+                         int32_t *iters_dev, void *stream);
+
+/*
+ * ps_eval_grid -- sigma_min on the grid G of Sec. 2.1, or on the masked subset of it.
+ *   g          grid parameters (host struct).
+ *   mask_dev   device uint8[ny][nx] or NULL.  NULL: every grid point (the plain method).
+ *              Otherwise the points with mask != 0 (the restricted region R of Sec. 4).
+ *   idx_dev    device int64[nx*ny] (required): on return idx_dev[p] is the flat grid index
+ *              of the p-th evaluated point, ascending; entries past the count are untouched.
+ *   count_dev  device int64[1] (required): number of evaluated points.
+ *   The outputs sigma_dev, u_dev, v_dev, info_dev, iters_dev are indexed by p (compacted,
+ *   like idx_dev) and must hold nx*ny entries (rows of n for u, v).
+ *   ws_dev / ws_bytes: as for ps_eval_points with npts = nx*ny.
+ *   eps, sens_dev: if sens_dev != NULL, sens_dev[p] = (sigma_dev[p] <= eps) (uint8), the
+ *              sensitive zone of Sec. 2.1 eq. (sensitive_zone) restricted to the points.
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE (grid bounds), PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, const ps_opts *o, void *ws_dev,
+                       size_t ws_bytes, int64_t *idx_dev, int64_t *count_dev, double *sigma_dev, ps_c128 *u_dev,
+                       ps_c128 *v_dev, int32_t *info_dev, int32_t *iters_dev, double eps, uint8_t *sens_dev,
+                       void *stream);
+
+/*
+ * ps_backward -- gradients of L = sum_p g_p sigma_min(z_p I - A) from the singular pairs.
+ * Passage: none in the paper (it has no gradients).  First-order perturbation of a simple
+ * singular value: d sigma = Re(u^H dM v) with dM = dz I - dA.  Conjugate-Wirtinger
+ * convention (d/dRe + i d/dIm), as torch uses for complex inputs:
+ *     grad_z[p]    = g_p conj(u_p^H v_p)
+ *     grad_A[i][j] = -sum_p g_p u_p[i] conj(v_p[j])      on the band only
+ *   (with PS_REAL_A the band gradient's imaginary part is zeroed).
+ *   grad_sigma_dev device double[npts];  u_dev, v_dev device ps_c128[npts][n] as returned by
+ *   the eval calls.  grad_z_dev: device ps_c128[npts] or NULL.  grad_band_dev: device
+ *   ps_c128 in the GB layout of ps_create_banded with ldab = kl + ku + 1 (n columns), or
+ *   NULL; overwritten (not accumulated).  The band sum uses a fixed order (deterministic).
+ *   ws_dev / ws_bytes >= ps_backward_workspace_size(m, npts).
+ * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_backward_workspace_size(ps_matrix m, int64_t npts, size_t *bytes);
+ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, const ps_c128 *u_dev,
+                      const ps_c128 *v_dev, ps_c128 *grad_z_dev, ps_c128 *grad_band_dev, void *ws_dev,
+                      size_t ws_bytes, void *stream);
+
+/* Thread-local description of the last error on the calling thread ("" if none). */
+const char *ps_last_error(void);
+
+/* Library version string. */
+const char *ps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PS_H_ */

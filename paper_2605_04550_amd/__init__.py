@@ -1,0 +1,165 @@
+"""Python binding of the MI355X sigma_min(zI - A) library (``libps.so``, C ABI in include/ps.h).
+
+The functions named ``ps_*`` mirror the C entry points one to one (argument
+marshalling only); every step of the computation runs in the HIP kernels.  PyTorch
+supplies device memory and the current stream.  Higher-level helpers
+(``BandedMatrix``, ``sigma_min``, ``eval_grid``, ``SigmaMin``, ``newton_contour``)
+live in ``paper_2605_04550_amd.api``.
+
+There is no CPU fallback: if ``libps.so`` is missing this module raises on import of
+any entry point.  Build it with ``python -m paper_2605_04550_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libps.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ps.h")
+
+PS_OK, PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP, PS_ERR_UNSUPPORTED = range(6)
+PS_PT_CONVERGED, PS_PT_SINGULAR, PS_PT_MAXITER, PS_PT_UNDERFLOW = 0, 1, 2, 4
+PS_DEVICE_PTR, PS_REAL_A = 1, 2
+
+STATUS_NAMES = {0: "PS_OK", 1: "PS_ERR_INVALID", 2: "PS_ERR_NONFINITE", 3: "PS_ERR_WORKSPACE", 4: "PS_ERR_HIP",
+                5: "PS_ERR_UNSUPPORTED"}
+
+
+class ps_c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class ps_grid(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double), ("d", ctypes.c_double),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64)]
+
+
+class ps_opts(ctypes.Structure):
+    _fields_ = [("tol_norm", ctypes.c_double), ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("want_vectors", ctypes.c_int32), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+_SIGNATURES = {
+    "ps_opts_default": (None, [ctypes.POINTER(ps_opts)]),
+    "ps_last_error": (ctypes.c_char_p, []),
+    "ps_version": (ctypes.c_char_p, []),
+    "ps_create_banded": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
+    "ps_destroy": (ctypes.c_int, [_P]),
+    "ps_matrix_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "ps_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_eval_points": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P, _P, _P,
+                                      _P, _P]),
+    "ps_eval_grid": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), _P, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t,
+                                    _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P]),
+    "ps_backward_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_backward": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+}
+
+
+def lib():
+    """The loaded ``libps.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libps.so not found at %s; build it with `python -m paper_2605_04550_amd.build` "
+                              "(there is no CPU fallback)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != PS_OK:
+        raise PsError(status, lib().ps_last_error().decode(errors="replace"))
+    return status
+
+
+def ps_last_error() -> str:
+    return lib().ps_last_error().decode(errors="replace")
+
+
+def ps_version() -> str:
+    return lib().ps_version().decode()
+
+
+def ps_opts_default(**overrides) -> ps_opts:
+    o = ps_opts()
+    lib().ps_opts_default(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def ps_create_banded(ab_ptr: int, ldab: int, n: int, kl: int, ku: int, flags: int = 0, stream: int = 0) -> int:
+    """Returns the opaque handle (an int).  ab_ptr: address of the GB band (host unless PS_DEVICE_PTR)."""
+    h = _P()
+    _check(lib().ps_create_banded(_P(ab_ptr), ldab, n, kl, ku, flags, _P(stream), ctypes.byref(h)))
+    return h.value
+
+
+def ps_destroy(handle: int) -> None:
+    _check(lib().ps_destroy(_P(handle)))
+
+
+def ps_matrix_info(handle: int):
+    n, kl, ku, fro = _I64(), _I32(), _I32(), ctypes.c_double()
+    _check(lib().ps_matrix_info(_P(handle), ctypes.byref(n), ctypes.byref(kl), ctypes.byref(ku), ctypes.byref(fro)))
+    return n.value, kl.value, ku.value, fro.value
+
+
+def ps_workspace_size(handle: int, npts: int, opts: ps_opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_workspace_size(_P(handle), npts, ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(b)))
+    return b.value
+
+
+def ps_eval_points(handle, z_ptr, npts, opts, ws_ptr, ws_bytes, sigma_ptr, u_ptr=0, v_ptr=0, info_ptr=0,
+                   iters_ptr=0, stream=0) -> None:
+    _check(lib().ps_eval_points(_P(handle), _P(z_ptr), npts, ctypes.byref(opts) if opts is not None else None,
+                                _P(ws_ptr), ws_bytes, _P(sigma_ptr), _P(u_ptr), _P(v_ptr), _P(info_ptr),
+                                _P(iters_ptr), _P(stream)))
+
+
+def ps_eval_grid(handle, grid: ps_grid, mask_ptr, opts, ws_ptr, ws_bytes, idx_ptr, count_ptr, sigma_ptr, u_ptr=0,
+                 v_ptr=0, info_ptr=0, iters_ptr=0, eps=0.0, sens_ptr=0, stream=0) -> None:
+    _check(lib().ps_eval_grid(_P(handle), ctypes.byref(grid), _P(mask_ptr),
+                              ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes, _P(idx_ptr),
+                              _P(count_ptr), _P(sigma_ptr), _P(u_ptr), _P(v_ptr), _P(info_ptr), _P(iters_ptr),
+                              float(eps), _P(sens_ptr), _P(stream)))
+
+
+def ps_backward_workspace_size(handle: int, npts: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_backward_workspace_size(_P(handle), npts, ctypes.byref(b)))
+    return b.value
+
+
+def ps_backward(handle, npts, grad_sigma_ptr, u_ptr, v_ptr, grad_z_ptr, grad_band_ptr, ws_ptr, ws_bytes,
+                stream=0) -> None:
+    _check(lib().ps_backward(_P(handle), npts, _P(grad_sigma_ptr), _P(u_ptr), _P(v_ptr), _P(grad_z_ptr),
+                             _P(grad_band_ptr), _P(ws_ptr), ws_bytes, _P(stream)))
+
+
+def header_symbols():
+    """Names of the functions declared in include/ps.h."""
+    import re
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ps_[a-z_0-9]+)\s*\(", text)) - {"ps_c128"})

@@ -1,0 +1,179 @@
+"""Torch-facing helpers over the C ABI (device memory and streams from torch, compute in HIP).
+
+* ``BandedMatrix``   -- owns a ``ps_matrix`` handle (ps_create_banded / ps_destroy).
+* ``sigma_min``      -- ps_eval_points on a complex128 CUDA tensor of shifts.
+* ``eval_grid``      -- ps_eval_grid on the grid of Sec. 2.1, optionally restricted by a mask (Sec. 4).
+* ``SigmaMin``       -- torch.autograd.Function: forward = ps_eval_points with vectors,
+                        backward = ps_backward (gradients w.r.t. the shifts and the band).
+* ``newton_contour`` -- Newton steps moving points onto the level curve sigma_min = eps.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import (PS_DEVICE_PTR, PS_REAL_A, ps_backward, ps_backward_workspace_size, ps_create_banded, ps_destroy,
+               ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_opts_default, ps_workspace_size)
+
+__all__ = ["BandedMatrix", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0):
+    return ps_opts_default(tol_norm=tol_norm, tol_rel=tol_rel, max_iter=max_iter,
+                           want_vectors=int(bool(want_vectors)), slots=int(slots))
+
+
+class BandedMatrix:
+    """A banded matrix registered with the library (GB storage, see include/ps.h)."""
+
+    def __init__(self, ab, n: int, kl: int, ku: int, real: bool = False):
+        if isinstance(ab, torch.Tensor):
+            t = ab.detach().to(torch.complex128).contiguous()
+            flags = PS_DEVICE_PTR if t.is_cuda else 0
+            ptr = t.data_ptr()
+            keep = t
+        else:
+            keep = np.ascontiguousarray(ab, dtype=np.complex128)
+            flags = 0
+            ptr = keep.ctypes.data
+        if real:
+            flags |= PS_REAL_A
+        self.handle = ps_create_banded(ptr, kl + ku + 1, n, kl, ku, flags, _stream_handle() if flags & 1 else 0)
+        del keep
+        self.n, self.kl, self.ku, self.fro = ps_matrix_info(self.handle)
+        self.real = real
+
+    @classmethod
+    def from_band(cls, band):
+        return cls(band.ab, band.n, band.kl, band.ku, real=bool(getattr(band, "real", False)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ps_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_norm=1e-10, tol_rel=1e-8,
+              max_iter=3000, slots=0, workspace: torch.Tensor | None = None, stream=None):
+    """sigma_min(z_p I - A) for every entry of the complex128 CUDA tensor z.  Returns a dict
+    with ``sigma`` (float64), ``info`` and ``iters`` (int32), and ``u``, ``v`` ([npts, n]) if asked."""
+    assert z.is_cuda and z.dtype == torch.complex128
+    z = z.contiguous()
+    npts = z.numel()
+    dev = z.device
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots)
+    out = dict(sigma=torch.empty(npts, dtype=torch.float64, device=dev),
+               info=torch.empty(npts, dtype=torch.int32, device=dev),
+               iters=torch.empty(npts, dtype=torch.int32, device=dev))
+    if want_vectors:
+        out["u"] = torch.empty((npts, mat.n), dtype=torch.complex128, device=dev)
+        out["v"] = torch.empty((npts, mat.n), dtype=torch.complex128, device=dev)
+    if npts == 0:
+        return out
+    need = ps_workspace_size(mat.handle, npts, o)
+    ws = workspace if workspace is not None else _workspace(need, dev)
+    ps_eval_points(mat.handle, z.data_ptr(), npts, o, ws.data_ptr(), ws.numel(), out["sigma"].data_ptr(),
+                   out["u"].data_ptr() if want_vectors else 0, out["v"].data_ptr() if want_vectors else 0,
+                   out["info"].data_ptr(), out["iters"].data_ptr(), _stream_handle(stream))
+    return out
+
+
+def eval_grid(mat: BandedMatrix, grid, mask: torch.Tensor | None = None, *, eps=None, want_vectors=False,
+              tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, device=None, stream=None,
+              workspace: torch.Tensor | None = None):
+    """sigma_min on the grid (a, b, c, d, nx, ny) of Sec. 2.1, or on the points where ``mask`` (uint8
+    [ny, nx] CUDA tensor) is nonzero.  Outputs are compacted: entry p belongs to flat grid index
+    ``idx[p]``, for p < ``count``."""
+    g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
+    npts = g.nx * g.ny
+    dev = mask.device if mask is not None else (device or torch.device("cuda"))
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots)
+    out = dict(idx=torch.empty(npts, dtype=torch.int64, device=dev),
+               count=torch.zeros(1, dtype=torch.int64, device=dev),
+               sigma=torch.empty(npts, dtype=torch.float64, device=dev),
+               info=torch.empty(npts, dtype=torch.int32, device=dev),
+               iters=torch.empty(npts, dtype=torch.int32, device=dev))
+    if eps is not None:
+        out["sens"] = torch.empty(npts, dtype=torch.uint8, device=dev)
+    if want_vectors:
+        out["u"] = torch.empty((npts, mat.n), dtype=torch.complex128, device=dev)
+        out["v"] = torch.empty((npts, mat.n), dtype=torch.complex128, device=dev)
+    if mask is not None:
+        assert mask.is_cuda and mask.dtype == torch.uint8 and mask.numel() == npts
+        mask = mask.contiguous()
+    need = ps_workspace_size(mat.handle, npts, o)
+    ws = workspace if workspace is not None else _workspace(need, dev)
+    ps_eval_grid(mat.handle, g, mask.data_ptr() if mask is not None else 0, o, ws.data_ptr(), ws.numel(),
+                 out["idx"].data_ptr(), out["count"].data_ptr(), out["sigma"].data_ptr(),
+                 out["u"].data_ptr() if want_vectors else 0, out["v"].data_ptr() if want_vectors else 0,
+                 out["info"].data_ptr(), out["iters"].data_ptr(), float(eps) if eps is not None else 0.0,
+                 out["sens"].data_ptr() if eps is not None else 0, _stream_handle(stream))
+    return out
+
+
+def backward(mat: BandedMatrix, grad_sigma: torch.Tensor, u: torch.Tensor, v: torch.Tensor, want_z=True,
+             want_band=True, stream=None):
+    """ps_backward: returns (grad_z [npts] complex128, grad_band [n, kl+ku+1] complex128 in GB layout)."""
+    npts = grad_sigma.numel()
+    dev = grad_sigma.device
+    gz = torch.empty(npts, dtype=torch.complex128, device=dev) if want_z else None
+    gb = torch.empty((mat.n, mat.kl + mat.ku + 1), dtype=torch.complex128, device=dev) if want_band else None
+    need = ps_backward_workspace_size(mat.handle, npts)
+    ws = _workspace(need, dev)
+    ps_backward(mat.handle, npts, grad_sigma.contiguous().data_ptr(), u.contiguous().data_ptr(),
+                v.contiguous().data_ptr(), gz.data_ptr() if gz is not None else 0,
+                gb.data_ptr() if gb is not None else 0, ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    return gz, gb
+
+
+class SigmaMin(torch.autograd.Function):
+    """sigma = SigmaMin.apply(band, z, mat): band is the complex128 GB tensor the handle was built from
+    (only its gradient slot is used), z the shifts.  Gradients follow the conjugate-Wirtinger
+    convention torch uses for complex tensors."""
+
+    @staticmethod
+    def forward(ctx, band, z, mat, tol_norm=1e-10, tol_rel=1e-8):
+        r = sigma_min(mat, z.detach(), want_vectors=True, tol_norm=tol_norm, tol_rel=tol_rel)
+        ctx.mat = mat
+        ctx.save_for_backward(r["u"], r["v"])
+        ctx.band_shape = band.shape
+        return r["sigma"]
+
+    @staticmethod
+    def backward(ctx, g):
+        u, v = ctx.saved_tensors
+        mat = ctx.mat
+        gz, gb = backward(mat, g.to(torch.float64), u, v, want_z=ctx.needs_input_grad[1],
+                          want_band=ctx.needs_input_grad[0])
+        return gb, gz, None, None, None
+
+
+def newton_contour(mat: BandedMatrix, z0: torch.Tensor, eps: float, steps: int = 3):
+    """Newton on phi(z) = ln(sigma_min(z)/eps) along its gradient g = conj(u^H v):
+    z <- z - sigma ln(sigma/eps) g / |g|^2.  Returns the refined points and their sigma."""
+    z = z0.clone()
+    for _ in range(steps):
+        r = sigma_min(mat, z, want_vectors=True, tol_rel=1e-12, tol_norm=1e-14)
+        gz, _ = backward(mat, torch.ones_like(r["sigma"]), r["u"], r["v"], want_band=False)
+        s = r["sigma"]
+        z = z - (s * torch.log(s / eps)).to(torch.complex128) * gz / (gz.abs() ** 2)
+    r = sigma_min(mat, z, tol_rel=1e-12, tol_norm=1e-14)
+    return z, r["sigma"]

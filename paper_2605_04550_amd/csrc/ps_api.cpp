@@ -1,0 +1,345 @@
+// Host side of the C ABI declared in include/ps.h: argument validation, the matrix
+// handle, workspace planning and kernel launches on the caller's stream.
+
+#include "../../include/ps.h"
+#include "ps_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+struct ps_matrix_s {
+    int64_t n;
+    int32_t kl, ku;
+    uint32_t flags;
+    double fro;
+    double2 *arow;   // device, [n][kl+ku+1]
+    int device;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+ps_status fail(ps_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+ps_status ok() {
+    g_err[0] = 0;
+    return PS_OK;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(PS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kSlotQuantum = 256;
+constexpr int64_t kMaxSlots = 131072;
+constexpr double kDefaultWsBudget = 48.0 * (1ull << 30);   // bytes the default plan may use
+constexpr int kVecBasisMax = 64;
+
+ps_opts resolve(const ps_opts *o) {
+    ps_opts r;
+    ps_opts_default(&r);
+    if (o) r = *o;
+    return r;
+}
+
+ps_status check_opts(const ps_opts &o) {
+    if (!(o.tol_norm >= 0.0) || !(o.tol_rel >= 0.0) || !isfinite(o.tol_norm) || !isfinite(o.tol_rel))
+        return fail(PS_ERR_INVALID, "tolerances must be finite and >= 0");
+    if (o.tol_norm == 0.0 && o.tol_rel == 0.0) return fail(PS_ERR_INVALID, "tol_norm and tol_rel are both 0");
+    if (o.max_iter < 1 || o.max_iter > ps::kMaxIterCap)
+        return fail(PS_ERR_INVALID, "max_iter must be in [1, %d]", ps::kMaxIterCap);
+    if (o.slots < 0) return fail(PS_ERR_INVALID, "slots must be >= 0");
+    return PS_OK;
+}
+
+int kvec_of(const ps_opts &o) { return o.want_vectors ? (o.max_iter < kVecBasisMax ? o.max_iter : kVecBasisMax) : 0; }
+
+int64_t round_slots(int64_t s) {
+    s = (s / kSlotQuantum) * kSlotQuantum;
+    return s;
+}
+
+// Slots of the default plan for npts shifts.
+int64_t default_slots(const ps_matrix_s *m, int64_t npts, const ps_opts &o) {
+    int64_t want = ((npts + kSlotQuantum - 1) / kSlotQuantum) * kSlotQuantum;
+    if (o.slots > 0) want = round_slots(o.slots);
+    if (want < kSlotQuantum) want = kSlotQuantum;
+    if (want > kMaxSlots) want = kMaxSlots;
+    const int kvec = kvec_of(o);
+    // shrink until the workspace fits the default budget
+    while (want > kSlotQuantum &&
+           (double)ps::workspace_bytes(m->n, m->kl, m->ku, want, o.max_iter, kvec, npts) > kDefaultWsBudget)
+        want -= kSlotQuantum;
+    return want;
+}
+
+// Largest slot count <= the default whose workspace fits ws_bytes (0 if none).
+int64_t slots_for(const ps_matrix_s *m, int64_t npts, const ps_opts &o, size_t ws_bytes) {
+    int64_t s = default_slots(m, npts, o);
+    const int kvec = kvec_of(o);
+    while (s >= kSlotQuantum && ps::workspace_bytes(m->n, m->kl, m->ku, s, o.max_iter, kvec, npts) > ws_bytes)
+        s -= kSlotQuantum;
+    return s >= kSlotQuantum ? s : 0;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+ps_status check_handle(ps_matrix m) {
+    if (!m) return fail(PS_ERR_INVALID, "matrix handle is NULL");
+    return PS_OK;
+}
+
+ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws, size_t ws_bytes, double *sigma,
+                       ps_c128 *u, ps_c128 *v, ps::Workspace *w, ps::EvalArgs *a) {
+    if (!sigma) return fail(PS_ERR_INVALID, "sigma output is NULL");
+    if (o.want_vectors && (!u || !v)) return fail(PS_ERR_INVALID, "want_vectors needs u and v outputs");
+    if (!ws) return fail(PS_ERR_WORKSPACE, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    int64_t slots = slots_for(m, npts_max, o, ws_bytes);
+    if (slots == 0)
+        return fail(PS_ERR_WORKSPACE, "workspace of %zu bytes is below the minimum %zu", ws_bytes,
+                    ps::workspace_bytes(m->n, m->kl, m->ku, kSlotQuantum, o.max_iter, kvec_of(o), npts_max));
+    ps::carve_workspace(ws, m->n, m->kl, m->ku, slots, o.max_iter, kvec_of(o), npts_max, w);
+    a->n = m->n;
+    a->kl = m->kl;
+    a->ku = m->ku;
+    a->arow = m->arow;
+    a->normA = m->fro;
+    a->tol_norm = o.tol_norm;
+    a->tol_rel = o.tol_rel;
+    a->max_iter = o.max_iter;
+    a->want_vectors = o.want_vectors;
+    a->sigma = sigma;
+    a->u = (double2 *)u;
+    a->v = (double2 *)v;
+    a->count_dev = w->count;
+    return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ps_opts_default(ps_opts *o) {
+    if (!o) return;
+    o->tol_norm = 1e-10;
+    o->tol_rel = 1e-8;
+    o->max_iter = 3000;
+    o->want_vectors = 0;
+    o->slots = 0;
+    o->reserved = 0;
+}
+
+const char *ps_last_error(void) { return g_err; }
+
+const char *ps_version(void) { return "ps-mi355x 0.1 (gfx950, fp64)"; }
+
+ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t kl, int32_t ku, uint32_t flags,
+                           void *stream, ps_matrix *out) {
+    if (!out) return fail(PS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ab) return fail(PS_ERR_INVALID, "ab is NULL");
+    if (n < 1) return fail(PS_ERR_INVALID, "n must be >= 1 (got %lld)", (long long)n);
+    if (kl < 0 || ku < 0 || kl > n - 1 || ku > n - 1)
+        return fail(PS_ERR_INVALID, "need 0 <= kl, ku <= n - 1 (kl=%d ku=%d n=%lld)", kl, ku, (long long)n);
+    if (ldab < (int64_t)kl + ku + 1) return fail(PS_ERR_INVALID, "ldab must be >= kl + ku + 1");
+    if (flags & ~(uint32_t)(PS_DEVICE_PTR | PS_REAL_A)) return fail(PS_ERR_INVALID, "unknown flags");
+    if (kl > ps::kMaxKL || ku > ps::kMaxKU)
+        return fail(PS_ERR_UNSUPPORTED, "kl and ku must be <= %d (got kl=%d ku=%d)", ps::kMaxKL, kl, ku);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t w = (int64_t)kl + ku + 1;
+    std::vector<ps_c128> gb((size_t)(ldab * n));
+    if (flags & PS_DEVICE_PTR) {
+        HIP_TRY(hipMemcpyAsync(gb.data(), ab, sizeof(ps_c128) * gb.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        memcpy(gb.data(), ab, sizeof(ps_c128) * gb.size());
+    }
+    std::vector<double2> rows((size_t)(n * w));
+    double fro2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t d = 0; d < w; ++d) {
+            int64_t j = i - kl + d;
+            double2 v = make_double2(0.0, 0.0);
+            if (j >= 0 && j < n) {
+                ps_c128 e = gb[(size_t)((ku + i - j) + j * ldab)];
+                if (!isfinite(e.re) || !isfinite(e.im))
+                    return fail(PS_ERR_NONFINITE, "non-finite band entry A[%lld][%lld]", (long long)i, (long long)j);
+                v = make_double2(e.re, e.im);
+                fro2 += e.re * e.re + e.im * e.im;
+            }
+            rows[(size_t)(i * w + d)] = v;
+        }
+    }
+    ps_matrix m = new ps_matrix_s();
+    m->n = n;
+    m->kl = kl;
+    m->ku = ku;
+    m->flags = flags;
+    m->fro = sqrt(fro2);
+    m->arow = nullptr;
+    (void)hipGetDevice(&m->device);
+    hipError_t e = hipMalloc((void **)&m->arow, sizeof(double2) * rows.size());
+    if (e != hipSuccess) {
+        delete m;
+        return fail(PS_ERR_HIP, "hipMalloc of the band: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(m->arow, rows.data(), sizeof(double2) * rows.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(m->arow);
+        delete m;
+        return fail(PS_ERR_HIP, "band upload: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return ok();
+}
+
+ps_status ps_destroy(ps_matrix m) {
+    if (!m) return ok();
+    if (m->arow) (void)hipFree(m->arow);
+    delete m;
+    return ok();
+}
+
+ps_status ps_matrix_info(ps_matrix m, int64_t *n, int32_t *kl, int32_t *ku, double *fro) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (n) *n = m->n;
+    if (kl) *kl = m->kl;
+    if (ku) *ku = m->ku;
+    if (fro) *fro = m->fro;
+    return ok();
+}
+
+ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    ps_opts r = resolve(o);
+    if ((st = check_opts(r))) return st;
+    int64_t slots = default_slots(m, npts, r);
+    *bytes = ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, kvec_of(r), npts);
+    return ok();
+}
+
+ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const ps_opts *o, void *ws_dev,
+                         size_t ws_bytes, double *sigma_dev, ps_c128 *u_dev, ps_c128 *v_dev, int32_t *info_dev,
+                         int32_t *iters_dev, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    ps_opts r = resolve(o);
+    if ((st = check_opts(r))) return st;
+    if (npts == 0) return ok();
+    if (!z_dev) return fail(PS_ERR_INVALID, "z is NULL");
+    ps::Workspace w;
+    ps::EvalArgs a;
+    if ((st = prepare_eval(m, npts, r, ws_dev, ws_bytes, sigma_dev, u_dev, v_dev, &w, &a))) return st;
+    a.mode = ps::kShiftList;
+    a.z = (const double2 *)z_dev;
+    a.info = info_dev;
+    a.iters = iters_dev;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
+    HIP_TRY(ps::launch_eval(a, w, s));
+    return ok();
+}
+
+ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, const ps_opts *o, void *ws_dev,
+                       size_t ws_bytes, int64_t *idx_dev, int64_t *count_dev, double *sigma_dev, ps_c128 *u_dev,
+                       ps_c128 *v_dev, int32_t *info_dev, int32_t *iters_dev, double eps, uint8_t *sens_dev,
+                       void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (!g) return fail(PS_ERR_INVALID, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1) return fail(PS_ERR_INVALID, "grid needs nx, ny >= 1");
+    if (!isfinite(g->a) || !isfinite(g->b) || !isfinite(g->c) || !isfinite(g->d))
+        return fail(PS_ERR_NONFINITE, "non-finite grid bounds");
+    if (g->nx > (int64_t)1 << 31 || g->ny > (int64_t)1 << 31 || g->nx * g->ny > ((int64_t)1 << 40))
+        return fail(PS_ERR_INVALID, "grid too large");
+    if (!idx_dev || !count_dev) return fail(PS_ERR_INVALID, "idx and count outputs are required");
+    if (sens_dev && !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite");
+    ps_opts r = resolve(o);
+    if ((st = check_opts(r))) return st;
+    const int64_t npts = g->nx * g->ny;
+    ps::Workspace w;
+    ps::EvalArgs a;
+    if ((st = prepare_eval(m, npts, r, ws_dev, ws_bytes, sigma_dev, u_dev, v_dev, &w, &a))) return st;
+    a.mode = ps::kShiftGrid;
+    a.ga = g->a;
+    a.gb = g->b;
+    a.gc = g->c;
+    a.gd = g->d;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.info = info_dev;
+    a.iters = iters_dev;
+    a.eps = eps;
+    a.sens = sens_dev;
+    hipStream_t s = (hipStream_t)stream;
+    if (mask_dev) {
+        HIP_TRY(ps::launch_compact_mask(mask_dev, npts, idx_dev, w.count, w.blocksums, w.queue, s));
+        a.idx = idx_dev;
+    } else {
+        HIP_TRY(ps::launch_iota(idx_dev, npts, s));
+        HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
+        a.idx = nullptr;
+    }
+    a.count_dev = w.count;
+    HIP_TRY(hipMemcpyAsync(count_dev, w.count, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ps::launch_eval(a, w, s));
+    return ok();
+}
+
+ps_status ps_backward_workspace_size(ps_matrix m, int64_t npts, size_t *bytes) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    int64_t rows = ps::backward_partial_rows(npts);
+    *bytes = sizeof(double2) * (size_t)(rows > 0 ? rows : 1) * (size_t)m->n * (size_t)(m->kl + m->ku + 1);
+    return ok();
+}
+
+ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, const ps_c128 *u_dev,
+                      const ps_c128 *v_dev, ps_c128 *grad_z_dev, ps_c128 *grad_band_dev, void *ws_dev,
+                      size_t ws_bytes, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    if (!grad_z_dev && !grad_band_dev) return ok();
+    if (npts > 0 && (!grad_sigma_dev || !u_dev || !v_dev))
+        return fail(PS_ERR_INVALID, "grad_sigma, u and v are required");
+    hipStream_t s = (hipStream_t)stream;
+    if (npts == 0) {
+        if (grad_band_dev)
+            HIP_TRY(hipMemsetAsync(grad_band_dev, 0, sizeof(ps_c128) * (size_t)m->n * (m->kl + m->ku + 1), s));
+        return ok();
+    }
+    size_t need = 0;
+    ps_backward_workspace_size(m, npts, &need);
+    if (grad_band_dev && (!ws_dev || ws_bytes < need))
+        return fail(PS_ERR_WORKSPACE, "backward workspace needs %zu bytes (got %zu)", need, ws_bytes);
+    HIP_TRY(ps::launch_backward(m->n, m->kl, m->ku, npts, grad_sigma_dev, (const double2 *)u_dev,
+                                (const double2 *)v_dev, (double2 *)grad_z_dev, (double2 *)grad_band_dev,
+                                (double2 *)ws_dev, (m->flags & PS_REAL_A) ? 1 : 0, s));
+    return ok();
+}
+
+}  // extern "C"

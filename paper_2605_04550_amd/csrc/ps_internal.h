@@ -1,0 +1,86 @@
+// Internal declarations shared by the host layer (ps_api.cpp) and the kernels
+// (ps_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ps {
+
+// Maximum supported bandwidths of the compiled kernels.
+constexpr int kMaxKL = 4;
+constexpr int kMaxKU = 4;
+constexpr int kMaxIterCap = 4096;
+
+// Where the shifts of one evaluation come from.
+enum ShiftMode : int {
+    kShiftList = 0,   // z[p] from a device array
+    kShiftGrid = 1,   // grid point with flat index idx[p] (idx == nullptr: flat index p)
+};
+
+// Workspace carve-up of one evaluation: slots lanes, each with its own banded LU,
+// three Lanczos vectors with per-row binary exponents and the bidiagonal history.
+// Every per-slot array is laid out [row][component][slot] so that the 64 lanes of a
+// wavefront touch 64 consecutive elements.
+struct Workspace {
+    int64_t slots = 0;
+    double2 *L = nullptr;          // [n][kl][slots]   multipliers of column i
+    double2 *U = nullptr;          // [n][w][slots]    U[i][i+d], d = 0 holds 1/U[i][i]
+    uint8_t *piv = nullptr;        // [n][slots]       pivot row offset (0..kl)
+    double2 *vu = nullptr;         // [n][slots]       Lanczos vector u (unnormalised)
+    double2 *vv = nullptr;         // [n][slots]       Lanczos vector v (unnormalised)
+    double2 *vy = nullptr;         // [n][slots]       intermediate of the two-factor solves
+    int16_t *eu = nullptr;         // [n][slots]       binary exponent of each vu row
+    int16_t *ev = nullptr;
+    int16_t *ey = nullptr;
+    double *hist = nullptr;        // [kmax][2][slots] Lanczos tridiagonal: diag, offdiag^2
+    double2 *basis = nullptr;      // [kvec][n][slots] u-basis kept for singular vectors
+    int16_t *ebasis = nullptr;     // [kvec][n][slots]
+    double *bmeta = nullptr;       // [kvec][2][slots] per basis vector: 1/norm, exponent
+    unsigned long long *queue = nullptr;   // shift counter of the persistent launch
+    int64_t *count = nullptr;      // number of shifts (device)
+    int64_t *blocksums = nullptr;  // mask compaction scratch
+    int kmax = 0;
+    int kvec = 0;
+};
+
+struct EvalArgs {
+    int64_t n = 0;
+    int kl = 0, ku = 0;
+    const double2 *arow = nullptr; // [n][kl+ku+1] row band, zero outside the matrix
+    double normA = 0.0;
+    int mode = kShiftList;
+    const double2 *z = nullptr;
+    const int64_t *idx = nullptr;
+    double ga = 0, gb = 0, gc = 0, gd = 0;
+    int64_t nx = 1, ny = 1;
+    const int64_t *count_dev = nullptr;   // device count of shifts
+    double tol_norm = 1e-10, tol_rel = 1e-8;
+    int max_iter = 1000;
+    int want_vectors = 0;
+    uint64_t seed = 0x2605045500000001ull;
+    double *sigma = nullptr;
+    double2 *u = nullptr;
+    double2 *v = nullptr;
+    int32_t *info = nullptr;
+    int32_t *iters = nullptr;
+    double eps = 0.0;
+    uint8_t *sens = nullptr;
+};
+
+size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max);
+void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max,
+                     Workspace *ws);
+
+// Kernel launchers (enqueue on stream; return hipError_t of the launch).
+hipError_t launch_iota(int64_t *idx, int64_t npts, hipStream_t st);
+hipError_t launch_set_count(int64_t *count, int64_t value, unsigned long long *queue, hipStream_t st);
+hipError_t launch_compact_mask(const uint8_t *mask, int64_t npts, int64_t *idx, int64_t *count, int64_t *blocksums,
+                               unsigned long long *queue, hipStream_t st);
+hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st);
+hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double *g, const double2 *u,
+                           const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,
+                           hipStream_t st);
+int64_t backward_partial_rows(int64_t npts);
+
+}  // namespace ps
