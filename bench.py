@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=1)
+    ap.add_argument("--progress", action="store_true", help="synchronise and report after every timed step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,11 +102,18 @@ def main():
         ev[3].record(stream)
         return rf, rm, ev
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        print("bench: warmup step %d done" % (i + 1), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [step() for _ in range(args.steps)]
+    runs = []
+    for i in range(args.steps):
+        runs.append(step())
+        if args.progress:
+            torch.cuda.synchronize()
+            print("bench: step %d done (%.1f s)" % (i + 1, time.perf_counter() - t0), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -170,6 +178,7 @@ def main():
         import oracle
         zs = oracle.grid_points(grid)[rng.choice(npts_full, size=args.cpu_points, replace=False)]
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        print("bench: timing the CPU oracle on %d point(s)" % len(zs), file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(band, zs, threads)
     print(json.dumps(out), flush=True)
 

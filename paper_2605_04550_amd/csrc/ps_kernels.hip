@@ -186,7 +186,7 @@ struct Lane {
     int Eu, Ev, Ey;   // max row exponent of u, v, y
     double rdu, rdv;  // 1 / (norm mantissa) of u, v
     double nrm_h;     // squared norm of the start vector (fresh lanes)
-    bool active, fresh, sing, exhausted;
+    bool active, fresh, sing, exhausted, pending;
 };
 
 template <int KL, int KU, bool VEC>
@@ -387,12 +387,12 @@ struct Kern {
 
     // ---------------------------------------------------------------- forward sweep 2
     // y = U^{-H} u_k (u_k read normalised), column-oriented forward substitution.
-    static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+    static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, bool from_vu = false) {
         const int64_t n = a.n, T = w.slots;
         const bool act = ln.active;
         const double2 *uin = w.vu;
         const int16_t *euin = w.eu;
-        if (VEC) {
+        if (VEC && !from_vu) {
             int64_t stride = (int64_t)n * T;
             uin = w.basis + (int64_t)(ln.k - 1) * stride;
             euin = w.ebasis + (int64_t)(ln.k - 1) * stride;
@@ -489,18 +489,26 @@ struct Kern {
     }
 
     // ---------------------------------------------------------------- singular vectors
-    // v_min = U_k p (p: top left singular vector of B_k), u_min = M v_min / |M v_min|.
-    static __device__ void vectors(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double sigma) {
-        const int64_t n = a.n, T = w.slots;
+    // For every lane whose shift converged (ln.pending), all lanes of the wavefront together:
+    //   q = top eigenvector of T_k (two steps of inverse iteration at theta (1 + 2^-40)),
+    //   p = B_k q / |B_k q| (top left singular vector of the bidiagonal),
+    //   v = U_k p  (Ritz vector: right singular vector of M = zI - A), assembled in vu,
+    //   u = M^{-H} v / |M^{-H} v| through the lane's LU factors (one inverse-iteration
+    //       step: M^{-H} v_min = u_min / sigma_min, so the error in u shrinks by the gap
+    //       instead of growing by |M| / sigma as it would for u = M v / sigma),
+    // then both are written to the caller's [npts][n] arrays with the joint phase that makes
+    // the first entry of v of largest modulus real and positive.
+    static __device__ void ritz_coeffs(const Workspace &w, int64_t s, const Lane &ln) {
+        const int64_t T = w.slots;
         const int k = ln.k;
         // bmeta rows: [0, 2kvec) basis meta (1/norm, exponent); [2kvec, 3kvec) q;
         // [3kvec, 4kvec) pivots, then p; [4kvec, 6kvec) alpha'_j, beta'_j.
         double *q = w.bmeta + (int64_t)(2 * w.kvec) * T;
-        // top eigenvector of T_k by two steps of inverse iteration at theta (1 + 2^-40)
-        double mu = ln.theta * (1.0 + 0x1p-40) + 1e-300;
+        double *aux = q + (int64_t)w.kvec * T;
+        const double *ab = q + (int64_t)(2 * w.kvec) * T;
+        double mu = ln.theta * (1.0 + 0x1p-40);
         for (int j = 0; j < k; ++j) q[(int64_t)j * T + s] = 1.0;
         for (int it = 0; it < 2; ++it) {
-            // LDL^T of T - mu I (all pivots negative), solve in place
             double dprev = 0.0;
             for (int j = 0; j < k; ++j) {
                 double dj = w.hist[((int64_t)j * 2 + 0) * T + s] - mu;
@@ -512,19 +520,14 @@ struct Kern {
                     rhs -= lj * q[(int64_t)(j - 1) * T + s];
                 }
                 q[(int64_t)j * T + s] = rhs;
-                q[((int64_t)w.kvec + j) * T + s] = dj;   // pivot d_j
+                aux[(int64_t)j * T + s] = dj;
                 dprev = dj;
             }
-            // back substitution: x_j = (rhs_j - e_j x_{j+1}) / d_j  with L^T entries l_{j+1} = e_j / d_j
-            double xnext = 0.0;
-            double nrm = 0.0;
+            double xnext = 0.0, nrm = 0.0;
             for (int j = k - 1; j >= 0; --j) {
-                double dj = q[((int64_t)w.kvec + j) * T + s];
+                double dj = aux[(int64_t)j * T + s];
                 double x = q[(int64_t)j * T + s] / dj;
-                if (j < k - 1) {
-                    double e = sqrt(w.hist[((int64_t)j * 2 + 1) * T + s]);
-                    x -= (e / dj) * xnext;
-                }
+                if (j < k - 1) x -= (sqrt(w.hist[((int64_t)j * 2 + 1) * T + s]) / dj) * xnext;
                 q[(int64_t)j * T + s] = x;
                 xnext = x;
                 nrm += x * x;
@@ -532,55 +535,69 @@ struct Kern {
             double rn = 1.0 / sqrt(nrm);
             for (int j = 0; j < k; ++j) q[(int64_t)j * T + s] *= rn;
         }
-        // p = B_k q (upper bidiagonal: alpha'_j on the diagonal, beta'_j above it)
-        double *ab = q + (int64_t)(2 * w.kvec) * T;
         double pn = 0.0;
         for (int j = 0; j < k; ++j) {
             double pj = ab[((int64_t)j * 2 + 0) * T + s] * q[(int64_t)j * T + s];
             if (j + 1 < k) pj += ab[((int64_t)j * 2 + 1) * T + s] * q[(int64_t)(j + 1) * T + s];
-            q[((int64_t)w.kvec + j) * T + s] = pj;
+            aux[(int64_t)j * T + s] = pj;
             pn += pj * pj;
         }
         double rpn = 1.0 / sqrt(pn);
-        // v = sum_j p_j u_j, u_j = basis_j * (1/norm_j) * 2^(e - E_j)
-        double2 *vout = a.v + ln.pid * n;
-        double2 *uout = a.u + ln.pid * n;
+        for (int j = 0; j < k; ++j) aux[(int64_t)j * T + s] *= rpn;
+    }
+
+    static __device__ void vec_finalize(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        const int64_t n = a.n, T = w.slots;
+        const bool pend = ln.pending;
+        if (pend) ritz_coeffs(w, s, ln);
+        const double *coef = w.bmeta + (int64_t)(3 * w.kvec) * T;
         const int64_t stride = (int64_t)n * T;
+        const int k = ln.k;
         double vn = 0.0, amax = -1.0;
         cd vph = C(1.0, 0.0);
         for (int64_t i = 0; i < n; ++i) {
+            if (!pend) continue;
             cd acc = czero();
             for (int j = 0; j < k; ++j) {
                 double rd = w.bmeta[((int64_t)j * 2 + 0) * T + s];
                 int Ej = (int)w.bmeta[((int64_t)j * 2 + 1) * T + s];
                 cd uj = cldexp(cscale(w.basis[j * stride + i * T + s], rd), (int)w.ebasis[j * stride + i * T + s] - Ej);
-                double c = q[((int64_t)w.kvec + j) * T + s] * rpn;
+                double c = coef[(int64_t)j * T + s];
                 acc = C(fma(c, uj.x, acc.x), fma(c, uj.y, acc.y));
             }
-            vout[i] = acc;
+            w.vu[i * T + s] = acc;
+            w.eu[i * T + s] = 0;
             vn += cabs2(acc);
-            double m = sqrt(cabs2(acc));
+            double m = cabs2(acc);
             if (m > amax) { amax = m; vph = acc; }
         }
-        // phase: first max-modulus entry of v real positive; normalise
-        double rv = 1.0 / sqrt(vn);
-        cd ph = amax > 0.0 ? C(vph.x / amax * rv, -vph.y / amax * rv) : C(rv, 0.0);
-        for (int64_t i = 0; i < n; ++i) vout[i] = cmul(vout[i], ph);
-        // u = M v / |M v|
-        double un = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            cd acc = cmul(ln.z, vout[i]);
-#pragma unroll
-            for (int d = 0; d < W; ++d) {
-                int64_t c = i - KL + d;
-                if (c >= 0 && c < n) acc = cfnma(a.arow[i * W + d], vout[c], acc);
-            }
-            uout[i] = acc;
-            un += cabs2(acc);
+        // u direction: M^{-H} v through the factors (alpha = 0: no three-term correction)
+        const bool saved = ln.active;
+        ln.active = pend;
+        if (pend) {
+            ln.Eu = 0;
+            ln.rdu = 1.0 / sqrt(vn);
+            ln.a_m = 0.0;
+            ln.a_e = 0;
         }
-        double ru = un > 0.0 ? 1.0 / sqrt(un) : 0.0;
-        for (int64_t i = 0; i < n; ++i) uout[i] = cscale(uout[i], ru);
-        (void)sigma;
+        f2(a, w, s, ln, true);
+        double accu;
+        int eaccu;
+        b2(a, w, s, ln, accu, eaccu);
+        ln.active = saved;
+        if (!pend) return;
+        double am = sqrt(amax);
+        cd ph = am > 0.0 ? C(vph.x / am, -vph.y / am) : C(1.0, 0.0);
+        double rv = 1.0 / sqrt(vn);
+        double ru = 1.0 / sqrt(accu);
+        double2 *vout = a.v + ln.pid * n;
+        double2 *uout = a.u + ln.pid * n;
+        for (int64_t i = 0; i < n; ++i) {
+            vout[i] = cscale(cmul(w.vu[i * T + s], ph), rv);
+            cd uu = cldexp(cscale(w.vv[i * T + s], ru), (int)w.ev[i * T + s] - eaccu);
+            uout[i] = cmul(uu, ph);
+        }
+        ln.pending = false;
     }
 
     static __device__ void finish(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, int flags) {
@@ -598,14 +615,14 @@ struct Kern {
         if (a.sens) a.sens[ln.pid] = (uint8_t)(sigma <= a.eps);
         if (VEC) {
             if (ln.sing) {
-                // exactly singular: leave a null vector of the pivotless sweep undefined;
-                // report zeros so the caller sees sigma = 0 with the SINGULAR bit.
+                // exactly singular (zero pivot): no Lanczos data; report zero vectors with the
+                // SINGULAR bit set.
                 for (int64_t i = 0; i < a.n; ++i) {
                     a.u[ln.pid * a.n + i] = czero();
                     a.v[ln.pid * a.n + i] = czero();
                 }
             } else {
-                vectors(a, w, s, ln, sigma);
+                ln.pending = true;   // assembled by vec_finalize with the whole wavefront
             }
         }
         ln.active = false;
@@ -774,7 +791,9 @@ struct Kern {
         ln.ap_prev = ln.bp = 0.0;
         ln.gmax = ln.gopen = 0.0;
         ln.delta_prev = ln.rho_prev = 0.0;
+        ln.pending = false;
         while (true) {
+            if (VEC && __all(!ln.active) && __any(ln.pending)) vec_finalize(a, w, s, ln);
             bool may_refill = !ln.active && !ln.exhausted;
             if (VEC) may_refill = may_refill && __all(!ln.active);
             if (may_refill) {
