@@ -11,6 +11,10 @@ namespace ps {
 constexpr int kMaxKL = 4;
 constexpr int kMaxKU = 4;
 constexpr int kMaxIterCap = 4096;
+// Rows per chunk of the triangular sweeps.  Per-row arrays are allocated with
+// round_up(n, kChunk) + kChunk rows; rows past n hold zeros and make no contribution.
+constexpr int kChunk = 8;
+inline int64_t padded_rows(int64_t n) { return ((n + kChunk - 1) / kChunk) * kChunk + kChunk; }
 
 // Where the shifts of one evaluation come from.
 enum ShiftMode : int {
@@ -24,6 +28,7 @@ enum ShiftMode : int {
 // wavefront touch 64 consecutive elements.
 struct Workspace {
     int64_t slots = 0;
+    int64_t nrow = 0;              // allocated rows per slot of every per-row array
     double2 *L = nullptr;          // [n][kl][slots]   multipliers of column i
     double2 *U = nullptr;          // [n][w][slots]    U[i][i+d], d = 0 holds 1/U[i][i]
     uint8_t *piv = nullptr;        // [n][slots]       pivot row offset (0..kl)

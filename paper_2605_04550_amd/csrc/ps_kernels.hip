@@ -58,15 +58,19 @@ __device__ __forceinline__ cd cldexp(cd a, int e) { return C(ldexp(a.x, e), ldex
 __device__ __forceinline__ cd cscale(cd a, double s) { return C(a.x * s, a.y * s); }
 __device__ __forceinline__ cd csub(cd a, cd b) { return C(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ cd crecip(cd a) {
-    double s = fmax(fabs(a.x), fabs(a.y));
-    double ar = a.x / s, ai = a.y / s;
-    double d = s * fma(ar, ar, ai * ai);
-    return C(ar / d, -ai / d);
+    const double is = 1.0 / fmax(fabs(a.x), fabs(a.y));
+    const double ar = a.x * is, ai = a.y * is;     // scaled so that ar^2 + ai^2 cannot under/overflow
+    const double id = is / fma(ar, ar, ai * ai);
+    return C(ar * id, -ai * id);
 }
+// Conditional swap written per component, so that it lowers to v_cndmask (a select of the
+// whole struct would be lowered through private memory).
 __device__ __forceinline__ void cswap_if(bool c, cd &a, cd &b) {
-    cd ta = a, tb = b;
-    a = c ? tb : ta;
-    b = c ? ta : tb;
+    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+    a.x = c ? bx : ax;
+    a.y = c ? by : ay;
+    b.x = c ? ax : bx;
+    b.y = c ? ay : by;
 }
 
 constexpr double kBig = 0x1p400;       // rescale when a sweep value reaches this
@@ -204,6 +208,11 @@ struct Kern {
         return m;
     }
 
+    // Every sweep walks the rows in chunks of CH: the loads of a whole chunk are issued
+    // first (they do not depend on the recurrence), then the chunk's rows are computed in
+    // order.  A wavefront thus keeps CH rows of loads in flight instead of one.
+    static constexpr int CH = 8;
+
     // ---------------------------------------------------------------- forward sweep 1
     // Fresh lanes: LU of M fused with the L solve of the start vector h (also stored as v).
     // Other lanes: y = L^{-1} P^T v_k with v_k read normalised.
@@ -216,90 +225,120 @@ struct Kern {
         const bool act = ln.active, fresh = ln.fresh;
         const double tiny = 0x1p-1000 * fmax(1.0, a.normA + cabs1(ln.z));
         bool sing = false;
-        double2 *vin = w.vv;
-        auto load_in = [&](int64_t i) -> cd {
-            if (i >= n) return czero();
-            if (fresh) {
-                cd h = start_entry(a.seed, i);
-                vin[i * T + s] = h;
+        const double rdv = ln.rdv;
+        const int Ev = ln.Ev;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        auto gen_in = [&](int64_t i) -> cd {   // fresh lanes: start vector entry i, stored as v
+            if (i >= n) {                       // padding rows stay zero
+                w.vv[i * T + s] = czero();
                 w.ev[i * T + s] = 0;
-                nrm_h += cabs2(h);
-                return cldexp(h, -R);
+                return czero();
             }
-            cd q = vin[i * T + s];
-            int e = w.ev[i * T + s];
-            return cldexp(cscale(q, ln.rdv), e - ln.Ev - R);
+            cd h = start_entry(a.seed, i);
+            w.vv[i * T + s] = h;
+            w.ev[i * T + s] = 0;
+            nrm_h += cabs2(h);
+            return cldexp(h, -R);
         };
         if (act) {
-#pragma unroll
-            for (int r = 0; r < KL; ++r) b[r] = load_in(r);
             if (fresh) {
+#pragma unroll
+                for (int r = 0; r < KL; ++r) b[r] = gen_in(r);
 #pragma unroll
                 for (int r = 0; r < KL; ++r)
 #pragma unroll
                     for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, r, c, ln.z);
+            } else {
+#pragma unroll
+                for (int r = 0; r < KL; ++r) b[r] = cldexp(cscale(w.vv[r * T + s], rdv), (int)w.ev[r * T + s] - Ev);
             }
         }
-        for (int64_t j = 0; j < n; ++j) {
+        for (int64_t j0 = 0; j0 < npad; j0 += CH) {
             if (!act) continue;
-            b[KL] = load_in(j + KL);
-            int p = 0;
-            cd l[KL > 0 ? KL : 1];
-            if (fresh) {
+            cd pin[CH];
+            int ein[CH];
+            int pv[CH];
+            cd Lr[CH][KL > 0 ? KL : 1];
+            if (!fresh) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) Wm[KL][c] = mentry(a, j + KL, j + c, ln.z);
-                double best = cabs1(Wm[0][0]);
+                for (int c = 0; c < CH; ++c) {
+                    const int64_t j = j0 + c, ii = j + KL;
+                    pin[c] = w.vv[ii * T + s];
+                    ein[c] = (int)w.ev[ii * T + s];
+                    if (KL > 0) {
+                        pv[c] = (int)w.piv[j * T + s];
 #pragma unroll
-                for (int r = 1; r <= KL; ++r) {
-                    double v = cabs1(Wm[r][0]);
-                    if (v > best) { best = v; p = r; }
+                        for (int r = 0; r < KL; ++r) Lr[c][r] = w.L[(j * KL + r) * T + s];
+                    } else {
+                        pv[c] = 0;
+                    }
                 }
-#pragma unroll
-                for (int r = 1; r <= KL; ++r)
-#pragma unroll
-                    for (int c = 0; c < W; ++c) cswap_if(p == r, Wm[0][c], Wm[r][c]);
-                cd inv;
-                if (!(best >= tiny)) { sing = true; inv = czero(); }
-                else inv = crecip(Wm[0][0]);
-#pragma unroll
-                for (int r = 1; r <= KL; ++r) l[r - 1] = cmul(Wm[r][0], inv);
-#pragma unroll
-                for (int r = 1; r <= KL; ++r)
-#pragma unroll
-                    for (int c = 1; c < W; ++c) Wm[r][c] = cfnma(l[r - 1], Wm[0][c], Wm[r][c]);
-                w.U[(j * W + 0) * T + s] = inv;
-#pragma unroll
-                for (int c = 1; c < W; ++c) w.U[(j * W + c) * T + s] = Wm[0][c];
-#pragma unroll
-                for (int r = 0; r < KL; ++r) w.L[(j * KL + r) * T + s] = l[r];
-                w.piv[j * T + s] = (uint8_t)p;
-#pragma unroll
-                for (int r = 0; r < KL; ++r) {
-#pragma unroll
-                    for (int c = 0; c < W - 1; ++c) Wm[r][c] = Wm[r + 1][c + 1];
-                    Wm[r][W - 1] = czero();
-                }
-            } else {
-                p = w.piv[j * T + s];
-#pragma unroll
-                for (int r = 0; r < KL; ++r) l[r] = w.L[(j * KL + r) * T + s];
             }
 #pragma unroll
-            for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
-            cd y = b[0];
-            if (!(cabs1(y) < kBig)) {
-                int sh = rescale_shift(cabs1(y), 1.0);
+            for (int c = 0; c < CH; ++c) {
+                const int64_t j = j0 + c;
+                int p = 0;
+                cd l[KL > 0 ? KL : 1];
+                if (fresh) {
+                    b[KL] = gen_in(j + KL);
 #pragma unroll
-                for (int r = 0; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
-                y = b[0];
-                R += sh;
+                    for (int cc = 0; cc < W; ++cc) Wm[KL][cc] = mentry(a, j + KL, j + cc, ln.z);
+                    double best = cabs1(Wm[0][0]);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) {
+                        double v = cabs1(Wm[r][0]);
+                        if (v > best) { best = v; p = r; }
+                    }
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r)
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc) cswap_if(p == r, Wm[0][cc], Wm[r][cc]);
+                    // rows past n are zero rows: their pivot is 0 and they stay inert
+                    const bool ok = best >= tiny;
+                    sing = sing || (!ok && j < n);
+                    const cd rc = crecip(Wm[0][0]);
+                    const cd inv = C(ok ? rc.x : 0.0, ok ? rc.y : 0.0);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) l[r - 1] = cmul(Wm[r][0], inv);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r)
+#pragma unroll
+                        for (int cc = 1; cc < W; ++cc) Wm[r][cc] = cfnma(l[r - 1], Wm[0][cc], Wm[r][cc]);
+                    w.U[(j * W + 0) * T + s] = inv;
+#pragma unroll
+                    for (int cc = 1; cc < W; ++cc) w.U[(j * W + cc) * T + s] = Wm[0][cc];
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) w.L[(j * KL + r) * T + s] = l[r];
+                    w.piv[j * T + s] = (uint8_t)p;
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) {
+#pragma unroll
+                        for (int cc = 0; cc < W - 1; ++cc) Wm[r][cc] = Wm[r + 1][cc + 1];
+                        Wm[r][W - 1] = czero();
+                    }
+                } else {
+                    b[KL] = cldexp(cscale(pin[c], rdv), ein[c] - Ev - R);
+                    p = pv[c];
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) l[r] = Lr[c][r];
+                }
+#pragma unroll
+                for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
+                cd y = b[0];
+                if (!(cabs1(y) < kBig)) {
+                    int sh = rescale_shift(cabs1(y), 1.0);
+#pragma unroll
+                    for (int r = 0; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                    y = b[0];
+                    R += sh;
+                }
+                w.vy[j * T + s] = y;
+                w.ey[j * T + s] = (int16_t)R;
+#pragma unroll
+                for (int r = 1; r <= KL; ++r) b[r] = cfnma(l[r - 1], y, b[r]);
+#pragma unroll
+                for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
             }
-            w.vy[j * T + s] = y;
-            w.ey[j * T + s] = (int16_t)R;
-#pragma unroll
-            for (int r = 1; r <= KL; ++r) b[r] = cfnma(l[r - 1], y, b[r]);
-#pragma unroll
-            for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
         }
         if (act) {
             ln.Ey = R;
@@ -331,10 +370,10 @@ struct Kern {
         int16_t *euout = w.eu;
         const double2 *uold = w.vu;
         const int16_t *euold = w.eu;
-        double rd_old = ln.rdu;
-        int E_old = ln.Eu;
+        const double rd_old = ln.rdu;
+        const int E_old = ln.Eu;
         if (VEC) {
-            int64_t stride = (int64_t)n * T;
+            int64_t stride = w.nrow * T;
             uout = w.basis + (int64_t)ln.k * stride;
             euout = w.ebasis + (int64_t)ln.k * stride;
             if (ln.k > 0) {
@@ -344,41 +383,53 @@ struct Kern {
         }
         const double bm = ln.b_m;
         const int be = ln.b_e;
-        for (int64_t i = n - 1; i >= 0; --i) {
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        for (int64_t i0 = npad - 1; i0 >= 0; i0 -= CH) {
             if (!act) continue;
-            cd rhs = cldexp(w.vy[i * T + s], (int)w.ey[i * T + s] - R);
-            cd inv = w.U[(i * W + 0) * T + s];
+            cd Ur[CH][W];
+            cd yr[CH], ur[CH];
+            int eyr[CH], eur[CH];
 #pragma unroll
-            for (int d = 1; d < W; ++d) rhs = cfnma(w.U[(i * W + d) * T + s], xw[d], rhs);
-            cd t = cmul(rhs, inv);
-            if (!(cabs1(t) < kBig)) {
-                int sh = rescale_shift(cabs1(rhs), cabs1(inv));
-                rhs = cldexp(rhs, -sh);
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 - c;
 #pragma unroll
-                for (int d = 1; d < W; ++d) xw[d] = cldexp(xw[d], -sh);
-                R += sh;
-                t = cmul(rhs, inv);
+                for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
+                yr[c] = w.vy[i * T + s];
+                eyr[c] = (int)w.ey[i * T + s];
+                ur[c] = uold[i * T + s];          // read even when unused (no branch); selected away below
+                eur[c] = (int)euold[i * T + s];
             }
-            cd o = t;
-            int eo = R;
-            if (sub) {
-                cd uo = cldexp(cscale(uold[i * T + s], rd_old), (int)euold[i * T + s] - E_old);
-                eo = R > be ? R : be;
-                cd tt = cldexp(t, R - eo);
-                cd bu = cscale(cldexp(uo, be - eo), bm);
-                o = csub(tt, bu);
-            }
-            uout[i * T + s] = o;
-            euout[i * T + s] = (int16_t)eo;
-            if (eo > Eacc) {
-                acc = ldexp(acc, 2 * (Eacc - eo));
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 - c;
+                cd rhs = cldexp(yr[c], eyr[c] - R);
+                const cd inv = Ur[c][0];
+#pragma unroll
+                for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                cd t = cmul(rhs, inv);
+                if (!(cabs1(t) < kBig)) {
+                    int sh = rescale_shift(cabs1(rhs), cabs1(inv));
+                    rhs = cldexp(rhs, -sh);
+#pragma unroll
+                    for (int d = 1; d < W; ++d) xw[d] = cldexp(xw[d], -sh);
+                    R += sh;
+                    t = cmul(rhs, inv);
+                }
+                const cd uo = cldexp(cscale(ur[c], rd_old), eur[c] - E_old);
+                const int es = R > be ? R : be;
+                const cd tt = cldexp(t, R - es);
+                const cd bu = cscale(cldexp(uo, be - es), bm);
+                const int eo = sub ? es : R;
+                const cd o = sub ? csub(tt, bu) : t;
+                uout[i * T + s] = o;
+                euout[i * T + s] = (int16_t)eo;
+                acc = fma(o.x, o.x, fma(o.y, o.y, ldexp(acc, 2 * (Eacc - eo))));   // eo >= Eacc always
                 Eacc = eo;
-            }
-            acc += cabs2(o);
-            if constexpr (W > 1) {
+                if constexpr (W > 1) {
 #pragma unroll
-                for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
-                xw[1] = t;
+                    for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
+                    xw[1] = t;
+                }
             }
         }
         acc_out = acc;
@@ -393,38 +444,56 @@ struct Kern {
         const double2 *uin = w.vu;
         const int16_t *euin = w.eu;
         if (VEC && !from_vu) {
-            int64_t stride = (int64_t)n * T;
+            int64_t stride = w.nrow * T;
             uin = w.basis + (int64_t)(ln.k - 1) * stride;
             euin = w.ebasis + (int64_t)(ln.k - 1) * stride;
         }
+        const double rdu = ln.rdu;
+        const int Eu = ln.Eu;
         int R = 0;
         cd acc[W];
-        auto load_u = [&](int64_t i) -> cd {
-            if (i >= n) return czero();
-            return cldexp(cscale(uin[i * T + s], ln.rdu), (int)euin[i * T + s] - ln.Eu - R);
-        };
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
         if (act) {
 #pragma unroll
-            for (int d = 0; d < W - 1; ++d) acc[d] = load_u(d);
+            for (int d = 0; d < W - 1; ++d) acc[d] = cldexp(cscale(uin[d * T + s], rdu), (int)euin[d * T + s] - Eu);
         }
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t i0 = 0; i0 < npad; i0 += CH) {
             if (!act) continue;
-            acc[W - 1] = load_u(i + W - 1);
-            cd inv = w.U[(i * W + 0) * T + s];
-            cd wv = cmul(acc[0], cconj(inv));
-            if (!(cabs1(wv) < kBig)) {
-                int sh = rescale_shift(cabs1(acc[0]), cabs1(inv));
+            cd Ur[CH][W];
+            cd pin[CH];
+            int ein[CH];
 #pragma unroll
-                for (int d = 0; d < W; ++d) acc[d] = cldexp(acc[d], -sh);
-                R += sh;
-                wv = cmul(acc[0], cconj(inv));
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 + c, ii = i + W - 1;
+#pragma unroll
+                for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
+                // rows at or past npad were never written: read (in bounds) and discard
+                const cd q = uin[ii * T + s];
+                const int e = (int)euin[ii * T + s];
+                const bool in = ii < npad;
+                pin[c] = C(in ? q.x : 0.0, in ? q.y : 0.0);
+                ein[c] = in ? e : 0;
             }
-            w.vy[i * T + s] = wv;
-            w.ey[i * T + s] = (int16_t)R;
 #pragma unroll
-            for (int d = 1; d < W; ++d) acc[d] = cfnmac(w.U[(i * W + d) * T + s], wv, acc[d]);
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 + c;
+                acc[W - 1] = cldexp(cscale(pin[c], rdu), ein[c] - Eu - R);
+                const cd inv = Ur[c][0];
+                cd wv = cmul(acc[0], cconj(inv));
+                if (!(cabs1(wv) < kBig)) {
+                    int sh = rescale_shift(cabs1(acc[0]), cabs1(inv));
 #pragma unroll
-            for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+                    for (int d = 0; d < W; ++d) acc[d] = cldexp(acc[d], -sh);
+                    R += sh;
+                    wv = cmul(acc[0], cconj(inv));
+                }
+                w.vy[i * T + s] = wv;
+                w.ey[i * T + s] = (int16_t)R;
+#pragma unroll
+                for (int d = 1; d < W; ++d) acc[d] = cfnmac(Ur[c][d], wv, acc[d]);
+#pragma unroll
+                for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+            }
         }
         if (act) ln.Ey = R;
     }
@@ -443,46 +512,68 @@ struct Kern {
         int Eacc = R;
         const double am = ln.a_m;
         const int ae = ln.a_e;
-        auto emit = [&](int64_t i, cd val) {
-            cd vo = cldexp(cscale(w.vv[i * T + s], ln.rdv), (int)w.ev[i * T + s] - ln.Ev);
+        const double rdv = ln.rdv;
+        const int Ev = ln.Ev;
+        // out_i = val 2^R - alpha v_i (v_i normalised from its stored mantissa vo / exponent evo)
+        auto emit = [&](int64_t i, cd val, cd vo, int evo) {
+            cd vn = cldexp(cscale(vo, rdv), evo - Ev);
             int eo = R > ae ? R : ae;
-            cd o = csub(cldexp(val, R - eo), cscale(cldexp(vo, ae - eo), am));
+            cd o = csub(cldexp(val, R - eo), cscale(cldexp(vn, ae - eo), am));
             w.vv[i * T + s] = o;
             w.ev[i * T + s] = (int16_t)eo;
-            if (eo > Eacc) {
-                acc = ldexp(acc, 2 * (Eacc - eo));
-                Eacc = eo;
-            }
-            acc += cabs2(o);
+            acc = fma(o.x, o.x, fma(o.y, o.y, ldexp(acc, 2 * (Eacc - eo))));   // eo >= Eacc always
+            Eacc = eo;
         };
-        for (int64_t j = n - 1; j >= 0; --j) {
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        for (int64_t j0 = npad - 1; j0 >= 0; j0 -= CH) {
             if (!act) continue;
-            cd b0 = cldexp(w.vy[j * T + s], (int)w.ey[j * T + s] - R);
+            cd yr[CH], vr[CH];
+            int eyr[CH], evr[CH], pv[CH];
+            cd Lr[CH][KL > 0 ? KL : 1];
 #pragma unroll
-            for (int r = 1; r <= KL; ++r) b0 = cfnmac(w.L[(j * KL + (r - 1)) * T + s], b[r], b0);
-            if (!(cabs1(b0) < kBig)) {
-                int sh = rescale_shift(cabs1(b0), 1.0);
-                b0 = cldexp(b0, -sh);
+            for (int c = 0; c < CH; ++c) {
+                const int64_t j = j0 - c, io = j + KL;
+                yr[c] = w.vy[j * T + s];
+                eyr[c] = (int)w.ey[j * T + s];
+                if (KL > 0) {
+                    pv[c] = (int)w.piv[j * T + s];
 #pragma unroll
-                for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
-                R += sh;
+                    for (int r = 0; r < KL; ++r) Lr[c][r] = w.L[(j * KL + r) * T + s];
+                } else {
+                    pv[c] = 0;
+                }
+                vr[c] = w.vv[io * T + s];
+                evr[c] = (int)w.ev[io * T + s];
             }
-            b[0] = b0;
-            if (KL > 0) {
-                int p = w.piv[j * T + s];
 #pragma unroll
-                for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
-                if (j + KL < n) emit(j + KL, b[KL]);
+            for (int c = 0; c < CH; ++c) {
+                const int64_t j = j0 - c;
+                cd b0 = cldexp(yr[c], eyr[c] - R);
 #pragma unroll
-                for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
-            } else {
-                emit(j, b[0]);
+                for (int r = 1; r <= KL; ++r) b0 = cfnmac(Lr[c][r - 1], b[r], b0);
+                if (!(cabs1(b0) < kBig)) {
+                    int sh = rescale_shift(cabs1(b0), 1.0);
+                    b0 = cldexp(b0, -sh);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                    R += sh;
+                }
+                b[0] = b0;
+                if (KL > 0) {
+                    const int p = pv[c];
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
+                    emit(j + KL, b[KL], vr[c], evr[c]);   // rows past n carry zeros
+#pragma unroll
+                    for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
+                } else {
+                    emit(j, b[0], vr[c], evr[c]);
+                }
             }
         }
         if (act && KL > 0) {
 #pragma unroll
-            for (int r = KL; r >= 1; --r)
-                if (r - 1 < n) emit(r - 1, b[r]);
+            for (int r = KL; r >= 1; --r) emit(r - 1, b[r], w.vv[(r - 1) * T + s], (int)w.ev[(r - 1) * T + s]);
         }
         acc_out = acc;
         eacc_out = Eacc;
@@ -551,7 +642,7 @@ struct Kern {
         const bool pend = ln.pending;
         if (pend) ritz_coeffs(w, s, ln);
         const double *coef = w.bmeta + (int64_t)(3 * w.kvec) * T;
-        const int64_t stride = (int64_t)n * T;
+        const int64_t stride = w.nrow * T;
         const int k = ln.k;
         double vn = 0.0, amax = -1.0;
         cd vph = C(1.0, 0.0);
@@ -570,6 +661,11 @@ struct Kern {
             vn += cabs2(acc);
             double m = cabs2(acc);
             if (m > amax) { amax = m; vph = acc; }
+        }
+        for (int64_t i = n; i < w.nrow; ++i) {
+            if (!pend) continue;
+            w.vu[i * T + s] = czero();
+            w.eu[i * T + s] = 0;
         }
         // u direction: M^{-H} v through the factors (alpha = 0: no three-term correction)
         const bool saved = ln.active;
@@ -765,8 +861,38 @@ struct Kern {
         }
     }
 
-    static __device__ void run(const EvalArgs a, const Workspace w) {
-        const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // The workspace is laid out [wavefront][row][component][lane]: the 64 lanes of a
+    // wavefront touch one contiguous 1 KiB (complex) segment per access, and a chunk of
+    // consecutive rows of one wavefront is contiguous as well.  Each lane works on a view
+    // whose pointers are offset to its own column (slots = 64, lane index 0).
+    static __device__ Workspace lane_view(const Workspace &g, int64_t sg) {
+        Workspace w = g;
+        const int64_t wv = sg >> 6, l = sg & 63;
+        const int64_t wl = KL > 0 ? KL : 1;
+        const int64_t nr = g.nrow;
+        w.slots = 64;
+        w.L = g.L + wv * nr * wl * 64 + l;
+        w.U = g.U + wv * nr * W * 64 + l;
+        w.piv = g.piv + wv * nr * 64 + l;
+        w.vu = g.vu + wv * nr * 64 + l;
+        w.vv = g.vv + wv * nr * 64 + l;
+        w.vy = g.vy + wv * nr * 64 + l;
+        w.eu = g.eu + wv * nr * 64 + l;
+        w.ev = g.ev + wv * nr * 64 + l;
+        w.ey = g.ey + wv * nr * 64 + l;
+        w.hist = g.hist + wv * (int64_t)g.kmax * 2 * 64 + l;
+        if (VEC) {
+            w.basis = g.basis + wv * (int64_t)g.kvec * nr * 64 + l;
+            w.ebasis = g.ebasis + wv * (int64_t)g.kvec * nr * 64 + l;
+            w.bmeta = g.bmeta + wv * (int64_t)g.kvec * 6 * 64 + l;
+        }
+        return w;
+    }
+
+    static __device__ void run(const EvalArgs a, const Workspace wg) {
+        const int64_t sg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const Workspace w = lane_view(wg, sg);
+        const int64_t s = 0;
         const int64_t npts = *a.count_dev;
         const int kcap = VEC ? (a.max_iter < w.kvec ? a.max_iter : w.kvec) : a.max_iter;
         Lane ln;
@@ -995,9 +1121,11 @@ void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int k
         off += align256(bytes);
         return p;
     };
-    const size_t ns = (size_t)n * (size_t)slots;
+    const int64_t nrow = padded_rows(n);
+    const size_t ns = (size_t)nrow * (size_t)slots;
     const int wu = kl + ku + 1;
     w->slots = slots;
+    w->nrow = nrow;
     w->kmax = kmax;
     w->kvec = kvec;
     w->queue = (unsigned long long *)take(sizeof(unsigned long long));
