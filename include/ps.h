@@ -179,6 +179,40 @@ ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, c
                       const ps_c128 *v_dev, ps_c128 *grad_z_dev, ps_c128 *grad_band_dev, void *ws_dev,
                       size_t ws_bytes, void *stream);
 
+/*
+ * Batches of matrices.  A batch groups nmat registered matrices of possibly different n and
+ * bandwidths, each with its own grid (Sec. 2.1), for one call that evaluates all of them
+ * (the restricted evaluation of Sec. 4 applied to many matrices at once).  Outputs of all
+ * matrices are concatenated: matrix m owns entries [off_m, off_m + nx_m * ny_m), with
+ * off_m = sum of nx * ny of the matrices before m (ps_batch_info returns them).
+ *
+ * ps_create_batch -- mats: nmat handles (not owned; they must outlive the batch); grids:
+ *   host array of nmat grids.  Copies the per-matrix descriptors to the device once.
+ *   Errors: PS_ERR_INVALID (nmat < 1, NULL handle, bad grid), PS_ERR_NONFINITE, PS_ERR_HIP.
+ * ps_destroy_batch -- frees the batch (not the matrices).  NULL is accepted.
+ * ps_batch_info -- total number of grid points, and the offsets off_m (offsets may be NULL).
+ * ps_batch_workspace_size -- device workspace for ps_eval_batch with options o.
+ * ps_eval_batch -- sigma_min at the masked grid points of every matrix of the batch.
+ *   masks_dev  device array of nmat device pointers to uint8 [ny_m][nx_m] masks; a NULL
+ *              entry (or masks_dev == NULL) selects the full grid of that matrix.
+ *   idx_dev    device int64[total]: in the section of matrix m, the ascending flat grid
+ *              indices of its evaluated points (first counts_dev[m] entries).
+ *   counts_dev device int64[nmat]: number of evaluated points per matrix.
+ *   sigma_dev, info_dev, iters_dev: device arrays [total], indexed like idx_dev.
+ *   Vectors are not produced in batch mode (o->want_vectors must be 0).
+ *   Work: one compaction of all masks, then one persistent launch per (kl, ku) class whose
+ *   shift queue lists larger matrices first.  Calls on one batch must not overlap.
+ *   Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_UNSUPPORTED (want_vectors), PS_ERR_HIP.
+ */
+typedef struct ps_batch_s *ps_batch;
+ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *grids, ps_batch *out);
+ps_status ps_destroy_batch(ps_batch b);
+ps_status ps_batch_info(ps_batch b, int64_t *total_points, int64_t *offsets);
+ps_status ps_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes);
+ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_opts *o, void *ws_dev, size_t ws_bytes,
+                        int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
+                        int32_t *iters_dev, void *stream);
+
 /* Thread-local description of the last error on the calling thread ("" if none). */
 const char *ps_last_error(void);
 

@@ -66,6 +66,11 @@ _SIGNATURES = {
                                     _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P]),
     "ps_backward_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ctypes.c_size_t)]),
     "ps_backward": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "ps_create_batch": (ctypes.c_int, [_I32, ctypes.POINTER(_P), ctypes.POINTER(ps_grid), ctypes.POINTER(_P)]),
+    "ps_destroy_batch": (ctypes.c_int, [_P]),
+    "ps_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "ps_batch_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_eval_batch": (ctypes.c_int, [_P, _P, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
 }
 
 
@@ -156,6 +161,41 @@ def ps_backward(handle, npts, grad_sigma_ptr, u_ptr, v_ptr, grad_z_ptr, grad_ban
                 stream=0) -> None:
     _check(lib().ps_backward(_P(handle), npts, _P(grad_sigma_ptr), _P(u_ptr), _P(v_ptr), _P(grad_z_ptr),
                              _P(grad_band_ptr), _P(ws_ptr), ws_bytes, _P(stream)))
+
+
+def ps_create_batch(handles, grids) -> int:
+    """handles: matrix handles; grids: ps_grid structs (one per matrix).  Returns the batch handle."""
+    n = len(handles)
+    harr = (_P * n)(*[_P(h) for h in handles])
+    garr = (ps_grid * n)(*grids)
+    b = _P()
+    _check(lib().ps_create_batch(n, harr, garr, ctypes.byref(b)))
+    return b.value
+
+
+def ps_destroy_batch(batch: int) -> None:
+    _check(lib().ps_destroy_batch(_P(batch)))
+
+
+def ps_batch_info(batch: int, nmat: int):
+    tot = _I64()
+    offs = (_I64 * nmat)()
+    _check(lib().ps_batch_info(_P(batch), ctypes.byref(tot), offs))
+    return tot.value, list(offs)
+
+
+def ps_batch_workspace_size(batch: int, opts: ps_opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_batch_workspace_size(_P(batch), ctypes.byref(opts) if opts is not None else None,
+                                         ctypes.byref(b)))
+    return b.value
+
+
+def ps_eval_batch(batch, masks_ptr, opts, ws_ptr, ws_bytes, idx_ptr, counts_ptr, sigma_ptr, info_ptr=0,
+                  iters_ptr=0, stream=0) -> None:
+    _check(lib().ps_eval_batch(_P(batch), _P(masks_ptr), ctypes.byref(opts) if opts is not None else None,
+                               _P(ws_ptr), ws_bytes, _P(idx_ptr), _P(counts_ptr), _P(sigma_ptr), _P(info_ptr),
+                               _P(iters_ptr), _P(stream)))
 
 
 def header_symbols():

@@ -15,10 +15,12 @@ import math
 import numpy as np
 import torch
 
-from . import (PS_DEVICE_PTR, PS_REAL_A, ps_backward, ps_backward_workspace_size, ps_create_banded, ps_destroy,
-               ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_opts_default, ps_workspace_size)
+from . import (PS_DEVICE_PTR, PS_REAL_A, ps_backward, ps_backward_workspace_size, ps_batch_info,
+               ps_batch_workspace_size, ps_create_banded, ps_create_batch, ps_destroy, ps_destroy_batch,
+               ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_opts_default,
+               ps_workspace_size)
 
-__all__ = ["BandedMatrix", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
+__all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
 
 
 def _stream_handle(stream=None) -> int:
@@ -65,6 +67,62 @@ class BandedMatrix:
             self.close()
         except Exception:
             pass
+
+
+class BandedBatch:
+    """Many registered matrices, each with its own grid, evaluated by one ps_eval_batch call."""
+
+    def __init__(self, mats, grids):
+        self.mats = list(mats)
+        self.grids = [ps_grid(float(g.a), float(g.b), float(g.c), float(g.d), int(g.nx), int(g.ny)) for g in grids]
+        self.handle = ps_create_batch([m.handle for m in self.mats], self.grids)
+        self.total, self.offsets = ps_batch_info(self.handle, len(self.mats))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ps_destroy_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, device=None, stream=None,
+             workspace: torch.Tensor | None = None):
+        """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None.  Returns dict with
+        the concatenated idx, sigma, info, iters, and counts [nmat]; matrix m owns offsets[m] onward."""
+        dev = device or torch.device("cuda")
+        nmat = len(self.mats)
+        o = make_opts(tol_norm, tol_rel, max_iter, False, slots)
+        keep = []
+        mptr = 0
+        if masks is not None:
+            ptrs = []
+            for m, mk in enumerate(masks):
+                if mk is None:
+                    ptrs.append(0)
+                else:
+                    assert mk.is_cuda and mk.dtype == torch.uint8 and mk.numel() == self.grids[m].nx * self.grids[m].ny
+                    mk = mk.contiguous()
+                    keep.append(mk)
+                    ptrs.append(mk.data_ptr())
+            parr = torch.tensor(ptrs, dtype=torch.int64, device=dev)
+            keep.append(parr)
+            mptr = parr.data_ptr()
+        out = dict(idx=torch.empty(self.total, dtype=torch.int64, device=dev),
+                   counts=torch.zeros(nmat, dtype=torch.int64, device=dev),
+                   sigma=torch.full((self.total,), float("nan"), dtype=torch.float64, device=dev),
+                   info=torch.empty(self.total, dtype=torch.int32, device=dev),
+                   iters=torch.empty(self.total, dtype=torch.int32, device=dev),
+                   offsets=list(self.offsets))
+        need = ps_batch_workspace_size(self.handle, o)
+        ws = workspace if workspace is not None else _workspace(need, dev)
+        ps_eval_batch(self.handle, mptr, o, ws.data_ptr(), ws.numel(), out["idx"].data_ptr(), out["counts"].data_ptr(),
+                      out["sigma"].data_ptr(), out["info"].data_ptr(), out["iters"].data_ptr(), _stream_handle(stream))
+        out["_keep"] = keep
+        return out
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:

@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 struct ps_matrix_s {
@@ -339,6 +340,211 @@ ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, c
     HIP_TRY(ps::launch_backward(m->n, m->kl, m->ku, npts, grad_sigma_dev, (const double2 *)u_dev,
                                 (const double2 *)v_dev, (double2 *)grad_z_dev, (double2 *)grad_band_dev,
                                 (double2 *)ws_dev, (m->flags & PS_REAL_A) ? 1 : 0, s));
+    return ok();
+}
+
+}  // extern "C"
+
+struct ps_batch_s {
+    int32_t nmat = 0;
+    std::vector<int64_t> off;
+    std::vector<int64_t> npts;
+    int64_t total = 0;
+    int64_t max_npts = 0;
+    ps::MatDesc *desc_caller = nullptr;   // device, caller order
+    ps::MatDesc *desc_class = nullptr;    // device, grouped by (kl, ku), larger n first
+    struct Cls {
+        int kl, ku, begin, count;
+        int64_t nmax, npts;
+    };
+    std::vector<Cls> classes;
+};
+
+namespace {
+
+int64_t class_slots(const ps_batch_s::Cls &c, const ps_opts &o) {
+    int64_t want = ((c.npts + kSlotQuantum - 1) / kSlotQuantum) * kSlotQuantum;
+    if (o.slots > 0) want = round_slots(o.slots);
+    if (want < kSlotQuantum) want = kSlotQuantum;
+    if (want > kMaxSlots) want = kMaxSlots;
+    while (want > kSlotQuantum &&
+           (double)ps::workspace_bytes(c.nmax, c.kl, c.ku, want, o.max_iter, 0, 0) > kDefaultWsBudget)
+        want -= kSlotQuantum;
+    return want;
+}
+
+size_t batch_scratch_bytes(const ps_batch_s *b) {
+    int64_t nt = ps::batch_tiles(b->max_npts);
+    if (nt < 1) nt = 1;
+    size_t a = sizeof(int64_t) * (size_t)(nt * b->nmat);
+    a = (a + 255) & ~(size_t)255;
+    size_t f = sizeof(int64_t) * (size_t)b->nmat;
+    f = (f + 255) & ~(size_t)255;
+    return a + f;
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *grids, ps_batch *out) {
+    if (!out) return fail(PS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nmat < 1 || !mats || !grids) return fail(PS_ERR_INVALID, "need nmat >= 1, mats and grids");
+    ps_batch b = new ps_batch_s();
+    b->nmat = nmat;
+    std::vector<ps::MatDesc> dc((size_t)nmat);
+    for (int32_t m = 0; m < nmat; ++m) {
+        const ps_matrix a = mats[m];
+        const ps_grid &g = grids[m];
+        if (!a) { delete b; return fail(PS_ERR_INVALID, "matrix %d is NULL", m); }
+        if (g.nx < 1 || g.ny < 1 || g.nx * g.ny > ((int64_t)1 << 40)) {
+            delete b;
+            return fail(PS_ERR_INVALID, "bad grid size for matrix %d", m);
+        }
+        if (!isfinite(g.a) || !isfinite(g.b) || !isfinite(g.c) || !isfinite(g.d)) {
+            delete b;
+            return fail(PS_ERR_NONFINITE, "non-finite grid bounds for matrix %d", m);
+        }
+        ps::MatDesc d;
+        d.arow = a->arow;
+        d.n = a->n;
+        d.normA = a->fro;
+        d.ga = g.a;
+        d.gb = g.b;
+        d.gc = g.c;
+        d.gd = g.d;
+        d.nx = g.nx;
+        d.ny = g.ny;
+        d.out_off = b->total;
+        d.kl = a->kl;
+        d.ku = a->ku;
+        d.cidx = m;
+        d.pad = 0;
+        dc[(size_t)m] = d;
+        b->off.push_back(b->total);
+        b->npts.push_back(g.nx * g.ny);
+        b->total += g.nx * g.ny;
+        b->max_npts = std::max(b->max_npts, g.nx * g.ny);
+    }
+    std::vector<ps::MatDesc> dk = dc;
+    std::stable_sort(dk.begin(), dk.end(), [](const ps::MatDesc &x, const ps::MatDesc &y) {
+        if (x.kl != y.kl) return x.kl < y.kl;
+        if (x.ku != y.ku) return x.ku < y.ku;
+        return x.n > y.n;
+    });
+    for (int32_t i = 0; i < nmat;) {
+        ps_batch_s::Cls c;
+        c.kl = dk[(size_t)i].kl;
+        c.ku = dk[(size_t)i].ku;
+        c.begin = i;
+        c.count = 0;
+        c.nmax = 0;
+        c.npts = 0;
+        while (i < nmat && dk[(size_t)i].kl == c.kl && dk[(size_t)i].ku == c.ku) {
+            c.nmax = std::max(c.nmax, dk[(size_t)i].n);
+            c.npts += dk[(size_t)i].nx * dk[(size_t)i].ny;
+            ++c.count;
+            ++i;
+        }
+        b->classes.push_back(c);
+    }
+    hipError_t e = hipMalloc((void **)&b->desc_caller, sizeof(ps::MatDesc) * (size_t)nmat);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->desc_class, sizeof(ps::MatDesc) * (size_t)nmat);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->desc_caller, dc.data(), sizeof(ps::MatDesc) * (size_t)nmat, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->desc_class, dk.data(), sizeof(ps::MatDesc) * (size_t)nmat, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ps_destroy_batch(b);
+        return fail(PS_ERR_HIP, "batch descriptors: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return ok();
+}
+
+ps_status ps_destroy_batch(ps_batch b) {
+    if (!b) return ok();
+    if (b->desc_caller) (void)hipFree(b->desc_caller);
+    if (b->desc_class) (void)hipFree(b->desc_class);
+    delete b;
+    return ok();
+}
+
+ps_status ps_batch_info(ps_batch b, int64_t *total_points, int64_t *offsets) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    if (total_points) *total_points = b->total;
+    if (offsets)
+        for (int32_t m = 0; m < b->nmat; ++m) offsets[m] = b->off[(size_t)m];
+    return ok();
+}
+
+ps_status ps_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    ps_opts r = resolve(o);
+    ps_status st;
+    if ((st = check_opts(r))) return st;
+    size_t mx = 0;
+    for (const auto &c : b->classes) {
+        int64_t sl = class_slots(c, r);
+        mx = std::max(mx, ps::workspace_bytes(c.nmax, c.kl, c.ku, sl, r.max_iter, 0, 0));
+    }
+    *bytes = batch_scratch_bytes(b) + mx;
+    return ok();
+}
+
+ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_opts *o, void *ws_dev, size_t ws_bytes,
+                        int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
+                        int32_t *iters_dev, void *stream) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    ps_opts r = resolve(o);
+    ps_status st;
+    if ((st = check_opts(r))) return st;
+    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "vectors are not produced in batch mode");
+    if (!idx_dev || !counts_dev || !sigma_dev) return fail(PS_ERR_INVALID, "idx, counts and sigma are required");
+    if (!ws_dev) return fail(PS_ERR_WORKSPACE, "workspace is NULL");
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    ps_batch_workspace_size(b, &r, &need);
+    if (ws_bytes < need) return fail(PS_ERR_WORKSPACE, "batch workspace needs %zu bytes (got %zu)", need, ws_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws_dev;
+    int64_t nt = ps::batch_tiles(b->max_npts);
+    if (nt < 1) nt = 1;
+    int64_t *tilesums = (int64_t *)base;
+    size_t a0 = ((sizeof(int64_t) * (size_t)(nt * b->nmat)) + 255) & ~(size_t)255;
+    int64_t *mfirst = (int64_t *)(base + a0);
+    char *evbase = base + batch_scratch_bytes(b);
+    HIP_TRY(ps::launch_batch_compact(b->desc_caller, b->nmat, b->max_npts, masks_dev, idx_dev, counts_dev, tilesums,
+                                     s));
+    for (const auto &c : b->classes) {
+        ps::Workspace w;
+        int64_t sl = class_slots(c, r);
+        ps::carve_workspace(evbase, c.nmax, c.kl, c.ku, sl, r.max_iter, 0, 0, &w);
+        HIP_TRY(ps::launch_batch_prefix(b->desc_class + c.begin, counts_dev, c.count, mfirst + c.begin, w.count,
+                                        w.queue, s));
+        ps::EvalArgs a;
+        a.n = c.nmax;
+        a.kl = c.kl;
+        a.ku = c.ku;
+        a.arow = nullptr;
+        a.normA = 0.0;
+        a.mode = ps::kShiftGrid;
+        a.idx = idx_dev;
+        a.count_dev = w.count;
+        a.tol_norm = r.tol_norm;
+        a.tol_rel = r.tol_rel;
+        a.max_iter = r.max_iter;
+        a.want_vectors = 0;
+        a.sigma = sigma_dev;
+        a.info = info_dev;
+        a.iters = iters_dev;
+        a.mats = b->desc_class + c.begin;
+        a.nmat = c.count;
+        a.mfirst = mfirst + c.begin;
+        HIP_TRY(ps::launch_eval_batch(a, w, c.kl, c.ku, s));
+    }
     return ok();
 }
 

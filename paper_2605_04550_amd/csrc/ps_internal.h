@@ -49,6 +49,21 @@ struct Workspace {
     int kvec = 0;
 };
 
+// One matrix of a batch (device array, written once by ps_create_batch).  Matrices are
+// stored grouped by (kl, ku); outputs of matrix m occupy [out_off, out_off + nx*ny) of the
+// concatenated output arrays.
+struct MatDesc {
+    const double2 *arow;
+    int64_t n;
+    double normA;
+    double ga, gb, gc, gd;
+    int64_t nx, ny;
+    int64_t out_off;
+    int32_t kl, ku;
+    int32_t cidx;     // position of the matrix in the caller's order
+    int32_t pad;
+};
+
 struct EvalArgs {
     int64_t n = 0;
     int kl = 0, ku = 0;
@@ -71,6 +86,10 @@ struct EvalArgs {
     int32_t *iters = nullptr;
     double eps = 0.0;
     uint8_t *sens = nullptr;
+    // batch mode: the matrices of one (kl, ku) class
+    const MatDesc *mats = nullptr;
+    int nmat = 0;
+    const int64_t *mfirst = nullptr;   // device: first queue position of each matrix
 };
 
 size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max);
@@ -83,6 +102,14 @@ hipError_t launch_set_count(int64_t *count, int64_t value, unsigned long long *q
 hipError_t launch_compact_mask(const uint8_t *mask, int64_t npts, int64_t *idx, int64_t *count, int64_t *blocksums,
                                unsigned long long *queue, hipStream_t st);
 hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st);
+// Batch: masks compaction for all matrices at once (masks: device array of nmat device
+// pointers, NULL entries = full grid), then per class the queue prefix and the launch.
+hipError_t launch_batch_compact(const MatDesc *mats, int nmat, int64_t max_npts, const uint8_t *const *masks,
+                                int64_t *idx, int64_t *counts, int64_t *tilesums, hipStream_t st);
+hipError_t launch_batch_prefix(const MatDesc *mats_cls, const int64_t *counts, int nmat, int64_t *mfirst,
+                               int64_t *total, unsigned long long *queue, hipStream_t st);
+hipError_t launch_eval_batch(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st);
+int64_t batch_tiles(int64_t max_npts);
 hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double *g, const double2 *u,
                            const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,
                            hipStream_t st);

@@ -191,18 +191,31 @@ struct Lane {
     double rdu, rdv;  // 1 / (norm mantissa) of u, v
     double nrm_h;     // squared norm of the start vector (fresh lanes)
     bool active, fresh, sing, exhausted, pending;
+    // batch mode: the matrix of the current shift
+    int64_t n;
+    const double2 *arow;
+    double normA;
 };
 
-template <int KL, int KU, bool VEC>
+template <int KL, int KU, bool VEC, bool BATCH>
 struct Kern {
     static constexpr int W = KL + KU + 1;
 
+    // Order, band and Frobenius norm of the current shift's matrix (one matrix per launch,
+    // or per shift in batch mode).
+    static __device__ __forceinline__ int64_t nn(const EvalArgs &a, const Lane &ln) { return BATCH ? ln.n : a.n; }
+    static __device__ __forceinline__ const double2 *band(const EvalArgs &a, const Lane &ln) {
+        return BATCH ? ln.arow : a.arow;
+    }
+    static __device__ __forceinline__ double fro(const EvalArgs &a, const Lane &ln) { return BATCH ? ln.normA : a.normA; }
+
     // M[r][c] of M = zI - A from the row band (zero outside the matrix).
-    static __device__ __forceinline__ cd mentry(const EvalArgs &a, int64_t r, int64_t c, cd z) {
-        if (r >= a.n) return czero();
+    static __device__ __forceinline__ cd mentry(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
+        if (r >= nn(a, ln)) return czero();
         int64_t d = c - r + KL;
         if (d < 0 || d >= W) return czero();
-        cd v = a.arow[r * W + d];
+        const cd z = ln.z;
+        cd v = band(a, ln)[r * W + d];
         cd m = C(-v.x, -v.y);
         if (c == r) m = C(m.x + z.x, m.y + z.y);
         return m;
@@ -217,13 +230,13 @@ struct Kern {
     // Fresh lanes: LU of M fused with the L solve of the start vector h (also stored as v).
     // Other lanes: y = L^{-1} P^T v_k with v_k read normalised.
     static __device__ void f1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
-        const int64_t n = a.n, T = w.slots;
+        const int64_t n = nn(a, ln), T = w.slots;
         cd b[KL + 1];
         cd Wm[KL + 1][W];
         int R = 0;
         double nrm_h = 0.0;
         const bool act = ln.active, fresh = ln.fresh;
-        const double tiny = 0x1p-1000 * fmax(1.0, a.normA + cabs1(ln.z));
+        const double tiny = 0x1p-1000 * fmax(1.0, fro(a, ln) + cabs1(ln.z));
         bool sing = false;
         const double rdv = ln.rdv;
         const int Ev = ln.Ev;
@@ -247,7 +260,7 @@ struct Kern {
 #pragma unroll
                 for (int r = 0; r < KL; ++r)
 #pragma unroll
-                    for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, r, c, ln.z);
+                    for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, ln, r, c);
             } else {
 #pragma unroll
                 for (int r = 0; r < KL; ++r) b[r] = cldexp(cscale(w.vv[r * T + s], rdv), (int)w.ev[r * T + s] - Ev);
@@ -282,7 +295,7 @@ struct Kern {
                 if (fresh) {
                     b[KL] = gen_in(j + KL);
 #pragma unroll
-                    for (int cc = 0; cc < W; ++cc) Wm[KL][cc] = mentry(a, j + KL, j + cc, ln.z);
+                    for (int cc = 0; cc < W; ++cc) Wm[KL][cc] = mentry(a, ln, j + KL, j + cc);
                     double best = cabs1(Wm[0][0]);
 #pragma unroll
                     for (int r = 1; r <= KL; ++r) {
@@ -356,7 +369,7 @@ struct Kern {
     // |out|^2 = acc * 2^(2 Eacc).
     static __device__ void b1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
                               int &eacc_out) {
-        const int64_t n = a.n, T = w.slots;
+        const int64_t n = nn(a, ln), T = w.slots;
         const bool act = ln.active && !ln.sing;
         const bool sub = !ln.fresh;
         int R = ln.Ey;
@@ -439,7 +452,7 @@ struct Kern {
     // ---------------------------------------------------------------- forward sweep 2
     // y = U^{-H} u_k (u_k read normalised), column-oriented forward substitution.
     static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, bool from_vu = false) {
-        const int64_t n = a.n, T = w.slots;
+        const int64_t n = nn(a, ln), T = w.slots;
         const bool act = ln.active;
         const double2 *uin = w.vu;
         const int16_t *euin = w.eu;
@@ -502,7 +515,7 @@ struct Kern {
     // q = P L^{-H} y - alpha_k v_k; v updated in place; returns |q|^2 = acc * 2^(2 Eacc).
     static __device__ void b2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
                               int &eacc_out) {
-        const int64_t n = a.n, T = w.slots;
+        const int64_t n = nn(a, ln), T = w.slots;
         const bool act = ln.active;
         int R = ln.Ey;
         cd b[KL + 1];
@@ -638,7 +651,7 @@ struct Kern {
     }
 
     static __device__ void vec_finalize(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
-        const int64_t n = a.n, T = w.slots;
+        const int64_t n = nn(a, ln), T = w.slots;
         const bool pend = ln.pending;
         if (pend) ritz_coeffs(w, s, ln);
         const double *coef = w.bmeta + (int64_t)(3 * w.kvec) * T;
@@ -713,9 +726,9 @@ struct Kern {
             if (ln.sing) {
                 // exactly singular (zero pivot): no Lanczos data; report zero vectors with the
                 // SINGULAR bit set.
-                for (int64_t i = 0; i < a.n; ++i) {
-                    a.u[ln.pid * a.n + i] = czero();
-                    a.v[ln.pid * a.n + i] = czero();
+                for (int64_t i = 0; i < nn(a, ln); ++i) {
+                    a.u[ln.pid * nn(a, ln) + i] = czero();
+                    a.v[ln.pid * nn(a, ln) + i] = czero();
                 }
             } else {
                 ln.pending = true;   // assembled by vec_finalize with the whole wavefront
@@ -735,7 +748,7 @@ struct Kern {
     //    at working precision (then y_k is below what the inverse-iteration estimate can
     //    resolve, and r is overestimated).
     static __device__ bool converged(const EvalArgs &a, Lane &ln, double theta_new, double r) {
-        double r_abs = ldexp(a.tol_norm * a.normA * sqrt(theta_new), ln.E0);
+        double r_abs = ldexp(a.tol_norm * fro(a, ln) * sqrt(theta_new), ln.E0);
         double tol_th = 2.0 * (r_abs + a.tol_rel);
         double delta = fmax(theta_new - ln.theta, 0.0);
         bool flat = ln.nchecks >= 1 && delta <= 0x1p-44 * theta_new;
@@ -796,7 +809,7 @@ struct Kern {
             ln.gmax = 0.0;
             ln.gopen = ap * ap;
             if (VEC) abq[s] = ap;
-            double r_abs = ldexp(a.tol_norm * a.normA * ap, ln.E0);
+            double r_abs = ldexp(a.tol_norm * fro(a, ln) * ap, ln.E0);
             if (r_abs >= 2.0) {
                 ln.theta = ap * ap;
                 finish(a, w, s, ln, 0);
@@ -918,6 +931,9 @@ struct Kern {
         ln.gmax = ln.gopen = 0.0;
         ln.delta_prev = ln.rho_prev = 0.0;
         ln.pending = false;
+        ln.n = a.n;
+        ln.arow = a.arow;
+        ln.normA = a.normA;
         while (true) {
             if (VEC && __all(!ln.active) && __any(ln.pending)) vec_finalize(a, w, s, ln);
             bool may_refill = !ln.active && !ln.exhausted;
@@ -934,8 +950,32 @@ struct Kern {
                     ln.k = 0;
                     ln.b_m = 0.0;
                     ln.b_e = 0;
-                    if (a.mode == kShiftList) ln.z = a.z[ln.pid];
-                    else ln.z = grid_point(a, a.idx ? a.idx[ln.pid] : ln.pid);
+                    if (BATCH) {
+                        // matrix of queue position id: the last m with mfirst[m] <= id
+                        int lo = 0, hi = a.nmat - 1;
+                        while (lo < hi) {
+                            int mid = (lo + hi + 1) >> 1;
+                            if (a.mfirst[mid] <= (int64_t)id) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const MatDesc d = a.mats[lo];
+                        const int64_t q = (int64_t)id - a.mfirst[lo];
+                        ln.n = d.n;
+                        ln.arow = d.arow;
+                        ln.normA = d.normA;
+                        ln.pid = d.out_off + q;
+                        const int64_t flat = a.idx[ln.pid];
+                        const int64_t gi = flat / d.nx, gj = flat - gi * d.nx;
+                        const double x = d.nx > 1 ? __dadd_rn(d.ga, __ddiv_rn(__dmul_rn(d.gb - d.ga, (double)gj),
+                                                                               (double)(d.nx - 1))) : d.ga;
+                        const double y = d.ny > 1 ? __dadd_rn(d.gc, __ddiv_rn(__dmul_rn(d.gd - d.gc, (double)gi),
+                                                                               (double)(d.ny - 1))) : d.gc;
+                        ln.z = C(x, y);
+                    } else if (a.mode == kShiftList) {
+                        ln.z = a.z[ln.pid];
+                    } else {
+                        ln.z = grid_point(a, a.idx ? a.idx[ln.pid] : ln.pid);
+                    }
                 }
             }
             if (__all(!ln.active && ln.exhausted)) break;
@@ -954,9 +994,9 @@ struct Kern {
     }
 };
 
-template <int KL, int KU, bool VEC>
+template <int KL, int KU, bool VEC, bool BATCH>
 __global__ void __launch_bounds__(256) k_eval(EvalArgs a, Workspace w) {
-    Kern<KL, KU, VEC>::run(a, w);
+    Kern<KL, KU, VEC, BATCH>::run(a, w);
 }
 
 // ------------------------------------------------------------------------ small kernels
@@ -1178,39 +1218,140 @@ hipError_t launch_compact_mask(const uint8_t *mask, int64_t npts, int64_t *idx, 
 
 typedef void (*EvalKernel)(EvalArgs, Workspace);
 
+// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only
 template <int KL, int KU>
-static EvalKernel pick_vec(bool vec) {
-    return vec ? k_eval<KL, KU, true> : k_eval<KL, KU, false>;
-}
-
-template <int KL>
-static EvalKernel pick_ku(int ku, bool vec) {
-    switch (ku) {
-    case 0: return pick_vec<KL, 0>(vec);
-    case 1: return pick_vec<KL, 1>(vec);
-    case 2: return pick_vec<KL, 2>(vec);
-    case 3: return pick_vec<KL, 3>(vec);
-    case 4: return pick_vec<KL, 4>(vec);
+static EvalKernel pick_mode(int mode) {
+    switch (mode) {
+    case 0: return k_eval<KL, KU, false, false>;
+    case 1: return k_eval<KL, KU, true, false>;
+    case 2: return k_eval<KL, KU, false, true>;
     }
     return nullptr;
 }
 
-static EvalKernel pick(int kl, int ku, bool vec) {
+template <int KL>
+static EvalKernel pick_ku(int ku, int mode) {
+    switch (ku) {
+    case 0: return pick_mode<KL, 0>(mode);
+    case 1: return pick_mode<KL, 1>(mode);
+    case 2: return pick_mode<KL, 2>(mode);
+    case 3: return pick_mode<KL, 3>(mode);
+    case 4: return pick_mode<KL, 4>(mode);
+    }
+    return nullptr;
+}
+
+static EvalKernel pick(int kl, int ku, int mode) {
     switch (kl) {
-    case 0: return pick_ku<0>(ku, vec);
-    case 1: return pick_ku<1>(ku, vec);
-    case 2: return pick_ku<2>(ku, vec);
-    case 3: return pick_ku<3>(ku, vec);
-    case 4: return pick_ku<4>(ku, vec);
+    case 0: return pick_ku<0>(ku, mode);
+    case 1: return pick_ku<1>(ku, mode);
+    case 2: return pick_ku<2>(ku, mode);
+    case 3: return pick_ku<3>(ku, mode);
+    case 4: return pick_ku<4>(ku, mode);
     }
     return nullptr;
 }
 
 hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st) {
-    EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0);
+    EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
     int64_t blocks = ws.slots / 256;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, st, a, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_batch(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st) {
+    EvalKernel k = pick(kl, ku, 2);
+    if (!k) return hipErrorInvalidValue;
+    int64_t blocks = ws.slots / 256;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, st, a, ws);
+    return hipGetLastError();
+}
+
+int64_t batch_tiles(int64_t max_npts) { return (max_npts + kScanTile - 1) / kScanTile; }
+
+// Batched compaction: blockIdx.y = matrix, blockIdx.x = tile of kScanTile grid points.
+// A NULL mask selects every grid point of that matrix.
+__global__ void __launch_bounds__(kScanBlock) k_bmask_count(const MatDesc *mats, const uint8_t *const *masks,
+                                                            int64_t ntiles, int64_t *tilesums) {
+    __shared__ int64_t sh[kScanBlock];
+    const int m = blockIdx.y;
+    const int64_t npts = mats[m].nx * mats[m].ny;
+    const uint8_t *mask = masks ? masks[m] : nullptr;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < npts && (!mask || mask[base + q])) ++c;
+    int64_t total;
+    block_scan(c, sh, total);
+    if (threadIdx.x == 0) tilesums[(int64_t)m * ntiles + blockIdx.x] = total;
+}
+
+// One block per matrix: exclusive scan of its tile sums, count -> counts[m].
+__global__ void __launch_bounds__(kScanBlock) k_bscan(int64_t ntiles, int64_t *tilesums, int64_t *counts) {
+    __shared__ int64_t sh[kScanBlock];
+    const int m = blockIdx.x;
+    int64_t *ts = tilesums + (int64_t)m * ntiles;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kScanBlock) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = i < ntiles ? ts[i] : 0;
+        int64_t total;
+        int64_t ex = block_scan(v, sh, total);
+        if (i < ntiles) ts[i] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[m] = carry;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_bmask_scatter(const MatDesc *mats, const uint8_t *const *masks,
+                                                              int64_t ntiles, const int64_t *tilesums, int64_t *idx) {
+    __shared__ int64_t sh[kScanBlock];
+    const int m = blockIdx.y;
+    const int64_t npts = mats[m].nx * mats[m].ny;
+    const uint8_t *mask = masks ? masks[m] : nullptr;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < npts && (!mask || mask[base + q])) ++c;
+    int64_t total;
+    int64_t ex = block_scan(c, sh, total);
+    int64_t pos = tilesums[(int64_t)m * ntiles + blockIdx.x] + ex;
+    int64_t *out = idx + mats[m].out_off;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < npts && (!mask || mask[base + q])) out[pos++] = base + q;
+}
+
+// Queue positions of one class: mfirst[m] = sum of counts before m; total -> *total.
+__global__ void k_batch_prefix(const MatDesc *mats, const int64_t *counts, int nmat, int64_t *mfirst,
+                               int64_t *total, unsigned long long *queue) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t acc = 0;
+        for (int m = 0; m < nmat; ++m) {
+            mfirst[m] = acc;
+            acc += counts[mats[m].cidx];
+        }
+        *total = acc;
+        *queue = 0ull;
+    }
+}
+
+hipError_t launch_batch_compact(const MatDesc *mats, int nmat, int64_t max_npts, const uint8_t *const *masks,
+                                int64_t *idx, int64_t *counts, int64_t *tilesums, hipStream_t st) {
+    int64_t nt = batch_tiles(max_npts);
+    if (nt < 1) nt = 1;
+    hipLaunchKernelGGL(k_bmask_count, dim3((unsigned)nt, (unsigned)nmat), dim3(kScanBlock), 0, st, mats, masks, nt,
+                       tilesums);
+    hipLaunchKernelGGL(k_bscan, dim3((unsigned)nmat), dim3(kScanBlock), 0, st, nt, tilesums, counts);
+    hipLaunchKernelGGL(k_bmask_scatter, dim3((unsigned)nt, (unsigned)nmat), dim3(kScanBlock), 0, st, mats, masks, nt,
+                       (const int64_t *)tilesums, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prefix(const MatDesc *mats_cls, const int64_t *counts, int nmat, int64_t *mfirst,
+                               int64_t *total, unsigned long long *queue, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(64), 0, st, mats_cls, counts, nmat, mfirst, total, queue);
     return hipGetLastError();
 }
 

@@ -121,12 +121,9 @@ def random_banded(n: int, kl: int, ku: int, seed: int, scale: float = 1.0,
     ab = _cn(rng, (n, kl + ku + 1)) * scale
     if diag_uniform:
         ab[:, ku] += rng.uniform(-diag_uniform, diag_uniform, n)
-    # zero the slots that fall outside the matrix
-    for j in range(n):
-        for r in range(kl + ku + 1):
-            i = r - ku + j
-            if i < 0 or i >= n:
-                ab[j, r] = 0
+    # zero the slots that fall outside the matrix (row i = r - ku + j)
+    i = np.arange(kl + ku + 1)[None, :] - ku + np.arange(n)[:, None]
+    ab[(i < 0) | (i >= n)] = 0
     return Band(ab, n, kl, ku, False)
 
 
@@ -183,11 +180,13 @@ def gershgorin_box(band: Band):
     n, kl, ku = band.n, band.kl, band.ku
     centre = band.ab[:, ku].copy()            # ab[j, ku] = A[j, j]
     radius = np.zeros(n)
-    for j in range(n):
-        for r in range(kl + ku + 1):
-            i = r - ku + j
-            if 0 <= i < n and i != j:
-                radius[i] += abs(band.ab[j, r])
+    for r in range(kl + ku + 1):
+        if r == ku:
+            continue
+        j = np.arange(n)
+        i = r - ku + j                         # ab[j, r] = A[i, j]
+        ok = (i >= 0) & (i < n)
+        np.add.at(radius, i[ok], np.abs(band.ab[j[ok], r]))
     return (float(np.min(centre.real - radius)), float(np.max(centre.real + radius)),
             float(np.min(centre.imag - radius)), float(np.max(centre.imag + radius)))
 
