@@ -46,6 +46,13 @@ def algorithmic_bytes(n, kl, ku, iters):
     return float((kl + ku + 1) * 16 * n + np.sum(b_lu + iters * b_step + 16))
 
 
+def _grid_points(grid):
+    """Grid points of Sec. 2.1 in the library's convention (inclusive ends, row index <-> y)."""
+    xs = np.array([grid.a + (grid.b - grid.a) * j / (grid.nx - 1) for j in range(grid.nx)])
+    ys = np.array([grid.c + (grid.d - grid.c) * i / (grid.ny - 1) for i in range(grid.ny)])
+    return (xs[None, :] + 1j * ys[:, None]).ravel()
+
+
 def cpu_baseline(band, z_sample, threads):
     import oracle
     oracle.build(force=False)
@@ -65,6 +72,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=1)
     ap.add_argument("--progress", action="store_true", help="synchronise and report after every timed step")
+    ap.add_argument("--plain-points", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -131,6 +139,26 @@ def main():
     bytes_full = algorithmic_bytes(band.n, band.kl, band.ku, it_full)
     achieved = bytes_full / dur_full / 1e9
 
+    # plain per-shift GPU path (the speedup denominator): the same numerics and tolerance,
+    # one launch per shift, no batching, on a seeded sample of the full grid
+    rng = np.random.default_rng(2605_04550 + 7)
+    sample = rng.choice(npts_full, size=args.plain_points, replace=False)
+    zs_all = _grid_points(grid)
+    z1 = torch.tensor(zs_all[sample], dtype=torch.complex128, device=dev)
+    ws1 = torch.empty(ps_workspace_size(mat.handle, 1, o), dtype=torch.uint8, device=dev)
+    sig1 = torch.empty(1, dtype=torch.float64, device=dev)
+    from paper_2605_04550_amd import ps_eval_points
+    handle = stream.cuda_stream
+    ps_eval_points(mat.handle, z1[0:1].data_ptr(), 1, o, ws1.data_ptr(), ws1.numel(), sig1.data_ptr(), 0, 0, 0, 0,
+                   handle)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for p in range(args.plain_points):
+        ps_eval_points(mat.handle, z1[p:p + 1].data_ptr(), 1, o, ws1.data_ptr(), ws1.numel(), sig1.data_ptr(), 0, 0,
+                       0, 0, handle)
+    torch.cuda.synchronize()
+    plain_value = args.plain_points / (time.perf_counter() - tp0)
+
     traffic = None
     prof = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
     if os.path.exists(prof):
@@ -162,6 +190,10 @@ def main():
             "iters_mean_mask": float(it_mask.mean()) if cnt_mask else 0.0,
             "maxiter_points_full": int(np.sum((info_full & 2) != 0)),
         },
+        "plain": {"value": plain_value, "unit": "shifts/s",
+                  "sample": "%d seeded points of the full grid, one launch per shift (same kernel numerics and "
+                            "tolerance, no batching)" % args.plain_points},
+        "speedup_vs_plain": value / plain_value,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -175,8 +207,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(2605_04550)
-        import oracle
-        zs = oracle.grid_points(grid)[rng.choice(npts_full, size=args.cpu_points, replace=False)]
+        zs = _grid_points(grid)[rng.choice(npts_full, size=args.cpu_points, replace=False)]
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         print("bench: timing the CPU oracle on %d point(s)" % len(zs), file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(band, zs, threads)

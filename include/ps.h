@@ -89,7 +89,8 @@ typedef struct {
     int32_t max_iter;     /* default 3000  */
     int32_t want_vectors; /* 1: also return u, v (sizes [npts][n])          */
     int32_t slots;        /* 0: default                                       */
-    int32_t reserved;
+    int32_t check_shift;  /* Ritz-value checks every max(1, k >> check_shift)
+                             Lanczos steps (0: default 4); set by ps_autotune  */
 } ps_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -212,6 +213,32 @@ ps_status ps_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes);
 ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_opts *o, void *ws_dev, size_t ws_bytes,
                         int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
                         int32_t *iters_dev, void *stream);
+
+/*
+ * ps_newton_contour -- refine points toward the eps-level curve of sigma_min (the boundary of
+ * the eps-pseudospectrum drawn as the level curve log10 eps in Sec. 2.1).  Each of `steps`
+ * steps evaluates sigma_min with its singular vectors at every point, forms
+ * g = conj(u^H v) (the gradient of sigma_min in the conjugate-Wirtinger convention) and
+ * moves z <- z - sigma ln(sigma / eps) g / |g|^2 (Newton on ln(sigma / eps) along g).
+ *   z_dev      device ps_c128[npts], updated in place.  sigma_dev: device double[npts],
+ *              sigma_min at the final points.  info_dev: device int32[npts] or NULL.
+ *   eps > 0, steps >= 0.  o: options of the evaluations (vectors are implied).
+ *   ws_dev / ws_bytes >= ps_newton_workspace_size(m, npts, o).
+ * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_newton_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes);
+ps_status ps_newton_contour(ps_matrix m, ps_c128 *z_dev, int64_t npts, double eps, int32_t steps, const ps_opts *o,
+                            void *ws_dev, size_t ws_bytes, double *sigma_dev, int32_t *info_dev, void *stream);
+
+/*
+ * ps_autotune -- choose the plan for ps_eval_points / ps_eval_grid on this matrix: the number
+ * of slots (shifts in flight) and the Ritz-check schedule.  Times each candidate on
+ * z_dev[0 .. npts) (a representative sample of the shifts to be evaluated, on the device)
+ * with HIP events and writes the fastest into o->slots and o->check_shift.  Synchronous;
+ * allocates and frees its own workspace.  Results of the timed runs are discarded.
+ * Errors: PS_ERR_INVALID, PS_ERR_HIP.
+ */
+ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *o, void *stream);
 
 /* Thread-local description of the last error on the calling thread ("" if none). */
 const char *ps_last_error(void);

@@ -37,7 +37,7 @@ class ps_grid(ctypes.Structure):
 
 class ps_opts(ctypes.Structure):
     _fields_ = [("tol_norm", ctypes.c_double), ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("want_vectors", ctypes.c_int32), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("want_vectors", ctypes.c_int32), ("slots", ctypes.c_int32), ("check_shift", ctypes.c_int32)]
 
 
 class PsError(RuntimeError):
@@ -66,6 +66,10 @@ _SIGNATURES = {
                                     _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P]),
     "ps_backward_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ctypes.c_size_t)]),
     "ps_backward": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "ps_newton_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_newton_contour": (ctypes.c_int, [_P, _P, _I64, ctypes.c_double, _I32, ctypes.POINTER(ps_opts), _P,
+                                         ctypes.c_size_t, _P, _P, _P]),
+    "ps_autotune": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ps_opts), _P]),
     "ps_create_batch": (ctypes.c_int, [_I32, ctypes.POINTER(_P), ctypes.POINTER(ps_grid), ctypes.POINTER(_P)]),
     "ps_destroy_batch": (ctypes.c_int, [_P]),
     "ps_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -161,6 +165,25 @@ def ps_backward(handle, npts, grad_sigma_ptr, u_ptr, v_ptr, grad_z_ptr, grad_ban
                 stream=0) -> None:
     _check(lib().ps_backward(_P(handle), npts, _P(grad_sigma_ptr), _P(u_ptr), _P(v_ptr), _P(grad_z_ptr),
                              _P(grad_band_ptr), _P(ws_ptr), ws_bytes, _P(stream)))
+
+
+def ps_newton_workspace_size(handle: int, npts: int, opts: ps_opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_newton_workspace_size(_P(handle), npts, ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.byref(b)))
+    return b.value
+
+
+def ps_newton_contour(handle, z_ptr, npts, eps, steps, opts, ws_ptr, ws_bytes, sigma_ptr, info_ptr=0,
+                      stream=0) -> None:
+    _check(lib().ps_newton_contour(_P(handle), _P(z_ptr), npts, float(eps), int(steps),
+                                   ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
+                                   _P(sigma_ptr), _P(info_ptr), _P(stream)))
+
+
+def ps_autotune(handle, z_ptr, npts, opts: ps_opts, stream=0) -> ps_opts:
+    _check(lib().ps_autotune(_P(handle), _P(z_ptr), npts, ctypes.byref(opts), _P(stream)))
+    return opts
 
 
 def ps_create_batch(handles, grids) -> int:

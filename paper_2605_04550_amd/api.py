@@ -15,10 +15,10 @@ import math
 import numpy as np
 import torch
 
-from . import (PS_DEVICE_PTR, PS_REAL_A, ps_backward, ps_backward_workspace_size, ps_batch_info,
+from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_workspace_size, ps_batch_info,
                ps_batch_workspace_size, ps_create_banded, ps_create_batch, ps_destroy, ps_destroy_batch,
-               ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_opts_default,
-               ps_workspace_size)
+               ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
+               ps_newton_workspace_size, ps_opts_default, ps_workspace_size)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
 
@@ -28,9 +28,9 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0):
+def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0, check_shift=0):
     return ps_opts_default(tol_norm=tol_norm, tol_rel=tol_rel, max_iter=max_iter,
-                           want_vectors=int(bool(want_vectors)), slots=int(slots))
+                           want_vectors=int(bool(want_vectors)), slots=int(slots), check_shift=int(check_shift))
 
 
 class BandedMatrix:
@@ -224,14 +224,24 @@ class SigmaMin(torch.autograd.Function):
         return gb, gz, None, None, None
 
 
-def newton_contour(mat: BandedMatrix, z0: torch.Tensor, eps: float, steps: int = 3):
-    """Newton on phi(z) = ln(sigma_min(z)/eps) along its gradient g = conj(u^H v):
-    z <- z - sigma ln(sigma/eps) g / |g|^2.  Returns the refined points and their sigma."""
-    z = z0.clone()
-    for _ in range(steps):
-        r = sigma_min(mat, z, want_vectors=True, tol_rel=1e-12, tol_norm=1e-14)
-        gz, _ = backward(mat, torch.ones_like(r["sigma"]), r["u"], r["v"], want_band=False)
-        s = r["sigma"]
-        z = z - (s * torch.log(s / eps)).to(torch.complex128) * gz / (gz.abs() ** 2)
-    r = sigma_min(mat, z, tol_rel=1e-12, tol_norm=1e-14)
-    return z, r["sigma"]
+def newton_contour(mat: BandedMatrix, z0: torch.Tensor, eps: float, steps: int = 3, tol_rel=1e-12, tol_norm=1e-14,
+                   stream=None):
+    """ps_newton_contour: `steps` Newton steps on ln(sigma_min/eps) along g = conj(u^H v), all on the GPU.
+    Returns the refined points and sigma_min there."""
+    z = z0.detach().to(torch.complex128).contiguous().clone()
+    npts = z.numel()
+    dev = z.device
+    o = make_opts(tol_norm, tol_rel, 3000, True, 0)
+    sig = torch.empty(npts, dtype=torch.float64, device=dev)
+    info = torch.empty(npts, dtype=torch.int32, device=dev)
+    ws = _workspace(ps_newton_workspace_size(mat.handle, npts, o), dev)
+    ps_newton_contour(mat.handle, z.data_ptr(), npts, eps, steps, o, ws.data_ptr(), ws.numel(), sig.data_ptr(),
+                      info.data_ptr(), _stream_handle(stream))
+    return z, sig
+
+
+def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):
+    """ps_autotune on the shifts z: returns the options (slots, check_shift) that ran fastest."""
+    o = make_opts(**kw)
+    ps_autotune(mat.handle, z.contiguous().data_ptr(), z.numel(), o, _stream_handle())
+    return o

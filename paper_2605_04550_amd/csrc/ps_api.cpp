@@ -64,8 +64,11 @@ ps_status check_opts(const ps_opts &o) {
     if (o.max_iter < 1 || o.max_iter > ps::kMaxIterCap)
         return fail(PS_ERR_INVALID, "max_iter must be in [1, %d]", ps::kMaxIterCap);
     if (o.slots < 0) return fail(PS_ERR_INVALID, "slots must be >= 0");
+    if (o.check_shift < 0 || o.check_shift > 12) return fail(PS_ERR_INVALID, "check_shift must be in [0, 12]");
     return PS_OK;
 }
+
+int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 4; }
 
 int kvec_of(const ps_opts &o) { return o.want_vectors ? (o.max_iter < kVecBasisMax ? o.max_iter : kVecBasisMax) : 0; }
 
@@ -123,6 +126,7 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     a->tol_norm = o.tol_norm;
     a->tol_rel = o.tol_rel;
     a->max_iter = o.max_iter;
+    a->check_shift = check_shift_of(o);
     a->want_vectors = o.want_vectors;
     a->sigma = sigma;
     a->u = (double2 *)u;
@@ -142,7 +146,7 @@ void ps_opts_default(ps_opts *o) {
     o->max_iter = 3000;
     o->want_vectors = 0;
     o->slots = 0;
-    o->reserved = 0;
+    o->check_shift = 0;
 }
 
 const char *ps_last_error(void) { return g_err; }
@@ -330,7 +334,7 @@ ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, c
     hipStream_t s = (hipStream_t)stream;
     if (npts == 0) {
         if (grad_band_dev)
-            HIP_TRY(hipMemsetAsync(grad_band_dev, 0, sizeof(ps_c128) * (size_t)m->n * (m->kl + m->ku + 1), s));
+            HIP_TRY(ps::launch_zero(grad_band_dev, sizeof(ps_c128) * (size_t)m->n * (m->kl + m->ku + 1), s));
         return ok();
     }
     size_t need = 0;
@@ -386,6 +390,119 @@ size_t batch_scratch_bytes(const ps_batch_s *b) {
 }  // namespace
 
 extern "C" {
+
+ps_status ps_newton_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    ps_opts r = resolve(o);
+    r.want_vectors = 1;
+    if ((st = check_opts(r))) return st;
+    size_t ev = 0;
+    if ((st = ps_workspace_size(m, npts, &r, &ev))) return st;
+    ev = (ev + 255) & ~(size_t)255;
+    size_t vec = ((sizeof(ps_c128) * (size_t)npts * (size_t)m->n) + 255) & ~(size_t)255;
+    size_t gz = ((sizeof(ps_c128) * (size_t)npts) + 255) & ~(size_t)255;
+    *bytes = ev + 2 * vec + gz;
+    return ok();
+}
+
+ps_status ps_newton_contour(ps_matrix m, ps_c128 *z_dev, int64_t npts, double eps, int32_t steps, const ps_opts *o,
+                            void *ws_dev, size_t ws_bytes, double *sigma_dev, int32_t *info_dev, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (npts < 0 || steps < 0) return fail(PS_ERR_INVALID, "npts and steps must be >= 0");
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite and > 0");
+    if (npts == 0) return ok();
+    if (!z_dev || !sigma_dev) return fail(PS_ERR_INVALID, "z and sigma are required");
+    ps_opts rv = resolve(o);
+    rv.want_vectors = 1;
+    if ((st = check_opts(rv))) return st;
+    size_t need = 0;
+    ps_newton_workspace_size(m, npts, &rv, &need);
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "Newton workspace needs %zu bytes", need);
+    size_t ev = 0;
+    ps_workspace_size(m, npts, &rv, &ev);
+    ev = (ev + 255) & ~(size_t)255;
+    size_t vec = ((sizeof(ps_c128) * (size_t)npts * (size_t)m->n) + 255) & ~(size_t)255;
+    char *base = (char *)ws_dev;
+    ps_c128 *u = (ps_c128 *)(base + ev);
+    ps_c128 *v = (ps_c128 *)(base + ev + vec);
+    double2 *gz = (double2 *)(base + ev + 2 * vec);
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t it = 0; it < steps; ++it) {
+        if ((st = ps_eval_points(m, z_dev, npts, &rv, ws_dev, ev, sigma_dev, u, v, info_dev, nullptr, stream)))
+            return st;
+        HIP_TRY(ps::launch_backward(m->n, m->kl, m->ku, npts, nullptr, (const double2 *)u, (const double2 *)v, gz,
+                                    nullptr, nullptr, 0, s));
+        HIP_TRY(ps::launch_newton_update(npts, (double2 *)z_dev, sigma_dev, gz, eps, s));
+    }
+    ps_opts rs = rv;
+    rs.want_vectors = 0;
+    if ((st = ps_eval_points(m, z_dev, npts, &rs, ws_dev, ev, sigma_dev, nullptr, nullptr, info_dev, nullptr,
+                             stream)))
+        return st;
+    return ok();
+}
+
+ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *o, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (!o || !z_dev || npts < 1) return fail(PS_ERR_INVALID, "need options, shifts and npts >= 1");
+    if ((st = check_opts(*o))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    ps_opts base = *o;
+    base.slots = 0;
+    const int64_t s0 = default_slots(m, npts, base);
+    std::vector<int64_t> slot_cands;
+    for (int64_t sl = s0; sl >= kSlotQuantum && slot_cands.size() < 3; sl = round_slots(sl / 2))
+        slot_cands.push_back(sl);
+    const int shift_cands[3] = {3, 4, 5};
+    size_t wsb = 0;
+    if ((st = ps_workspace_size(m, npts, &base, &wsb))) return st;
+    void *ws = nullptr;
+    double *sig = nullptr;
+    HIP_TRY(hipMalloc(&ws, wsb));
+    hipError_t e = hipMalloc((void **)&sig, sizeof(double) * (size_t)npts);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = INFINITY;
+    ps_opts pick = base;
+    for (size_t i = 0; e == hipSuccess && i < slot_cands.size(); ++i) {
+        for (int c = 0; e == hipSuccess && c < 3; ++c) {
+            ps_opts t = base;
+            t.slots = (int32_t)slot_cands[i];
+            t.check_shift = shift_cands[c];
+            t.want_vectors = 0;
+            if ((st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr, nullptr, stream)))
+                break;
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess && (st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr,
+                                                        nullptr, stream)))
+                break;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                pick = t;
+            }
+        }
+        if (st) break;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sig);
+    (void)hipFree(ws);
+    if (st) return st;
+    if (e != hipSuccess) return fail(PS_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+    o->slots = pick.slots;
+    o->check_shift = pick.check_shift;
+    return ok();
+}
 
 ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *grids, ps_batch *out) {
     if (!out) return fail(PS_ERR_INVALID, "out is NULL");
@@ -536,6 +653,7 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
         a.tol_norm = r.tol_norm;
         a.tol_rel = r.tol_rel;
         a.max_iter = r.max_iter;
+        a.check_shift = check_shift_of(r);
         a.want_vectors = 0;
         a.sigma = sigma_dev;
         a.info = info_dev;

@@ -77,6 +77,7 @@ struct EvalArgs {
     const int64_t *count_dev = nullptr;   // device count of shifts
     double tol_norm = 1e-10, tol_rel = 1e-8;
     int max_iter = 1000;
+    int check_shift = 4;
     int want_vectors = 0;
     uint64_t seed = 0x2605045500000001ull;
     double *sigma = nullptr;
@@ -114,5 +115,8 @@ hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double
                            const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,
                            hipStream_t st);
 int64_t backward_partial_rows(int64_t npts);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_newton_update(int64_t npts, double2 *z, const double *sigma, const double2 *grad_z, double eps,
+                                hipStream_t st);
 
 }  // namespace ps

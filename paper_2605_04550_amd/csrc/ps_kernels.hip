@@ -124,7 +124,10 @@ __device__ TopEig top_eig(const double *hist, int64_t T, int64_t s, int k, doubl
     TopEig r;
     r.theta = hi;
     r.yk2 = 1.0;
-    double lam = hi;
+    // Ritz values move little between checks: probe just above the previous value first
+    // (lo > 0), widening the probe until it lies above every eigenvalue, then Newton.
+    int probe = lo > 0.0 ? 0 : 3;          // probe p sits at lo (1 + 2^(10 p - 24))
+    double lam = probe < 3 ? fmin(hi, lo * (1.0 + 0x1p-24)) : hi;
     double prev_step = INFINITY;
     double ssum_hi = 0.0;
     bool have_hi = false;
@@ -155,6 +158,16 @@ __device__ TopEig top_eig(const double *hist, int64_t T, int64_t s, int k, doubl
             lo = lam;
         }
         if (hi - lo <= 0x1p-46 * hi) break;
+        if (!have_hi && probe < 2) {        // probe was below the top eigenvalue: widen it
+            ++probe;
+            lam = fmin(hi, lo * (1.0 + ldexp(1.0, 10 * probe - 24)));
+            continue;
+        }
+        if (!have_hi && probe == 2) {       // fall back to the Gershgorin bound
+            probe = 3;
+            lam = hi;
+            continue;
+        }
         double next = 0.5 * (lo + hi);
         if (have_hi && ssum_hi > 0.0) {
             double step = 1.0 / ssum_hi;
@@ -221,10 +234,20 @@ struct Kern {
         return m;
     }
 
-    // Every sweep walks the rows in chunks of CH: the loads of a whole chunk are issued
-    // first (they do not depend on the recurrence), then the chunk's rows are computed in
-    // order.  A wavefront thus keeps CH rows of loads in flight instead of one.
+    // Every sweep walks the rows in chunks of CH = 8: the loads of a whole chunk are issued
+    // first (they do not depend on the recurrence), then the chunk's rows are computed.
+    //
+    // Block floating point: every stored vector carries one binary exponent per chunk of 8
+    // rows (value of row r = mantissa * 2^e[r / 8]).  A chunk is first computed on the fast
+    // path, where the sweep's running exponent R is fixed and every conversion is a
+    // multiplication by a per-chunk factor, while one flag records whether any value left
+    // the safe range (|x| >= 2^400, Inf or NaN).  Only if it did is the chunk recomputed on
+    // the careful path from the state saved at its start, rescaling row by row; its outputs
+    // are then brought to the chunk's final exponent before they are stored.
     static constexpr int CH = 8;
+
+    static __device__ __forceinline__ double p2(int e) { return ldexp(1.0, e); }
+    static __device__ __forceinline__ bool unsafe(cd v) { return !(cabs1(v) < kBig); }
 
     // ---------------------------------------------------------------- forward sweep 1
     // Fresh lanes: LU of M fused with the L solve of the start vector h (also stored as v).
@@ -238,46 +261,45 @@ struct Kern {
         const bool act = ln.active, fresh = ln.fresh;
         const double tiny = 0x1p-1000 * fmax(1.0, fro(a, ln) + cabs1(ln.z));
         bool sing = false;
-        const double rdv = ln.rdv;
-        const int Ev = ln.Ev;
+        // input v: normalised stored v (mantissa * rdv * 2^(e - Ev)); fresh lanes read h
+        const double rdv = fresh ? 1.0 : ln.rdv;
+        const int Ev = fresh ? 0 : ln.Ev;
         const int64_t npad = ((n + CH - 1) / CH) * CH;
-        auto gen_in = [&](int64_t i) -> cd {   // fresh lanes: start vector entry i, stored as v
-            if (i >= n) {                       // padding rows stay zero
-                w.vv[i * T + s] = czero();
-                w.ev[i * T + s] = 0;
-                return czero();
-            }
-            cd h = start_entry(a.seed, i);
+        auto gen = [&](int64_t i) -> cd {        // fresh lanes: start vector entry i, stored as v
+            cd h = i < n ? start_entry(a.seed, i) : czero();   // padding rows stay zero
             w.vv[i * T + s] = h;
-            w.ev[i * T + s] = 0;
             nrm_h += cabs2(h);
-            return cldexp(h, -R);
+            return h;
         };
         if (act) {
             if (fresh) {
+                w.ev[s] = 0;
 #pragma unroll
-                for (int r = 0; r < KL; ++r) b[r] = gen_in(r);
+                for (int r = 0; r < KL; ++r) b[r] = gen(r);
 #pragma unroll
                 for (int r = 0; r < KL; ++r)
 #pragma unroll
                     for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, ln, r, c);
             } else {
+                const double f0 = rdv * p2((int)w.ev[s] - Ev);
 #pragma unroll
-                for (int r = 0; r < KL; ++r) b[r] = cldexp(cscale(w.vv[r * T + s], rdv), (int)w.ev[r * T + s] - Ev);
+                for (int r = 0; r < KL; ++r) b[r] = cscale(w.vv[r * T + s], f0);
             }
         }
         for (int64_t j0 = 0; j0 < npad; j0 += CH) {
             if (!act) continue;
+            const int64_t q = j0 / CH;
             cd pin[CH];
-            int ein[CH];
             int pv[CH];
             cd Lr[CH][KL > 0 ? KL : 1];
+            int ea = 0, eb = 0;
             if (!fresh) {
+                ea = (int)w.ev[q * T + s];
+                eb = KL > 0 ? (int)w.ev[(q + 1) * T + s] : ea;
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
-                    const int64_t j = j0 + c, ii = j + KL;
-                    pin[c] = w.vv[ii * T + s];
-                    ein[c] = (int)w.ev[ii * T + s];
+                    const int64_t j = j0 + c;
+                    pin[c] = w.vv[(j + KL) * T + s];
                     if (KL > 0) {
                         pv[c] = (int)w.piv[j * T + s];
 #pragma unroll
@@ -286,17 +308,17 @@ struct Kern {
                         pv[c] = 0;
                     }
                 }
-            }
+            } else {
+                // LU rows of this chunk (stored once; multipliers and pivots kept for the solve)
+                w.ev[(q + 1) * T + s] = 0;
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int64_t j = j0 + c;
-                int p = 0;
-                cd l[KL > 0 ? KL : 1];
-                if (fresh) {
-                    b[KL] = gen_in(j + KL);
+                for (int c = 0; c < CH; ++c) {
+                    const int64_t j = j0 + c;
+                    pin[c] = gen(j + KL);
 #pragma unroll
                     for (int cc = 0; cc < W; ++cc) Wm[KL][cc] = mentry(a, ln, j + KL, j + cc);
                     double best = cabs1(Wm[0][0]);
+                    int p = 0;
 #pragma unroll
                     for (int r = 1; r <= KL; ++r) {
                         double v = cabs1(Wm[r][0]);
@@ -312,46 +334,80 @@ struct Kern {
                     const cd rc = crecip(Wm[0][0]);
                     const cd inv = C(ok ? rc.x : 0.0, ok ? rc.y : 0.0);
 #pragma unroll
-                    for (int r = 1; r <= KL; ++r) l[r - 1] = cmul(Wm[r][0], inv);
+                    for (int r = 1; r <= KL; ++r) Lr[c][r - 1] = cmul(Wm[r][0], inv);
 #pragma unroll
                     for (int r = 1; r <= KL; ++r)
 #pragma unroll
-                        for (int cc = 1; cc < W; ++cc) Wm[r][cc] = cfnma(l[r - 1], Wm[0][cc], Wm[r][cc]);
+                        for (int cc = 1; cc < W; ++cc) Wm[r][cc] = cfnma(Lr[c][r - 1], Wm[0][cc], Wm[r][cc]);
                     w.U[(j * W + 0) * T + s] = inv;
 #pragma unroll
                     for (int cc = 1; cc < W; ++cc) w.U[(j * W + cc) * T + s] = Wm[0][cc];
 #pragma unroll
-                    for (int r = 0; r < KL; ++r) w.L[(j * KL + r) * T + s] = l[r];
+                    for (int r = 0; r < KL; ++r) w.L[(j * KL + r) * T + s] = Lr[c][r];
                     w.piv[j * T + s] = (uint8_t)p;
+                    pv[c] = p;
 #pragma unroll
                     for (int r = 0; r < KL; ++r) {
 #pragma unroll
                         for (int cc = 0; cc < W - 1; ++cc) Wm[r][cc] = Wm[r + 1][cc + 1];
                         Wm[r][W - 1] = czero();
                     }
-                } else {
-                    b[KL] = cldexp(cscale(pin[c], rdv), ein[c] - Ev - R);
-                    p = pv[c];
-#pragma unroll
-                    for (int r = 0; r < KL; ++r) l[r] = Lr[c][r];
                 }
-#pragma unroll
-                for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
-                cd y = b[0];
-                if (!(cabs1(y) < kBig)) {
-                    int sh = rescale_shift(cabs1(y), 1.0);
-#pragma unroll
-                    for (int r = 0; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
-                    y = b[0];
-                    R += sh;
-                }
-                w.vy[j * T + s] = y;
-                w.ey[j * T + s] = (int16_t)R;
-#pragma unroll
-                for (int r = 1; r <= KL; ++r) b[r] = cfnma(l[r - 1], y, b[r]);
-#pragma unroll
-                for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
             }
+            // L solve of the chunk
+            cd bs[KL + 1];
+#pragma unroll
+            for (int r = 0; r <= KL; ++r) bs[r] = b[r];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            {
+                const double fa = rdv * p2(ea - Ev - R), fb = rdv * p2(eb - Ev - R);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    b[KL] = cscale(pin[c], c + KL < CH ? fa : fb);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    const cd y = b[0];
+                    flag = flag || unsafe(y);
+                    ob[c] = y;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b[r] = cfnma(Lr[c][r - 1], y, b[r]);
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
+                }
+            }
+            if (flag) {   // careful path: rescale row by row
+#pragma unroll
+                for (int r = 0; r <= KL; ++r) b[r] = bs[r];
+                R = Rs;
+                int Rc[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    b[KL] = cscale(pin[c], rdv * p2((c + KL < CH ? ea : eb) - Ev - R));
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    cd y = b[0];
+                    if (unsafe(y)) {
+                        const int sh = rescale_shift(cabs1(y), 1.0);
+#pragma unroll
+                        for (int r = 0; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                        y = b[0];
+                        R += sh;
+                    }
+                    ob[c] = y;
+                    Rc[c] = R;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b[r] = cfnma(Lr[c][r - 1], y, b[r]);
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Rc[c] - R);
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) w.vy[(j0 + c) * T + s] = ob[c];
+            w.ey[q * T + s] = (int16_t)R;
         }
         if (act) {
             ln.Ey = R;
@@ -397,53 +453,93 @@ struct Kern {
         const double bm = ln.b_m;
         const int be = ln.b_e;
         const int64_t npad = ((n + CH - 1) / CH) * CH;
-        for (int64_t i0 = npad - 1; i0 >= 0; i0 -= CH) {
+        for (int64_t q = npad / CH - 1; q >= 0; --q) {
             if (!act) continue;
+            const int64_t i0 = q * CH + CH - 1;
             cd Ur[CH][W];
             cd yr[CH], ur[CH];
-            int eyr[CH], eur[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int64_t i = i0 - c;
 #pragma unroll
                 for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
                 yr[c] = w.vy[i * T + s];
-                eyr[c] = (int)w.ey[i * T + s];
                 ur[c] = uold[i * T + s];          // read even when unused (no branch); selected away below
-                eur[c] = (int)euold[i * T + s];
             }
+            const int ey = (int)w.ey[q * T + s];
+            const int eu = (int)euold[q * T + s];
+            cd xs[W];
+#pragma unroll
+            for (int d = 0; d < W; ++d) xs[d] = xw[d];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            int eo;
+            {
+                const int es = R > be ? R : be;
+                eo = sub ? es : R;
+                const double fy = p2(ey - R), ft = p2(R - es);
+                const double fu = bm * rd_old * p2(eu - E_old + be - es);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    cd rhs = cscale(yr[c], fy);
+#pragma unroll
+                    for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                    const cd t = cmul(rhs, Ur[c][0]);
+                    flag = flag || unsafe(t);
+                    const cd o = C(fma(-fu, ur[c].x, ft * t.x), fma(-fu, ur[c].y, ft * t.y));
+                    ob[c] = sub ? o : t;
+                    if constexpr (W > 1) {
+#pragma unroll
+                        for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
+                        xw[1] = t;
+                    }
+                }
+            }
+            if (flag) {   // careful path
+#pragma unroll
+                for (int d = 0; d < W; ++d) xw[d] = xs[d];
+                R = Rs;
+                int Ec[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    cd rhs = cldexp(yr[c], ey - R);
+#pragma unroll
+                    for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                    const cd inv = Ur[c][0];
+                    cd t = cmul(rhs, inv);
+                    if (unsafe(t)) {
+                        const int sh = rescale_shift(cabs1(rhs), cabs1(inv));
+                        rhs = cldexp(rhs, -sh);
+#pragma unroll
+                        for (int d = 1; d < W; ++d) xw[d] = cldexp(xw[d], -sh);
+                        R += sh;
+                        t = cmul(rhs, inv);
+                    }
+                    const int es = R > be ? R : be;
+                    const cd tt = cldexp(t, R - es);
+                    const cd bu = cscale(cldexp(ur[c], eu - E_old + be - es), bm * rd_old);
+                    ob[c] = sub ? csub(tt, bu) : t;
+                    Ec[c] = sub ? es : R;
+                    if constexpr (W > 1) {
+#pragma unroll
+                        for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
+                        xw[1] = t;
+                    }
+                }
+                eo = Ec[CH - 1];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Ec[c] - eo);
+            }
+            double cs = 0.0;
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                const int64_t i = i0 - c;
-                cd rhs = cldexp(yr[c], eyr[c] - R);
-                const cd inv = Ur[c][0];
-#pragma unroll
-                for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
-                cd t = cmul(rhs, inv);
-                if (!(cabs1(t) < kBig)) {
-                    int sh = rescale_shift(cabs1(rhs), cabs1(inv));
-                    rhs = cldexp(rhs, -sh);
-#pragma unroll
-                    for (int d = 1; d < W; ++d) xw[d] = cldexp(xw[d], -sh);
-                    R += sh;
-                    t = cmul(rhs, inv);
-                }
-                const cd uo = cldexp(cscale(ur[c], rd_old), eur[c] - E_old);
-                const int es = R > be ? R : be;
-                const cd tt = cldexp(t, R - es);
-                const cd bu = cscale(cldexp(uo, be - es), bm);
-                const int eo = sub ? es : R;
-                const cd o = sub ? csub(tt, bu) : t;
-                uout[i * T + s] = o;
-                euout[i * T + s] = (int16_t)eo;
-                acc = fma(o.x, o.x, fma(o.y, o.y, ldexp(acc, 2 * (Eacc - eo))));   // eo >= Eacc always
-                Eacc = eo;
-                if constexpr (W > 1) {
-#pragma unroll
-                    for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
-                    xw[1] = t;
-                }
+                uout[(i0 - c) * T + s] = ob[c];
+                cs = fma(ob[c].x, ob[c].x, fma(ob[c].y, ob[c].y, cs));
             }
+            euout[q * T + s] = (int16_t)eo;
+            acc = ldexp(acc, 2 * (Eacc - eo)) + cs;     // exponents of a sweep's outputs never decrease
+            Eacc = eo;
         }
         acc_out = acc;
         eacc_out = Eacc;
@@ -467,52 +563,87 @@ struct Kern {
         cd acc[W];
         const int64_t npad = ((n + CH - 1) / CH) * CH;
         if (act) {
+            const double f0 = rdu * p2((int)euin[s] - Eu);
 #pragma unroll
-            for (int d = 0; d < W - 1; ++d) acc[d] = cldexp(cscale(uin[d * T + s], rdu), (int)euin[d * T + s] - Eu);
+            for (int d = 0; d < W - 1; ++d) acc[d] = cscale(uin[d * T + s], f0);
         }
         for (int64_t i0 = 0; i0 < npad; i0 += CH) {
             if (!act) continue;
+            const int64_t q = i0 / CH;
             cd Ur[CH][W];
             cd pin[CH];
-            int ein[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int64_t i = i0 + c, ii = i + W - 1;
-#pragma unroll
-                for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
-                // rows at or past npad were never written: read (in bounds) and discard
-                const cd q = uin[ii * T + s];
-                const int e = (int)euin[ii * T + s];
-                const bool in = ii < npad;
-                pin[c] = C(in ? q.x : 0.0, in ? q.y : 0.0);
-                ein[c] = in ? e : 0;
-            }
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int64_t i = i0 + c;
-                acc[W - 1] = cldexp(cscale(pin[c], rdu), ein[c] - Eu - R);
-                const cd inv = Ur[c][0];
-                cd wv = cmul(acc[0], cconj(inv));
-                if (!(cabs1(wv) < kBig)) {
-                    int sh = rescale_shift(cabs1(acc[0]), cabs1(inv));
 #pragma unroll
-                    for (int d = 0; d < W; ++d) acc[d] = cldexp(acc[d], -sh);
-                    R += sh;
-                    wv = cmul(acc[0], cconj(inv));
-                }
-                w.vy[i * T + s] = wv;
-                w.ey[i * T + s] = (int16_t)R;
-#pragma unroll
-                for (int d = 1; d < W; ++d) acc[d] = cfnmac(Ur[c][d], wv, acc[d]);
-#pragma unroll
-                for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+                for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
+                pin[c] = uin[(i + W - 1) * T + s];
             }
+            const int ea = (int)euin[q * T + s];
+            const bool last = i0 + CH >= npad;                 // rows at or past npad were never written
+            const int eb = (W > 1 && !last) ? (int)euin[(q + 1) * T + s] : ea;
+            cd as[W];
+#pragma unroll
+            for (int d = 0; d < W; ++d) as[d] = acc[d];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            {
+                const double fa = rdu * p2(ea - Eu - R), fb = last ? 0.0 : rdu * p2(eb - Eu - R);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const cd x = cscale(pin[c], c + W - 1 < CH ? fa : fb);
+                    acc[W - 1] = (c + W - 1 < CH || !last) ? x : czero();
+                    const cd wv = cmul(acc[0], cconj(Ur[c][0]));
+                    flag = flag || unsafe(wv);
+                    ob[c] = wv;
+#pragma unroll
+                    for (int d = 1; d < W; ++d) acc[d] = cfnmac(Ur[c][d], wv, acc[d]);
+#pragma unroll
+                    for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+                }
+            }
+            if (flag) {   // careful path
+#pragma unroll
+                for (int d = 0; d < W; ++d) acc[d] = as[d];
+                R = Rs;
+                int Rc[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const bool in = c + W - 1 < CH || !last;
+                    const cd x = cscale(pin[c], rdu * p2((c + W - 1 < CH ? ea : eb) - Eu - R));
+                    acc[W - 1] = in ? x : czero();
+                    const cd inv = Ur[c][0];
+                    cd wv = cmul(acc[0], cconj(inv));
+                    if (unsafe(wv)) {
+                        const int sh = rescale_shift(cabs1(acc[0]), cabs1(inv));
+#pragma unroll
+                        for (int d = 0; d < W; ++d) acc[d] = cldexp(acc[d], -sh);
+                        R += sh;
+                        wv = cmul(acc[0], cconj(inv));
+                    }
+                    ob[c] = wv;
+                    Rc[c] = R;
+#pragma unroll
+                    for (int d = 1; d < W; ++d) acc[d] = cfnmac(Ur[c][d], wv, acc[d]);
+#pragma unroll
+                    for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Rc[c] - R);
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) w.vy[(i0 + c) * T + s] = ob[c];
+            w.ey[q * T + s] = (int16_t)R;
         }
         if (act) ln.Ey = R;
     }
 
     // ---------------------------------------------------------------- backward sweep 2
     // q = P L^{-H} y - alpha_k v_k; v updated in place; returns |q|^2 = acc * 2^(2 Eacc).
+    // Step j finalises entry j + kl, so the steps of output chunk p are j = 8p+7-kl .. 8p-kl;
+    // the kl steps above the top chunk run first (their outputs lie past the padding), and
+    // steps j < 0 carry zero data (they only flush the window).
     static __device__ void b2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
                               int &eacc_out) {
         const int64_t n = nn(a, ln), T = w.slots;
@@ -527,66 +658,127 @@ struct Kern {
         const int ae = ln.a_e;
         const double rdv = ln.rdv;
         const int Ev = ln.Ev;
-        // out_i = val 2^R - alpha v_i (v_i normalised from its stored mantissa vo / exponent evo)
-        auto emit = [&](int64_t i, cd val, cd vo, int evo) {
-            cd vn = cldexp(cscale(vo, rdv), evo - Ev);
-            int eo = R > ae ? R : ae;
-            cd o = csub(cldexp(val, R - eo), cscale(cldexp(vn, ae - eo), am));
-            w.vv[i * T + s] = o;
-            w.ev[i * T + s] = (int16_t)eo;
-            acc = fma(o.x, o.x, fma(o.y, o.y, ldexp(acc, 2 * (Eacc - eo))));   // eo >= Eacc always
-            Eacc = eo;
-        };
         const int64_t npad = ((n + CH - 1) / CH) * CH;
-        for (int64_t j0 = npad - 1; j0 >= 0; j0 -= CH) {
+        // one step of the L^H P sweep at row j (careful form, used for the top kl steps)
+        auto step_careful = [&](int64_t j, int ey) {
+            cd b0 = cldexp(w.vy[j * T + s], ey - R);
+#pragma unroll
+            for (int r = 1; r <= KL; ++r) b0 = cfnmac(w.L[(j * KL + (r - 1)) * T + s], b[r], b0);
+            if (unsafe(b0)) {
+                const int sh = rescale_shift(cabs1(b0), 1.0);
+                b0 = cldexp(b0, -sh);
+#pragma unroll
+                for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                R += sh;
+            }
+            b[0] = b0;
+            const int p = w.piv[j * T + s];
+#pragma unroll
+            for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
+#pragma unroll
+            for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
+        };
+        if (act && KL > 0) {
+            const int eyt = (int)w.ey[(npad / CH - 1) * T + s];
+            for (int64_t j = npad - 1; j >= npad - KL; --j) step_careful(j, eyt);
+        }
+        for (int64_t pq = npad / CH - 1; pq >= 0; --pq) {
             if (!act) continue;
+            const int64_t jtop = pq * CH + CH - 1 - KL;
             cd yr[CH], vr[CH];
-            int eyr[CH], evr[CH], pv[CH];
+            int pv[CH];
             cd Lr[CH][KL > 0 ? KL : 1];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                const int64_t j = j0 - c, io = j + KL;
-                yr[c] = w.vy[j * T + s];
-                eyr[c] = (int)w.ey[j * T + s];
+                const int64_t j = jtop - c;
+                const int64_t jc = j >= 0 ? j : 0;              // steps j < 0 carry zero data
+                const bool in = j >= 0;
+                const cd y = w.vy[jc * T + s];
+                yr[c] = C(in ? y.x : 0.0, in ? y.y : 0.0);
                 if (KL > 0) {
-                    pv[c] = (int)w.piv[j * T + s];
+                    pv[c] = in ? (int)w.piv[jc * T + s] : 0;
 #pragma unroll
-                    for (int r = 0; r < KL; ++r) Lr[c][r] = w.L[(j * KL + r) * T + s];
+                    for (int r = 0; r < KL; ++r) {
+                        const cd l = w.L[(jc * KL + r) * T + s];
+                        Lr[c][r] = C(in ? l.x : 0.0, in ? l.y : 0.0);
+                    }
                 } else {
                     pv[c] = 0;
                 }
-                vr[c] = w.vv[io * T + s];
-                evr[c] = (int)w.ev[io * T + s];
+                vr[c] = w.vv[(j + KL) * T + s];
             }
+            const int eyh = (int)w.ey[pq * T + s];                  // rows >= 8 pq
+            const int eyl = pq > 0 ? (int)w.ey[(pq - 1) * T + s] : eyh;   // rows < 8 pq
+            const int evp = (int)w.ev[pq * T + s];
+            cd bs[KL + 1];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int64_t j = j0 - c;
-                cd b0 = cldexp(yr[c], eyr[c] - R);
+            for (int r = 0; r <= KL; ++r) bs[r] = b[r];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            int eo;
+            {
+                const int es = R > ae ? R : ae;
+                eo = es;
+                const double fh = p2(eyh - R), fl = p2(eyl - R), fbv = p2(R - es);
+                const double fv = am * rdv * p2(evp - Ev + ae - es);
 #pragma unroll
-                for (int r = 1; r <= KL; ++r) b0 = cfnmac(Lr[c][r - 1], b[r], b0);
-                if (!(cabs1(b0) < kBig)) {
-                    int sh = rescale_shift(cabs1(b0), 1.0);
-                    b0 = cldexp(b0, -sh);
+                for (int c = 0; c < CH; ++c) {
+                    // row j = jtop - c lies in chunk pq iff c + kl < 8
+                    cd b0 = cscale(yr[c], c + KL < CH ? fh : fl);
 #pragma unroll
-                    for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
-                    R += sh;
-                }
-                b[0] = b0;
-                if (KL > 0) {
-                    const int p = pv[c];
+                    for (int r = 1; r <= KL; ++r) b0 = cfnmac(Lr[c][r - 1], b[r], b0);
+                    flag = flag || unsafe(b0);
+                    b[0] = b0;
 #pragma unroll
-                    for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
-                    emit(j + KL, b[KL], vr[c], evr[c]);   // rows past n carry zeros
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    const cd val = b[KL];
+                    ob[c] = C(fma(-fv, vr[c].x, fbv * val.x), fma(-fv, vr[c].y, fbv * val.y));
 #pragma unroll
                     for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
-                } else {
-                    emit(j, b[0], vr[c], evr[c]);
                 }
             }
-        }
-        if (act && KL > 0) {
+            if (flag) {   // careful path
 #pragma unroll
-            for (int r = KL; r >= 1; --r) emit(r - 1, b[r], w.vv[(r - 1) * T + s], (int)w.ev[(r - 1) * T + s]);
+                for (int r = 0; r <= KL; ++r) b[r] = bs[r];
+                R = Rs;
+                int Ec[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    cd b0 = cldexp(yr[c], (c + KL < CH ? eyh : eyl) - R);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b0 = cfnmac(Lr[c][r - 1], b[r], b0);
+                    if (unsafe(b0)) {
+                        const int sh = rescale_shift(cabs1(b0), 1.0);
+                        b0 = cldexp(b0, -sh);
+#pragma unroll
+                        for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                        R += sh;
+                    }
+                    b[0] = b0;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    const int es = R > ae ? R : ae;
+                    const cd val = cldexp(b[KL], R - es);
+                    const cd vo = cscale(cldexp(vr[c], evp - Ev + ae - es), am * rdv);
+                    ob[c] = csub(val, vo);
+                    Ec[c] = es;
+#pragma unroll
+                    for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
+                }
+                eo = Ec[CH - 1];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Ec[c] - eo);
+            }
+            double cs = 0.0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                w.vv[(pq * CH + CH - 1 - c) * T + s] = ob[c];
+                cs = fma(ob[c].x, ob[c].x, fma(ob[c].y, ob[c].y, cs));
+            }
+            w.ev[pq * T + s] = (int16_t)eo;
+            acc = ldexp(acc, 2 * (Eacc - eo)) + cs;
+            Eacc = eo;
         }
         acc_out = acc;
         eacc_out = Eacc;
@@ -665,12 +857,12 @@ struct Kern {
             for (int j = 0; j < k; ++j) {
                 double rd = w.bmeta[((int64_t)j * 2 + 0) * T + s];
                 int Ej = (int)w.bmeta[((int64_t)j * 2 + 1) * T + s];
-                cd uj = cldexp(cscale(w.basis[j * stride + i * T + s], rd), (int)w.ebasis[j * stride + i * T + s] - Ej);
+                cd uj = cldexp(cscale(w.basis[j * stride + i * T + s], rd),
+                               (int)w.ebasis[j * stride + (i / CH) * T + s] - Ej);
                 double c = coef[(int64_t)j * T + s];
                 acc = C(fma(c, uj.x, acc.x), fma(c, uj.y, acc.y));
             }
             w.vu[i * T + s] = acc;
-            w.eu[i * T + s] = 0;
             vn += cabs2(acc);
             double m = cabs2(acc);
             if (m > amax) { amax = m; vph = acc; }
@@ -678,7 +870,10 @@ struct Kern {
         for (int64_t i = n; i < w.nrow; ++i) {
             if (!pend) continue;
             w.vu[i * T + s] = czero();
-            w.eu[i * T + s] = 0;
+        }
+        for (int64_t q = 0; q < w.nrow / CH; ++q) {
+            if (!pend) continue;
+            w.eu[q * T + s] = 0;
         }
         // u direction: M^{-H} v through the factors (alpha = 0: no three-term correction)
         const bool saved = ln.active;
@@ -703,7 +898,7 @@ struct Kern {
         double2 *uout = a.u + ln.pid * n;
         for (int64_t i = 0; i < n; ++i) {
             vout[i] = cscale(cmul(w.vu[i * T + s], ph), rv);
-            cd uu = cldexp(cscale(w.vv[i * T + s], ru), (int)w.ev[i * T + s] - eaccu);
+            cd uu = cldexp(cscale(w.vv[i * T + s], ru), (int)w.ev[(i / CH) * T + s] - eaccu);
             uout[i] = cmul(uu, ph);
         }
         ln.pending = false;
@@ -857,7 +1052,7 @@ struct Kern {
             bool conv = converged(a, ln, te.theta, r);
             ln.theta = te.theta;
             ln.nchecks += 1;
-            int step = ln.k >> 5;
+            int step = ln.k >> a.check_shift;
             ln.next_check = ln.k + (step > 1 ? step : 1);
             checked = true;
             if (conv) {
@@ -1099,7 +1294,8 @@ __global__ void __launch_bounds__(256) k_grad_z(int64_t n, int64_t npts, const d
         re += __shfl_xor(re, off);
         im += __shfl_xor(im, off);
     }
-    if (lane == 0) grad_z[p] = make_double2(g[p] * re, -g[p] * im);
+    const double gp = g ? g[p] : 1.0;     // NULL weights: the plain gradient of sigma_min
+    if (lane == 0) grad_z[p] = make_double2(gp * re, -gp * im);
 }
 
 constexpr int kBwdRows = 64;   // shifts summed per partial row (fixed order)
@@ -1356,6 +1552,41 @@ hipError_t launch_batch_prefix(const MatDesc *mats_cls, const int64_t *counts, i
 }
 
 int64_t backward_partial_rows(int64_t npts) { return (npts + kBwdRows - 1) / kBwdRows; }
+
+// Zero fill (used where a memset node must not appear in captured graphs).
+__global__ void k_zero(uint64_t *p, int64_t words) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < words) p[t] = 0ull;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    int64_t words = (int64_t)(bytes / 8);
+    if (words > 0)
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, (uint64_t *)p, words);
+    return hipGetLastError();
+}
+
+// Newton step toward the level curve sigma = eps: z <- z - sigma ln(sigma/eps) g / |g|^2,
+// with g = grad_z (conjugate-Wirtinger gradient of sigma_min).  Points with sigma = 0 or a
+// vanishing gradient stay where they are.
+__global__ void k_newton_update(int64_t npts, double2 *z, const double *sigma, const double2 *g, double eps) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const double s = sigma[p];
+    const double2 gp = g[p];
+    const double g2 = fma(gp.x, gp.x, gp.y * gp.y);
+    if (!(s > 0.0) || !(g2 > 0.0)) return;
+    const double f = s * log(s / eps) / g2;
+    z[p] = make_double2(z[p].x - f * gp.x, z[p].y - f * gp.y);
+}
+
+hipError_t launch_newton_update(int64_t npts, double2 *z, const double *sigma, const double2 *grad_z, double eps,
+                                hipStream_t st) {
+    if (npts > 0)
+        hipLaunchKernelGGL(k_newton_update, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, npts, z, sigma,
+                           grad_z, eps);
+    return hipGetLastError();
+}
 
 hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double *g, const double2 *u,
                            const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,
