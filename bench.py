@@ -10,6 +10,10 @@ ps_eval_grid.  value = shifts evaluated per second over the timed steps (65536 +
 shifts per step), inputs resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --counter-pass            (under rocprofv3 --pmc: copy calibration + one
+                                               full-grid launch, nothing timed)
+    python bench.py --summarize-counters FETCH.csv WRITE.csv
+                                              (writes profiles/toeplitz2000_traffic.json)
 
 Prints ONE JSON line.  The roofline object prices the dominant kernel (the persistent
 LU + inverse-Lanczos kernel, full-grid launch) by its algorithmic bytes: per shift
@@ -36,6 +40,71 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 EPS_ZONE = 1e-2
+CALIB_BYTES = 1 << 30          # the calibration copy: 1 GiB read, 1 GiB written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
+KERNEL_TAG = "k_eval<1, 1, false, false>"
+
+
+def source_hash():
+    """Hash of everything that decides the measured kernel's traffic on this workload (the
+    HIP sources and the input generator); a stored traffic figure is used only while it
+    matches."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_04550_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "workloads", "gen.py"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """HBM bytes per full-grid launch from two rocprofv3 --pmc runs of --counter-pass.  Each
+    counter is scaled by what it reads for the calibration copy of known size (the first
+    copy kernel of the run, CALIB_BYTES each way)."""
+    import csv
+
+    def rows(path, counter):
+        out = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        return sorted(out)
+
+    res = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rs = rows(path, counter)
+        calib = [v for _, k, v in rs if "copyBuffer" in k and v > 1000.0][0]
+        kern = [v for _, k, v in rs if KERNEL_TAG in k][0]
+        factor = (CALIB_BYTES / 1024.0) / calib
+        res[counter] = dict(kib=kern, calib_kib=calib, factor=factor, bytes=kern * 1024.0 * factor)
+    traffic = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
+    doc = dict(kernel="ps::" + KERNEL_TAG + " (full-grid launch of toeplitz2000)",
+               source_hash=source_hash(), traffic_bytes_per_launch=traffic,
+               fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
+               commands=["timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch "
+                         "-o fetch -- python3 bench.py --counter-pass",
+                         "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write "
+                         "-o write -- python3 bench.py --counter-pass",
+                         "python bench.py --summarize-counters <out>/pmc_fetch/fetch_counter_collection.csv "
+                         "<out>/pmc_write/write_counter_collection.csv"])
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(doc, f, indent=1)
+        f.write("\n")
+    print(json.dumps(doc, indent=1))
+
+
+def stored_traffic():
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        doc = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if doc.get("source_hash") != source_hash():
+        return None        # kernel or workload changed since the counters were taken
+    return doc.get("traffic_bytes_per_launch")
 
 
 def algorithmic_bytes(n, kl, ku, iters):
@@ -73,7 +142,13 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=1)
     ap.add_argument("--progress", action="store_true", help="synchronise and report after every timed step")
     ap.add_argument("--plain-points", type=int, default=32)
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="calibration copy + one full-grid launch, for rocprofv3 --pmc")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(shifts are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
@@ -93,6 +168,20 @@ def main():
     mask = torch.tensor(w["mask"], dtype=torch.uint8, device=dev)
     npts_full = grid.npts
     npts_mask = int(w["mask"].sum())
+
+    if args.counter_pass:
+        x = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print("bench: calibration copy done (%d bytes each way)" % CALIB_BYTES, file=sys.stderr, flush=True)
+        del x, y
+        r = api.eval_grid(mat, grid, eps=EPS_ZONE, device=dev)
+        torch.cuda.synchronize()
+        print("bench: full-grid launch done, iterations mean %.2f" % r["iters"].double().mean().item(),
+              file=sys.stderr, flush=True)
+        return
 
     # workspaces allocated once, outside the timed region
     from paper_2605_04550_amd import ps_workspace_size
@@ -159,13 +248,7 @@ def main():
     torch.cuda.synchronize()
     plain_value = args.plain_points / (time.perf_counter() - tp0)
 
-    traffic = None
-    prof = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
-    if os.path.exists(prof):
-        try:
-            traffic = json.load(open(prof)).get("traffic_bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = stored_traffic()
 
     out = {
         "metric": "shifts/sec sigma_min(zI-A) FP64 (|dsigma|<=1e-10||A||_F+1e-8 sigma)",

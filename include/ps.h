@@ -90,7 +90,7 @@ typedef struct {
     int32_t want_vectors; /* 1: also return u, v (sizes [npts][n])          */
     int32_t slots;        /* 0: default                                       */
     int32_t check_shift;  /* Ritz-value checks every max(1, k >> check_shift)
-                             Lanczos steps (0: default 4); set by ps_autotune  */
+                             Lanczos steps (0: default 5); set by ps_autotune  */
 } ps_opts;
 
 /* Fills *o with the defaults listed above. */

@@ -68,7 +68,7 @@ ps_status check_opts(const ps_opts &o) {
     return PS_OK;
 }
 
-int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 4; }
+int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
 
 int kvec_of(const ps_opts &o) { return o.want_vectors ? (o.max_iter < kVecBasisMax ? o.max_iter : kVecBasisMax) : 0; }
 

@@ -1189,8 +1189,13 @@ struct Kern {
     }
 };
 
+// One wavefront per workgroup: a launch of S slots is S / 64 workgroups, which the dispatcher
+// spreads over all compute units (and their four SIMDs) even when S / 64 is below the SIMD
+// count, instead of packing four wavefronts onto each of S / 256 compute units.
+constexpr int kEvalBlock = 64;
+
 template <int KL, int KU, bool VEC, bool BATCH>
-__global__ void __launch_bounds__(256) k_eval(EvalArgs a, Workspace w) {
+__global__ void __launch_bounds__(kEvalBlock) k_eval(EvalArgs a, Workspace w) {
     Kern<KL, KU, VEC, BATCH>::run(a, w);
 }
 
@@ -1451,16 +1456,16 @@ static EvalKernel pick(int kl, int ku, int mode) {
 hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st) {
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
-    int64_t blocks = ws.slots / 256;
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, st, a, ws);
+    int64_t blocks = ws.slots / kEvalBlock;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
 }
 
 hipError_t launch_eval_batch(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st) {
     EvalKernel k = pick(kl, ku, 2);
     if (!k) return hipErrorInvalidValue;
-    int64_t blocks = ws.slots / 256;
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, st, a, ws);
+    int64_t blocks = ws.slots / kEvalBlock;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
 }
 
