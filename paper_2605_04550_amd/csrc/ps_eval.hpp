@@ -1,0 +1,1240 @@
+// HIP device code for gfx950 (MI355X): sigma_min(zI - A) of a banded matrix at many shifts.
+//
+// One lane owns one shift at a time.  Per shift:
+//   1. complex banded LU with partial pivoting of M = zI - A (gbtf2-style elimination
+//      streamed row by row through a register window of (kl+1) x (kl+ku+1) entries),
+//   2. Golub-Kahan bidiagonalisation of B = M^{-1} (inverse Lanczos):
+//        p = B v_k - beta_{k-1} u_{k-1},  alpha_k = |p|,  u_k = p / alpha_k
+//        q = B^H u_k - alpha_k v_k,       beta_k  = |q|,  v_{k+1} = q / beta_k
+//      with B v = U^{-1} L^{-1} P^T v (forward sweep, backward sweep) and
+//      B^H u = P L^{-H} U^{-H} u (forward sweep, backward sweep),
+//   3. theta_k = largest eigenvalue of T_k = B_k^H B_k (B_k upper bidiagonal with
+//      alpha on the diagonal, beta above it), found by a Sturm-safeguarded Newton iteration
+//      on det(T_k - lambda I) from an upper bound; sigma_min(M) = 1/sqrt(theta) once theta
+//      has converged.
+// This reaches the quantity of the paper's Sec. 2.1 (sigma_min(z) = s_n of the SVD of
+// zI - A) to a stated tolerance, without the O(n^3) dense SVD per shift.
+//
+// Memory layout: every per-shift array lives in a caller-provided workspace, tiled
+// [wavefront][row][component][lane]: the 64 lanes of a wavefront sweep the same row at
+// the same time, so each load or store of a wavefront is one contiguous 1 KiB (complex)
+// segment, and consecutive rows of one wavefront are contiguous.  The band of A is read by
+// all lanes at the same address (wave-uniform).
+//
+// Overflow safety: sigma_min can be far below the double range (it decays like
+// 10^(-0.3 n) inside the pseudospectrum of a non-normal Toeplitz matrix), so every stored
+// vector is kept in block floating point: one binary exponent per chunk of 8 rows.  A
+// sweep carries a running exponent R; when a value would exceed 2^400 the chunk is redone
+// row by row with rescaling, and readers bring each chunk to their own frame with ldexp.
+//
+// The persistent launch pulls shifts from a device counter; a lane whose shift has
+// finished takes the next one at the start of the following cycle and factorises it
+// during the forward sweep that the other lanes spend on their L solves.
+//
+// This header holds the persistent kernel (k_eval) and the complex helpers it shares with
+// the small kernels.  ps_kernels.hip includes it for the helpers; each ps_eval_kl<K>.hip
+// instantiates k_eval for one lower bandwidth, so the 75 instantiations compile in parallel.
+#pragma once
+
+#include "ps_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace ps {
+
+typedef double2 cd;
+
+__device__ __forceinline__ cd C(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ cd czero() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return C(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)); }
+__device__ __forceinline__ cd cconj(cd a) { return C(a.x, -a.y); }
+// acc - a * b
+__device__ __forceinline__ cd cfnma(cd a, cd b, cd acc) {
+    return C(fma(a.y, b.y, fma(-a.x, b.x, acc.x)), fma(-a.y, b.x, fma(-a.x, b.y, acc.y)));
+}
+// acc - conj(a) * b
+__device__ __forceinline__ cd cfnmac(cd a, cd b, cd acc) {
+    return C(fma(-a.y, b.y, fma(-a.x, b.x, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y)));
+}
+__device__ __forceinline__ double cabs1(cd a) { return fabs(a.x) + fabs(a.y); }
+__device__ __forceinline__ double cabs2(cd a) { return fma(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ cd cldexp(cd a, int e) { return C(ldexp(a.x, e), ldexp(a.y, e)); }
+__device__ __forceinline__ cd cscale(cd a, double s) { return C(a.x * s, a.y * s); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return C(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd crecip(cd a) {
+    const double is = 1.0 / fmax(fabs(a.x), fabs(a.y));
+    const double ar = a.x * is, ai = a.y * is;     // scaled so that ar^2 + ai^2 cannot under/overflow
+    const double id = is / fma(ar, ar, ai * ai);
+    return C(ar * id, -ai * id);
+}
+// Conditional swap written per component, so that it lowers to v_cndmask (a select of the
+// whole struct would be lowered through private memory).
+__device__ __forceinline__ void cswap_if(bool c, cd &a, cd &b) {
+    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+    a.x = c ? bx : ax;
+    a.y = c ? by : ay;
+    b.x = c ? ax : bx;
+    b.y = c ? ay : by;
+}
+
+constexpr double kBig = 0x1p400;       // rescale when a sweep value reaches this
+constexpr int kAfterRescale = 112;     // a rescaled value lands near 2^-112
+
+// Shift needed to bring |t| (possibly Inf) well below kBig, given that t = r * s.
+__device__ __forceinline__ int rescale_shift(double r_abs, double s_abs) {
+    int e = ilogb(r_abs) + ilogb(s_abs) + 2;
+    int sh = e + kAfterRescale;
+    return sh < 64 ? 64 : sh;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): counter-based start vector for inverse Lanczos.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ cd start_entry(uint64_t seed, int64_t i) {
+    uint64_t h1 = splitmix64(seed ^ ((uint64_t)i * 0xD1B54A32D192ED03ull));
+    uint64_t h2 = splitmix64(h1);
+    return C((double)(h1 >> 11) * 0x1p-52 - 1.0, (double)(h2 >> 11) * 0x1p-52 - 1.0);
+}
+
+__device__ __forceinline__ cd grid_point(const EvalArgs &a, int64_t flat) {
+    int64_t i = flat / a.nx, j = flat - i * a.nx;
+    double x = a.nx > 1 ? __dadd_rn(a.ga, __ddiv_rn(__dmul_rn(a.gb - a.ga, (double)j), (double)(a.nx - 1))) : a.ga;
+    double y = a.ny > 1 ? __dadd_rn(a.gc, __ddiv_rn(__dmul_rn(a.gd - a.gc, (double)i), (double)(a.ny - 1))) : a.gc;
+    return C(x, y);
+}
+
+// Largest eigenvalue of the k x k symmetric tridiagonal T_k (diagonal hist[j][0], squared
+// off-diagonal hist[j][1] between rows j and j+1) inside the bracket [lo, hi].
+// One pass at lambda forms the LDL^T pivots d_j of T - lambda I: the number of positive
+// pivots counts the eigenvalues above lambda (Sylvester inertia), and sum_j d_j'/d_j is
+// d/dlambda log|det(T - lambda I)|, the Newton step for the largest root from above
+// (monotone there).  Newton steps are taken while they at least halve; otherwise (a
+// cluster of Ritz values) the bracket is bisected.  Returns the upper end of a bracket of
+// relative width 2^-46.
+// The same pass accumulates S = sum_j prod_{i>=j} l_i^2 (l_i = multipliers), so that
+// x = (T - lambda I)^{-1} e_k has x_k^2 / |x|^2 = 1 / S: one step of inverse iteration
+// from e_k, whose last component estimates y_k^2 for the top eigenvector y (it can only
+// overestimate y_k^2 once y_k is below the shift's distance to theta).
+struct TopEig {
+    double theta;
+    double yk2;
+};
+
+static __device__ TopEig top_eig(const double *hist, int64_t T, int64_t s, int k, double lo, double hi) {
+    TopEig r;
+    r.theta = hi;
+    r.yk2 = 1.0;
+    // Ritz values move little between checks: probe just above the previous value first
+    // (lo > 0), widening the probe until it lies above every eigenvalue, then Newton.
+    int probe = lo > 0.0 ? 0 : 3;          // probe p sits at lo (1 + 2^(10 p - 24))
+    double lam = probe < 3 ? fmin(hi, lo * (1.0 + 0x1p-24)) : hi;
+    double prev_step = INFINITY;
+    double ssum_hi = 0.0;
+    bool have_hi = false;
+    for (int it = 0; it < 100; ++it) {
+        double d = hist[s] - lam;
+        double dd = -1.0;
+        int cnt = d > 0.0;
+        double rinv = 1.0 / d;
+        double ssum = dd * rinv;
+        double S = 1.0;
+        for (int j = 1; j < k; ++j) {
+            double b2 = hist[((int64_t)(j - 1) * 2 + 1) * T + s];
+            double t = b2 * rinv;
+            S = fma(S, t * rinv, 1.0);
+            d = hist[((int64_t)j * 2 + 0) * T + s] - lam - t;
+            dd = fma(t * dd, rinv, -1.0);
+            cnt += d > 0.0;
+            rinv = 1.0 / d;
+            ssum = fma(dd, rinv, ssum);
+        }
+        if (cnt == 0) {
+            hi = lam;
+            r.theta = lam;
+            r.yk2 = 1.0 / S;
+            ssum_hi = ssum;
+            have_hi = true;
+        } else {
+            lo = lam;
+        }
+        if (hi - lo <= 0x1p-46 * hi) break;
+        if (!have_hi && probe < 2) {        // probe was below the top eigenvalue: widen it
+            ++probe;
+            lam = fmin(hi, lo * (1.0 + ldexp(1.0, 10 * probe - 24)));
+            continue;
+        }
+        if (!have_hi && probe == 2) {       // fall back to the Gershgorin bound
+            probe = 3;
+            lam = hi;
+            continue;
+        }
+        double next = 0.5 * (lo + hi);
+        if (have_hi && ssum_hi > 0.0) {
+            double step = 1.0 / ssum_hi;
+            double cand = hi - step;
+            if (cand > lo) {
+                if (step <= 0x1p-47 * hi) next = hi * (1.0 - 0x1p-46);   // probe just below: closes the bracket
+                else if (step <= 0.5 * prev_step) { next = cand; prev_step = step; }
+            }
+        }
+        if (!(next > lo && next < hi)) break;
+        lam = next;
+    }
+    return r;
+}
+
+struct Lane {
+    int64_t pid;
+    cd z;
+    int k;            // number of alphas so far
+    int next_check;   // Lanczos step at which theta is next evaluated
+    int nchecks;
+    int E0;           // reference exponent of the bidiagonal entries
+    double theta;     // top Ritz value at the last check (units 2^(2 E0))
+    double delta_prev, rho_prev;
+    double ap_prev;   // alpha'_k in units of 2^E0
+    double bp;        // beta'_k in units of 2^E0
+    double gmax;      // Gershgorin bound over the closed rows of T_k
+    double gopen;     // diagonal + left off-diagonal of the last row of T_k
+    double a_m;       // alpha_k = a_m * 2^a_e, a_m in [1, 2)
+    int a_e;
+    double b_m;
+    int b_e;
+    int Eu, Ev, Ey;   // max row exponent of u, v, y
+    double rdu, rdv;  // 1 / (norm mantissa) of u, v
+    double nrm_h;     // squared norm of the start vector (fresh lanes)
+    bool active, fresh, sing, exhausted, pending;
+    // batch mode: the matrix of the current shift
+    int64_t n;
+    const double2 *arow;
+    double normA;
+};
+
+template <int KL, int KU, bool VEC, bool BATCH>
+struct Kern {
+    static constexpr int W = KL + KU + 1;
+
+    // Order, band and Frobenius norm of the current shift's matrix (one matrix per launch,
+    // or per shift in batch mode).
+    static __device__ __forceinline__ int64_t nn(const EvalArgs &a, const Lane &ln) { return BATCH ? ln.n : a.n; }
+    static __device__ __forceinline__ const double2 *band(const EvalArgs &a, const Lane &ln) {
+        return BATCH ? ln.arow : a.arow;
+    }
+    static __device__ __forceinline__ double fro(const EvalArgs &a, const Lane &ln) { return BATCH ? ln.normA : a.normA; }
+
+    // M[r][c] of M = zI - A from the row band (zero outside the matrix).
+    static __device__ __forceinline__ cd mentry(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
+        if (r >= nn(a, ln)) return czero();
+        int64_t d = c - r + KL;
+        if (d < 0 || d >= W) return czero();
+        const cd z = ln.z;
+        cd v = band(a, ln)[r * W + d];
+        cd m = C(-v.x, -v.y);
+        if (c == r) m = C(m.x + z.x, m.y + z.y);
+        return m;
+    }
+
+    // Every sweep walks the rows in chunks of CH = 8: the loads of a whole chunk are issued
+    // first (they do not depend on the recurrence), then the chunk's rows are computed.
+    //
+    // Block floating point: every stored vector carries one binary exponent per chunk of 8
+    // rows (value of row r = mantissa * 2^e[r / 8]).  A chunk is first computed on the fast
+    // path, where the sweep's running exponent R is fixed and every conversion is a
+    // multiplication by a per-chunk factor, while one flag records whether any value left
+    // the safe range (|x| >= 2^400, Inf or NaN).  Only if it did is the chunk recomputed on
+    // the careful path from the state saved at its start, rescaling row by row; its outputs
+    // are then brought to the chunk's final exponent before they are stored.
+    static constexpr int CH = 8;
+
+    static __device__ __forceinline__ double p2(int e) { return ldexp(1.0, e); }
+    static __device__ __forceinline__ bool unsafe(cd v) { return !(cabs1(v) < kBig); }
+
+    // ---------------------------------------------------------------- forward sweep 1
+    // Fresh lanes: LU of M fused with the L solve of the start vector h (also stored as v).
+    // Other lanes: y = L^{-1} P^T v_k with v_k read normalised.
+    static __device__ void f1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        cd b[KL + 1];
+        cd Wm[KL + 1][W];
+        int R = 0;
+        double nrm_h = 0.0;
+        const bool act = ln.active, fresh = ln.fresh;
+        const double tiny = 0x1p-1000 * fmax(1.0, fro(a, ln) + cabs1(ln.z));
+        bool sing = false;
+        // input v: normalised stored v (mantissa * rdv * 2^(e - Ev)); fresh lanes read h
+        const double rdv = fresh ? 1.0 : ln.rdv;
+        const int Ev = fresh ? 0 : ln.Ev;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        auto gen = [&](int64_t i) -> cd {        // fresh lanes: start vector entry i, stored as v
+            cd h = i < n ? start_entry(a.seed, i) : czero();   // padding rows stay zero
+            w.vv[i * T + s] = h;
+            nrm_h += cabs2(h);
+            return h;
+        };
+        if (act) {
+            if (fresh) {
+                w.ev[s] = 0;
+#pragma unroll
+                for (int r = 0; r < KL; ++r) b[r] = gen(r);
+#pragma unroll
+                for (int r = 0; r < KL; ++r)
+#pragma unroll
+                    for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, ln, r, c);
+            } else {
+                const double f0 = rdv * p2((int)w.ev[s] - Ev);
+#pragma unroll
+                for (int r = 0; r < KL; ++r) b[r] = cscale(w.vv[r * T + s], f0);
+            }
+        }
+        for (int64_t j0 = 0; j0 < npad; j0 += CH) {
+            if (!act) continue;
+            const int64_t q = j0 / CH;
+            cd pin[CH];
+            int pv[CH];
+            cd Lr[CH][KL > 0 ? KL : 1];
+            int ea = 0, eb = 0;
+            if (!fresh) {
+                ea = (int)w.ev[q * T + s];
+                eb = KL > 0 ? (int)w.ev[(q + 1) * T + s] : ea;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int64_t j = j0 + c;
+                    pin[c] = w.vv[(j + KL) * T + s];
+                    if (KL > 0) {
+                        pv[c] = (int)w.piv[j * T + s];
+#pragma unroll
+                        for (int r = 0; r < KL; ++r) Lr[c][r] = w.L[(j * KL + r) * T + s];
+                    } else {
+                        pv[c] = 0;
+                    }
+                }
+            } else {
+                // LU rows of this chunk (stored once; multipliers and pivots kept for the solve)
+                w.ev[(q + 1) * T + s] = 0;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int64_t j = j0 + c;
+                    pin[c] = gen(j + KL);
+#pragma unroll
+                    for (int cc = 0; cc < W; ++cc) Wm[KL][cc] = mentry(a, ln, j + KL, j + cc);
+                    double best = cabs1(Wm[0][0]);
+                    int p = 0;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) {
+                        double v = cabs1(Wm[r][0]);
+                        if (v > best) { best = v; p = r; }
+                    }
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r)
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc) cswap_if(p == r, Wm[0][cc], Wm[r][cc]);
+                    // rows past n are zero rows: their pivot is 0 and they stay inert
+                    const bool ok = best >= tiny;
+                    sing = sing || (!ok && j < n);
+                    const cd rc = crecip(Wm[0][0]);
+                    const cd inv = C(ok ? rc.x : 0.0, ok ? rc.y : 0.0);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) Lr[c][r - 1] = cmul(Wm[r][0], inv);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r)
+#pragma unroll
+                        for (int cc = 1; cc < W; ++cc) Wm[r][cc] = cfnma(Lr[c][r - 1], Wm[0][cc], Wm[r][cc]);
+                    w.U[(j * W + 0) * T + s] = inv;
+#pragma unroll
+                    for (int cc = 1; cc < W; ++cc) w.U[(j * W + cc) * T + s] = Wm[0][cc];
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) w.L[(j * KL + r) * T + s] = Lr[c][r];
+                    w.piv[j * T + s] = (uint8_t)p;
+                    pv[c] = p;
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) {
+#pragma unroll
+                        for (int cc = 0; cc < W - 1; ++cc) Wm[r][cc] = Wm[r + 1][cc + 1];
+                        Wm[r][W - 1] = czero();
+                    }
+                }
+            }
+            // L solve of the chunk
+            cd bs[KL + 1];
+#pragma unroll
+            for (int r = 0; r <= KL; ++r) bs[r] = b[r];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            {
+                const double fa = rdv * p2(ea - Ev - R), fb = rdv * p2(eb - Ev - R);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    b[KL] = cscale(pin[c], c + KL < CH ? fa : fb);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    const cd y = b[0];
+                    flag = flag || unsafe(y);
+                    ob[c] = y;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b[r] = cfnma(Lr[c][r - 1], y, b[r]);
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
+                }
+            }
+            if (flag) {   // careful path: rescale row by row
+#pragma unroll
+                for (int r = 0; r <= KL; ++r) b[r] = bs[r];
+                R = Rs;
+                int Rc[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    b[KL] = cscale(pin[c], rdv * p2((c + KL < CH ? ea : eb) - Ev - R));
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    cd y = b[0];
+                    if (unsafe(y)) {
+                        const int sh = rescale_shift(cabs1(y), 1.0);
+#pragma unroll
+                        for (int r = 0; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                        y = b[0];
+                        R += sh;
+                    }
+                    ob[c] = y;
+                    Rc[c] = R;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b[r] = cfnma(Lr[c][r - 1], y, b[r]);
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) b[r] = b[r + 1];
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Rc[c] - R);
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) w.vy[(j0 + c) * T + s] = ob[c];
+            w.ey[q * T + s] = (int16_t)R;
+        }
+        if (act) {
+            ln.Ey = R;
+            if (fresh) {
+                ln.nrm_h = nrm_h;
+                ln.sing = sing;
+                ln.Ev = 0;
+                ln.rdv = 1.0 / sqrt(nrm_h);
+            }
+        }
+    }
+
+    // ---------------------------------------------------------------- backward sweep 1
+    // x = U^{-1} y (= B v_k), out = x - beta u_{k-1}; out stored unnormalised; returns
+    // |out|^2 = acc * 2^(2 Eacc).
+    static __device__ void b1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
+                              int &eacc_out) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const bool act = ln.active && !ln.sing;
+        const bool sub = !ln.fresh;
+        int R = ln.Ey;
+        cd xw[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) xw[d] = czero();
+        double acc = 0.0;
+        int Eacc = R;
+        // VEC: write u_k into basis slot k (k = ln.k), read u_{k-1} from slot k-1.
+        double2 *uout = w.vu;
+        int16_t *euout = w.eu;
+        const double2 *uold = w.vu;
+        const int16_t *euold = w.eu;
+        const double rd_old = ln.rdu;
+        const int E_old = ln.Eu;
+        if (VEC) {
+            int64_t stride = w.nrow * T;
+            uout = w.basis + (int64_t)ln.k * stride;
+            euout = w.ebasis + (int64_t)ln.k * stride;
+            if (ln.k > 0) {
+                uold = w.basis + (int64_t)(ln.k - 1) * stride;
+                euold = w.ebasis + (int64_t)(ln.k - 1) * stride;
+            }
+        }
+        const double bm = ln.b_m;
+        const int be = ln.b_e;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        for (int64_t q = npad / CH - 1; q >= 0; --q) {
+            if (!act) continue;
+            const int64_t i0 = q * CH + CH - 1;
+            cd Ur[CH][W];
+            cd yr[CH], ur[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 - c;
+#pragma unroll
+                for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
+                yr[c] = w.vy[i * T + s];
+                ur[c] = uold[i * T + s];          // read even when unused (no branch); selected away below
+            }
+            const int ey = (int)w.ey[q * T + s];
+            const int eu = (int)euold[q * T + s];
+            cd xs[W];
+#pragma unroll
+            for (int d = 0; d < W; ++d) xs[d] = xw[d];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            int eo;
+            {
+                const int es = R > be ? R : be;
+                eo = sub ? es : R;
+                const double fy = p2(ey - R), ft = p2(R - es);
+                const double fu = bm * rd_old * p2(eu - E_old + be - es);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    cd rhs = cscale(yr[c], fy);
+#pragma unroll
+                    for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                    const cd t = cmul(rhs, Ur[c][0]);
+                    flag = flag || unsafe(t);
+                    const cd o = C(fma(-fu, ur[c].x, ft * t.x), fma(-fu, ur[c].y, ft * t.y));
+                    ob[c] = sub ? o : t;
+                    if constexpr (W > 1) {
+#pragma unroll
+                        for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
+                        xw[1] = t;
+                    }
+                }
+            }
+            if (flag) {   // careful path
+#pragma unroll
+                for (int d = 0; d < W; ++d) xw[d] = xs[d];
+                R = Rs;
+                int Ec[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    cd rhs = cldexp(yr[c], ey - R);
+#pragma unroll
+                    for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                    const cd inv = Ur[c][0];
+                    cd t = cmul(rhs, inv);
+                    if (unsafe(t)) {
+                        const int sh = rescale_shift(cabs1(rhs), cabs1(inv));
+                        rhs = cldexp(rhs, -sh);
+#pragma unroll
+                        for (int d = 1; d < W; ++d) xw[d] = cldexp(xw[d], -sh);
+                        R += sh;
+                        t = cmul(rhs, inv);
+                    }
+                    const int es = R > be ? R : be;
+                    const cd tt = cldexp(t, R - es);
+                    const cd bu = cscale(cldexp(ur[c], eu - E_old + be - es), bm * rd_old);
+                    ob[c] = sub ? csub(tt, bu) : t;
+                    Ec[c] = sub ? es : R;
+                    if constexpr (W > 1) {
+#pragma unroll
+                        for (int d = W - 1; d >= 2; --d) xw[d] = xw[d - 1];
+                        xw[1] = t;
+                    }
+                }
+                eo = Ec[CH - 1];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Ec[c] - eo);
+            }
+            double cs = 0.0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                uout[(i0 - c) * T + s] = ob[c];
+                cs = fma(ob[c].x, ob[c].x, fma(ob[c].y, ob[c].y, cs));
+            }
+            euout[q * T + s] = (int16_t)eo;
+            acc = ldexp(acc, 2 * (Eacc - eo)) + cs;     // exponents of a sweep's outputs never decrease
+            Eacc = eo;
+        }
+        acc_out = acc;
+        eacc_out = Eacc;
+    }
+
+    // ---------------------------------------------------------------- forward sweep 2
+    // y = U^{-H} u_k (u_k read normalised), column-oriented forward substitution.
+    static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, bool from_vu = false) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const bool act = ln.active;
+        const double2 *uin = w.vu;
+        const int16_t *euin = w.eu;
+        if (VEC && !from_vu) {
+            int64_t stride = w.nrow * T;
+            uin = w.basis + (int64_t)(ln.k - 1) * stride;
+            euin = w.ebasis + (int64_t)(ln.k - 1) * stride;
+        }
+        const double rdu = ln.rdu;
+        const int Eu = ln.Eu;
+        int R = 0;
+        cd acc[W];
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        if (act) {
+            const double f0 = rdu * p2((int)euin[s] - Eu);
+#pragma unroll
+            for (int d = 0; d < W - 1; ++d) acc[d] = cscale(uin[d * T + s], f0);
+        }
+        for (int64_t i0 = 0; i0 < npad; i0 += CH) {
+            if (!act) continue;
+            const int64_t q = i0 / CH;
+            cd Ur[CH][W];
+            cd pin[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 + c;
+#pragma unroll
+                for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
+                pin[c] = uin[(i + W - 1) * T + s];
+            }
+            const int ea = (int)euin[q * T + s];
+            const bool last = i0 + CH >= npad;                 // rows at or past npad were never written
+            const int eb = (W > 1 && !last) ? (int)euin[(q + 1) * T + s] : ea;
+            cd as[W];
+#pragma unroll
+            for (int d = 0; d < W; ++d) as[d] = acc[d];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            {
+                const double fa = rdu * p2(ea - Eu - R), fb = last ? 0.0 : rdu * p2(eb - Eu - R);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const cd x = cscale(pin[c], c + W - 1 < CH ? fa : fb);
+                    acc[W - 1] = (c + W - 1 < CH || !last) ? x : czero();
+                    const cd wv = cmul(acc[0], cconj(Ur[c][0]));
+                    flag = flag || unsafe(wv);
+                    ob[c] = wv;
+#pragma unroll
+                    for (int d = 1; d < W; ++d) acc[d] = cfnmac(Ur[c][d], wv, acc[d]);
+#pragma unroll
+                    for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+                }
+            }
+            if (flag) {   // careful path
+#pragma unroll
+                for (int d = 0; d < W; ++d) acc[d] = as[d];
+                R = Rs;
+                int Rc[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const bool in = c + W - 1 < CH || !last;
+                    const cd x = cscale(pin[c], rdu * p2((c + W - 1 < CH ? ea : eb) - Eu - R));
+                    acc[W - 1] = in ? x : czero();
+                    const cd inv = Ur[c][0];
+                    cd wv = cmul(acc[0], cconj(inv));
+                    if (unsafe(wv)) {
+                        const int sh = rescale_shift(cabs1(acc[0]), cabs1(inv));
+#pragma unroll
+                        for (int d = 0; d < W; ++d) acc[d] = cldexp(acc[d], -sh);
+                        R += sh;
+                        wv = cmul(acc[0], cconj(inv));
+                    }
+                    ob[c] = wv;
+                    Rc[c] = R;
+#pragma unroll
+                    for (int d = 1; d < W; ++d) acc[d] = cfnmac(Ur[c][d], wv, acc[d]);
+#pragma unroll
+                    for (int d = 0; d < W - 1; ++d) acc[d] = acc[d + 1];
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Rc[c] - R);
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) w.vy[(i0 + c) * T + s] = ob[c];
+            w.ey[q * T + s] = (int16_t)R;
+        }
+        if (act) ln.Ey = R;
+    }
+
+    // ---------------------------------------------------------------- backward sweep 2
+    // q = P L^{-H} y - alpha_k v_k; v updated in place; returns |q|^2 = acc * 2^(2 Eacc).
+    // Step j finalises entry j + kl, so the steps of output chunk p are j = 8p+7-kl .. 8p-kl;
+    // the kl steps above the top chunk run first (their outputs lie past the padding), and
+    // steps j < 0 carry zero data (they only flush the window).
+    static __device__ void b2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
+                              int &eacc_out) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const bool act = ln.active;
+        int R = ln.Ey;
+        cd b[KL + 1];
+#pragma unroll
+        for (int r = 0; r <= KL; ++r) b[r] = czero();
+        double acc = 0.0;
+        int Eacc = R;
+        const double am = ln.a_m;
+        const int ae = ln.a_e;
+        const double rdv = ln.rdv;
+        const int Ev = ln.Ev;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        // one step of the L^H P sweep at row j (careful form, used for the top kl steps)
+        auto step_careful = [&](int64_t j, int ey) {
+            cd b0 = cldexp(w.vy[j * T + s], ey - R);
+#pragma unroll
+            for (int r = 1; r <= KL; ++r) b0 = cfnmac(w.L[(j * KL + (r - 1)) * T + s], b[r], b0);
+            if (unsafe(b0)) {
+                const int sh = rescale_shift(cabs1(b0), 1.0);
+                b0 = cldexp(b0, -sh);
+#pragma unroll
+                for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                R += sh;
+            }
+            b[0] = b0;
+            const int p = w.piv[j * T + s];
+#pragma unroll
+            for (int r = 1; r <= KL; ++r) cswap_if(p == r, b[0], b[r]);
+#pragma unroll
+            for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
+        };
+        if (act && KL > 0) {
+            const int eyt = (int)w.ey[(npad / CH - 1) * T + s];
+            for (int64_t j = npad - 1; j >= npad - KL; --j) step_careful(j, eyt);
+        }
+        for (int64_t pq = npad / CH - 1; pq >= 0; --pq) {
+            if (!act) continue;
+            const int64_t jtop = pq * CH + CH - 1 - KL;
+            cd yr[CH], vr[CH];
+            int pv[CH];
+            cd Lr[CH][KL > 0 ? KL : 1];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t j = jtop - c;
+                const int64_t jc = j >= 0 ? j : 0;              // steps j < 0 carry zero data
+                const bool in = j >= 0;
+                const cd y = w.vy[jc * T + s];
+                yr[c] = C(in ? y.x : 0.0, in ? y.y : 0.0);
+                if (KL > 0) {
+                    pv[c] = in ? (int)w.piv[jc * T + s] : 0;
+#pragma unroll
+                    for (int r = 0; r < KL; ++r) {
+                        const cd l = w.L[(jc * KL + r) * T + s];
+                        Lr[c][r] = C(in ? l.x : 0.0, in ? l.y : 0.0);
+                    }
+                } else {
+                    pv[c] = 0;
+                }
+                vr[c] = w.vv[(j + KL) * T + s];
+            }
+            const int eyh = (int)w.ey[pq * T + s];                  // rows >= 8 pq
+            const int eyl = pq > 0 ? (int)w.ey[(pq - 1) * T + s] : eyh;   // rows < 8 pq
+            const int evp = (int)w.ev[pq * T + s];
+            cd bs[KL + 1];
+#pragma unroll
+            for (int r = 0; r <= KL; ++r) bs[r] = b[r];
+            const int Rs = R;
+            cd ob[CH];
+            bool flag = false;
+            int eo;
+            {
+                const int es = R > ae ? R : ae;
+                eo = es;
+                const double fh = p2(eyh - R), fl = p2(eyl - R), fbv = p2(R - es);
+                const double fv = am * rdv * p2(evp - Ev + ae - es);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    // row j = jtop - c lies in chunk pq iff c + kl < 8
+                    cd b0 = cscale(yr[c], c + KL < CH ? fh : fl);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b0 = cfnmac(Lr[c][r - 1], b[r], b0);
+                    flag = flag || unsafe(b0);
+                    b[0] = b0;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    const cd val = b[KL];
+                    ob[c] = C(fma(-fv, vr[c].x, fbv * val.x), fma(-fv, vr[c].y, fbv * val.y));
+#pragma unroll
+                    for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
+                }
+            }
+            if (flag) {   // careful path
+#pragma unroll
+                for (int r = 0; r <= KL; ++r) b[r] = bs[r];
+                R = Rs;
+                int Ec[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    cd b0 = cldexp(yr[c], (c + KL < CH ? eyh : eyl) - R);
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) b0 = cfnmac(Lr[c][r - 1], b[r], b0);
+                    if (unsafe(b0)) {
+                        const int sh = rescale_shift(cabs1(b0), 1.0);
+                        b0 = cldexp(b0, -sh);
+#pragma unroll
+                        for (int r = 1; r <= KL; ++r) b[r] = cldexp(b[r], -sh);
+                        R += sh;
+                    }
+                    b[0] = b0;
+#pragma unroll
+                    for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
+                    const int es = R > ae ? R : ae;
+                    const cd val = cldexp(b[KL], R - es);
+                    const cd vo = cscale(cldexp(vr[c], evp - Ev + ae - es), am * rdv);
+                    ob[c] = csub(val, vo);
+                    Ec[c] = es;
+#pragma unroll
+                    for (int r = KL; r >= 1; --r) b[r] = b[r - 1];
+                }
+                eo = Ec[CH - 1];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) ob[c] = cldexp(ob[c], Ec[c] - eo);
+            }
+            double cs = 0.0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                w.vv[(pq * CH + CH - 1 - c) * T + s] = ob[c];
+                cs = fma(ob[c].x, ob[c].x, fma(ob[c].y, ob[c].y, cs));
+            }
+            w.ev[pq * T + s] = (int16_t)eo;
+            acc = ldexp(acc, 2 * (Eacc - eo)) + cs;
+            Eacc = eo;
+        }
+        acc_out = acc;
+        eacc_out = Eacc;
+    }
+
+    // ---------------------------------------------------------------- singular vectors
+    // For every lane whose shift converged (ln.pending), all lanes of the wavefront together:
+    //   q = top eigenvector of T_k (two steps of inverse iteration at theta (1 + 2^-40)),
+    //   p = B_k q / |B_k q| (top left singular vector of the bidiagonal),
+    //   v = U_k p  (Ritz vector: right singular vector of M = zI - A), assembled in vu,
+    //   u = M^{-H} v / |M^{-H} v| through the lane's LU factors (one inverse-iteration
+    //       step: M^{-H} v_min = u_min / sigma_min, so the error in u shrinks by the gap
+    //       instead of growing by |M| / sigma as it would for u = M v / sigma),
+    // then both are written to the caller's [npts][n] arrays with the joint phase that makes
+    // the first entry of v of largest modulus real and positive.
+    static __device__ void ritz_coeffs(const Workspace &w, int64_t s, const Lane &ln) {
+        const int64_t T = w.slots;
+        const int k = ln.k;
+        // bmeta rows: [0, 2kvec) basis meta (1/norm, exponent); [2kvec, 3kvec) q;
+        // [3kvec, 4kvec) pivots, then p; [4kvec, 6kvec) alpha'_j, beta'_j.
+        double *q = w.bmeta + (int64_t)(2 * w.kvec) * T;
+        double *aux = q + (int64_t)w.kvec * T;
+        const double *ab = q + (int64_t)(2 * w.kvec) * T;
+        double mu = ln.theta * (1.0 + 0x1p-40);
+        for (int j = 0; j < k; ++j) q[(int64_t)j * T + s] = 1.0;
+        for (int it = 0; it < 2; ++it) {
+            double dprev = 0.0;
+            for (int j = 0; j < k; ++j) {
+                double dj = w.hist[((int64_t)j * 2 + 0) * T + s] - mu;
+                double rhs = q[(int64_t)j * T + s];
+                if (j > 0) {
+                    double e = sqrt(w.hist[((int64_t)(j - 1) * 2 + 1) * T + s]);
+                    double lj = e / dprev;
+                    dj -= lj * e;
+                    rhs -= lj * q[(int64_t)(j - 1) * T + s];
+                }
+                q[(int64_t)j * T + s] = rhs;
+                aux[(int64_t)j * T + s] = dj;
+                dprev = dj;
+            }
+            double xnext = 0.0, nrm = 0.0;
+            for (int j = k - 1; j >= 0; --j) {
+                double dj = aux[(int64_t)j * T + s];
+                double x = q[(int64_t)j * T + s] / dj;
+                if (j < k - 1) x -= (sqrt(w.hist[((int64_t)j * 2 + 1) * T + s]) / dj) * xnext;
+                q[(int64_t)j * T + s] = x;
+                xnext = x;
+                nrm += x * x;
+            }
+            double rn = 1.0 / sqrt(nrm);
+            for (int j = 0; j < k; ++j) q[(int64_t)j * T + s] *= rn;
+        }
+        double pn = 0.0;
+        for (int j = 0; j < k; ++j) {
+            double pj = ab[((int64_t)j * 2 + 0) * T + s] * q[(int64_t)j * T + s];
+            if (j + 1 < k) pj += ab[((int64_t)j * 2 + 1) * T + s] * q[(int64_t)(j + 1) * T + s];
+            aux[(int64_t)j * T + s] = pj;
+            pn += pj * pj;
+        }
+        double rpn = 1.0 / sqrt(pn);
+        for (int j = 0; j < k; ++j) aux[(int64_t)j * T + s] *= rpn;
+    }
+
+    static __device__ void vec_finalize(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const bool pend = ln.pending;
+        if (pend) ritz_coeffs(w, s, ln);
+        const double *coef = w.bmeta + (int64_t)(3 * w.kvec) * T;
+        const int64_t stride = w.nrow * T;
+        const int k = ln.k;
+        double vn = 0.0, amax = -1.0;
+        cd vph = C(1.0, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+            if (!pend) continue;
+            cd acc = czero();
+            for (int j = 0; j < k; ++j) {
+                double rd = w.bmeta[((int64_t)j * 2 + 0) * T + s];
+                int Ej = (int)w.bmeta[((int64_t)j * 2 + 1) * T + s];
+                cd uj = cldexp(cscale(w.basis[j * stride + i * T + s], rd),
+                               (int)w.ebasis[j * stride + (i / CH) * T + s] - Ej);
+                double c = coef[(int64_t)j * T + s];
+                acc = C(fma(c, uj.x, acc.x), fma(c, uj.y, acc.y));
+            }
+            w.vu[i * T + s] = acc;
+            vn += cabs2(acc);
+            double m = cabs2(acc);
+            if (m > amax) { amax = m; vph = acc; }
+        }
+        for (int64_t i = n; i < w.nrow; ++i) {
+            if (!pend) continue;
+            w.vu[i * T + s] = czero();
+        }
+        for (int64_t q = 0; q < w.nrow / CH; ++q) {
+            if (!pend) continue;
+            w.eu[q * T + s] = 0;
+        }
+        // u direction: M^{-H} v through the factors (alpha = 0: no three-term correction)
+        const bool saved = ln.active;
+        ln.active = pend;
+        if (pend) {
+            ln.Eu = 0;
+            ln.rdu = 1.0 / sqrt(vn);
+            ln.a_m = 0.0;
+            ln.a_e = 0;
+        }
+        f2(a, w, s, ln, true);
+        double accu;
+        int eaccu;
+        b2(a, w, s, ln, accu, eaccu);
+        ln.active = saved;
+        if (!pend) return;
+        double am = sqrt(amax);
+        cd ph = am > 0.0 ? C(vph.x / am, -vph.y / am) : C(1.0, 0.0);
+        double rv = 1.0 / sqrt(vn);
+        double ru = 1.0 / sqrt(accu);
+        double2 *vout = a.v + ln.pid * n;
+        double2 *uout = a.u + ln.pid * n;
+        for (int64_t i = 0; i < n; ++i) {
+            vout[i] = cscale(cmul(w.vu[i * T + s], ph), rv);
+            cd uu = cldexp(cscale(w.vv[i * T + s], ru), (int)w.ev[(i / CH) * T + s] - eaccu);
+            uout[i] = cmul(uu, ph);
+        }
+        ln.pending = false;
+    }
+
+    static __device__ void finish(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, int flags) {
+        double sigma;
+        if (ln.sing) {
+            sigma = 0.0;
+            flags |= 1;
+        } else {
+            sigma = ldexp(1.0 / sqrt(ln.theta), -ln.E0);
+            if (!(sigma >= 0x1p-1022)) flags |= 4;
+        }
+        a.sigma[ln.pid] = sigma;
+        if (a.info) a.info[ln.pid] = flags;
+        if (a.iters) a.iters[ln.pid] = ln.k;
+        if (a.sens) a.sens[ln.pid] = (uint8_t)(sigma <= a.eps);
+        if (VEC) {
+            if (ln.sing) {
+                // exactly singular (zero pivot): no Lanczos data; report zero vectors with the
+                // SINGULAR bit set.
+                for (int64_t i = 0; i < nn(a, ln); ++i) {
+                    a.u[ln.pid * nn(a, ln) + i] = czero();
+                    a.v[ln.pid * nn(a, ln) + i] = czero();
+                }
+            } else {
+                ln.pending = true;   // assembled by vec_finalize with the whole wavefront
+            }
+        }
+        ln.active = false;
+    }
+
+    // Convergence test at a check (theta_new = top Ritz value of T_k, r = residual norm
+    // alpha_k beta_k |y_k| of its Ritz pair for (M M^H)^{-1}, both in units of 2^(2 E0)).
+    // The target |sigma - sigma_min| <= tol_norm ||A|| + tol_rel sigma is a relative
+    // tolerance tol_th = 2 (tol_norm ||A|| / sigma + tol_rel) on theta = 1 / sigma^2.
+    //  * sigma_est <= tol_norm ||A|| / 2: done (the Ritz value only underestimates theta,
+    //    so 0 <= sigma_est - sigma_min <= sigma_est).
+    //  * r <= tol_th theta / 2: done (an eigenvalue lies within r of theta).
+    //  * theta unchanged to 2^-44 (relative) over two consecutive checks: the Ritz value has settled
+    //    at working precision (then y_k is below what the inverse-iteration estimate can
+    //    resolve, and r is overestimated).
+    static __device__ bool converged(const EvalArgs &a, Lane &ln, double theta_new, double r) {
+        double r_abs = ldexp(a.tol_norm * fro(a, ln) * sqrt(theta_new), ln.E0);
+        double tol_th = 2.0 * (r_abs + a.tol_rel);
+        double delta = fmax(theta_new - ln.theta, 0.0);
+        bool flat = ln.nchecks >= 1 && delta <= 0x1p-44 * theta_new;
+        bool flat_prev = ln.rho_prev > 0.0;
+        ln.delta_prev = delta;
+        ln.rho_prev = flat ? 1.0 : 0.0;
+        if (r_abs >= 2.0) return true;
+        if (r <= 0.5 * tol_th * theta_new) return true;
+        return flat && flat_prev;
+    }
+
+    static __device__ void check_theta(const Workspace &w, int64_t s, Lane &ln, TopEig &te) {
+        if (ln.k == 1) {
+            te.theta = w.hist[s];
+            te.yk2 = 1.0;
+        } else {
+            te = top_eig(w.hist, w.slots, s, ln.k, ln.theta, fmax(ln.gmax, ln.gopen));
+        }
+    }
+
+    static __device__ void after_b1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double acc,
+                                    int eacc) {
+        const int64_t T = w.slots;
+        double av = sqrt(ln.fresh ? acc / ln.nrm_h : acc);
+        ln.Eu = eacc;
+        ln.rdu = 1.0 / sqrt(acc);
+        if (VEC) {
+            w.bmeta[((int64_t)ln.k * 2 + 0) * T + s] = ln.rdu;
+            w.bmeta[((int64_t)ln.k * 2 + 1) * T + s] = (double)ln.Eu;
+        }
+        if (!(av > 0.0)) {
+            // B v_k = beta u_{k-1} exactly: the Krylov space is invariant and T_k is exact.
+            if (ln.fresh) {
+                ln.sing = true;
+            } else {
+                TopEig te;
+                check_theta(w, s, ln, te);
+                ln.theta = te.theta;
+            }
+            finish(a, w, s, ln, 0);
+            return;
+        }
+        int ea = ilogb(av);
+        ln.a_m = ldexp(av, -ea);
+        ln.a_e = eacc + ea;
+        double *abq = VEC ? w.bmeta + (int64_t)(4 * w.kvec) * T : nullptr;
+        if (ln.fresh) {
+            ln.E0 = ln.a_e;
+            double ap = ln.a_m;
+            w.hist[s] = ap * ap;
+            ln.theta = 0.0;
+            ln.ap_prev = ap;
+            ln.k = 1;
+            ln.fresh = false;
+            ln.next_check = 1;
+            ln.nchecks = 0;
+            ln.delta_prev = ln.rho_prev = 0.0;
+            ln.gmax = 0.0;
+            ln.gopen = ap * ap;
+            if (VEC) abq[s] = ap;
+            double r_abs = ldexp(a.tol_norm * fro(a, ln) * ap, ln.E0);
+            if (r_abs >= 2.0) {
+                ln.theta = ap * ap;
+                finish(a, w, s, ln, 0);
+            }
+        } else {
+            double ap = ldexp(ln.a_m, ln.a_e - ln.E0);
+            double b2 = ln.ap_prev * ln.ap_prev * ln.bp * ln.bp;
+            int k = ln.k;
+            w.hist[((int64_t)(k - 1) * 2 + 1) * T + s] = b2;
+            double dk = fma(ap, ap, ln.bp * ln.bp);
+            w.hist[((int64_t)k * 2 + 0) * T + s] = dk;
+            double off = sqrt(b2);
+            ln.gmax = fmax(ln.gmax, ln.gopen + off);
+            ln.gopen = dk + off;
+            if (VEC) {
+                abq[((int64_t)(k - 1) * 2 + 1) * T + s] = ln.bp;
+                abq[((int64_t)k * 2 + 0) * T + s] = ap;
+            }
+            ln.k = k + 1;
+            ln.ap_prev = ap;
+        }
+    }
+
+    static __device__ void after_b2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double acc,
+                                    int eacc, int kcap) {
+        double bv = sqrt(acc);
+        ln.Ev = eacc;
+        ln.rdv = 1.0 / sqrt(acc);
+        TopEig te;
+        if (!(bv > 0.0)) {
+            // B^H u_k = alpha_k v_k exactly: invariant Krylov space, T_k exact.
+            check_theta(w, s, ln, te);
+            ln.theta = te.theta;
+            finish(a, w, s, ln, 0);
+            return;
+        }
+        int eb = ilogb(bv);
+        ln.b_m = ldexp(bv, -eb);
+        ln.b_e = eacc + eb;
+        ln.bp = ldexp(ln.b_m, ln.b_e - ln.E0);
+        bool checked = false;
+        if (ln.k >= ln.next_check) {
+            check_theta(w, s, ln, te);
+            double r = ln.ap_prev * ln.bp * sqrt(te.yk2);
+            bool conv = converged(a, ln, te.theta, r);
+            ln.theta = te.theta;
+            ln.nchecks += 1;
+            int step = ln.k >> a.check_shift;
+            ln.next_check = ln.k + (step > 1 ? step : 1);
+            checked = true;
+            if (conv) {
+                finish(a, w, s, ln, 0);
+                return;
+            }
+        }
+        if (ln.k >= kcap) {
+            if (!checked) {
+                check_theta(w, s, ln, te);
+                ln.theta = te.theta;
+            }
+            finish(a, w, s, ln, 2);
+        }
+    }
+
+    // The workspace is laid out [wavefront][row][component][lane]: the 64 lanes of a
+    // wavefront touch one contiguous 1 KiB (complex) segment per access, and a chunk of
+    // consecutive rows of one wavefront is contiguous as well.  Each lane works on a view
+    // whose pointers are offset to its own column (slots = 64, lane index 0).
+    static __device__ Workspace lane_view(const Workspace &g, int64_t sg) {
+        Workspace w = g;
+        const int64_t wv = sg >> 6, l = sg & 63;
+        const int64_t wl = KL > 0 ? KL : 1;
+        const int64_t nr = g.nrow;
+        w.slots = 64;
+        w.L = g.L + wv * nr * wl * 64 + l;
+        w.U = g.U + wv * nr * W * 64 + l;
+        w.piv = g.piv + wv * nr * 64 + l;
+        w.vu = g.vu + wv * nr * 64 + l;
+        w.vv = g.vv + wv * nr * 64 + l;
+        w.vy = g.vy + wv * nr * 64 + l;
+        w.eu = g.eu + wv * nr * 64 + l;
+        w.ev = g.ev + wv * nr * 64 + l;
+        w.ey = g.ey + wv * nr * 64 + l;
+        w.hist = g.hist + wv * (int64_t)g.kmax * 2 * 64 + l;
+        if (VEC) {
+            w.basis = g.basis + wv * (int64_t)g.kvec * nr * 64 + l;
+            w.ebasis = g.ebasis + wv * (int64_t)g.kvec * nr * 64 + l;
+            w.bmeta = g.bmeta + wv * (int64_t)g.kvec * 6 * 64 + l;
+        }
+        return w;
+    }
+
+    static __device__ void run(const EvalArgs a, const Workspace wg) {
+        const int64_t sg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const Workspace w = lane_view(wg, sg);
+        const int64_t s = 0;
+        const int64_t npts = *a.count_dev;
+        const int kcap = VEC ? (a.max_iter < w.kvec ? a.max_iter : w.kvec) : a.max_iter;
+        Lane ln;
+        ln.active = false;
+        ln.exhausted = false;
+        ln.fresh = false;
+        ln.sing = false;
+        ln.k = 0;
+        ln.next_check = 1;
+        ln.nchecks = 0;
+        ln.pid = -1;
+        ln.z = czero();
+        ln.theta = 0.0;
+        ln.b_m = 0.0;
+        ln.b_e = 0;
+        ln.a_m = 0.0;
+        ln.a_e = 0;
+        ln.Eu = ln.Ev = ln.Ey = 0;
+        ln.rdu = ln.rdv = 1.0;
+        ln.E0 = 0;
+        ln.nrm_h = 1.0;
+        ln.ap_prev = ln.bp = 0.0;
+        ln.gmax = ln.gopen = 0.0;
+        ln.delta_prev = ln.rho_prev = 0.0;
+        ln.pending = false;
+        ln.n = a.n;
+        ln.arow = a.arow;
+        ln.normA = a.normA;
+        while (true) {
+            if (VEC && __all(!ln.active) && __any(ln.pending)) vec_finalize(a, w, s, ln);
+            bool may_refill = !ln.active && !ln.exhausted;
+            if (VEC) may_refill = may_refill && __all(!ln.active);
+            if (may_refill) {
+                unsigned long long id = atomicAdd(w.queue, 1ull);
+                if ((int64_t)id >= npts) {
+                    ln.exhausted = true;
+                } else {
+                    ln.pid = (int64_t)id;
+                    ln.active = true;
+                    ln.fresh = true;
+                    ln.sing = false;
+                    ln.k = 0;
+                    ln.b_m = 0.0;
+                    ln.b_e = 0;
+                    if (BATCH) {
+                        // matrix of queue position id: the last m with mfirst[m] <= id
+                        int lo = 0, hi = a.nmat - 1;
+                        while (lo < hi) {
+                            int mid = (lo + hi + 1) >> 1;
+                            if (a.mfirst[mid] <= (int64_t)id) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const MatDesc d = a.mats[lo];
+                        const int64_t q = (int64_t)id - a.mfirst[lo];
+                        ln.n = d.n;
+                        ln.arow = d.arow;
+                        ln.normA = d.normA;
+                        ln.pid = d.out_off + q;
+                        const int64_t flat = a.idx[ln.pid];
+                        const int64_t gi = flat / d.nx, gj = flat - gi * d.nx;
+                        const double x = d.nx > 1 ? __dadd_rn(d.ga, __ddiv_rn(__dmul_rn(d.gb - d.ga, (double)gj),
+                                                                               (double)(d.nx - 1))) : d.ga;
+                        const double y = d.ny > 1 ? __dadd_rn(d.gc, __ddiv_rn(__dmul_rn(d.gd - d.gc, (double)gi),
+                                                                               (double)(d.ny - 1))) : d.gc;
+                        ln.z = C(x, y);
+                    } else if (a.mode == kShiftList) {
+                        ln.z = a.z[ln.pid];
+                    } else {
+                        ln.z = grid_point(a, a.idx ? a.idx[ln.pid] : ln.pid);
+                    }
+                }
+            }
+            if (__all(!ln.active && ln.exhausted)) break;
+            if (__all(!ln.active)) continue;
+
+            double acc;
+            int eacc;
+            f1(a, w, s, ln);
+            if (ln.active && ln.sing) finish(a, w, s, ln, 0);
+            b1(a, w, s, ln, acc, eacc);
+            if (ln.active) after_b1(a, w, s, ln, acc, eacc);
+            f2(a, w, s, ln);
+            b2(a, w, s, ln, acc, eacc);
+            if (ln.active) after_b2(a, w, s, ln, acc, eacc, kcap);
+        }
+    }
+};
+
+// One wavefront per workgroup: a launch of S slots is S / 64 workgroups, which the dispatcher
+// spreads over all compute units (and their four SIMDs) even when S / 64 is below the SIMD
+// count, instead of packing four wavefronts onto each of S / 256 compute units.
+constexpr int kEvalBlock = 64;
+
+template <int KL, int KU, bool VEC, bool BATCH>
+__global__ void __launch_bounds__(kEvalBlock) k_eval(EvalArgs a, Workspace w) {
+    Kern<KL, KU, VEC, BATCH>::run(a, w);
+}
+
+typedef void (*EvalKernel)(EvalArgs, Workspace);
+
+// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only
+template <int KL, int KU>
+EvalKernel pick_mode(int mode) {
+    switch (mode) {
+    case 0: return k_eval<KL, KU, false, false>;
+    case 1: return k_eval<KL, KU, true, false>;
+    case 2: return k_eval<KL, KU, false, true>;
+    }
+    return nullptr;
+}
+
+template <int KL>
+EvalKernel pick_ku(int ku, int mode) {
+    switch (ku) {
+    case 0: return pick_mode<KL, 0>(mode);
+    case 1: return pick_mode<KL, 1>(mode);
+    case 2: return pick_mode<KL, 2>(mode);
+    case 3: return pick_mode<KL, 3>(mode);
+    case 4: return pick_mode<KL, 4>(mode);
+    }
+    return nullptr;
+}
+
+// Defined in ps_eval_kl<K>.hip.
+EvalKernel pick_eval_kl0(int ku, int mode);
+EvalKernel pick_eval_kl1(int ku, int mode);
+EvalKernel pick_eval_kl2(int ku, int mode);
+EvalKernel pick_eval_kl3(int ku, int mode);
+EvalKernel pick_eval_kl4(int ku, int mode);
+
+}  // namespace ps

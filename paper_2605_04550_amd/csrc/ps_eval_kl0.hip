@@ -1,0 +1,8 @@
+// k_eval instantiations for lower bandwidth 0 (every upper bandwidth 0..4, three modes).
+#include "ps_eval.hpp"
+
+namespace ps {
+
+EvalKernel pick_eval_kl0(int ku, int mode) { return pick_ku<0>(ku, mode); }
+
+}  // namespace ps
