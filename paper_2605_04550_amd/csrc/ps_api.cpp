@@ -1,7 +1,7 @@
 // Host side of the C ABI declared in include/ps.h: argument validation, the matrix
 // handle, workspace planning and kernel launches on the caller's stream.
 
-#include "../../include/ps.h"
+#include "ps.h"
 #include "ps_internal.h"
 
 #include <hip/hip_runtime.h>

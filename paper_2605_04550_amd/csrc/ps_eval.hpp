@@ -102,6 +102,24 @@ __device__ __forceinline__ cd start_entry(uint64_t seed, int64_t i) {
     return C((double)(h1 >> 11) * 0x1p-52 - 1.0, (double)(h2 >> 11) * 0x1p-52 - 1.0);
 }
 
+// Order in which a full-grid launch visits the grid: tiles of 8 x 8 points, tile rows top
+// to bottom, tiles left to right, points row-major inside a tile (ragged tiles at the right
+// and bottom edges).  Queue position id maps to the flat row-major index returned.  A
+// wavefront takes 64 consecutive queue positions, i.e. one tile, whose shifts need similar
+// Lanczos step counts because the count varies smoothly over the plane; a 64-point strip
+// of one grid row spans a wider stretch and mixes short and long shifts.
+__device__ __forceinline__ int64_t tile_flat(int64_t id, int64_t nx, int64_t ny) {
+    const int64_t r0 = (id / (8 * nx)) * 8;          // first row of the tile row
+    const int64_t h = ny - r0 < 8 ? ny - r0 : 8;       // its height
+    const int64_t rem = id - r0 * nx;
+    const int64_t ntx = (nx + 7) / 8;
+    int64_t tx = rem / (8 * h);
+    if (tx > ntx - 1) tx = ntx - 1;
+    const int64_t tw = tx == ntx - 1 ? nx - 8 * (ntx - 1) : 8;
+    const int64_t r2 = rem - tx * 8 * h;
+    return (r0 + r2 / tw) * nx + 8 * tx + r2 % tw;
+}
+
 __device__ __forceinline__ cd grid_point(const EvalArgs &a, int64_t flat) {
     int64_t i = flat / a.nx, j = flat - i * a.nx;
     double x = a.nx > 1 ? __dadd_rn(a.ga, __ddiv_rn(__dmul_rn(a.gb - a.ga, (double)j), (double)(a.nx - 1))) : a.ga;
@@ -1174,8 +1192,11 @@ struct Kern {
                         ln.z = C(x, y);
                     } else if (a.mode == kShiftList) {
                         ln.z = a.z[ln.pid];
+                    } else if (a.idx) {
+                        ln.z = grid_point(a, a.idx[ln.pid]);
                     } else {
-                        ln.z = grid_point(a, a.idx ? a.idx[ln.pid] : ln.pid);
+                        ln.pid = tile_flat((int64_t)id, a.nx, a.ny);   // full grid: output at the flat index
+                        ln.z = grid_point(a, ln.pid);
                     }
                 }
             }
