@@ -15,6 +15,11 @@ Contents (each function names the passage of the paper it follows):
                           perturbation of a simple singular value; the paper is silent).
   * ``newton_step``    -- one Newton step on ln(sigma/eps) toward the eps-level curve
                           (the level curve of Sec. 2.1; the paper is silent on refinement).
+  * ``contour_seeds``  -- starting points on the eps-level curve from sign changes of
+                          sigma - eps along grid edges (Sec. 2.1 level curve).
+  * ``count_below``    -- number of singular values of zI - A below t, by the inertia of a
+                          banded Hermitian augmented matrix (``inertia.c``); certifies
+                          sigma_min at sizes where a dense SVD per shift is too slow.
 Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
 closed forms, invariants, brute force and the paper's Jordan example.
 """
@@ -27,7 +32,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "jacobi.c")
+_SRCS = [os.path.join(_HERE, "jacobi.c"), os.path.join(_HERE, "inertia.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -36,7 +41,7 @@ def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (OpenMP, no LAPACK)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC,
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", *_SRCS,
                                "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -55,6 +60,8 @@ def _load():
         lib.oracle_sigma_min.restype = ctypes.c_int
         lib.oracle_svd_dense.argtypes = [i64, P, P, P, P, P]
         lib.oracle_svd_dense.restype = ctypes.c_int
+        lib.oracle_count_below.argtypes = [i64, i64, i64, P, i64, i64, P, P, P, ctypes.c_int]
+        lib.oracle_count_below.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -169,3 +176,41 @@ def newton_step(z, sigma, grad_z, eps):
     sigma = np.asarray(sigma, dtype=np.float64)
     g = np.asarray(grad_z, dtype=np.complex128)
     return z - sigma * np.log(sigma / eps) * g / np.abs(g) ** 2
+
+
+def count_below(band, z, t, nthreads: int | None = None) -> np.ndarray:
+    """#{singular values of z_p I - A below t_p} for each point (inertia of
+    [[-t I, M], [M^H, -t I]] by a banded L D L^H, ``inertia.c``); -1 marks an exactly zero pivot."""
+    lib = _load()
+    z = np.ascontiguousarray(np.atleast_1d(z), dtype=np.complex128)
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), z.shape))
+    ab = np.ascontiguousarray(band.ab, dtype=np.complex128)
+    out = np.zeros(z.shape, dtype=np.int64)
+    lib.oracle_count_below(band.n, band.kl, band.ku, _ptr(ab), band.kl + band.ku + 1, len(z), _ptr(z), _ptr(t),
+                           _ptr(out), nthreads or default_threads())
+    return out
+
+
+def contour_seeds(grid, sigma, eps) -> np.ndarray:
+    """Points on the eps-level curve of sigma_min (the curve the paper draws at log10 eps,
+    Sec. 2.1), one per grid edge whose two end points lie on different sides of the
+    inclusive test sigma <= eps.  On such an edge z1 -> z2 the seed is z1 + tau (z2 - z1),
+    tau = (ln eps - ln s1) / (ln s2 - ln s1), linear interpolation of ln sigma (sigma is
+    clamped to 2^-1022 before the logarithm).  Order: the horizontal edges (i, j)-(i, j+1)
+    in row-major order of (i, j), then the vertical edges (i, j)-(i+1, j) likewise."""
+    nx, ny = int(grid.nx), int(grid.ny)
+    s = np.asarray(sigma, dtype=np.float64).reshape(ny, nx)
+    z = grid_points(grid).reshape(ny, nx)
+    inside = s <= eps
+    ls = np.log(np.maximum(s, 2.0 ** -1022))
+    le = np.log(eps)
+    out = []
+    for (a, b) in (((slice(None), slice(0, nx - 1)), (slice(None), slice(1, nx))),
+                   ((slice(0, ny - 1), slice(None)), (slice(1, ny), slice(None)))):
+        sel = inside[a] != inside[b]
+        l1, l2 = ls[a][sel], ls[b][sel]
+        z1, z2 = z[a][sel], z[b][sel]
+        tau = (le - l1) / (l2 - l1)
+        out.append(z1 + tau * (z2 - z1))
+    return np.concatenate(out)
+

@@ -351,6 +351,81 @@ def test_newton_step_circle_contour():
     np.testing.assert_allclose(np.abs(z - a), eps, rtol=1e-6)
 
 
+# ----------------------------------------------------------------------------- inertia count
+
+def test_count_below_closed_form_diagonal():
+    # normal A: the singular values of zI - A are |z - a_k| exactly
+    rng = _rng(41)
+    vals = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    band = W.diagonal(vals)
+    z = rng.standard_normal(5) + 1j * rng.standard_normal(5)
+    for zz in z:
+        s = np.sort(np.abs(zz - vals))
+        ts = np.concatenate([[0.5 * s[0]], 0.5 * (s[:-1] + s[1:]), [2 * s[-1]]])
+        got = oracle.count_below(band, np.full(len(ts), zz), ts)
+        assert np.array_equal(got, np.arange(len(ts))), (zz, got)
+
+
+def test_count_below_matches_all_singular_values():
+    # general banded matrices: counts at thresholds between consecutive singular values of
+    # the dense SVD (all of them, from the Jacobi oracle) and just around sigma_min
+    for k, (n, kl, ku) in enumerate([(17, 2, 1), (25, 0, 3), (30, 3, 0), (12, 4, 4), (40, 1, 1)]):
+        band = W.random_banded(n, kl, ku, seed=60 + k)
+        rng = _rng(50 + k)
+        z = rng.uniform(-2, 2, 3) + 1j * rng.uniform(-2, 2, 3)
+        r = oracle.sigma_min(band, z, all_sv=True)
+        lap = np.linalg.svd(z[:, None, None] * np.eye(n) - W.to_dense(band), compute_uv=False)
+        for p in range(len(z)):
+            s = np.sort(r["sall"][p])
+            np.testing.assert_allclose(s, np.sort(lap[p]), atol=1e-12)
+            ts = np.concatenate([[s[0] * (1 - 1e-6), s[0] * (1 + 1e-6)], 0.5 * (s[1:-1] + s[2:])])
+            expect = np.concatenate([[0, 1], np.arange(2, n)])
+            got = oracle.count_below(band, np.full(len(ts), z[p]), ts)
+            assert np.array_equal(got, expect), (n, kl, ku, p, got, expect)
+
+
+def test_count_below_toeplitz_larger_n():
+    # the non-normal tridiagonal Toeplitz matrix at n = 500, away from and near its spectrum:
+    # count(sigma_min (1 -/+ 1e-9)) = 0 / >= 1 with sigma_min from the Jacobi oracle
+    band = W.toeplitz(500, 0.25, 0.0, 1.0)
+    z = np.array([1.9 + 1.9j, -1.7 + 0.2j])
+    r = oracle.sigma_min(band, z)
+    lo = oracle.count_below(band, z, r["sigma"] * (1 - 1e-9))
+    hi = oracle.count_below(band, z, r["sigma"] * (1 + 1e-9))
+    assert np.all(lo == 0) and np.all(hi >= 1), (lo, hi)
+
+
+# ----------------------------------------------------------------------------- contour seeds
+
+def test_contour_seeds_on_a_circle():
+    # n = 1, A = [a]: sigma_min(z) = |z - a|, so the eps-level curve is the circle |z - a| = eps
+    a = 0.1 - 0.05j
+    band = W.diagonal([a])
+    grid = W.Grid(-1.0, 1.0, -1.0, 1.0, 81, 61)
+    z = oracle.grid_points(grid)
+    sigma = np.abs(z - a)
+    eps = 0.55
+    seeds = oracle.contour_seeds(grid, sigma, eps)
+    inside = (sigma <= eps).reshape(61, 81)
+    n_edges = np.sum(inside[:, 1:] != inside[:, :-1]) + np.sum(inside[1:, :] != inside[:-1, :])
+    assert len(seeds) == n_edges > 0
+    # every seed lies on a grid edge crossing the circle, close to the circle (second-order
+    # error of the ln-linear interpolation over a spacing of 1/40)
+    assert np.all(np.abs(np.abs(seeds - a) - eps) < 2e-3)
+    hx, hy = 2.0 / 80, 2.0 / 60
+    on_h = np.abs((seeds.imag + 1.0) / hy - np.round((seeds.imag + 1.0) / hy)) < 1e-9
+    on_v = np.abs((seeds.real + 1.0) / hx - np.round((seeds.real + 1.0) / hx)) < 1e-9
+    assert np.all(on_h | on_v)
+    # order: horizontal edges first (row-major), then vertical edges
+    nh = np.sum(inside[:, 1:] != inside[:, :-1])
+    assert np.all(on_h[:nh]) and np.all(np.diff(np.round((seeds[:nh].imag + 1.0) / hy)) >= 0)
+    # a grid point exactly on the level set (sigma == eps) is inside: the seed is that point
+    g2 = W.Grid(-1.0, 1.0, 0.0, 0.0, 21, 1)
+    s2 = np.abs(oracle.grid_points(g2))
+    sd = oracle.contour_seeds(g2, s2, 0.5)
+    np.testing.assert_allclose(np.sort(sd.real), [-0.5, 0.5], atol=1e-15)
+
+
 # ----------------------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
