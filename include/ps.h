@@ -132,7 +132,10 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
  *   sigma_dev  device double[npts] (required).
  *   u_dev, v_dev  device ps_c128[npts][n] or NULL; required when o->want_vectors.
  *              Unit singular vectors with (zI - A) v = sigma u; the joint phase makes the
- *              first entry of v of largest modulus real and positive.
+ *              first entry of v of largest modulus real and positive.  v is the Ritz vector
+ *              of the converged Lanczos process (a second pass replays its steps exactly and
+ *              accumulates it, so vectors cost about twice the steps of sigma alone) and u
+ *              one inverse-iteration step from it, u = (zI - A)^{-H} v / |(zI - A)^{-H} v|.
  *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL.
  * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
  */
@@ -229,6 +232,27 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
 ps_status ps_newton_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes);
 ps_status ps_newton_contour(ps_matrix m, ps_c128 *z_dev, int64_t npts, double eps, int32_t steps, const ps_opts *o,
                             void *ws_dev, size_t ws_bytes, double *sigma_dev, int32_t *info_dev, void *stream);
+
+/*
+ * ps_contour_seeds -- starting points for ps_newton_contour on the eps-level curve of sigma_min
+ * (the boundary of the eps-pseudospectrum, drawn as the level curve log10 eps in Sec. 2.1):
+ * one point on every grid edge whose two end points lie on different sides of the inclusive
+ * test sigma <= eps (eq. sensitive_zone), at z1 + tau (z2 - z1) with
+ * tau = (ln eps - ln s1) / (ln s2 - ln s1) (ln sigma linear along the edge; sigma is clamped to
+ * 2^-1022 first).  Edge order: the horizontal edges (i, j)-(i, j+1) in row-major order of
+ * (i, j), then the vertical edges (i, j)-(i+1, j) likewise.  No matrix is involved.
+ *   g          the grid the values belong to (nx, ny >= 1).
+ *   sigma_dev  device double[ny * nx], row-major (ps_eval_grid's output for mask NULL).
+ *   eps > 0, finite.
+ *   seeds_dev  device ps_c128[max_seeds] (may be NULL when max_seeds == 0): the first
+ *              min(count, max_seeds) seeds in edge order.
+ *   count_dev  device int64: the number of sign-change edges (may exceed max_seeds).
+ *   ws_dev / ws_bytes >= ps_contour_seeds_workspace_size(g).
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_contour_seeds_workspace_size(const ps_grid *g, size_t *bytes);
+ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps, ps_c128 *seeds_dev,
+                           int64_t max_seeds, int64_t *count_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
 /*
  * ps_autotune -- choose the plan for ps_eval_points / ps_eval_grid on this matrix: the number

@@ -69,6 +69,9 @@ _SIGNATURES = {
     "ps_newton_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "ps_newton_contour": (ctypes.c_int, [_P, _P, _I64, ctypes.c_double, _I32, ctypes.POINTER(ps_opts), _P,
                                          ctypes.c_size_t, _P, _P, _P]),
+    "ps_contour_seeds_workspace_size": (ctypes.c_int, [ctypes.POINTER(ps_grid), ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_contour_seeds": (ctypes.c_int, [ctypes.POINTER(ps_grid), _P, ctypes.c_double, _P, _I64, _P, _P,
+                                        ctypes.c_size_t, _P]),
     "ps_autotune": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ps_opts), _P]),
     "ps_create_batch": (ctypes.c_int, [_I32, ctypes.POINTER(_P), ctypes.POINTER(ps_grid), ctypes.POINTER(_P)]),
     "ps_destroy_batch": (ctypes.c_int, [_P]),
@@ -179,6 +182,18 @@ def ps_newton_contour(handle, z_ptr, npts, eps, steps, opts, ws_ptr, ws_bytes, s
     _check(lib().ps_newton_contour(_P(handle), _P(z_ptr), npts, float(eps), int(steps),
                                    ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
                                    _P(sigma_ptr), _P(info_ptr), _P(stream)))
+
+
+def ps_contour_seeds_workspace_size(grid: ps_grid) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_contour_seeds_workspace_size(ctypes.byref(grid), ctypes.byref(b)))
+    return b.value
+
+
+def ps_contour_seeds(grid: ps_grid, sigma_ptr, eps, seeds_ptr, max_seeds, count_ptr, ws_ptr, ws_bytes,
+                     stream=0) -> None:
+    _check(lib().ps_contour_seeds(ctypes.byref(grid), _P(sigma_ptr), float(eps), _P(seeds_ptr), int(max_seeds),
+                                  _P(count_ptr), _P(ws_ptr), ws_bytes, _P(stream)))
 
 
 def ps_autotune(handle, z_ptr, npts, opts: ps_opts, stream=0) -> ps_opts:

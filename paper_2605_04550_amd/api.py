@@ -18,7 +18,8 @@ import torch
 from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_workspace_size, ps_batch_info,
                ps_batch_workspace_size, ps_create_banded, ps_create_batch, ps_destroy, ps_destroy_batch,
                ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
-               ps_newton_workspace_size, ps_opts_default, ps_workspace_size)
+               ps_newton_workspace_size, ps_opts_default, ps_workspace_size, ps_contour_seeds,
+               ps_contour_seeds_workspace_size)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
 
@@ -238,6 +239,24 @@ def newton_contour(mat: BandedMatrix, z0: torch.Tensor, eps: float, steps: int =
     ps_newton_contour(mat.handle, z.data_ptr(), npts, eps, steps, o, ws.data_ptr(), ws.numel(), sig.data_ptr(),
                       info.data_ptr(), _stream_handle(stream))
     return z, sig
+
+
+def contour_seeds(grid, sigma: torch.Tensor, eps: float, max_seeds: int | None = None, stream=None):
+    """ps_contour_seeds: points on the eps-level curve from sign changes of sigma - eps along the
+    edges of the grid whose full-grid sigma (row-major [ny * nx], on the device) is given.
+    Returns (seeds [min(count, max_seeds)] complex128, count)."""
+    g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
+    dev = sigma.device
+    assert sigma.dtype == torch.float64 and sigma.numel() == g.nx * g.ny
+    if max_seeds is None:
+        max_seeds = g.ny * (g.nx - 1) + (g.ny - 1) * g.nx
+    seeds = torch.empty(max(int(max_seeds), 1), dtype=torch.complex128, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = _workspace(ps_contour_seeds_workspace_size(g), dev)
+    ps_contour_seeds(g, sigma.contiguous().data_ptr(), eps, seeds.data_ptr(), int(max_seeds), count.data_ptr(),
+                     ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    c = int(count.item())
+    return seeds[:min(c, int(max_seeds))], c
 
 
 def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):

@@ -47,8 +47,9 @@ ps_status ok() {
 
 constexpr int64_t kSlotQuantum = 256;
 constexpr int64_t kMaxSlots = 131072;
-constexpr double kDefaultWsBudget = 48.0 * (1ull << 30);   // bytes the default plan may use
-constexpr int kVecBasisMax = 64;
+// Bytes the default plan may use: enough slots to give every SIMD a wavefront at n = 10^4
+// (1.9 MB per slot there), under half of the 288 GB of HBM.
+constexpr double kDefaultWsBudget = 128.0 * (1ull << 30);
 
 ps_opts resolve(const ps_opts *o) {
     ps_opts r;
@@ -70,7 +71,7 @@ ps_status check_opts(const ps_opts &o) {
 
 int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
 
-int kvec_of(const ps_opts &o) { return o.want_vectors ? (o.max_iter < kVecBasisMax ? o.max_iter : kVecBasisMax) : 0; }
+int vec_of(const ps_opts &o) { return o.want_vectors ? 1 : 0; }
 
 int64_t round_slots(int64_t s) {
     s = (s / kSlotQuantum) * kSlotQuantum;
@@ -83,10 +84,10 @@ int64_t default_slots(const ps_matrix_s *m, int64_t npts, const ps_opts &o) {
     if (o.slots > 0) want = round_slots(o.slots);
     if (want < kSlotQuantum) want = kSlotQuantum;
     if (want > kMaxSlots) want = kMaxSlots;
-    const int kvec = kvec_of(o);
+    const int vec = vec_of(o);
     // shrink until the workspace fits the default budget
     while (want > kSlotQuantum &&
-           (double)ps::workspace_bytes(m->n, m->kl, m->ku, want, o.max_iter, kvec, npts) > kDefaultWsBudget)
+           (double)ps::workspace_bytes(m->n, m->kl, m->ku, want, o.max_iter, vec, npts) > kDefaultWsBudget)
         want -= kSlotQuantum;
     return want;
 }
@@ -94,13 +95,23 @@ int64_t default_slots(const ps_matrix_s *m, int64_t npts, const ps_opts &o) {
 // Largest slot count <= the default whose workspace fits ws_bytes (0 if none).
 int64_t slots_for(const ps_matrix_s *m, int64_t npts, const ps_opts &o, size_t ws_bytes) {
     int64_t s = default_slots(m, npts, o);
-    const int kvec = kvec_of(o);
-    while (s >= kSlotQuantum && ps::workspace_bytes(m->n, m->kl, m->ku, s, o.max_iter, kvec, npts) > ws_bytes)
+    const int vec = vec_of(o);
+    while (s >= kSlotQuantum && ps::workspace_bytes(m->n, m->kl, m->ku, s, o.max_iter, vec, npts) > ws_bytes)
         s -= kSlotQuantum;
     return s >= kSlotQuantum ? s : 0;
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+ps_status check_grid(const ps_grid *g) {
+    if (!g) return fail(PS_ERR_INVALID, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1) return fail(PS_ERR_INVALID, "grid needs nx, ny >= 1");
+    if (!isfinite(g->a) || !isfinite(g->b) || !isfinite(g->c) || !isfinite(g->d))
+        return fail(PS_ERR_NONFINITE, "non-finite grid bounds");
+    if (g->nx > (int64_t)1 << 31 || g->ny > (int64_t)1 << 31 || g->nx * g->ny > ((int64_t)1 << 40))
+        return fail(PS_ERR_INVALID, "grid too large");
+    return PS_OK;
+}
 
 ps_status check_handle(ps_matrix m) {
     if (!m) return fail(PS_ERR_INVALID, "matrix handle is NULL");
@@ -116,8 +127,8 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     int64_t slots = slots_for(m, npts_max, o, ws_bytes);
     if (slots == 0)
         return fail(PS_ERR_WORKSPACE, "workspace of %zu bytes is below the minimum %zu", ws_bytes,
-                    ps::workspace_bytes(m->n, m->kl, m->ku, kSlotQuantum, o.max_iter, kvec_of(o), npts_max));
-    ps::carve_workspace(ws, m->n, m->kl, m->ku, slots, o.max_iter, kvec_of(o), npts_max, w);
+                    ps::workspace_bytes(m->n, m->kl, m->ku, kSlotQuantum, o.max_iter, vec_of(o), npts_max));
+    ps::carve_workspace(ws, m->n, m->kl, m->ku, slots, o.max_iter, vec_of(o), npts_max, w);
     a->n = m->n;
     a->kl = m->kl;
     a->ku = m->ku;
@@ -239,7 +250,7 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
     ps_opts r = resolve(o);
     if ((st = check_opts(r))) return st;
     int64_t slots = default_slots(m, npts, r);
-    *bytes = ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, kvec_of(r), npts);
+    *bytes = ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, vec_of(r), npts);
     return ok();
 }
 
@@ -272,12 +283,7 @@ ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, c
                        void *stream) {
     ps_status st = check_handle(m);
     if (st) return st;
-    if (!g) return fail(PS_ERR_INVALID, "grid is NULL");
-    if (g->nx < 1 || g->ny < 1) return fail(PS_ERR_INVALID, "grid needs nx, ny >= 1");
-    if (!isfinite(g->a) || !isfinite(g->b) || !isfinite(g->c) || !isfinite(g->d))
-        return fail(PS_ERR_NONFINITE, "non-finite grid bounds");
-    if (g->nx > (int64_t)1 << 31 || g->ny > (int64_t)1 << 31 || g->nx * g->ny > ((int64_t)1 << 40))
-        return fail(PS_ERR_INVALID, "grid too large");
+    if ((st = check_grid(g))) return st;
     if (!idx_dev || !count_dev) return fail(PS_ERR_INVALID, "idx and count outputs are required");
     if (sens_dev && !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite");
     ps_opts r = resolve(o);
@@ -390,6 +396,34 @@ size_t batch_scratch_bytes(const ps_batch_s *b) {
 }  // namespace
 
 extern "C" {
+
+ps_status ps_contour_seeds_workspace_size(const ps_grid *g, size_t *bytes) {
+    ps_status st = check_grid(g);
+    if (st) return st;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    // scan queue word (unused by the seeds) + one block sum per tile of edges
+    *bytes = 256 + sizeof(int64_t) * (size_t)ps::contour_edge_tiles(g->nx, g->ny);
+    return ok();
+}
+
+ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps, ps_c128 *seeds_dev,
+                           int64_t max_seeds, int64_t *count_dev, void *ws_dev, size_t ws_bytes, void *stream) {
+    ps_status st = check_grid(g);
+    if (st) return st;
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite and > 0");
+    if (max_seeds < 0) return fail(PS_ERR_INVALID, "max_seeds must be >= 0");
+    if (!sigma_dev || !count_dev) return fail(PS_ERR_INVALID, "sigma and count are required");
+    if (max_seeds > 0 && !seeds_dev) return fail(PS_ERR_INVALID, "seeds is NULL with max_seeds > 0");
+    size_t need = 0;
+    ps_contour_seeds_workspace_size(g, &need);
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "contour-seed workspace needs %zu bytes", need);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    char *base = (char *)ws_dev;
+    HIP_TRY(ps::launch_contour_seeds(g->a, g->b, g->c, g->d, g->nx, g->ny, sigma_dev, eps, (double2 *)seeds_dev,
+                                     max_seeds, count_dev, (int64_t *)(base + 256), (unsigned long long *)base,
+                                     (hipStream_t)stream));
+    return ok();
+}
 
 ps_status ps_newton_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes) {
     ps_status st = check_handle(m);

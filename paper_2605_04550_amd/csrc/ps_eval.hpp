@@ -227,7 +227,16 @@ struct Lane {
     int Eu, Ev, Ey;   // max row exponent of u, v, y
     double rdu, rdv;  // 1 / (norm mantissa) of u, v
     double nrm_h;     // squared norm of the start vector (fresh lanes)
-    bool active, fresh, sing, exhausted, pending;
+    bool active, fresh, sing, exhausted;
+    // Singular vectors (VEC): stage 0 runs the Lanczos process to convergence; stage 1
+    // replays its first kfinal steps bit for bit from the same start vector, accumulating
+    // v = sum_j p_j u_j (p = top left singular vector of B_kfinal) in vacc; stage 2 applies
+    // one inverse-iteration step u = M^{-H} v / |M^{-H} v| and writes the pair.
+    int stage;
+    int kfinal;
+    double vnorm2;    // |v|^2 of the accumulated vector (known after its last step)
+    double vamax;     // largest |v_i|^2 so far (first index on ties)
+    cd vph;           // the entry that attains it
     // batch mode: the matrix of the current shift
     int64_t n;
     const double2 *arow;
@@ -283,6 +292,7 @@ struct Kern {
         int R = 0;
         double nrm_h = 0.0;
         const bool act = ln.active, fresh = ln.fresh;
+        const bool lu = fresh && (!VEC || ln.stage == 0);   // a replay keeps the factors it has
         const double tiny = 0x1p-1000 * fmax(1.0, fro(a, ln) + cabs1(ln.z));
         bool sing = false;
         // input v: normalised stored v (mantissa * rdv * 2^(e - Ev)); fresh lanes read h
@@ -300,10 +310,12 @@ struct Kern {
                 w.ev[s] = 0;
 #pragma unroll
                 for (int r = 0; r < KL; ++r) b[r] = gen(r);
+                if (lu) {
 #pragma unroll
-                for (int r = 0; r < KL; ++r)
+                    for (int r = 0; r < KL; ++r)
 #pragma unroll
-                    for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, ln, r, c);
+                        for (int c = 0; c < W; ++c) Wm[r][c] = mentry(a, ln, r, c);
+                }
             } else {
                 const double f0 = rdv * p2((int)w.ev[s] - Ev);
 #pragma unroll
@@ -339,6 +351,16 @@ struct Kern {
                 for (int c = 0; c < CH; ++c) {
                     const int64_t j = j0 + c;
                     pin[c] = gen(j + KL);
+                    if (!lu) {       // replay: the multipliers and pivots stored by the LU
+                        if (KL > 0) {
+                            pv[c] = (int)w.piv[j * T + s];
+#pragma unroll
+                            for (int r = 0; r < KL; ++r) Lr[c][r] = w.L[(j * KL + r) * T + s];
+                        } else {
+                            pv[c] = 0;
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int cc = 0; cc < W; ++cc) Wm[KL][cc] = mentry(a, ln, j + KL, j + cc);
                     double best = cabs1(Wm[0][0]);
@@ -437,7 +459,7 @@ struct Kern {
             ln.Ey = R;
             if (fresh) {
                 ln.nrm_h = nrm_h;
-                ln.sing = sing;
+                if (lu) ln.sing = sing;
                 ln.Ev = 0;
                 ln.rdv = 1.0 / sqrt(nrm_h);
             }
@@ -458,22 +480,13 @@ struct Kern {
         for (int d = 0; d < W; ++d) xw[d] = czero();
         double acc = 0.0;
         int Eacc = R;
-        // VEC: write u_k into basis slot k (k = ln.k), read u_{k-1} from slot k-1.
+        // u_{k-1} is read and u_k written in place (row i is read before it is written)
         double2 *uout = w.vu;
         int16_t *euout = w.eu;
         const double2 *uold = w.vu;
         const int16_t *euold = w.eu;
         const double rd_old = ln.rdu;
         const int E_old = ln.Eu;
-        if (VEC) {
-            int64_t stride = w.nrow * T;
-            uout = w.basis + (int64_t)ln.k * stride;
-            euout = w.ebasis + (int64_t)ln.k * stride;
-            if (ln.k > 0) {
-                uold = w.basis + (int64_t)(ln.k - 1) * stride;
-                euold = w.ebasis + (int64_t)(ln.k - 1) * stride;
-            }
-        }
         const double bm = ln.b_m;
         const int be = ln.b_e;
         const int64_t npad = ((n + CH - 1) / CH) * CH;
@@ -571,25 +584,50 @@ struct Kern {
 
     // ---------------------------------------------------------------- forward sweep 2
     // y = U^{-H} u_k (u_k read normalised), column-oriented forward substitution.
-    static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, bool from_vu = false) {
+    // VEC stage 1 also adds p_k u_k to the accumulated singular vector (vacc); stage 2 solves
+    // with the accumulated vector itself (plain doubles, exponent 0) instead of u_k.
+    static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
         const int64_t n = nn(a, ln), T = w.slots;
         const bool act = ln.active;
-        const double2 *uin = w.vu;
+        const bool fin = VEC && ln.stage == 2;
+        const bool rep = VEC && ln.stage == 1;
+        const double2 *uin = fin ? w.vacc : w.vu;
         const int16_t *euin = w.eu;
-        if (VEC && !from_vu) {
-            int64_t stride = w.nrow * T;
-            uin = w.basis + (int64_t)(ln.k - 1) * stride;
-            euin = w.ebasis + (int64_t)(ln.k - 1) * stride;
-        }
-        const double rdu = ln.rdu;
-        const int Eu = ln.Eu;
+        const double rdu = fin ? 1.0 / sqrt(ln.vnorm2) : ln.rdu;
+        const int Eu = fin ? 0 : ln.Eu;
+        auto ex = [&](int64_t q) -> int { return fin ? 0 : (int)euin[q * T + s]; };
+        // replay: vacc[r] (+)= p_k u_k[r]; the last replayed step also yields |v|^2 and the
+        // first entry of largest modulus (for the phase convention)
+        const bool first = rep && ln.k == 1, lastk = rep && ln.k == ln.kfinal;
+        const double cf = rep ? w.vmeta[((int64_t)(ln.k - 1) * 4 + 3) * T + s] : 0.0;
+        double vn = 0.0, vam = -1.0;
+        cd vph = C(1.0, 0.0);
+        auto accum = [&](int64_t r, cd un) {
+            cd v = C(cf * un.x, cf * un.y);
+            if (!first) {
+                const cd o = w.vacc[r * T + s];
+                v = C(o.x + v.x, o.y + v.y);
+            }
+            w.vacc[r * T + s] = v;
+            if (lastk && r < n) {
+                const double m = cabs2(v);
+                vn += m;
+                if (m > vam) {
+                    vam = m;
+                    vph = v;
+                }
+            }
+        };
         int R = 0;
         cd acc[W];
         const int64_t npad = ((n + CH - 1) / CH) * CH;
         if (act) {
-            const double f0 = rdu * p2((int)euin[s] - Eu);
+            const double f0 = rdu * p2(ex(0) - Eu);
 #pragma unroll
-            for (int d = 0; d < W - 1; ++d) acc[d] = cscale(uin[d * T + s], f0);
+            for (int d = 0; d < W - 1; ++d) {
+                acc[d] = cscale(uin[d * T + s], f0);
+                if (rep) accum(d, acc[d]);
+            }
         }
         for (int64_t i0 = 0; i0 < npad; i0 += CH) {
             if (!act) continue;
@@ -603,9 +641,15 @@ struct Kern {
                 for (int d = 0; d < W; ++d) Ur[c][d] = w.U[(i * W + d) * T + s];
                 pin[c] = uin[(i + W - 1) * T + s];
             }
-            const int ea = (int)euin[q * T + s];
+            const int ea = ex(q);
             const bool last = i0 + CH >= npad;                 // rows at or past npad were never written
-            const int eb = (W > 1 && !last) ? (int)euin[(q + 1) * T + s] : ea;
+            const int eb = (W > 1 && !last) ? ex(q + 1) : ea;
+            if (rep) {
+                const double ga = rdu * p2(ea - Eu), gb = rdu * p2(eb - Eu);
+#pragma unroll
+                for (int c = 0; c < CH; ++c)
+                    if (c + W - 1 < CH || !last) accum(i0 + c + W - 1, cscale(pin[c], c + W - 1 < CH ? ga : gb));
+            }
             cd as[W];
 #pragma unroll
             for (int d = 0; d < W; ++d) as[d] = acc[d];
@@ -661,6 +705,11 @@ struct Kern {
             w.ey[q * T + s] = (int16_t)R;
         }
         if (act) ln.Ey = R;
+        if (act && lastk) {
+            ln.vnorm2 = vn;
+            ln.vamax = vam;
+            ln.vph = vph;
+        }
     }
 
     // ---------------------------------------------------------------- backward sweep 2
@@ -809,123 +858,75 @@ struct Kern {
     }
 
     // ---------------------------------------------------------------- singular vectors
-    // For every lane whose shift converged (ln.pending), all lanes of the wavefront together:
+    // Coefficients of the Ritz vector for sigma_min (per lane, O(k)): with T_k = B_k^H B_k
+    // (B_k upper bidiagonal, alpha'_j on the diagonal, beta'_j above it),
     //   q = top eigenvector of T_k (two steps of inverse iteration at theta (1 + 2^-40)),
-    //   p = B_k q / |B_k q| (top left singular vector of the bidiagonal),
-    //   v = U_k p  (Ritz vector: right singular vector of M = zI - A), assembled in vu,
-    //   u = M^{-H} v / |M^{-H} v| through the lane's LU factors (one inverse-iteration
-    //       step: M^{-H} v_min = u_min / sigma_min, so the error in u shrinks by the gap
-    //       instead of growing by |M| / sigma as it would for u = M v / sigma),
-    // then both are written to the caller's [npts][n] arrays with the joint phase that makes
-    // the first entry of v of largest modulus real and positive.
+    //   p = B_k q / |B_k q|  (top left singular vector of B_k).
+    // The left Lanczos vectors u_j of B = M^{-1} then give v = sum_j p_j u_j, the Ritz
+    // approximation of the top left singular vector of B, which is the right singular vector
+    // of M = zI - A for sigma_min.  vmeta columns: 0 alpha'_j, 1 beta'_j, 2 q_j, 3 pivots of
+    // the tridiagonal solve and finally p_j.
     static __device__ void ritz_coeffs(const Workspace &w, int64_t s, const Lane &ln) {
         const int64_t T = w.slots;
         const int k = ln.k;
-        // bmeta rows: [0, 2kvec) basis meta (1/norm, exponent); [2kvec, 3kvec) q;
-        // [3kvec, 4kvec) pivots, then p; [4kvec, 6kvec) alpha'_j, beta'_j.
-        double *q = w.bmeta + (int64_t)(2 * w.kvec) * T;
-        double *aux = q + (int64_t)w.kvec * T;
-        const double *ab = q + (int64_t)(2 * w.kvec) * T;
+        auto vm = [&](int j, int c) -> double & { return w.vmeta[((int64_t)j * 4 + c) * T + s]; };
         double mu = ln.theta * (1.0 + 0x1p-40);
-        for (int j = 0; j < k; ++j) q[(int64_t)j * T + s] = 1.0;
+        for (int j = 0; j < k; ++j) vm(j, 2) = 1.0;
         for (int it = 0; it < 2; ++it) {
             double dprev = 0.0;
             for (int j = 0; j < k; ++j) {
                 double dj = w.hist[((int64_t)j * 2 + 0) * T + s] - mu;
-                double rhs = q[(int64_t)j * T + s];
+                double rhs = vm(j, 2);
                 if (j > 0) {
                     double e = sqrt(w.hist[((int64_t)(j - 1) * 2 + 1) * T + s]);
                     double lj = e / dprev;
                     dj -= lj * e;
-                    rhs -= lj * q[(int64_t)(j - 1) * T + s];
+                    rhs -= lj * vm(j - 1, 2);
                 }
-                q[(int64_t)j * T + s] = rhs;
-                aux[(int64_t)j * T + s] = dj;
+                vm(j, 2) = rhs;
+                vm(j, 3) = dj;
                 dprev = dj;
             }
             double xnext = 0.0, nrm = 0.0;
             for (int j = k - 1; j >= 0; --j) {
-                double dj = aux[(int64_t)j * T + s];
-                double x = q[(int64_t)j * T + s] / dj;
+                double dj = vm(j, 3);
+                double x = vm(j, 2) / dj;
                 if (j < k - 1) x -= (sqrt(w.hist[((int64_t)j * 2 + 1) * T + s]) / dj) * xnext;
-                q[(int64_t)j * T + s] = x;
+                vm(j, 2) = x;
                 xnext = x;
                 nrm += x * x;
             }
             double rn = 1.0 / sqrt(nrm);
-            for (int j = 0; j < k; ++j) q[(int64_t)j * T + s] *= rn;
+            for (int j = 0; j < k; ++j) vm(j, 2) *= rn;
         }
         double pn = 0.0;
         for (int j = 0; j < k; ++j) {
-            double pj = ab[((int64_t)j * 2 + 0) * T + s] * q[(int64_t)j * T + s];
-            if (j + 1 < k) pj += ab[((int64_t)j * 2 + 1) * T + s] * q[(int64_t)(j + 1) * T + s];
-            aux[(int64_t)j * T + s] = pj;
+            double pj = vm(j, 0) * vm(j, 2);
+            if (j + 1 < k) pj += vm(j, 1) * vm(j + 1, 2);
+            vm(j, 3) = pj;
             pn += pj * pj;
         }
         double rpn = 1.0 / sqrt(pn);
-        for (int j = 0; j < k; ++j) aux[(int64_t)j * T + s] *= rpn;
+        for (int j = 0; j < k; ++j) vm(j, 3) *= rpn;
     }
 
-    static __device__ void vec_finalize(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+    // Stage 2 output, after the inverse-iteration step left M^{-H} v in vv (|.|^2 = acc 2^(2 eacc)):
+    // v = vacc / |vacc|, u = that direction normalised, both rotated by the unit scalar that
+    // makes the first entry of v of largest modulus real and positive.
+    static __device__ void write_vectors(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln,
+                                         double acc, int eacc) {
         const int64_t n = nn(a, ln), T = w.slots;
-        const bool pend = ln.pending;
-        if (pend) ritz_coeffs(w, s, ln);
-        const double *coef = w.bmeta + (int64_t)(3 * w.kvec) * T;
-        const int64_t stride = w.nrow * T;
-        const int k = ln.k;
-        double vn = 0.0, amax = -1.0;
-        cd vph = C(1.0, 0.0);
-        for (int64_t i = 0; i < n; ++i) {
-            if (!pend) continue;
-            cd acc = czero();
-            for (int j = 0; j < k; ++j) {
-                double rd = w.bmeta[((int64_t)j * 2 + 0) * T + s];
-                int Ej = (int)w.bmeta[((int64_t)j * 2 + 1) * T + s];
-                cd uj = cldexp(cscale(w.basis[j * stride + i * T + s], rd),
-                               (int)w.ebasis[j * stride + (i / CH) * T + s] - Ej);
-                double c = coef[(int64_t)j * T + s];
-                acc = C(fma(c, uj.x, acc.x), fma(c, uj.y, acc.y));
-            }
-            w.vu[i * T + s] = acc;
-            vn += cabs2(acc);
-            double m = cabs2(acc);
-            if (m > amax) { amax = m; vph = acc; }
-        }
-        for (int64_t i = n; i < w.nrow; ++i) {
-            if (!pend) continue;
-            w.vu[i * T + s] = czero();
-        }
-        for (int64_t q = 0; q < w.nrow / CH; ++q) {
-            if (!pend) continue;
-            w.eu[q * T + s] = 0;
-        }
-        // u direction: M^{-H} v through the factors (alpha = 0: no three-term correction)
-        const bool saved = ln.active;
-        ln.active = pend;
-        if (pend) {
-            ln.Eu = 0;
-            ln.rdu = 1.0 / sqrt(vn);
-            ln.a_m = 0.0;
-            ln.a_e = 0;
-        }
-        f2(a, w, s, ln, true);
-        double accu;
-        int eaccu;
-        b2(a, w, s, ln, accu, eaccu);
-        ln.active = saved;
-        if (!pend) return;
-        double am = sqrt(amax);
-        cd ph = am > 0.0 ? C(vph.x / am, -vph.y / am) : C(1.0, 0.0);
-        double rv = 1.0 / sqrt(vn);
-        double ru = 1.0 / sqrt(accu);
+        const double am = sqrt(ln.vamax);
+        const cd ph = am > 0.0 ? C(ln.vph.x / am, -ln.vph.y / am) : C(1.0, 0.0);
+        const double rv = 1.0 / sqrt(ln.vnorm2);
+        const double ru = 1.0 / sqrt(acc);
         double2 *vout = a.v + ln.pid * n;
         double2 *uout = a.u + ln.pid * n;
         for (int64_t i = 0; i < n; ++i) {
-            vout[i] = cscale(cmul(w.vu[i * T + s], ph), rv);
-            cd uu = cldexp(cscale(w.vv[i * T + s], ru), (int)w.ev[(i / CH) * T + s] - eaccu);
+            vout[i] = cscale(cmul(w.vacc[i * T + s], ph), rv);
+            const cd uu = cldexp(cscale(w.vv[i * T + s], ru), (int)w.ev[(i / CH) * T + s] - eacc);
             uout[i] = cmul(uu, ph);
         }
-        ln.pending = false;
     }
 
     static __device__ void finish(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, int flags) {
@@ -950,7 +951,15 @@ struct Kern {
                     a.v[ln.pid * nn(a, ln) + i] = czero();
                 }
             } else {
-                ln.pending = true;   // assembled by vec_finalize with the whole wavefront
+                // replay the same kfinal steps from the same start vector (the factors stay)
+                ritz_coeffs(w, s, ln);
+                ln.kfinal = ln.k;
+                ln.stage = 1;
+                ln.fresh = true;
+                ln.k = 0;
+                ln.b_m = 0.0;
+                ln.b_e = 0;
+                return;      // the lane stays active
             }
         }
         ln.active = false;
@@ -994,11 +1003,9 @@ struct Kern {
         double av = sqrt(ln.fresh ? acc / ln.nrm_h : acc);
         ln.Eu = eacc;
         ln.rdu = 1.0 / sqrt(acc);
-        if (VEC) {
-            w.bmeta[((int64_t)ln.k * 2 + 0) * T + s] = ln.rdu;
-            w.bmeta[((int64_t)ln.k * 2 + 1) * T + s] = (double)ln.Eu;
-        }
-        if (!(av > 0.0)) {
+        // a replay repeats the recurrence only; it ends before any step where the first pass stopped
+        const bool first_pass = !VEC || ln.stage == 0;
+        if (!(av > 0.0) && first_pass) {
             // B v_k = beta u_{k-1} exactly: the Krylov space is invariant and T_k is exact.
             if (ln.fresh) {
                 ln.sing = true;
@@ -1013,7 +1020,7 @@ struct Kern {
         int ea = ilogb(av);
         ln.a_m = ldexp(av, -ea);
         ln.a_e = eacc + ea;
-        double *abq = VEC ? w.bmeta + (int64_t)(4 * w.kvec) * T : nullptr;
+        auto vm = [&](int j, int c) -> double & { return w.vmeta[((int64_t)j * 4 + c) * T + s]; };
         if (ln.fresh) {
             ln.E0 = ln.a_e;
             double ap = ln.a_m;
@@ -1027,9 +1034,9 @@ struct Kern {
             ln.delta_prev = ln.rho_prev = 0.0;
             ln.gmax = 0.0;
             ln.gopen = ap * ap;
-            if (VEC) abq[s] = ap;
+            if (VEC && first_pass) vm(0, 0) = ap;
             double r_abs = ldexp(a.tol_norm * fro(a, ln) * ap, ln.E0);
-            if (r_abs >= 2.0) {
+            if (r_abs >= 2.0 && first_pass) {
                 ln.theta = ap * ap;
                 finish(a, w, s, ln, 0);
             }
@@ -1043,9 +1050,9 @@ struct Kern {
             double off = sqrt(b2);
             ln.gmax = fmax(ln.gmax, ln.gopen + off);
             ln.gopen = dk + off;
-            if (VEC) {
-                abq[((int64_t)(k - 1) * 2 + 1) * T + s] = ln.bp;
-                abq[((int64_t)k * 2 + 0) * T + s] = ap;
+            if (VEC && first_pass) {
+                vm(k - 1, 1) = ln.bp;
+                vm(k, 0) = ap;
             }
             ln.k = k + 1;
             ln.ap_prev = ap;
@@ -1058,7 +1065,8 @@ struct Kern {
         ln.Ev = eacc;
         ln.rdv = 1.0 / sqrt(acc);
         TopEig te;
-        if (!(bv > 0.0)) {
+        const bool first_pass = !VEC || ln.stage == 0;
+        if (!(bv > 0.0) && first_pass) {
             // B^H u_k = alpha_k v_k exactly: invariant Krylov space, T_k exact.
             check_theta(w, s, ln, te);
             ln.theta = te.theta;
@@ -1069,6 +1077,7 @@ struct Kern {
         ln.b_m = ldexp(bv, -eb);
         ln.b_e = eacc + eb;
         ln.bp = ldexp(ln.b_m, ln.b_e - ln.E0);
+        if (!first_pass) return;     // replay: no checks (it stops at the first pass's step count)
         bool checked = false;
         if (ln.k >= ln.next_check) {
             check_theta(w, s, ln, te);
@@ -1114,9 +1123,8 @@ struct Kern {
         w.ey = g.ey + wv * nr * 64 + l;
         w.hist = g.hist + wv * (int64_t)g.kmax * 2 * 64 + l;
         if (VEC) {
-            w.basis = g.basis + wv * (int64_t)g.kvec * nr * 64 + l;
-            w.ebasis = g.ebasis + wv * (int64_t)g.kvec * nr * 64 + l;
-            w.bmeta = g.bmeta + wv * (int64_t)g.kvec * 6 * 64 + l;
+            w.vacc = g.vacc + wv * nr * 64 + l;
+            w.vmeta = g.vmeta + wv * (int64_t)g.kmax * 4 * 64 + l;
         }
         return w;
     }
@@ -1126,7 +1134,7 @@ struct Kern {
         const Workspace w = lane_view(wg, sg);
         const int64_t s = 0;
         const int64_t npts = *a.count_dev;
-        const int kcap = VEC ? (a.max_iter < w.kvec ? a.max_iter : w.kvec) : a.max_iter;
+        const int kcap = a.max_iter;
         Lane ln;
         ln.active = false;
         ln.exhausted = false;
@@ -1149,14 +1157,16 @@ struct Kern {
         ln.ap_prev = ln.bp = 0.0;
         ln.gmax = ln.gopen = 0.0;
         ln.delta_prev = ln.rho_prev = 0.0;
-        ln.pending = false;
+        ln.stage = 0;
+        ln.kfinal = 0;
+        ln.vnorm2 = 1.0;
+        ln.vamax = -1.0;
+        ln.vph = C(1.0, 0.0);
         ln.n = a.n;
         ln.arow = a.arow;
         ln.normA = a.normA;
         while (true) {
-            if (VEC && __all(!ln.active) && __any(ln.pending)) vec_finalize(a, w, s, ln);
             bool may_refill = !ln.active && !ln.exhausted;
-            if (VEC) may_refill = may_refill && __all(!ln.active);
             if (may_refill) {
                 unsigned long long id = atomicAdd(w.queue, 1ull);
                 if ((int64_t)id >= npts) {
@@ -1165,6 +1175,7 @@ struct Kern {
                     ln.pid = (int64_t)id;
                     ln.active = true;
                     ln.fresh = true;
+                    ln.stage = 0;
                     ln.sing = false;
                     ln.k = 0;
                     ln.b_m = 0.0;
@@ -1205,13 +1216,46 @@ struct Kern {
 
             double acc;
             int eacc;
+            if (!VEC) {
+                f1(a, w, s, ln);
+                if (ln.active && ln.sing) finish(a, w, s, ln, 0);
+                b1(a, w, s, ln, acc, eacc);
+                if (ln.active) after_b1(a, w, s, ln, acc, eacc);
+                f2(a, w, s, ln);
+                b2(a, w, s, ln, acc, eacc);
+                if (ln.active) after_b2(a, w, s, ln, acc, eacc, kcap);
+                continue;
+            }
+            // With vectors a cycle serves lanes in all three stages; lanes sit out the sweeps
+            // their stage does not need (ln.active is cleared around those calls).
+            const bool act0 = ln.active;
+            const bool fin = act0 && ln.stage == 2;        // only f2 and b2, from vacc
+            if (fin) ln.active = false;
             f1(a, w, s, ln);
             if (ln.active && ln.sing) finish(a, w, s, ln, 0);
             b1(a, w, s, ln, acc, eacc);
+            const int st0 = ln.stage;
             if (ln.active) after_b1(a, w, s, ln, acc, eacc);
+            const bool hold = ln.active && ln.stage != st0;   // entered the replay: starts next cycle
+            if (fin) {
+                ln.active = true;
+                ln.a_m = 0.0;                               // no -alpha v term
+                ln.a_e = 0;
+            }
+            if (hold) ln.active = false;
             f2(a, w, s, ln);
+            const bool endrep = ln.active && ln.stage == 1 && ln.k == ln.kfinal;   // vacc is complete
+            if (endrep) ln.active = false;
             b2(a, w, s, ln, acc, eacc);
-            if (ln.active) after_b2(a, w, s, ln, acc, eacc, kcap);
+            if (hold || endrep) ln.active = true;
+            if (endrep) {
+                ln.stage = 2;
+            } else if (fin) {
+                write_vectors(a, w, s, ln, acc, eacc);
+                ln.active = false;
+            } else if (ln.active && !hold) {
+                after_b2(a, w, s, ln, acc, eacc, kcap);
+            }
         }
     }
 };

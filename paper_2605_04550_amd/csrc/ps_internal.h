@@ -23,9 +23,11 @@ enum ShiftMode : int {
 };
 
 // Workspace carve-up of one evaluation: slots lanes, each with its own banded LU,
-// three Lanczos vectors with per-row binary exponents and the bidiagonal history.
-// Every per-slot array is laid out [row][component][slot] so that the 64 lanes of a
-// wavefront touch 64 consecutive elements.
+// three Lanczos vectors with block exponents and the Lanczos tridiagonal; with singular
+// vectors also an accumulator vector and per-step bidiagonal entries and coefficients.
+// Every per-slot array is tiled [wavefront][row][component][lane]: the 64 lanes of a
+// wavefront touch 64 consecutive elements, and consecutive rows of one wavefront are
+// contiguous (the shapes below list the logical indices).
 struct Workspace {
     int64_t slots = 0;
     int64_t nrow = 0;              // allocated rows per slot of every per-row array
@@ -35,18 +37,17 @@ struct Workspace {
     double2 *vu = nullptr;         // [n][slots]       Lanczos vector u (unnormalised)
     double2 *vv = nullptr;         // [n][slots]       Lanczos vector v (unnormalised)
     double2 *vy = nullptr;         // [n][slots]       intermediate of the two-factor solves
-    int16_t *eu = nullptr;         // [n][slots]       binary exponent of each vu row
+    int16_t *eu = nullptr;         // [n/8][slots]     binary exponent of each 8-row chunk of vu
     int16_t *ev = nullptr;
     int16_t *ey = nullptr;
     double *hist = nullptr;        // [kmax][2][slots] Lanczos tridiagonal: diag, offdiag^2
-    double2 *basis = nullptr;      // [kvec][n][slots] u-basis kept for singular vectors
-    int16_t *ebasis = nullptr;     // [kvec][n][slots]
-    double *bmeta = nullptr;       // [kvec][2][slots] per basis vector: 1/norm, exponent
+    double2 *vacc = nullptr;       // [n][slots]       singular-vector accumulator (vectors only)
+    double *vmeta = nullptr;       // [kmax][4][slots] alpha', beta', Ritz work, coefficients (vectors only)
     unsigned long long *queue = nullptr;   // shift counter of the persistent launch
     int64_t *count = nullptr;      // number of shifts (device)
     int64_t *blocksums = nullptr;  // mask compaction scratch
     int kmax = 0;
-    int kvec = 0;
+    int vec = 0;                   // 1: singular vectors wanted
 };
 
 // One matrix of a batch (device array, written once by ps_create_batch).  Matrices are
@@ -93,8 +94,8 @@ struct EvalArgs {
     const int64_t *mfirst = nullptr;   // device: first queue position of each matrix
 };
 
-size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max);
-void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max,
+size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max);
+void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max,
                      Workspace *ws);
 
 // Kernel launchers (enqueue on stream; return hipError_t of the launch).
@@ -116,6 +117,10 @@ hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double
                            hipStream_t st);
 int64_t backward_partial_rows(int64_t npts);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+int64_t contour_edge_tiles(int64_t nx, int64_t ny);
+hipError_t launch_contour_seeds(double a, double b, double c, double d, int64_t nx, int64_t ny, const double *sigma,
+                                double eps, double2 *seeds, int64_t max_seeds, int64_t *count, int64_t *blocksums,
+                                unsigned long long *scratch_queue, hipStream_t st);
 hipError_t launch_newton_update(int64_t npts, double2 *z, const double *sigma, const double2 *grad_z, double eps,
                                 hipStream_t st);
 

@@ -2,7 +2,8 @@
 // small kernels around it: queue and count set-up, mask compaction (a block scan over the
 // mask, then a scatter of the selected flat indices in grid order), the batch variants of
 // both, workspace carving, the adjoint (gradients of sigma_min with respect to z and to the
-// band of A) and the Newton update of contour points.
+// band of A), seeds on the eps-level curve from grid-edge sign changes, and the Newton
+// update of contour points.
 
 #include "ps_eval.hpp"
 
@@ -88,6 +89,105 @@ __global__ void __launch_bounds__(kScanBlock) k_mask_scatter(const uint8_t *mask
         if (base + q < npts && mask[base + q]) idx[pos++] = base + q;
 }
 
+// ------------------------------------------------------------------------ contour seeds
+// Edge e of an nx x ny grid: the first ny (nx - 1) edges are horizontal, (i, j)-(i, j+1) in
+// row-major order; the next (ny - 1) nx are vertical, (i, j)-(i+1, j).  An edge seeds the
+// eps-level curve when its ends lie on different sides of sigma <= eps.
+
+struct EdgeGrid {
+    double a, b, c, d;
+    int64_t nx, ny, nh, ne;   // nh horizontal edges, ne edges in all
+};
+
+__device__ __forceinline__ void edge_ends(const EdgeGrid &g, int64_t e, int64_t &p1, int64_t &p2) {
+    if (e < g.nh) {
+        const int64_t i = e / (g.nx - 1), j = e - i * (g.nx - 1);
+        p1 = i * g.nx + j;
+        p2 = p1 + 1;
+    } else {
+        p1 = e - g.nh;
+        p2 = p1 + g.nx;
+    }
+}
+
+__device__ __forceinline__ bool edge_flag(const EdgeGrid &g, const double *sigma, double eps, int64_t e) {
+    if (e >= g.ne) return false;
+    int64_t p1, p2;
+    edge_ends(g, e, p1, p2);
+    return (sigma[p1] <= eps) != (sigma[p2] <= eps);
+}
+
+__device__ __forceinline__ cd edge_grid_point(const EdgeGrid &g, int64_t flat) {
+    const int64_t i = flat / g.nx, j = flat - i * g.nx;
+    const double x = g.nx > 1 ? __dadd_rn(g.a, __ddiv_rn(__dmul_rn(g.b - g.a, (double)j), (double)(g.nx - 1))) : g.a;
+    const double y = g.ny > 1 ? __dadd_rn(g.c, __ddiv_rn(__dmul_rn(g.d - g.c, (double)i), (double)(g.ny - 1))) : g.c;
+    return C(x, y);
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_edge_count(EdgeGrid g, const double *sigma, double eps,
+                                                           int64_t *blocksums) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q) c += edge_flag(g, sigma, eps, base + q) ? 1 : 0;
+    int64_t total;
+    block_scan(c, sh, total);
+    if (threadIdx.x == 0) blocksums[blockIdx.x] = total;
+}
+
+// Seed on a flagged edge z1 -> z2: z1 + tau (z2 - z1), tau = (ln eps - ln s1)/(ln s2 - ln s1),
+// sigma clamped to the smallest normal double before the logarithm.
+__global__ void __launch_bounds__(kScanBlock) k_edge_scatter(EdgeGrid g, const double *sigma, double eps,
+                                                             const int64_t *blocksums, double2 *seeds,
+                                                             int64_t max_seeds) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q) c += edge_flag(g, sigma, eps, base + q) ? 1 : 0;
+    int64_t total;
+    int64_t pos = blocksums[blockIdx.x] + block_scan(c, sh, total);
+    const double le = log(eps);
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t e = base + q;
+        if (!edge_flag(g, sigma, eps, e)) continue;
+        if (pos < max_seeds) {
+            int64_t p1, p2;
+            edge_ends(g, e, p1, p2);
+            const double l1 = log(fmax(sigma[p1], 0x1p-1022)), l2 = log(fmax(sigma[p2], 0x1p-1022));
+            const double tau = (le - l1) / (l2 - l1);
+            const cd z1 = edge_grid_point(g, p1), z2 = edge_grid_point(g, p2);
+            seeds[pos] = C(fma(tau, z2.x - z1.x, z1.x), fma(tau, z2.y - z1.y, z1.y));
+        }
+        ++pos;
+    }
+}
+
+int64_t contour_edge_tiles(int64_t nx, int64_t ny) {
+    const int64_t ne = ny * (nx - 1) + (ny - 1) * nx;
+    const int64_t nt = (ne + kScanTile - 1) / kScanTile;
+    return nt > 0 ? nt : 1;
+}
+
+hipError_t launch_contour_seeds(double a, double b, double c, double d, int64_t nx, int64_t ny, const double *sigma,
+                                double eps, double2 *seeds, int64_t max_seeds, int64_t *count, int64_t *blocksums,
+                                unsigned long long *scratch_queue, hipStream_t st) {
+    EdgeGrid g;
+    g.a = a;
+    g.b = b;
+    g.c = c;
+    g.d = d;
+    g.nx = nx;
+    g.ny = ny;
+    g.nh = ny * (nx - 1);
+    g.ne = g.nh + (ny - 1) * nx;
+    const int64_t nt = contour_edge_tiles(nx, ny);
+    hipLaunchKernelGGL(k_edge_count, dim3((unsigned)nt), dim3(kScanBlock), 0, st, g, sigma, eps, blocksums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, blocksums, nt, count, scratch_queue);
+    hipLaunchKernelGGL(k_edge_scatter, dim3((unsigned)nt), dim3(kScanBlock), 0, st, g, sigma, eps,
+                       (const int64_t *)blocksums, seeds, max_seeds);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------ adjoint
 
 // grad_z[p] = g_p conj(u_p^H v_p): one wavefront per shift, lanes stride over rows.
@@ -156,13 +256,13 @@ __global__ void __launch_bounds__(256) k_grad_band_sum(int64_t n, int w, int64_t
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max) {
+size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max) {
     Workspace w;
-    carve_workspace(nullptr, n, kl, ku, slots, kmax, kvec, npts_max, &w);
+    carve_workspace(nullptr, n, kl, ku, slots, kmax, vec, npts_max, &w);
     return (size_t)(uintptr_t)w.blocksums + align256(sizeof(int64_t) * (size_t)((npts_max + kScanTile - 1) / kScanTile + 1));
 }
 
-void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int kvec, int64_t npts_max,
+void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max,
                      Workspace *w) {
     size_t off = 0;
     char *b = (char *)base;
@@ -177,7 +277,7 @@ void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int k
     w->slots = slots;
     w->nrow = nrow;
     w->kmax = kmax;
-    w->kvec = kvec;
+    w->vec = vec;
     w->queue = (unsigned long long *)take(sizeof(unsigned long long));
     w->count = (int64_t *)take(sizeof(int64_t));
     w->L = (double2 *)take(sizeof(double2) * ns * (size_t)(kl > 0 ? kl : 1));
@@ -190,15 +290,12 @@ void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int k
     w->ev = (int16_t *)take(sizeof(int16_t) * ns);
     w->ey = (int16_t *)take(sizeof(int16_t) * ns);
     w->hist = (double *)take(sizeof(double) * (size_t)kmax * 2 * (size_t)slots);
-    if (kvec > 0) {
-        w->basis = (double2 *)take(sizeof(double2) * ns * (size_t)kvec);
-        w->ebasis = (int16_t *)take(sizeof(int16_t) * ns * (size_t)kvec);
-        // meta pairs [kvec][2], q [kvec], pivots/p [kvec], alpha'/beta' [kvec][2]
-        w->bmeta = (double *)take(sizeof(double) * (size_t)kvec * 6 * (size_t)slots);
+    if (vec) {
+        w->vacc = (double2 *)take(sizeof(double2) * ns);
+        w->vmeta = (double *)take(sizeof(double) * (size_t)kmax * 4 * (size_t)slots);
     } else {
-        w->basis = nullptr;
-        w->ebasis = nullptr;
-        w->bmeta = nullptr;
+        w->vacc = nullptr;
+        w->vmeta = nullptr;
     }
     w->blocksums = (int64_t *)take(8);
     // blocksums extends to the end (sized by workspace_bytes)

@@ -87,3 +87,36 @@ def test_null_handle_errors():
     P.ps_destroy(0)   # NULL is accepted
     with pytest.raises(P.PsError):
         P.ps_matrix_info(0)
+
+
+def test_contour_seed_and_batch_argument_checks():
+    """Argument validation of entry points that need no matrix, before any device call."""
+    _lib()
+    g = P.ps_grid(-1.0, 1.0, -1.0, 1.0, 5, 4)
+    need = P.ps_contour_seeds_workspace_size(g)
+    assert need >= 256 + 8
+    bad = P.ps_grid(-1.0, 1.0, -1.0, 1.0, 0, 4)
+    with pytest.raises(P.PsError) as e:
+        P.ps_contour_seeds_workspace_size(bad)
+    assert e.value.status == P.PS_ERR_INVALID
+    nan = P.ps_grid(float("nan"), 1.0, -1.0, 1.0, 5, 4)
+    with pytest.raises(P.PsError) as e:
+        P.ps_contour_seeds_workspace_size(nan)
+    assert e.value.status == P.PS_ERR_NONFINITE
+    fake = 1 << 20       # never dereferenced: every call below fails validation first
+    for eps in (0.0, -1.0, float("inf")):
+        with pytest.raises(P.PsError) as e:
+            P.ps_contour_seeds(g, fake, eps, fake, 10, fake, fake, need)
+        assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:            # missing sigma
+        P.ps_contour_seeds(g, 0, 1e-3, fake, 10, fake, fake, need)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:            # seeds NULL with capacity
+        P.ps_contour_seeds(g, fake, 1e-3, 0, 10, fake, fake, need)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:            # workspace too small
+        P.ps_contour_seeds(g, fake, 1e-3, fake, 10, fake, fake, need - 1)
+    assert e.value.status == P.PS_ERR_WORKSPACE
+    with pytest.raises(P.PsError) as e:
+        P.ps_create_batch([], [])
+    assert e.value.status == P.PS_ERR_INVALID

@@ -158,3 +158,32 @@ def test_sigmamin_autograd_function():
     gz, gb = api.backward(mat, torch.tensor([1.0, -2.0], dtype=torch.float64, device="cuda"), r["u"], r["v"])
     np.testing.assert_allclose(z.grad.cpu().numpy(), gz.cpu().numpy(), atol=1e-8)
     np.testing.assert_allclose(ab.grad.cpu().numpy(), gb.cpu().numpy(), atol=1e-8)
+
+
+def test_contour_seeds_vs_oracle():
+    """ps_contour_seeds on the grcar100 grid (the GPU's own sigma values feed both sides, so
+    the sign decisions are the same): same edges in the same order, same points."""
+    api = _api()
+    import torch
+    w = W.workload("grcar100")
+    mat = api.BandedMatrix.from_band(w["band"])
+    grid = w["grid"]
+    r = api.eval_grid(mat, grid)
+    sig = r["sigma"].cpu().numpy()
+    for eps in (1e-1, 1e-3, 1e-6):
+        seeds, count = api.contour_seeds(grid, r["sigma"], eps)
+        ref = oracle.contour_seeds(grid, sig, eps)
+        assert count == len(ref) > 0, (eps, count, len(ref))
+        np.testing.assert_allclose(seeds.cpu().numpy(), ref, rtol=0, atol=1e-13)
+    # capacity below the count: the first max_seeds in edge order, the full count reported
+    seeds, count = api.contour_seeds(grid, r["sigma"], 1e-3, max_seeds=7)
+    assert count == len(oracle.contour_seeds(grid, sig, 1e-3)) and seeds.numel() == 7
+    np.testing.assert_allclose(seeds.cpu().numpy(), oracle.contour_seeds(grid, sig, 1e-3)[:7], rtol=0, atol=1e-13)
+    # ragged sizes: a single row and a single column (only one kind of edge)
+    for g in (W.Grid(-1.0, 3.0, 0.5, 0.5, 37, 1), W.Grid(0.2, 0.2, -3.0, 3.0, 1, 29)):
+        rr = api.eval_grid(mat, g)
+        s = rr["sigma"].cpu().numpy()
+        seeds, count = api.contour_seeds(g, rr["sigma"], 1e-2)
+        ref = oracle.contour_seeds(g, s, 1e-2)
+        assert count == len(ref)
+        np.testing.assert_allclose(seeds.cpu().numpy(), ref, rtol=0, atol=1e-13)
