@@ -23,8 +23,10 @@ LU + inverse-Lanczos kernel, full-grid launch) by its algorithmic bytes: per shi
   B_step = (2 (w_L + w_U) + 10) 16 n + 2 n      (factors read twice, ten vector passes,
                                                   pivots read twice) per Lanczos step
   B_out  = 16
-plus the band of A (kl + ku + 1) 16 n once per launch, with w_L = kl, w_U = kl + ku + 1 and
-the Lanczos step count of each shift as returned by the kernel.  Duration: HIP events on
+plus, for a shift that switched to shift-and-invert Lanczos, w_U 16 n per factorisation of
+(zI-A)^H (zI-A) - s I and (2 w_U + 8) 16 n per step of it, plus the band of A
+(kl + ku + 1) 16 n once per launch, with w_L = kl, w_U = kl + ku + 1 and the step counts of
+each shift as returned by the kernel (iters and the info word).  Duration: HIP events on
 the stream the kernel runs on.  Peak: 8 TB/s (MI355X HBM3E).
 """
 from __future__ import annotations
@@ -109,12 +111,23 @@ def stored_traffic():
     return doc.get("traffic_bytes_per_launch")
 
 
-def algorithmic_bytes(n, kl, ku, iters):
+def algorithmic_bytes(n, kl, ku, iters, info=None):
+    """Bytes the method must move for one launch: the band once, and per shift the LU, its
+    Golub-Kahan steps and, for shifts that switched to shift-and-invert (info bit 8), each
+    factorisation of (zI-A)^H (zI-A) - s I (the factor written once) and each of its steps
+    (the factor read twice, eight vector passes)."""
     wl, wu = kl, kl + ku + 1
     b_lu = (wl + wu) * 16 * n + n
     b_step = (2 * (wl + wu) + 10) * 16 * n + 2 * n
     iters = np.asarray(iters, dtype=np.float64)
-    return float((kl + ku + 1) * 16 * n + np.sum(b_lu + iters * b_step + 16))
+    total = (kl + ku + 1) * 16 * n + np.sum(b_lu + iters * b_step + 16)
+    if info is not None:
+        info = np.asarray(info, dtype=np.int64)
+        si = (info & 8) != 0
+        nfac = ((info >> 4) & 15)[si].astype(np.float64)
+        ksi = (info >> 8)[si].astype(np.float64)
+        total += np.sum(nfac * wu * 16 * n + ksi * (2 * wu + 8) * 16 * n)
+    return float(total)
 
 
 def _grid_points(grid):
@@ -238,9 +251,11 @@ def main():
     info_full = rf["info"].cpu().numpy()
     cnt_mask = int(rm["count"].item())
     it_mask = rm["iters"][:cnt_mask].cpu().numpy()
-    bytes_full = algorithmic_bytes(band.n, band.kl, band.ku, it_full)
+    info_mask = rm["info"][:cnt_mask].cpu().numpy()
+    bytes_full = algorithmic_bytes(band.n, band.kl, band.ku, it_full, info_full)
     achieved = bytes_full / dur_full / 1e9
-    bytes_mask = algorithmic_bytes(band.n, band.kl, band.ku, it_mask)
+    bytes_mask = algorithmic_bytes(band.n, band.kl, band.ku, it_mask, info_mask)
+    si_full = (info_full & 8) != 0
 
     # plain per-shift GPU path (the speedup denominator): the same numerics and tolerance,
     # one launch per shift, no batching, on a seeded sample of the full grid
@@ -287,6 +302,8 @@ def main():
             "iters_mean_full": float(it_full.mean()), "iters_max_full": int(it_full.max()),
             "iters_mean_mask": float(it_mask.mean()) if cnt_mask else 0.0,
             "maxiter_points_full": int(np.sum((info_full & 2) != 0)),
+            "shift_invert_points_full": int(si_full.sum()),
+            "shift_invert_steps_mean": float((info_full[si_full] >> 8).mean()) if si_full.any() else 0.0,
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded points of the full grid, one launch per shift (same kernel numerics and "

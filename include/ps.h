@@ -62,7 +62,11 @@ enum {
     PS_PT_CONVERGED = 0,
     PS_PT_SINGULAR = 1,   /* the LU met an exactly zero (or negligible) pivot: sigma_min = 0 */
     PS_PT_MAXITER = 2,    /* iteration cap reached: sigma is the best (upper) estimate        */
-    PS_PT_UNDERFLOW = 4   /* sigma_min below the smallest double: reported as 0               */
+    PS_PT_UNDERFLOW = 4,  /* sigma_min below the smallest double: reported as 0               */
+    PS_PT_SHIFT_INVERT = 8 /* sigma came from the shift-and-invert phase; then bits 4..7 of
+                              info hold the number of factorisations of (zI-A)^H (zI-A) - s I
+                              it took (a shift found above sigma_min^2 is lowered and the
+                              factorisation repeated) and bits 8..31 its Lanczos steps      */
 };
 
 /* Flags of ps_create_banded. */
@@ -91,6 +95,11 @@ typedef struct {
     int32_t slots;        /* 0: default                                       */
     int32_t check_shift;  /* Ritz-value checks every max(1, k >> check_shift)
                              Lanczos steps (0: default 5); set by ps_autotune  */
+    int32_t shift_invert; /* 0 (default): a shift whose Lanczos iteration is still
+                             running after 24 steps may switch to shift-and-invert
+                             Lanczos on ((zI-A)^H (zI-A) - s I)^{-1}, s just below
+                             the estimated sigma_min^2 (sigma only, kl + ku <= 4);
+                             -1: never switch                                   */
 } ps_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -136,7 +145,8 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
  *              of the converged Lanczos process (a second pass replays its steps exactly and
  *              accumulates it, so vectors cost about twice the steps of sigma alone) and u
  *              one inverse-iteration step from it, u = (zI - A)^{-H} v / |(zI - A)^{-H} v|.
- *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL.
+ *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL:
+ *              Golub-Kahan (inverse Lanczos) steps; shift-and-invert steps are in info.
  * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
  */
 ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const ps_opts *o, void *ws_dev,

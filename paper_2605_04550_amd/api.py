@@ -29,9 +29,11 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0, check_shift=0):
+def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0, check_shift=0,
+              shift_invert=True):
     return ps_opts_default(tol_norm=tol_norm, tol_rel=tol_rel, max_iter=max_iter,
-                           want_vectors=int(bool(want_vectors)), slots=int(slots), check_shift=int(check_shift))
+                           want_vectors=int(bool(want_vectors)), slots=int(slots), check_shift=int(check_shift),
+                           shift_invert=0 if shift_invert else -1)
 
 
 class BandedMatrix:
@@ -90,13 +92,13 @@ class BandedBatch:
         except Exception:
             pass
 
-    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, device=None, stream=None,
-             workspace: torch.Tensor | None = None):
+    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, shift_invert=True,
+             device=None, stream=None, workspace: torch.Tensor | None = None):
         """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None.  Returns dict with
         the concatenated idx, sigma, info, iters, and counts [nmat]; matrix m owns offsets[m] onward."""
         dev = device or torch.device("cuda")
         nmat = len(self.mats)
-        o = make_opts(tol_norm, tol_rel, max_iter, False, slots)
+        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, shift_invert=shift_invert)
         keep = []
         mptr = 0
         if masks is not None:
@@ -131,14 +133,14 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_norm=1e-10, tol_rel=1e-8,
-              max_iter=3000, slots=0, workspace: torch.Tensor | None = None, stream=None):
+              max_iter=3000, slots=0, shift_invert=True, workspace: torch.Tensor | None = None, stream=None):
     """sigma_min(z_p I - A) for every entry of the complex128 CUDA tensor z.  Returns a dict
     with ``sigma`` (float64), ``info`` and ``iters`` (int32), and ``u``, ``v`` ([npts, n]) if asked."""
     assert z.is_cuda and z.dtype == torch.complex128
     z = z.contiguous()
     npts = z.numel()
     dev = z.device
-    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots)
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, shift_invert=shift_invert)
     out = dict(sigma=torch.empty(npts, dtype=torch.float64, device=dev),
                info=torch.empty(npts, dtype=torch.int32, device=dev),
                iters=torch.empty(npts, dtype=torch.int32, device=dev))
@@ -156,7 +158,7 @@ def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_nor
 
 
 def eval_grid(mat: BandedMatrix, grid, mask: torch.Tensor | None = None, *, eps=None, want_vectors=False,
-              tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, device=None, stream=None,
+              tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, shift_invert=True, device=None, stream=None,
               workspace: torch.Tensor | None = None):
     """sigma_min on the grid (a, b, c, d, nx, ny) of Sec. 2.1, or on the points where ``mask`` (uint8
     [ny, nx] CUDA tensor) is nonzero.  Outputs are compacted: entry p belongs to flat grid index
@@ -164,7 +166,7 @@ def eval_grid(mat: BandedMatrix, grid, mask: torch.Tensor | None = None, *, eps=
     g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
     npts = g.nx * g.ny
     dev = mask.device if mask is not None else (device or torch.device("cuda"))
-    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots)
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, shift_invert=shift_invert)
     out = dict(idx=torch.empty(npts, dtype=torch.int64, device=dev),
                count=torch.zeros(1, dtype=torch.int64, device=dev),
                sigma=torch.empty(npts, dtype=torch.float64, device=dev),

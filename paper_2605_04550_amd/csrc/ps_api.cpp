@@ -18,6 +18,7 @@ struct ps_matrix_s {
     int32_t kl, ku;
     uint32_t flags;
     double fro;
+    double norm2;    // sqrt(||A||_1 ||A||_inf) >= ||A||_2
     double2 *arow;   // device, [n][kl+ku+1]
     int device;
 };
@@ -66,6 +67,7 @@ ps_status check_opts(const ps_opts &o) {
         return fail(PS_ERR_INVALID, "max_iter must be in [1, %d]", ps::kMaxIterCap);
     if (o.slots < 0) return fail(PS_ERR_INVALID, "slots must be >= 0");
     if (o.check_shift < 0 || o.check_shift > 12) return fail(PS_ERR_INVALID, "check_shift must be in [0, 12]");
+    if (o.shift_invert != 0 && o.shift_invert != -1) return fail(PS_ERR_INVALID, "shift_invert must be 0 or -1");
     return PS_OK;
 }
 
@@ -134,6 +136,8 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     a->ku = m->ku;
     a->arow = m->arow;
     a->normA = m->fro;
+    a->norm2A = m->norm2;
+    a->shift_invert = o.shift_invert == 0 ? 1 : 0;
     a->tol_norm = o.tol_norm;
     a->tol_rel = o.tol_rel;
     a->max_iter = o.max_iter;
@@ -158,6 +162,7 @@ void ps_opts_default(ps_opts *o) {
     o->want_vectors = 0;
     o->slots = 0;
     o->check_shift = 0;
+    o->shift_invert = 0;
 }
 
 const char *ps_last_error(void) { return g_err; }
@@ -186,7 +191,8 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
         memcpy(gb.data(), ab, sizeof(ps_c128) * gb.size());
     }
     std::vector<double2> rows((size_t)(n * w));
-    double fro2 = 0.0;
+    std::vector<double> colsum((size_t)n, 0.0);
+    double fro2 = 0.0, rowmax = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t d = 0; d < w; ++d) {
             int64_t j = i - kl + d;
@@ -200,13 +206,23 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
             }
             rows[(size_t)(i * w + d)] = v;
         }
+        double rs = 0.0;
+        for (int64_t d = 0; d < w; ++d) {
+            const double a = hypot(rows[(size_t)(i * w + d)].x, rows[(size_t)(i * w + d)].y);
+            rs += a;
+            if (i - kl + d >= 0 && i - kl + d < n) colsum[(size_t)(i - kl + d)] += a;
+        }
+        rowmax = rs > rowmax ? rs : rowmax;
     }
+    double colmax = 0.0;
+    for (double c : colsum) colmax = c > colmax ? c : colmax;
     ps_matrix m = new ps_matrix_s();
     m->n = n;
     m->kl = kl;
     m->ku = ku;
     m->flags = flags;
     m->fro = sqrt(fro2);
+    m->norm2 = sqrt(rowmax * colmax);
     m->arow = nullptr;
     (void)hipGetDevice(&m->device);
     hipError_t e = hipMalloc((void **)&m->arow, sizeof(double2) * rows.size());
@@ -561,6 +577,7 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         d.arow = a->arow;
         d.n = a->n;
         d.normA = a->fro;
+        d.norm2A = a->norm2;
         d.ga = g.a;
         d.gb = g.b;
         d.gc = g.c;
@@ -688,6 +705,7 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
         a.tol_rel = r.tol_rel;
         a.max_iter = r.max_iter;
         a.check_shift = check_shift_of(r);
+        a.shift_invert = r.shift_invert == 0 ? 1 : 0;
         a.want_vectors = 0;
         a.sigma = sigma_dev;
         a.info = info_dev;

@@ -237,10 +237,20 @@ struct Lane {
     double vnorm2;    // |v|^2 of the accumulated vector (known after its last step)
     double vamax;     // largest |v_i|^2 so far (first index on ties)
     cd vph;           // the entry that attains it
+    // Shift-and-invert phase (sigma only): phase 0 Golub-Kahan, 1 factorise
+    // M^H M - sh I next, 2 Lanczos on (M^H M - sh I)^{-1}.  In phases 1-2, k counts the
+    // shift-and-invert steps, theta / gmax / gopen / nchecks / next_check / rho_prev serve
+    // its Ritz checks, a_m = alpha_{k} and b_m = beta_{k} of its tridiagonal, bp = beta_{k-1}.
+    int phase;
+    int nfac;         // factorisations tried
+    int kgk;          // Golub-Kahan steps taken before the switch
+    double sh;        // the shift, below sigma_min^2
+    double sig_gk;    // the Golub-Kahan estimate of sigma_min at the switch (an upper bound)
     // batch mode: the matrix of the current shift
     int64_t n;
     const double2 *arow;
     double normA;
+    double norm2A;
 };
 
 template <int KL, int KU, bool VEC, bool BATCH>
@@ -254,6 +264,14 @@ struct Kern {
         return BATCH ? ln.arow : a.arow;
     }
     static __device__ __forceinline__ double fro(const EvalArgs &a, const Lane &ln) { return BATCH ? ln.normA : a.normA; }
+    static __device__ __forceinline__ double nrm2(const EvalArgs &a, const Lane &ln) {
+        return BATCH ? ln.norm2A : a.norm2A;
+    }
+
+    // Shift-and-invert is compiled for sigma-only kernels with kl + ku >= 1 (the
+    // half-bandwidth of M^H M); a lane uses it only while it is in phase 1 or 2.
+    static constexpr bool SI = !VEC && (KL + KU) >= 1;
+    static __device__ __forceinline__ bool gk(const Lane &ln) { return !SI || ln.phase == 0; }
 
     // M[r][c] of M = zI - A from the row band (zero outside the matrix).
     static __device__ __forceinline__ cd mentry(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
@@ -291,7 +309,7 @@ struct Kern {
         cd Wm[KL + 1][W];
         int R = 0;
         double nrm_h = 0.0;
-        const bool act = ln.active, fresh = ln.fresh;
+        const bool act = ln.active && gk(ln), fresh = ln.fresh;
         const bool lu = fresh && (!VEC || ln.stage == 0);   // a replay keeps the factors it has
         const double tiny = 0x1p-1000 * fmax(1.0, fro(a, ln) + cabs1(ln.z));
         bool sing = false;
@@ -472,7 +490,7 @@ struct Kern {
     static __device__ void b1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
                               int &eacc_out) {
         const int64_t n = nn(a, ln), T = w.slots;
-        const bool act = ln.active && !ln.sing;
+        const bool act = ln.active && gk(ln) && !ln.sing;
         const bool sub = !ln.fresh;
         int R = ln.Ey;
         cd xw[W];
@@ -588,7 +606,7 @@ struct Kern {
     // with the accumulated vector itself (plain doubles, exponent 0) instead of u_k.
     static __device__ void f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
         const int64_t n = nn(a, ln), T = w.slots;
-        const bool act = ln.active;
+        const bool act = ln.active && gk(ln);
         const bool fin = VEC && ln.stage == 2;
         const bool rep = VEC && ln.stage == 1;
         const double2 *uin = fin ? w.vacc : w.vu;
@@ -720,7 +738,7 @@ struct Kern {
     static __device__ void b2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double &acc_out,
                               int &eacc_out) {
         const int64_t n = nn(a, ln), T = w.slots;
-        const bool act = ln.active;
+        const bool act = ln.active && gk(ln);
         int R = ln.Ey;
         cd b[KL + 1];
 #pragma unroll
@@ -855,6 +873,274 @@ struct Kern {
         }
         acc_out = acc;
         eacc_out = Eacc;
+    }
+
+    // ---------------------------------------------------------------- shift-and-invert phase
+    // Far from the spectrum the smallest singular values of M = zI - A cluster (relative gaps
+    // of 1e-5 and below), and the Lanczos process on (M^H M)^{-1} needs up to ~n/2 steps.
+    // Once the Golub-Kahan Ritz value gives sigma_est >= sigma_min with a few correct digits,
+    // such a lane switches to Lanczos on (H - sh I)^{-1}, H = M^H M, sh = sigma_est^2 (1 - delta)
+    // below sigma_min^2: the top eigenvalue mu = 1 / (sigma_min^2 - sh) stands out ~1/delta
+    // times further relative to the rest of the spectrum, and sigma_min^2 = sh + 1/mu needs mu
+    // only to a relative accuracy ~tol/delta.  H - sh I is positive definite exactly when
+    // sh < sigma_min^2: its banded Cholesky factor (half-bandwidth kl + ku) completes or meets a
+    // non-positive pivot, and then delta grows (2e-3, 1.6e-2, 0.128, then sh = 0) and the
+    // factorisation is repeated.  H is formed from the band inside the factorisation pass; its
+    // rounding (|dH| ~ eps |M|^2) moves sigma by ~eps |M|^2 / sigma, so a lane switches only
+    // where that is far below the tolerance.  With sigma_min bounded away from zero nothing
+    // overflows, so this phase keeps plain doubles (no block exponents).
+    static constexpr int kSiStart = 24;      // Golub-Kahan steps before a lane may switch
+    static constexpr int kSiMaxFac = 4;
+    static constexpr int HB = KL + KU;       // half-bandwidth of H
+    static __device__ __forceinline__ double si_delta(int nfac) {
+        return nfac == 0 ? 2e-3 : nfac == 1 ? 1.6e-2 : nfac == 2 ? 0.128 : 1.0;
+    }
+
+    // M[r][c] (zero outside the matrix, including r < 0).
+    static __device__ __forceinline__ cd si_m(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
+        if (r < 0 || c < 0) return czero();
+        return mentry(a, ln, r, c);
+    }
+
+    // Factorisation pass: H - sh I = L L^H with F[i][0] = 1 / L_ii (real) and F[i][e] = L[i][i-e]
+    // (e = 1..HB) stored in the U array; rows past n are identity rows.  The entries of the
+    // previous rows that row i needs are read back from the rows just written.  Returns
+    // false when a pivot is not positive (sh is not below sigma_min^2).
+    static __device__ bool si_factor(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        const double sh = ln.sh;
+        bool ok = true;
+        for (int64_t i = 0; i < npad; ++i) {
+            cd li[HB + 1];
+#pragma unroll
+            for (int e = 0; e <= HB; ++e) li[e] = czero();
+            double lii = 1.0;
+            if (i < n) {
+                // H[i][i-e] = sum_r conj(M[r][i]) M[r][i-e] over r in [i - ku, i - e + kl]
+                cd h[HB + 1];
+#pragma unroll
+                for (int e = 0; e <= HB; ++e) {
+                    double hx = 0.0, hy = 0.0;
+#pragma unroll
+                    for (int t = 0; t <= HB - e; ++t) {
+                        const int64_t r = i - KU + t;
+                        const cd mi = si_m(a, ln, r, i), mj = si_m(a, ln, r, i - e);
+                        hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
+                        hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
+                    }
+                    h[e] = C(hx, hy);
+                }
+                double dsq = h[0].x - sh;
+#pragma unroll
+                for (int e = HB; e >= 1; --e) {
+                    // L[i][j], j = i - e: (H[i][j] - sum_{m < j} L[i][m] conj(L[j][m])) / L[j][j]
+                    const int64_t j = i - e;
+                    if (j < 0) continue;
+                    cd acc = h[e];
+#pragma unroll
+                    for (int e2 = HB; e2 > e; --e2)
+                        acc = cfnmac(w.U[(j * W + (e2 - e)) * T + s], li[e2], acc);   // L[j][i-e2]
+                    li[e] = cscale(acc, w.U[(j * W + 0) * T + s].x);                  // times 1 / L[j][j]
+                    dsq -= cabs2(li[e]);
+                }
+                if (!(dsq > 0.0)) {
+                    ok = false;
+                    dsq = 1.0;        // keep going with finite numbers; the factor is discarded
+                }
+                lii = sqrt(dsq);
+            }
+            w.U[(i * W + 0) * T + s] = C(1.0 / lii, 0.0);
+#pragma unroll
+            for (int e = 1; e <= HB; ++e) w.U[(i * W + e) * T + s] = li[e];
+        }
+        return ok;
+    }
+
+    // Forward pass of step k = ln.k + 1: r_k = Z - (alpha_{k-1} / beta_{k-1}) X with Z = w' of
+    // the previous step and X = r_{k-1}; r_k is stored over Z, y = L^{-1} r_k into vy.  Returns
+    // |r_k|^2.  The two vectors alternate between vu and vv with the parity of k.  Step 1 starts
+    // from the shift's random start vector h / |h| again: the last Golub-Kahan vector would be
+    // a poor start, being orthogonal to the Krylov space that holds the best approximation of
+    // the wanted singular vector.
+    static __device__ double si_fwd(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        const int k = ln.k + 1;
+        double2 *Z = (k & 1) ? w.vv : w.vu;
+        const double2 *X = (k & 1) ? w.vu : w.vv;
+        const bool first = k == 1;
+        const double cx = first ? 0.0 : ln.a_m / ln.b_m;
+        cd yw[HB + 1];             // yw[d] = y_{i-d}
+#pragma unroll
+        for (int d = 0; d <= HB; ++d) yw[d] = czero();
+        double nr = 0.0;
+        for (int64_t q = 0; q < npad / CH; ++q) {
+            const int64_t i0 = q * CH;
+            cd Fr[CH][W], zr[CH], xr[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 + c;
+#pragma unroll
+                for (int d = 0; d < W; ++d) Fr[c][d] = w.U[(i * W + d) * T + s];
+                zr[c] = Z[i * T + s];
+                xr[c] = X[i * T + s];
+                if (first) zr[c] = i < n ? start_entry(a.seed, i) : czero();
+            }
+            const double fz = first ? 1.0 / sqrt(ln.nrm_h) : 1.0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const cd r = C(fma(-cx, xr[c].x, fz * zr[c].x), fma(-cx, xr[c].y, fz * zr[c].y));
+                cd acc = r;
+#pragma unroll
+                for (int d = 1; d <= HB; ++d) acc = cfnma(Fr[c][d], yw[d], acc);
+                const cd y = cscale(acc, Fr[c][0].x);
+                Z[(i0 + c) * T + s] = r;
+                w.vy[(i0 + c) * T + s] = y;
+                nr = fma(r.x, r.x, fma(r.y, r.y, nr));
+#pragma unroll
+                for (int d = HB; d >= 2; --d) yw[d] = yw[d - 1];
+                yw[1] = y;
+            }
+        }
+        return nr;
+    }
+
+    // Backward pass of step k = ln.k: x = L^{-H} y (= beta_k (H - sh I)^{-1} q_k), and
+    // w' = x / beta_k - (beta_k / beta_{k-1}) r_{k-1} stored over X.  Returns Re(r_k^H x)
+    // = alpha_k beta_k^2.
+    static __device__ double si_bwd(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        const int k = ln.k;
+        const double2 *Z = (k & 1) ? w.vv : w.vu;    // r_k
+        double2 *X = (k & 1) ? w.vu : w.vv;          // r_{k-1}, then w'
+        const double ib = 1.0 / ln.b_m;
+        const double cx = k == 1 ? 0.0 : ln.b_m / ln.bp;
+        cd P[HB + 1];              // P[t]: sum of conj(L[j][i-t]) x_j over the rows j > i done so far
+#pragma unroll
+        for (int t = 0; t <= HB; ++t) P[t] = czero();
+        double al = 0.0;
+        for (int64_t q = npad / CH - 1; q >= 0; --q) {
+            const int64_t i0 = q * CH + CH - 1;
+            cd Fr[CH][W], yr[CH], zr[CH], xr[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t i = i0 - c;
+#pragma unroll
+                for (int d = 0; d < W; ++d) Fr[c][d] = w.U[(i * W + d) * T + s];
+                yr[c] = w.vy[i * T + s];
+                zr[c] = Z[i * T + s];
+                xr[c] = X[i * T + s];
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const cd x = cscale(C(yr[c].x - P[0].x, yr[c].y - P[0].y), Fr[c][0].x);
+#pragma unroll
+                for (int t = 0; t < HB; ++t) {
+                    const cd f = Fr[c][t + 1];        // L[i][i-t-1]
+                    const cd base = t + 1 < HB ? P[t + 1] : czero();
+                    P[t] = C(base.x + f.x * x.x + f.y * x.y, base.y + f.x * x.y - f.y * x.x);
+                }
+                X[(i0 - c) * T + s] = C(fma(-cx, xr[c].x, x.x * ib), fma(-cx, xr[c].y, x.y * ib));
+                al = fma(zr[c].x, x.x, fma(zr[c].y, x.y, al));
+            }
+        }
+        return al;
+    }
+
+    // Ritz check of the shift-and-invert tridiagonal T_k (alpha_1..alpha_k, beta_2..beta_k)
+    // with the next beta known: mu is within r = beta_{k+1} |y_k| of theta, and
+    // sigma^2 = sh + 1/mu moves by at most r / theta^2, sigma by r / (2 sigma theta^2).
+    // That bound holds for the eigenvalue nearest theta.  When sigma_min has a neighbour
+    // within ~1e-7 (relative), a Ritz vector mixing the two still has a small residual
+    // (|r| ~ |c1 c2| (mu_1 - mu_2)) while theta sits nearer mu_2; so the residual must also
+    // fall below 2^-30 theta, small enough that the pair has separated, before a shift
+    // counts as converged.  These steps are cheap: the residual falls geometrically.  As in
+    // the Golub-Kahan phase, theta unchanged to 2^-44 over two checks also ends the phase
+    // (after convergence the residual estimate can stall once Ritz values repeat).
+    static __device__ bool si_check(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, int k,
+                                    double beta_next) {
+        TopEig te = top_eig(w.hist, w.slots, s, k, ln.theta, fmax(ln.gmax, ln.gopen));
+        const double th = te.theta;
+        if (!(th > 0.0)) return false;
+        const double sig = sqrt(ln.sh + 1.0 / th);
+        const double r = beta_next * sqrt(te.yk2);
+        const double target = a.tol_norm * fro(a, ln) + a.tol_rel * sig;
+        const double delta = fmax(th - ln.theta, 0.0);
+        const bool flat = ln.nchecks >= 1 && delta <= 0x1p-44 * th;
+        const bool flat_prev = ln.rho_prev > 0.0;
+        ln.rho_prev = flat ? 1.0 : 0.0;
+        ln.theta = th;
+        ln.nchecks += 1;
+        const bool sep = r <= 0x1p-30 * th;
+        return (r <= 2.0 * sig * th * th * target && sep) || (flat && flat_prev);
+    }
+
+    // One cycle of a lane in the shift-and-invert phase: the factorisation (phase 1), or one
+    // Lanczos step (phase 2).  Finishes the shift when converged.
+    static __device__ void si_cycle(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        const int64_t T = w.slots;
+        if (ln.phase == 1) {
+            const bool ok = si_factor(a, w, s, ln);
+            ln.nfac += 1;
+            if (ok) {
+                ln.phase = 2;
+                ln.k = 0;
+                ln.theta = 0.0;
+                ln.gmax = ln.gopen = 0.0;
+                ln.nchecks = 0;
+                ln.next_check = 1;
+                ln.rho_prev = 0.0;
+                ln.a_m = 0.0;
+                ln.b_m = 1.0;
+                ln.bp = 1.0;
+            } else if (ln.nfac < kSiMaxFac) {
+                ln.sh = ln.sig_gk * ln.sig_gk * (1.0 - si_delta(ln.nfac));
+            } else {
+                // M^H M is not numerically positive definite: report the Golub-Kahan estimate
+                ln.k = 0;
+                finish_si(a, ln, ln.sig_gk, 2);
+            }
+            return;
+        }
+        const int kn = ln.k + 1;                       // step whose vector is formed now
+        const double beta = sqrt(si_fwd(a, w, s, ln));
+        if (kn >= 2) {
+            w.hist[((int64_t)(kn - 2) * 2 + 1) * T + s] = beta * beta;
+            const int k = kn - 1;                      // T_k is complete
+            const bool cap = kn >= a.max_iter;
+            if (!(beta > 0.0) || k >= ln.next_check || cap) {
+                const bool conv = si_check(a, w, s, ln, k, beta) || !(beta > 0.0);
+                const int step = k >> 3;
+                ln.next_check = k + (step > 1 ? step : 1);
+                if (conv || cap) {
+                    // theta > 0 for the positive definite (H - sh I)^{-1}; otherwise keep the
+                    // Golub-Kahan bound
+                    const bool good = ln.theta > 0.0;
+                    finish_si(a, ln, good ? sqrt(ln.sh + 1.0 / ln.theta) : ln.sig_gk, conv && good ? 0 : 2);
+                    return;
+                }
+            }
+            ln.gmax = fmax(ln.gmax, ln.gopen + beta);
+        }
+        ln.bp = ln.b_m;
+        ln.b_m = beta;
+        ln.k = kn;
+        const double al = si_bwd(a, w, s, ln) / (beta * beta);
+        w.hist[((int64_t)(kn - 1) * 2 + 0) * T + s] = al;
+        ln.a_m = al;
+        ln.gopen = fabs(al) + (kn >= 2 ? beta : 0.0);
+    }
+
+    static __device__ void finish_si(const EvalArgs &a, Lane &ln, double sigma, int flags) {
+        flags |= PS_PT_SHIFT_INVERT | ((ln.nfac < 15 ? ln.nfac : 15) << 4) | (ln.k << 8);
+        a.sigma[ln.pid] = sigma;
+        if (a.info) a.info[ln.pid] = flags;
+        if (a.iters) a.iters[ln.pid] = ln.kgk;
+        if (a.sens) a.sens[ln.pid] = (uint8_t)(sigma <= a.eps);
+        ln.active = false;
+        ln.phase = 0;
     }
 
     // ---------------------------------------------------------------- singular vectors
@@ -1092,6 +1378,21 @@ struct Kern {
                 finish(a, w, s, ln, 0);
                 return;
             }
+            if (SI && a.shift_invert && ln.k >= kSiStart && ln.k < kcap) {
+                // switch to shift-and-invert where the rounding of M^H M (about
+                // 32 eps |M|^2 / sigma in sigma) stays below an eighth of the target
+                const double sig = ldexp(1.0 / sqrt(te.theta), -ln.E0);   // >= sigma_min
+                const double mn = hypot(ln.z.x, ln.z.y) + nrm2(a, ln);
+                const double target = a.tol_norm * fro(a, ln) + a.tol_rel * sig;
+                if (mn < 1e100 && sig < 1e100 && 32.0 * 0x1p-52 * mn * mn <= 0.125 * sig * target) {
+                    ln.phase = 1;
+                    ln.nfac = 0;
+                    ln.kgk = ln.k;
+                    ln.sig_gk = sig;
+                    ln.sh = sig * sig * (1.0 - si_delta(0));
+                    return;
+                }
+            }
         }
         if (ln.k >= kcap) {
             if (!checked) {
@@ -1165,6 +1466,12 @@ struct Kern {
         ln.n = a.n;
         ln.arow = a.arow;
         ln.normA = a.normA;
+        ln.norm2A = a.norm2A;
+        ln.phase = 0;
+        ln.nfac = 0;
+        ln.kgk = 0;
+        ln.sh = 0.0;
+        ln.sig_gk = 0.0;
         while (true) {
             bool may_refill = !ln.active && !ln.exhausted;
             if (may_refill) {
@@ -1176,6 +1483,7 @@ struct Kern {
                     ln.active = true;
                     ln.fresh = true;
                     ln.stage = 0;
+                    ln.phase = 0;
                     ln.sing = false;
                     ln.k = 0;
                     ln.b_m = 0.0;
@@ -1193,6 +1501,7 @@ struct Kern {
                         ln.n = d.n;
                         ln.arow = d.arow;
                         ln.normA = d.normA;
+                        ln.norm2A = d.norm2A;
                         ln.pid = d.out_off + q;
                         const int64_t flat = a.idx[ln.pid];
                         const int64_t gi = flat / d.nx, gj = flat - gi * d.nx;
@@ -1217,13 +1526,21 @@ struct Kern {
             double acc;
             int eacc;
             if (!VEC) {
-                f1(a, w, s, ln);
-                if (ln.active && ln.sing) finish(a, w, s, ln, 0);
-                b1(a, w, s, ln, acc, eacc);
-                if (ln.active) after_b1(a, w, s, ln, acc, eacc);
-                f2(a, w, s, ln);
-                b2(a, w, s, ln, acc, eacc);
-                if (ln.active) after_b2(a, w, s, ln, acc, eacc, kcap);
+                // Golub-Kahan lanes take the four sweeps; lanes in the shift-and-invert phase
+                // take one factorisation or step per cycle.  Each part runs only if a lane of
+                // the wavefront needs it.
+                if (__any(ln.active && gk(ln))) {
+                    f1(a, w, s, ln);
+                    if (ln.active && gk(ln) && ln.sing) finish(a, w, s, ln, 0);
+                    b1(a, w, s, ln, acc, eacc);
+                    if (ln.active && gk(ln)) after_b1(a, w, s, ln, acc, eacc);
+                    f2(a, w, s, ln);
+                    b2(a, w, s, ln, acc, eacc);
+                    if (ln.active && gk(ln)) after_b2(a, w, s, ln, acc, eacc, kcap);
+                }
+                if (SI && __any(ln.active && !gk(ln))) {
+                    if (ln.active && !gk(ln)) si_cycle(a, w, s, ln);
+                }
                 continue;
             }
             // With vectors a cycle serves lanes in all three stages; lanes sit out the sweeps

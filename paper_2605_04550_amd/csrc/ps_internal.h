@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ps.h"
+
 namespace ps {
 
 // Maximum supported bandwidths of the compiled kernels.
@@ -57,6 +59,7 @@ struct MatDesc {
     const double2 *arow;
     int64_t n;
     double normA;
+    double norm2A;    // upper bound on ||A||_2
     double ga, gb, gc, gd;
     int64_t nx, ny;
     int64_t out_off;
@@ -69,7 +72,9 @@ struct EvalArgs {
     int64_t n = 0;
     int kl = 0, ku = 0;
     const double2 *arow = nullptr; // [n][kl+ku+1] row band, zero outside the matrix
-    double normA = 0.0;
+    double normA = 0.0;            // ||A||_F
+    double norm2A = 0.0;           // upper bound on ||A||_2 (sqrt(||A||_1 ||A||_inf))
+    int shift_invert = 1;          // 1: slow shifts may switch to shift-and-invert Lanczos
     int mode = kShiftList;
     const double2 *z = nullptr;
     const int64_t *idx = nullptr;
