@@ -98,8 +98,9 @@ typedef struct {
     int32_t shift_invert; /* 0 (default): a shift whose Lanczos iteration is still
                              running after 24 steps may switch to shift-and-invert
                              Lanczos on ((zI-A)^H (zI-A) - s I)^{-1}, s just below
-                             the estimated sigma_min^2 (sigma only, kl + ku <= 4);
-                             -1: never switch                                   */
+                             the estimated sigma_min^2 (sigma only, kl + ku >= 1);
+                             k in 4..512: switch after k steps instead of 24;
+                             -1: never switch; set by ps_autotune              */
 } ps_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -266,10 +267,12 @@ ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps
 
 /*
  * ps_autotune -- choose the plan for ps_eval_points / ps_eval_grid on this matrix: the number
- * of slots (shifts in flight) and the Ritz-check schedule.  Times each candidate on
+ * of slots (shifts in flight), the Ritz-check schedule and the step at which slow shifts
+ * switch to shift-and-invert (left off if o->shift_invert is -1).  Times each candidate on
  * z_dev[0 .. npts) (a representative sample of the shifts to be evaluated, on the device)
- * with HIP events and writes the fastest into o->slots and o->check_shift.  Synchronous;
- * allocates and frees its own workspace.  Results of the timed runs are discarded.
+ * with HIP events and writes the fastest into o->slots, o->check_shift and o->shift_invert.
+ * Synchronous; allocates and frees its own workspace.  Results of the timed runs are
+ * discarded.
  * Errors: PS_ERR_INVALID, PS_ERR_HIP.
  */
 ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *o, void *stream);

@@ -33,7 +33,8 @@ def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, s
               shift_invert=True):
     return ps_opts_default(tol_norm=tol_norm, tol_rel=tol_rel, max_iter=max_iter,
                            want_vectors=int(bool(want_vectors)), slots=int(slots), check_shift=int(check_shift),
-                           shift_invert=0 if shift_invert else -1)
+                           shift_invert=(0 if shift_invert is True else -1 if shift_invert is False
+                                         else int(shift_invert)))
 
 
 class BandedMatrix:
@@ -262,7 +263,7 @@ def contour_seeds(grid, sigma: torch.Tensor, eps: float, max_seeds: int | None =
 
 
 def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):
-    """ps_autotune on the shifts z: returns the options (slots, check_shift) that ran fastest."""
+    """ps_autotune on the shifts z: returns the options (slots, check_shift, shift_invert) that ran fastest."""
     o = make_opts(**kw)
     ps_autotune(mat.handle, z.contiguous().data_ptr(), z.numel(), o, _stream_handle())
     return o

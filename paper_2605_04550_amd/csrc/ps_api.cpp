@@ -67,11 +67,15 @@ ps_status check_opts(const ps_opts &o) {
         return fail(PS_ERR_INVALID, "max_iter must be in [1, %d]", ps::kMaxIterCap);
     if (o.slots < 0) return fail(PS_ERR_INVALID, "slots must be >= 0");
     if (o.check_shift < 0 || o.check_shift > 12) return fail(PS_ERR_INVALID, "check_shift must be in [0, 12]");
-    if (o.shift_invert != 0 && o.shift_invert != -1) return fail(PS_ERR_INVALID, "shift_invert must be 0 or -1");
+    if (o.shift_invert != 0 && o.shift_invert != -1 && (o.shift_invert < 4 || o.shift_invert > 512))
+        return fail(PS_ERR_INVALID, "shift_invert must be 0, -1 or in [4, 512]");
     return PS_OK;
 }
 
 int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
+
+// Golub-Kahan steps before a slow shift may switch to shift-and-invert (0: never).
+int si_start_of(const ps_opts &o) { return o.shift_invert < 0 ? 0 : o.shift_invert > 0 ? o.shift_invert : 24; }
 
 int vec_of(const ps_opts &o) { return o.want_vectors ? 1 : 0; }
 
@@ -137,7 +141,7 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     a->arow = m->arow;
     a->normA = m->fro;
     a->norm2A = m->norm2;
-    a->shift_invert = o.shift_invert == 0 ? 1 : 0;
+    a->si_start = si_start_of(o);
     a->tol_norm = o.tol_norm;
     a->tol_rel = o.tol_rel;
     a->max_iter = o.max_iter;
@@ -509,6 +513,10 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     for (int64_t sl = s0; sl >= kSlotQuantum && slot_cands.size() < 3; sl = round_slots(sl / 2))
         slot_cands.push_back(sl);
     const int shift_cands[3] = {3, 4, 5};
+    // switch points of the shift-and-invert phase (unless the caller turned it off)
+    const int si_cands[3] = {base.shift_invert < 0 ? -1 : 12, base.shift_invert < 0 ? -1 : 24,
+                             base.shift_invert < 0 ? -1 : 48};
+    const int n_si = base.shift_invert < 0 ? 1 : 3;
     size_t wsb = 0;
     if ((st = ps_workspace_size(m, npts, &base, &wsb))) return st;
     void *ws = nullptr;
@@ -521,10 +529,11 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     float best = INFINITY;
     ps_opts pick = base;
     for (size_t i = 0; e == hipSuccess && i < slot_cands.size(); ++i) {
-        for (int c = 0; e == hipSuccess && c < 3; ++c) {
+        for (int c = 0; e == hipSuccess && c < 3 * n_si; ++c) {
             ps_opts t = base;
             t.slots = (int32_t)slot_cands[i];
-            t.check_shift = shift_cands[c];
+            t.check_shift = shift_cands[c % 3];
+            t.shift_invert = si_cands[c / 3];
             t.want_vectors = 0;
             if ((st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr, nullptr, stream)))
                 break;
@@ -551,6 +560,7 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     if (e != hipSuccess) return fail(PS_ERR_HIP, "autotune: %s", hipGetErrorString(e));
     o->slots = pick.slots;
     o->check_shift = pick.check_shift;
+    o->shift_invert = pick.shift_invert;
     return ok();
 }
 
@@ -705,7 +715,7 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
         a.tol_rel = r.tol_rel;
         a.max_iter = r.max_iter;
         a.check_shift = check_shift_of(r);
-        a.shift_invert = r.shift_invert == 0 ? 1 : 0;
+        a.si_start = si_start_of(r);
         a.want_vectors = 0;
         a.sigma = sigma_dev;
         a.info = info_dev;

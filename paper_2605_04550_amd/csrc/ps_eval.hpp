@@ -878,8 +878,8 @@ struct Kern {
     // ---------------------------------------------------------------- shift-and-invert phase
     // Far from the spectrum the smallest singular values of M = zI - A cluster (relative gaps
     // of 1e-5 and below), and the Lanczos process on (M^H M)^{-1} needs up to ~n/2 steps.
-    // Once the Golub-Kahan Ritz value gives sigma_est >= sigma_min with a few correct digits,
-    // such a lane switches to Lanczos on (H - sh I)^{-1}, H = M^H M, sh = sigma_est^2 (1 - delta)
+    // Once the Golub-Kahan Ritz value gives sigma_est >= sigma_min with a few correct digits
+    // (after EvalArgs::si_start steps, 24 by default), such a lane switches to Lanczos on (H - sh I)^{-1}, H = M^H M, sh = sigma_est^2 (1 - delta)
     // below sigma_min^2: the top eigenvalue mu = 1 / (sigma_min^2 - sh) stands out ~1/delta
     // times further relative to the rest of the spectrum, and sigma_min^2 = sh + 1/mu needs mu
     // only to a relative accuracy ~tol/delta.  H - sh I is positive definite exactly when
@@ -889,7 +889,6 @@ struct Kern {
     // rounding (|dH| ~ eps |M|^2) moves sigma by ~eps |M|^2 / sigma, so a lane switches only
     // where that is far below the tolerance.  With sigma_min bounded away from zero nothing
     // overflows, so this phase keeps plain doubles (no block exponents).
-    static constexpr int kSiStart = 24;      // Golub-Kahan steps before a lane may switch
     static constexpr int kSiMaxFac = 4;
     static constexpr int HB = KL + KU;       // half-bandwidth of H
     static __device__ __forceinline__ double si_delta(int nfac) {
@@ -1378,7 +1377,7 @@ struct Kern {
                 finish(a, w, s, ln, 0);
                 return;
             }
-            if (SI && a.shift_invert && ln.k >= kSiStart && ln.k < kcap) {
+            if (SI && a.si_start > 0 && ln.k >= a.si_start && ln.k < kcap) {
                 // switch to shift-and-invert where the rounding of M^H M (about
                 // 32 eps |M|^2 / sigma in sigma) stays below an eighth of the target
                 const double sig = ldexp(1.0 / sqrt(te.theta), -ln.E0);   // >= sigma_min
