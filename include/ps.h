@@ -261,6 +261,29 @@ ps_status ps_newton_contour(ps_matrix m, ps_c128 *z_dev, int64_t npts, double ep
  *   ws_dev / ws_bytes >= ps_contour_seeds_workspace_size(g).
  * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP.
  */
+/*
+ * ps_label_grid -- the sensitive zone S_eps of Sec. 2.1 (eq. sensitive_zone: z in S_eps iff
+ * sigma_min(zI - A) <= eps) on the whole grid g, exactly, evaluating sigma_min only where the
+ * answer is not already implied (the exclusion-region labelling the paper uses to generate
+ * its training labels, Sec. 1 and Sec. 3.2).  sigma_min is 1-Lipschitz in z, so a computed
+ * sigma(z0) > eps excludes every grid point closer to z0 than sigma(z0) - eps - margin
+ * (margin = twice the evaluation tolerance tol_norm ||A||_F + tol_rel sigma(z0)).  The still
+ * unknown points of the lattices of stride 8, 4, 2 and 1 (coarser strides are skipped on
+ * small grids) are evaluated in turn, each level followed by the exclusion disks of its
+ * points.  All steps run on the stream without host synchronisation.
+ *   label_dev  device uint8[ny][nx] (required): 1 where sigma_min <= eps, else 0.
+ *   sigma_dev  device double[ny][nx] or NULL: sigma_min where it was evaluated, -1 where the
+ *              point was excluded.
+ *   evals_dev  device int64[1] or NULL: the number of shifts evaluated.
+ *   eps > 0, finite.  o: options of the evaluations (vectors are not allowed).
+ *   ws_dev / ws_bytes >= ps_label_workspace_size(m, g, o).
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_UNSUPPORTED (vectors),
+ * PS_ERR_HIP.
+ */
+ps_status ps_label_workspace_size(ps_matrix m, const ps_grid *g, const ps_opts *o, size_t *bytes);
+ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts *o, void *ws_dev, size_t ws_bytes,
+                        uint8_t *label_dev, double *sigma_dev, int64_t *evals_dev, void *stream);
+
 ps_status ps_contour_seeds_workspace_size(const ps_grid *g, size_t *bytes);
 ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps, ps_c128 *seeds_dev,
                            int64_t max_seeds, int64_t *count_dev, void *ws_dev, size_t ws_bytes, void *stream);

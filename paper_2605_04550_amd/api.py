@@ -19,7 +19,7 @@ from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_w
                ps_batch_workspace_size, ps_create_banded, ps_create_batch, ps_destroy, ps_destroy_batch,
                ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
                ps_newton_workspace_size, ps_opts_default, ps_workspace_size, ps_contour_seeds,
-               ps_contour_seeds_workspace_size)
+               ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
 
@@ -260,6 +260,23 @@ def contour_seeds(grid, sigma: torch.Tensor, eps: float, max_seeds: int | None =
                      ws.data_ptr(), ws.numel(), _stream_handle(stream))
     c = int(count.item())
     return seeds[:min(c, int(max_seeds))], c
+
+
+def label_grid(mat: BandedMatrix, grid, eps: float, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0,
+               shift_invert=True, device=None, stream=None):
+    """ps_label_grid: the sensitive zone S_eps on the whole grid (label 1 iff sigma_min <= eps),
+    evaluating sigma_min only outside the exclusion disks of points already evaluated.
+    Returns dict(label [ny, nx] uint8, sigma [ny, nx] float64 (-1 where excluded), evals)."""
+    g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
+    dev = device or torch.device("cuda")
+    o = make_opts(tol_norm, tol_rel, max_iter, False, slots, shift_invert=shift_invert)
+    label = torch.empty((g.ny, g.nx), dtype=torch.uint8, device=dev)
+    sigma = torch.empty((g.ny, g.nx), dtype=torch.float64, device=dev)
+    evals = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = _workspace(ps_label_workspace_size(mat.handle, g, o), dev)
+    ps_label_grid(mat.handle, g, eps, o, ws.data_ptr(), ws.numel(), label.data_ptr(), sigma.data_ptr(),
+                  evals.data_ptr(), _stream_handle(stream))
+    return dict(label=label, sigma=sigma, evals=evals)
 
 
 def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):

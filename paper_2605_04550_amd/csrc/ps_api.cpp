@@ -417,6 +417,80 @@ size_t batch_scratch_bytes(const ps_batch_s *b) {
 
 extern "C" {
 
+// Label workspace: the evaluation workspace for every grid point, then status and mask bytes,
+// compacted indices, compacted sigma and the evaluation counter.
+static size_t label_aux_bytes(int64_t npts) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 2 * al((size_t)npts) + 2 * al(sizeof(int64_t) * (size_t)npts) + 256;
+}
+
+ps_status ps_label_workspace_size(ps_matrix m, const ps_grid *g, const ps_opts *o, size_t *bytes) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if ((st = check_grid(g))) return st;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    ps_opts r = resolve(o);
+    if ((st = check_opts(r))) return st;
+    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "labelling does not produce vectors");
+    const int64_t npts = g->nx * g->ny;
+    size_t ev = 0;
+    if ((st = ps_workspace_size(m, npts, &r, &ev))) return st;
+    *bytes = ((ev + 255) & ~(size_t)255) + label_aux_bytes(npts);
+    return ok();
+}
+
+ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts *o, void *ws_dev, size_t ws_bytes,
+                        uint8_t *label_dev, double *sigma_dev, int64_t *evals_dev, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if ((st = check_grid(g))) return st;
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite and > 0");
+    if (!label_dev) return fail(PS_ERR_INVALID, "label output is NULL");
+    ps_opts r = resolve(o);
+    if ((st = check_opts(r))) return st;
+    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "labelling does not produce vectors");
+    size_t need = 0;
+    ps_label_workspace_size(m, g, &r, &need);
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "label workspace needs %zu bytes", need);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const int64_t npts = g->nx * g->ny;
+    const size_t evb = ((need - label_aux_bytes(npts)) + 255) & ~(size_t)255;
+    char *aux = (char *)ws_dev + evb;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    uint8_t *status = (uint8_t *)aux;
+    uint8_t *mask = status + al((size_t)npts);
+    int64_t *idx = (int64_t *)(mask + al((size_t)npts));
+    double *sig_c = (double *)((char *)idx + al(sizeof(int64_t) * (size_t)npts));
+    int64_t *evals = (int64_t *)((char *)sig_c + al(sizeof(double) * (size_t)npts));
+    if (evals_dev) evals = evals_dev;
+    ps::Workspace w;
+    ps::EvalArgs a;
+    if ((st = prepare_eval(m, npts, r, ws_dev, evb, sig_c, nullptr, nullptr, &w, &a))) return st;
+    a.mode = ps::kShiftGrid;
+    a.ga = g->a;
+    a.gb = g->b;
+    a.gc = g->c;
+    a.gd = g->d;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.idx = idx;
+    a.count_dev = w.count;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ps::launch_label_init(status, sigma_dev, npts, evals, s));
+    int stride = 1;
+    while (stride < 8 && (g->nx >= 24 * stride || g->ny >= 24 * stride)) stride *= 2;
+    for (; stride >= 1; stride /= 2) {
+        const int64_t lattice = ((g->ny + stride - 1) / stride) * ((g->nx + stride - 1) / stride);
+        HIP_TRY(ps::launch_label_mask(status, g->nx, npts, stride, mask, s));
+        HIP_TRY(ps::launch_compact_mask(mask, npts, idx, w.count, w.blocksums, w.queue, s));
+        HIP_TRY(ps::launch_eval(a, w, s));
+        HIP_TRY(ps::launch_label_update(g->a, g->b, g->c, g->d, g->nx, g->ny, idx, w.count, lattice, sig_c, eps,
+                                        r.tol_norm * m->fro, r.tol_rel, status, sigma_dev, evals, s));
+    }
+    HIP_TRY(ps::launch_label_finish(status, label_dev, npts, s));
+    return ok();
+}
+
 ps_status ps_contour_seeds_workspace_size(const ps_grid *g, size_t *bytes) {
     ps_status st = check_grid(g);
     if (st) return st;

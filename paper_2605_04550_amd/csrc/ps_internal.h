@@ -124,6 +124,14 @@ hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double
 int64_t backward_partial_rows(int64_t npts);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 int64_t contour_edge_tiles(int64_t nx, int64_t ny);
+hipError_t launch_label_init(uint8_t *status, double *sig_out, int64_t npts, int64_t *evals, hipStream_t st);
+hipError_t launch_label_mask(const uint8_t *status, int64_t nx, int64_t npts, int stride, uint8_t *mask,
+                             hipStream_t st);
+hipError_t launch_label_update(double a, double b, double c, double d, int64_t nx, int64_t ny, const int64_t *idx,
+                               const int64_t *count, int64_t max_count, const double *sigma, double eps,
+                               double tol_abs, double tol_rel, uint8_t *status, double *sig_out, int64_t *evals,
+                               hipStream_t st);
+hipError_t launch_label_finish(const uint8_t *status, uint8_t *label, int64_t npts, hipStream_t st);
 hipError_t launch_contour_seeds(double a, double b, double c, double d, int64_t nx, int64_t ny, const double *sigma,
                                 double eps, double2 *seeds, int64_t max_seeds, int64_t *count, int64_t *blocksums,
                                 unsigned long long *scratch_queue, hipStream_t st);

@@ -2,8 +2,8 @@
 // small kernels around it: queue and count set-up, mask compaction (a block scan over the
 // mask, then a scatter of the selected flat indices in grid order), the batch variants of
 // both, workspace carving, the adjoint (gradients of sigma_min with respect to z and to the
-// band of A), seeds on the eps-level curve from grid-edge sign changes, and the Newton
-// update of contour points.
+// band of A), seeds on the eps-level curve from grid-edge sign changes, the Newton update of
+// contour points, and the exclusion-region labelling of the sensitive zone.
 
 #include "ps_eval.hpp"
 
@@ -185,6 +185,118 @@ hipError_t launch_contour_seeds(double a, double b, double c, double d, int64_t 
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, blocksums, nt, count, scratch_queue);
     hipLaunchKernelGGL(k_edge_scatter, dim3((unsigned)nt), dim3(kScanBlock), 0, st, g, sigma, eps,
                        (const int64_t *)blocksums, seeds, max_seeds);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------ exclusion-region labels
+// Status of a grid point: 0 unknown, 1 sigma <= eps (evaluated), 2 sigma > eps (evaluated, or
+// inside the exclusion disk of an evaluated point).
+
+__global__ void k_label_init(uint8_t *status, double *sig_out, int64_t npts, int64_t *evals) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < npts) {
+        status[t] = 0;
+        if (sig_out) sig_out[t] = -1.0;
+    }
+    if (t == 0 && evals) *evals = 0;
+}
+
+// Points of the lattice of the given stride that are still unknown (stride 1: all unknown).
+__global__ void k_label_mask(const uint8_t *status, int64_t nx, int64_t npts, int stride, uint8_t *mask) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts) return;
+    const int64_t i = t / nx, j = t - i * nx;
+    mask[t] = (uint8_t)(status[t] == 0 && i % stride == 0 && j % stride == 0);
+}
+
+__global__ void k_label_mark(const int64_t *idx, const int64_t *count, const double *sigma, double eps,
+                             uint8_t *status, double *sig_out, int64_t *evals) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = *count;
+    if (p == 0 && evals) *evals += c;
+    if (p >= c) return;
+    const int64_t f = idx[p];
+    status[f] = sigma[p] <= eps ? 1 : 2;
+    if (sig_out) sig_out[f] = sigma[p];
+}
+
+// One workgroup per evaluated point z0 with sigma(z0) > eps: sigma_min is 1-Lipschitz in z
+// (|sigma(z) - sigma(z0)| <= |z - z0|), so every grid point with
+// |z - z0| < sigma(z0) - eps - margin has sigma(z) > eps, where margin (twice the evaluation
+// tolerance) covers the error of the computed sigma(z0).
+__global__ void __launch_bounds__(256) k_label_exclude(EdgeGrid g, const int64_t *idx, const int64_t *count,
+                                                       const double *sigma, double eps, double tol_abs,
+                                                       double tol_rel, uint8_t *status) {
+    const int64_t p = blockIdx.x;
+    if (p >= *count) return;
+    const double sg = sigma[p];
+    const double rho = sg - eps - 2.0 * (tol_abs + tol_rel * sg);
+    if (!(rho > 0.0)) return;
+    const int64_t f = idx[p];
+    const int64_t i0 = f / g.nx, j0 = f - i0 * g.nx;
+    const cd z0 = edge_grid_point(g, f);
+    const double hx = g.nx > 1 ? (g.b - g.a) / (double)(g.nx - 1) : 0.0;
+    const double hy = g.ny > 1 ? (g.d - g.c) / (double)(g.ny - 1) : 0.0;
+    const int64_t rj = hx > 0.0 ? (int64_t)fmin(rho / hx + 1.0, (double)g.nx) : 0;
+    const int64_t ri = hy > 0.0 ? (int64_t)fmin(rho / hy + 1.0, (double)g.ny) : 0;
+    const int64_t ilo = i0 - ri > 0 ? i0 - ri : 0, ihi = i0 + ri < g.ny - 1 ? i0 + ri : g.ny - 1;
+    const int64_t jlo = j0 - rj > 0 ? j0 - rj : 0, jhi = j0 + rj < g.nx - 1 ? j0 + rj : g.nx - 1;
+    const int64_t bw = jhi - jlo + 1, cells = (ihi - ilo + 1) * bw;
+    for (int64_t q = threadIdx.x; q < cells; q += blockDim.x) {
+        const int64_t i = ilo + q / bw, j = jlo + q % bw;
+        const int64_t t = i * g.nx + j;
+        if (status[t] != 0) continue;
+        const cd zq = edge_grid_point(g, t);
+        if (hypot(zq.x - z0.x, zq.y - z0.y) < rho) status[t] = 2;
+    }
+}
+
+__global__ void k_label_finish(const uint8_t *status, uint8_t *label, int64_t npts) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < npts) label[t] = (uint8_t)(status[t] == 1);
+}
+
+static EdgeGrid make_edge_grid(double a, double b, double c, double d, int64_t nx, int64_t ny) {
+    EdgeGrid g;
+    g.a = a;
+    g.b = b;
+    g.c = c;
+    g.d = d;
+    g.nx = nx;
+    g.ny = ny;
+    g.nh = ny * (nx - 1);
+    g.ne = g.nh + (ny - 1) * nx;
+    return g;
+}
+
+hipError_t launch_label_init(uint8_t *status, double *sig_out, int64_t npts, int64_t *evals, hipStream_t st) {
+    hipLaunchKernelGGL(k_label_init, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, status, sig_out, npts,
+                       evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_mask(const uint8_t *status, int64_t nx, int64_t npts, int stride, uint8_t *mask,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_label_mask, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, status, nx, npts, stride,
+                       mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_update(double a, double b, double c, double d, int64_t nx, int64_t ny, const int64_t *idx,
+                               const int64_t *count, int64_t max_count, const double *sigma, double eps,
+                               double tol_abs, double tol_rel, uint8_t *status, double *sig_out, int64_t *evals,
+                               hipStream_t st) {
+    if (max_count < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_label_mark, dim3((unsigned)((max_count + 255) / 256)), dim3(256), 0, st, idx, count, sigma,
+                       eps, status, sig_out, evals);
+    const EdgeGrid g = make_edge_grid(a, b, c, d, nx, ny);
+    hipLaunchKernelGGL(k_label_exclude, dim3((unsigned)max_count), dim3(256), 0, st, g, idx, count, sigma, eps, tol_abs,
+                       tol_rel, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_finish(const uint8_t *status, uint8_t *label, int64_t npts, hipStream_t st) {
+    hipLaunchKernelGGL(k_label_finish, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, status, label, npts);
     return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ Sets (file ``tests/golden/<set>.npz``):
   grcar400_vec       Grcar n=400, 32 seeded points of the 256x256 grid on [-1.5,3]x[-3.5,3.5],
                      with singular vectors and the two smallest singular values.
   batch_pts          One seeded point for each matrix of the 64-matrix batch with n <= 1200.
+  paper_labels       The first three matrices of the label workload of Sec. 3.2 (n = 64,
+                     100x100 grid on [-4,4]^2): sigma at all 10^4 points and the labels
+                     sigma <= 0.01 (keys sigma0.., label0..).
 Each file holds: idx (flat grid index, or -1), z, sigma, s2 (second smallest singular
 value), and where stated u, v.
 """
@@ -115,8 +118,20 @@ def batch_pts(threads):
     _save("batch_pts", mat=m.astype(np.int64), idx=k.astype(np.int64), z=zz.astype(complex), sigma=s, s2=s2)
 
 
+def paper_labels(threads):
+    w = W.paper_label_workload(3)
+    z = oracle.grid_points(w["grid"])
+    out = {}
+    for m, band in enumerate(w["mats"]):
+        r = oracle.sigma_min(band, z, nthreads=threads, parallel_pairs=False)
+        out["sigma%d" % m] = r["sigma"]
+        out["label%d" % m] = oracle.sensitive(r["sigma"], w["eps"])
+        print("paper-class matrix", m, "beta", band.kl, "sensitive", int(out["label%d" % m].sum()), flush=True)
+    _save("paper_labels", **out)
+
+
 SETS = dict(grcar100_all=grcar100_all, toeplitz2000_pts=toeplitz2000_pts, random1000_grid=random1000_grid,
-            grcar400_vec=grcar400_vec, batch_pts=batch_pts)
+            grcar400_vec=grcar400_vec, batch_pts=batch_pts, paper_labels=paper_labels)
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()

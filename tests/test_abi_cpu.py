@@ -120,3 +120,15 @@ def test_contour_seed_and_batch_argument_checks():
     with pytest.raises(P.PsError) as e:
         P.ps_create_batch([], [])
     assert e.value.status == P.PS_ERR_INVALID
+
+
+def test_label_argument_checks():
+    _lib()
+    g = P.ps_grid(-1.0, 1.0, -1.0, 1.0, 5, 4)
+    fake = 1 << 20
+    with pytest.raises(P.PsError) as e:
+        P.ps_label_workspace_size(0, g)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:
+        P.ps_label_grid(0, g, 0.01, None, fake, 1 << 30, fake)
+    assert e.value.status == P.PS_ERR_INVALID

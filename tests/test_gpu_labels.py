@@ -1,0 +1,71 @@
+"""GPU tests of the exclusion-region labelling (ps_label_grid): the sensitive zone of
+Sec. 2.1 on the label workload of Sec. 3.2 (n = 64 matrices of the class of eq. (matrix),
+100 x 100 grid on [-4, 4]^2, eps = 0.01), against the oracle's labels at every grid point
+and against the plain evaluation of every point.  A point whose sigma lies within the parity
+bar of eps may go either way; every other label must agree."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import golden, need_gpu, tol
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    need_gpu()
+    from paper_2605_04550_amd import api
+    return api
+
+
+def test_labels_match_oracle_on_the_paper_class():
+    api = _api()
+    import torch
+    g = golden("paper_labels")
+    w = W.paper_label_workload(3)
+    grid, eps = w["grid"], w["eps"]
+    for m, band in enumerate(w["mats"]):
+        mat = api.BandedMatrix.from_band(band)
+        r = api.label_grid(mat, grid, eps)
+        torch.cuda.synchronize()
+        lab = r["label"].cpu().numpy().ravel()
+        sig = r["sigma"].cpu().numpy().ravel()
+        evals = int(r["evals"].item())
+        s_or, l_or = g["sigma%d" % m], g["label%d" % m]
+        bar = tol(band.fro, s_or)
+        sure = np.abs(s_or - eps) > 2 * bar
+        assert np.array_equal(lab[sure], l_or[sure]), (m, np.flatnonzero(lab[sure] != l_or[sure])[:10])
+        done = sig >= 0
+        assert np.all(np.abs(sig[done] - s_or[done]) <= bar[done])
+        assert np.all(done[l_or == 1] | ~sure[l_or == 1])      # sensitive points are evaluated
+        print("paper-class matrix %d: %d sensitive, %d of %d shifts evaluated (%.1f %%)"
+              % (m, int(lab.sum()), evals, grid.npts, 100.0 * evals / grid.npts), flush=True)
+        assert evals == int(done.sum()) and evals < 0.5 * grid.npts
+        # the plain method on every point gives the same labels
+        full = api.eval_grid(mat, grid, eps=eps)
+        plain = full["sens"].cpu().numpy()
+        assert np.array_equal(lab[sure], plain[sure])
+
+
+def test_labels_edge_cases():
+    api = _api()
+    import torch
+    band = W.paper_training_matrix(W.SEED_BASE + 6100)
+    mat = api.BandedMatrix.from_band(band)
+    z_all = None
+    for grid, eps in [(W.Grid(-4.0, 4.0, -4.0, 4.0, 7, 5), 0.01),      # tiny grid: stride 1 only
+                      (W.Grid(-4.0, 4.0, 0.5, 0.5, 61, 1), 0.05),      # one row
+                      (W.Grid(0.3, 0.3, -4.0, 4.0, 1, 53), 0.05),      # one column
+                      (W.Grid(-4.0, 4.0, -4.0, 4.0, 40, 40), 100.0),   # everything sensitive
+                      (W.Grid(-4.0, 4.0, -4.0, 4.0, 40, 40), 1e-12)]:  # almost nothing sensitive
+        r = api.label_grid(mat, grid, eps)
+        full = api.eval_grid(mat, grid, eps=eps)
+        lab = r["label"].cpu().numpy().ravel()
+        s = full["sigma"].cpu().numpy()
+        sure = np.abs(s - eps) > 2 * tol(band.fro, s)
+        assert np.array_equal(lab[sure], full["sens"].cpu().numpy()[sure]), (grid, eps)
+        ev = int(r["evals"].item())
+        assert 1 <= ev <= grid.npts
+        if eps == 100.0:
+            assert lab.all() and ev == grid.npts        # no exclusion possible

@@ -25,7 +25,7 @@ __all__ = [
     "Band", "Grid", "SEED_BASE", "band_from_rows", "grcar", "toeplitz", "random_banded",
     "diagonal", "jordan", "jordan_perturbed", "hermitian_toeplitz_tridiag", "band_poly_hermitian",
     "circulant_full", "gershgorin_box", "paper_training_matrix", "annulus_list",
-    "random_mask", "workload", "WORKLOADS", "batch_workload", "to_dense",
+    "random_mask", "workload", "WORKLOADS", "batch_workload", "paper_label_workload", "to_dense",
 ]
 
 
@@ -287,6 +287,15 @@ def _w_grcar4000():
     grid = Grid(-1.5, 3.0, -3.5, 3.5, 256, 256)
     return dict(name="grcar4000", band=grcar(4000), grid=grid,
                 weights=rng.standard_normal(grid.npts), eps=1e-3)
+
+
+def paper_label_workload(nmat: int = 500, first: int = 0):
+    """The label-generation setting of Sec. 3.2: matrices of the class of eq. (matrix), n = 64,
+    each labelled on a 100 x 100 grid over [-4, 4] x [-4, 4] with eps = 0.01 (z sensitive iff
+    sigma_min(zI - A) <= eps).  Matrix m uses seed base + 6000 + m."""
+    grid = Grid(-4.0, 4.0, -4.0, 4.0, 100, 100)
+    mats = [paper_training_matrix(SEED_BASE + 6000 + m) for m in range(first, first + nmat)]
+    return dict(name="paper_labels", mats=mats, grid=grid, eps=0.01)
 
 
 WORKLOADS = {
