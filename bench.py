@@ -148,6 +148,45 @@ def cpu_baseline(band, z_sample, threads):
                        "round-robin pairs over %d threads; %.1f s" % (len(z_sample), threads, dt))
 
 
+def label_bench(args):
+    """Label workload of Sec. 3.2: NMAT matrices (n = 64, eq. (matrix)), 100 x 100 grid on
+    [-4, 4]^2, eps = 0.01, as one batch.  Times ps_label_batch (exclusion regions) against the
+    plain method (ps_eval_batch on every point, labels sigma <= eps)."""
+    import torch
+    import workloads as W
+    from paper_2605_04550_amd import api
+    w = W.paper_label_workload(args.labels)
+    grid, eps = w["grid"], w["eps"]
+    mats = [api.BandedMatrix.from_band(b) for b in w["mats"]]
+    batch = api.BandedBatch(mats, [grid] * len(mats))
+    batch.label(eps)
+    batch.eval(None)                          # warm-up of both paths
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = batch.label(eps)
+    torch.cuda.synchronize()
+    t_label = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p = batch.eval(None)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    npts = grid.npts * len(mats)
+    plain_lab = (p["sigma"] <= eps).to(torch.uint8)
+    agree = int((plain_lab == r["label"]).sum().item())
+    print(json.dumps({
+        "metric": "grid points labelled per second (sensitive zone, eps = 0.01)", "value": npts / t_label,
+        "unit": "points/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Sec. 3.2 label workload: %d matrices n=64 (eq. (matrix)), 100x100 grid on "
+                               "[-4,4]^2, one batch" % len(mats), "matrices": len(mats)},
+        "label_s": t_label, "plain_s": t_plain, "plain_points_per_s": npts / t_plain,
+        "speedup_vs_plain_method": t_plain / t_label,
+        "evaluated_fraction": int(r["evals"].item()) / npts,
+        "labels_equal_to_plain": agree, "points": npts}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +200,9 @@ def main():
     ap.add_argument("--counter-pass", action="store_true",
                     help="calibration copy + one full-grid launch, for rocprofv3 --pmc")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--labels", type=int, default=0, metavar="NMAT",
+                    help="instead of the headline: label NMAT matrices of the Sec. 3.2 workload by exclusion "
+                         "regions and by the plain method, one JSON line")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
@@ -178,6 +220,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.labels:
+        label_bench(args)
+        return
     w = W.workload("toeplitz2000")
     band, grid = w["band"], w["grid"]
     mat = api.BandedMatrix.from_band(band)

@@ -229,6 +229,22 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
                         int32_t *iters_dev, void *stream);
 
 /*
+ * ps_label_batch -- ps_label_grid for every matrix of a batch at once (the label generation
+ * of Sec. 3.2 runs over many matrices): each level builds the masks of all matrices, evaluates
+ * them with one persistent launch per (kl, ku) class as ps_eval_batch does, then marks and
+ * excludes for all matrices together.  Matrix m's labels (and sigma) occupy
+ * [offsets[m], offsets[m] + nx ny) of the concatenated outputs (offsets from ps_batch_info).
+ *   label_dev  device uint8[total] (required).   sigma_dev: device double[total] or NULL.
+ *   evals_dev  device int64[1] or NULL: shifts evaluated over all matrices.
+ *   ws_dev / ws_bytes >= ps_label_batch_workspace_size(b, o).  Calls on one batch must not
+ *   overlap.
+ * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_UNSUPPORTED (vectors), PS_ERR_HIP.
+ */
+ps_status ps_label_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes);
+ps_status ps_label_batch(ps_batch b, double eps, const ps_opts *o, void *ws_dev, size_t ws_bytes, uint8_t *label_dev,
+                         double *sigma_dev, int64_t *evals_dev, void *stream);
+
+/*
  * ps_newton_contour -- refine points toward the eps-level curve of sigma_min (the boundary of
  * the eps-pseudospectrum drawn as the level curve log10 eps in Sec. 2.1).  Each of `steps`
  * steps evaluates sigma_min with its singular vectors at every point, forms

@@ -70,6 +70,9 @@ _SIGNATURES = {
     "ps_newton_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "ps_newton_contour": (ctypes.c_int, [_P, _P, _I64, ctypes.c_double, _I32, ctypes.POINTER(ps_opts), _P,
                                          ctypes.c_size_t, _P, _P, _P]),
+    "ps_label_batch_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_label_batch": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P, _P,
+                                      _P]),
     "ps_label_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), ctypes.POINTER(ps_opts),
                                                ctypes.POINTER(ctypes.c_size_t)]),
     "ps_label_grid": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), ctypes.c_double, ctypes.POINTER(ps_opts), _P,
@@ -187,6 +190,18 @@ def ps_newton_contour(handle, z_ptr, npts, eps, steps, opts, ws_ptr, ws_bytes, s
     _check(lib().ps_newton_contour(_P(handle), _P(z_ptr), npts, float(eps), int(steps),
                                    ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
                                    _P(sigma_ptr), _P(info_ptr), _P(stream)))
+
+
+def ps_label_batch_workspace_size(handle, opts: ps_opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_label_batch_workspace_size(_P(handle), ctypes.byref(opts) if opts is not None else None,
+                                               ctypes.byref(b)))
+    return b.value
+
+
+def ps_label_batch(handle, eps, opts, ws_ptr, ws_bytes, label_ptr, sigma_ptr=0, evals_ptr=0, stream=0) -> None:
+    _check(lib().ps_label_batch(_P(handle), float(eps), ctypes.byref(opts) if opts is not None else None, _P(ws_ptr),
+                                ws_bytes, _P(label_ptr), _P(sigma_ptr), _P(evals_ptr), _P(stream)))
 
 
 def ps_label_workspace_size(handle, grid: ps_grid, opts: ps_opts | None = None) -> int:

@@ -19,7 +19,8 @@ from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_w
                ps_batch_workspace_size, ps_create_banded, ps_create_batch, ps_destroy, ps_destroy_batch,
                ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
                ps_newton_workspace_size, ps_opts_default, ps_workspace_size, ps_contour_seeds,
-               ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size)
+               ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size, ps_label_batch,
+               ps_label_batch_workspace_size)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
 
@@ -126,6 +127,20 @@ class BandedBatch:
         ps_eval_batch(self.handle, mptr, o, ws.data_ptr(), ws.numel(), out["idx"].data_ptr(), out["counts"].data_ptr(),
                       out["sigma"].data_ptr(), out["info"].data_ptr(), out["iters"].data_ptr(), _stream_handle(stream))
         out["_keep"] = keep
+        return out
+
+    def label(self, eps: float, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, shift_invert=True,
+              device=None, stream=None):
+        """ps_label_batch: labels (sigma_min <= eps) of every grid point of every matrix, by exclusion
+        regions.  Returns dict(label [total] uint8, sigma [total] (-1 where excluded), evals, offsets)."""
+        dev = device or torch.device("cuda")
+        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, shift_invert=shift_invert)
+        out = dict(label=torch.empty(self.total, dtype=torch.uint8, device=dev),
+                   sigma=torch.empty(self.total, dtype=torch.float64, device=dev),
+                   evals=torch.zeros(1, dtype=torch.int64, device=dev), offsets=list(self.offsets))
+        ws = _workspace(ps_label_batch_workspace_size(self.handle, o), dev)
+        ps_label_batch(self.handle, eps, o, ws.data_ptr(), ws.numel(), out["label"].data_ptr(),
+                       out["sigma"].data_ptr(), out["evals"].data_ptr(), _stream_handle(stream))
         return out
 
 

@@ -377,6 +377,7 @@ ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, c
 
 struct ps_batch_s {
     int32_t nmat = 0;
+    std::vector<ps_grid> grids;
     std::vector<int64_t> off;
     std::vector<int64_t> npts;
     int64_t total = 0;
@@ -674,6 +675,7 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         d.cidx = m;
         d.pad = 0;
         dc[(size_t)m] = d;
+        b->grids.push_back(g);
         b->off.push_back(b->total);
         b->npts.push_back(g.nx * g.ny);
         b->total += g.nx * g.ny;
@@ -746,22 +748,11 @@ ps_status ps_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes) {
     return ok();
 }
 
-ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_opts *o, void *ws_dev, size_t ws_bytes,
-                        int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
-                        int32_t *iters_dev, void *stream) {
-    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
-    ps_opts r = resolve(o);
-    ps_status st;
-    if ((st = check_opts(r))) return st;
-    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "vectors are not produced in batch mode");
-    if (!idx_dev || !counts_dev || !sigma_dev) return fail(PS_ERR_INVALID, "idx, counts and sigma are required");
-    if (!ws_dev) return fail(PS_ERR_WORKSPACE, "workspace is NULL");
-    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    size_t need = 0;
-    ps_batch_workspace_size(b, &r, &need);
-    if (ws_bytes < need) return fail(PS_ERR_WORKSPACE, "batch workspace needs %zu bytes (got %zu)", need, ws_bytes);
-    hipStream_t s = (hipStream_t)stream;
-    char *base = (char *)ws_dev;
+// Compaction of the masks and one persistent launch per (kl, ku) class; evbase holds the
+// evaluation workspace (past the batch scratch).
+static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, const ps_opts &r, char *base,
+                                 int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
+                                 int32_t *iters_dev, hipStream_t s) {
     int64_t nt = ps::batch_tiles(b->max_npts);
     if (nt < 1) nt = 1;
     int64_t *tilesums = (int64_t *)base;
@@ -799,6 +790,88 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
         a.mfirst = mfirst + c.begin;
         HIP_TRY(ps::launch_eval_batch(a, w, c.kl, c.ku, s));
     }
+    return ok();
+}
+
+ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_opts *o, void *ws_dev, size_t ws_bytes,
+                        int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
+                        int32_t *iters_dev, void *stream) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    ps_opts r = resolve(o);
+    ps_status st;
+    if ((st = check_opts(r))) return st;
+    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "vectors are not produced in batch mode");
+    if (!idx_dev || !counts_dev || !sigma_dev) return fail(PS_ERR_INVALID, "idx, counts and sigma are required");
+    if (!ws_dev) return fail(PS_ERR_WORKSPACE, "workspace is NULL");
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    ps_batch_workspace_size(b, &r, &need);
+    if (ws_bytes < need) return fail(PS_ERR_WORKSPACE, "batch workspace needs %zu bytes (got %zu)", need, ws_bytes);
+    return batch_eval_core(b, masks_dev, r, (char *)ws_dev, idx_dev, counts_dev, sigma_dev, info_dev, iters_dev,
+                           (hipStream_t)stream);
+}
+
+// Batched labelling workspace past the batch evaluation workspace: status and mask bytes for
+// every point, the mask pointer array, compacted indices and sigma, counts, the counter.
+static size_t blabel_aux_bytes(ps_batch b) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t tot = (size_t)b->total;
+    return 2 * al(tot) + al(sizeof(void *) * (size_t)b->nmat) + 2 * al(8 * tot) + al(8 * (size_t)b->nmat) + 256;
+}
+
+ps_status ps_label_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    size_t ev = 0;
+    ps_status st = ps_batch_workspace_size(b, o, &ev);
+    if (st) return st;
+    *bytes = ((ev + 255) & ~(size_t)255) + blabel_aux_bytes(b);
+    return ok();
+}
+
+ps_status ps_label_batch(ps_batch b, double eps, const ps_opts *o, void *ws_dev, size_t ws_bytes, uint8_t *label_dev,
+                         double *sigma_dev, int64_t *evals_dev, void *stream) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite and > 0");
+    if (!label_dev) return fail(PS_ERR_INVALID, "label output is NULL");
+    ps_opts r = resolve(o);
+    ps_status st;
+    if ((st = check_opts(r))) return st;
+    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "labelling does not produce vectors");
+    size_t need = 0;
+    if ((st = ps_label_batch_workspace_size(b, &r, &need))) return st;
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "batch label workspace needs %zu bytes", need);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t tot = (size_t)b->total;
+    char *aux = (char *)ws_dev + (need - blabel_aux_bytes(b));
+    uint8_t *status = (uint8_t *)aux;
+    uint8_t *mask = status + al(tot);
+    uint8_t **mptr = (uint8_t **)(mask + al(tot));
+    int64_t *idx = (int64_t *)((char *)mptr + al(sizeof(void *) * (size_t)b->nmat));
+    double *sig_c = (double *)((char *)idx + al(8 * tot));
+    int64_t *counts = (int64_t *)((char *)sig_c + al(8 * tot));
+    int64_t *evals = (int64_t *)((char *)counts + al(8 * (size_t)b->nmat));
+    if (evals_dev) evals = evals_dev;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nxmax = 0, nymax = 0;
+    for (size_t m = 0; m < b->grids.size(); ++m) {
+        nxmax = std::max(nxmax, b->grids[m].nx);
+        nymax = std::max(nymax, b->grids[m].ny);
+    }
+    HIP_TRY(ps::launch_blabel_init(b->desc_caller, b->nmat, b->max_npts, status, sigma_dev, mask, mptr, evals, s));
+    int stride = 1;
+    while (stride < 8 && (nxmax >= 24 * stride || nymax >= 24 * stride)) stride *= 2;
+    for (; stride >= 1; stride /= 2) {
+        const int64_t lattice = ((nymax + stride - 1) / stride) * ((nxmax + stride - 1) / stride);
+        HIP_TRY(ps::launch_blabel_mask(b->desc_caller, b->nmat, b->max_npts, status, stride, mask, s));
+        if ((st = batch_eval_core(b, (const uint8_t *const *)mptr, r, (char *)ws_dev, idx, counts, sig_c, nullptr,
+                                  nullptr, s)))
+            return st;
+        HIP_TRY(ps::launch_blabel_update(b->desc_caller, b->nmat, lattice, idx, counts, sig_c, eps, r.tol_norm,
+                                         r.tol_rel, status, sigma_dev, evals, s));
+    }
+    HIP_TRY(ps::launch_label_finish(status, label_dev, b->total, s));
     return ok();
 }
 

@@ -300,6 +300,108 @@ hipError_t launch_label_finish(const uint8_t *status, uint8_t *label, int64_t np
     return hipGetLastError();
 }
 
+// Batched labelling: the same steps for every matrix of a batch at once.  Matrix m's points
+// occupy [out_off, out_off + nx ny) of the concatenated status, mask, label and sigma arrays
+// (its grid from its MatDesc); blockIdx.y is the matrix.
+
+__global__ void k_blabel_init(const MatDesc *mats, uint8_t *status, double *sig_out, uint8_t *mask_base,
+                              uint8_t **mask_ptrs, int64_t *evals) {
+    const int m = blockIdx.y;
+    const MatDesc d = mats[m];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d.nx * d.ny) {
+        status[d.out_off + t] = 0;
+        if (sig_out) sig_out[d.out_off + t] = -1.0;
+    }
+    if (t == 0) mask_ptrs[m] = mask_base + d.out_off;
+    if (t == 0 && m == 0 && evals) *evals = 0;
+}
+
+__global__ void k_blabel_mask(const MatDesc *mats, const uint8_t *status, int stride, uint8_t *mask) {
+    const MatDesc d = mats[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d.nx * d.ny) return;
+    const int64_t i = t / d.nx, j = t - i * d.nx;
+    mask[d.out_off + t] = (uint8_t)(status[d.out_off + t] == 0 && i % stride == 0 && j % stride == 0);
+}
+
+__global__ void k_blabel_mark(const MatDesc *mats, const int64_t *idx, const int64_t *counts, const double *sigma,
+                              double eps, uint8_t *status, double *sig_out, int64_t *evals) {
+    const int m = blockIdx.y;
+    const MatDesc d = mats[m];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = counts[m];
+    if (p == 0 && evals) atomicAdd((unsigned long long *)evals, (unsigned long long)c);
+    if (p >= c) return;
+    const int64_t f = idx[d.out_off + p];
+    const double sg = sigma[d.out_off + p];
+    status[d.out_off + f] = sg <= eps ? 1 : 2;
+    if (sig_out) sig_out[d.out_off + f] = sg;
+}
+
+__global__ void __launch_bounds__(256) k_blabel_exclude(const MatDesc *mats, const int64_t *idx,
+                                                        const int64_t *counts, const double *sigma, double eps,
+                                                        double tol_norm, double tol_rel, uint8_t *status) {
+    const int m = blockIdx.y;
+    const MatDesc d = mats[m];
+    const int64_t p = blockIdx.x;
+    if (p >= counts[m]) return;
+    const double sg = sigma[d.out_off + p];
+    const double rho = sg - eps - 2.0 * (tol_norm * d.normA + tol_rel * sg);
+    if (!(rho > 0.0)) return;
+    EdgeGrid g;
+    g.a = d.ga;
+    g.b = d.gb;
+    g.c = d.gc;
+    g.d = d.gd;
+    g.nx = d.nx;
+    g.ny = d.ny;
+    g.nh = g.ne = 0;
+    const int64_t f = idx[d.out_off + p];
+    const int64_t i0 = f / g.nx, j0 = f - i0 * g.nx;
+    const cd z0 = edge_grid_point(g, f);
+    const double hx = g.nx > 1 ? (g.b - g.a) / (double)(g.nx - 1) : 0.0;
+    const double hy = g.ny > 1 ? (g.d - g.c) / (double)(g.ny - 1) : 0.0;
+    const int64_t rj = hx > 0.0 ? (int64_t)fmin(rho / hx + 1.0, (double)g.nx) : 0;
+    const int64_t ri = hy > 0.0 ? (int64_t)fmin(rho / hy + 1.0, (double)g.ny) : 0;
+    const int64_t ilo = i0 - ri > 0 ? i0 - ri : 0, ihi = i0 + ri < g.ny - 1 ? i0 + ri : g.ny - 1;
+    const int64_t jlo = j0 - rj > 0 ? j0 - rj : 0, jhi = j0 + rj < g.nx - 1 ? j0 + rj : g.nx - 1;
+    const int64_t bw = jhi - jlo + 1, cells = (ihi - ilo + 1) * bw;
+    uint8_t *st = status + d.out_off;
+    for (int64_t q = threadIdx.x; q < cells; q += blockDim.x) {
+        const int64_t i = ilo + q / bw, j = jlo + q % bw;
+        const int64_t t = i * g.nx + j;
+        if (st[t] != 0) continue;
+        const cd zq = edge_grid_point(g, t);
+        if (hypot(zq.x - z0.x, zq.y - z0.y) < rho) st[t] = 2;
+    }
+}
+
+hipError_t launch_blabel_init(const MatDesc *mats, int nmat, int64_t max_npts, uint8_t *status, double *sig_out,
+                              uint8_t *mask_base, uint8_t **mask_ptrs, int64_t *evals, hipStream_t st) {
+    hipLaunchKernelGGL(k_blabel_init, dim3((unsigned)((max_npts + 255) / 256), (unsigned)nmat), dim3(256), 0, st,
+                       mats, status, sig_out, mask_base, mask_ptrs, evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_blabel_mask(const MatDesc *mats, int nmat, int64_t max_npts, const uint8_t *status, int stride,
+                              uint8_t *mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_blabel_mask, dim3((unsigned)((max_npts + 255) / 256), (unsigned)nmat), dim3(256), 0, st,
+                       mats, status, stride, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_blabel_update(const MatDesc *mats, int nmat, int64_t max_count, const int64_t *idx,
+                                const int64_t *counts, const double *sigma, double eps, double tol_norm,
+                                double tol_rel, uint8_t *status, double *sig_out, int64_t *evals, hipStream_t st) {
+    if (max_count < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_blabel_mark, dim3((unsigned)((max_count + 255) / 256), (unsigned)nmat), dim3(256), 0, st,
+                       mats, idx, counts, sigma, eps, status, sig_out, evals);
+    hipLaunchKernelGGL(k_blabel_exclude, dim3((unsigned)max_count, (unsigned)nmat), dim3(256), 0, st, mats, idx,
+                       counts, sigma, eps, tol_norm, tol_rel, status);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------ adjoint
 
 // grad_z[p] = g_p conj(u_p^H v_p): one wavefront per shift, lanes stride over rows.

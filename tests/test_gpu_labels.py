@@ -69,3 +69,44 @@ def test_labels_edge_cases():
         assert 1 <= ev <= grid.npts
         if eps == 100.0:
             assert lab.all() and ev == grid.npts        # no exclusion possible
+
+
+def test_batched_labels_match_single_matrix_and_oracle():
+    """ps_label_batch over matrices of the label workload (plus one matrix on a small ragged
+    grid of its own): per matrix the labels of ps_label_grid and, for the three with stored
+    oracle values, the oracle's labels."""
+    api = _api()
+    import torch
+    g = golden("paper_labels")
+    w = W.paper_label_workload(8)
+    grid, eps = w["grid"], w["eps"]
+    bands = list(w["mats"]) + [W.paper_training_matrix(W.SEED_BASE + 6200)]
+    grids = [grid] * 8 + [W.Grid(-3.0, 2.0, -1.0, 4.0, 37, 29)]
+    mats = [api.BandedMatrix.from_band(b) for b in bands]
+    batch = api.BandedBatch(mats, grids)
+    r = batch.label(eps)
+    torch.cuda.synchronize()
+    lab = r["label"].cpu().numpy()
+    sig = r["sigma"].cpu().numpy()
+    total_evals = 0
+    for m, (band, gr) in enumerate(zip(bands, grids)):
+        off = r["offsets"][m]
+        lm = lab[off:off + gr.npts]
+        sm = sig[off:off + gr.npts]
+        single = api.label_grid(mats[m], gr, eps)
+        ls = single["label"].cpu().numpy().ravel()
+        full = api.eval_grid(mats[m], gr, eps=eps)
+        sf = full["sigma"].cpu().numpy()
+        sure = np.abs(sf - eps) > 2 * tol(band.fro, sf)
+        assert np.array_equal(lm[sure], ls[sure]) and np.array_equal(lm[sure], full["sens"].cpu().numpy()[sure]), m
+        done = sm >= 0
+        assert np.all(np.abs(sm[done] - sf[done]) <= tol(band.fro, sf[done]))
+        total_evals += int(done.sum())
+        if m < 3:
+            s_or, l_or = g["sigma%d" % m], g["label%d" % m]
+            sure_o = np.abs(s_or - eps) > 2 * tol(band.fro, s_or)
+            assert np.array_equal(lm[sure_o], l_or[sure_o]), m
+    assert int(r["evals"].item()) == total_evals
+    npts = sum(gr.npts for gr in grids)
+    print("batched labels: %d matrices, %d of %d shifts evaluated (%.1f %%)"
+          % (len(bands), total_evals, npts, 100.0 * total_evals / npts), flush=True)
