@@ -57,7 +57,7 @@ def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_04550_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".h")):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
             h.update(open(os.path.join(csrc, f), "rb").read())
     h.update(open(os.path.join(ROOT, "workloads", "gen.py"), "rb").read())
     return h.hexdigest()[:16]
@@ -112,22 +112,29 @@ def stored_traffic():
 
 
 def algorithmic_bytes(n, kl, ku, iters, info=None):
-    """Bytes the method must move for one launch: the band once, and per shift the LU, its
-    Golub-Kahan steps and, for shifts that switched to shift-and-invert (info bit 8), each
-    factorisation of (zI-A)^H (zI-A) - s I (the factor written once) and each of its steps
-    (the factor read twice, eight vector passes)."""
+    """Bytes the method must move for one launch: the band once, and per Golub-Kahan shift
+    the LU and its steps.  A shift that took the inertia bisection (info bit 8) moves only its
+    result: its passes read the band (cached) and keep the factor rows in registers."""
     wl, wu = kl, kl + ku + 1
     b_lu = (wl + wu) * 16 * n + n
     b_step = (2 * (wl + wu) + 10) * 16 * n + 2 * n
     iters = np.asarray(iters, dtype=np.float64)
-    total = (kl + ku + 1) * 16 * n + np.sum(b_lu + iters * b_step + 16)
-    if info is not None:
-        info = np.asarray(info, dtype=np.int64)
-        si = (info & 8) != 0
-        nfac = ((info >> 4) & 15)[si].astype(np.float64)
-        ksi = (info >> 8)[si].astype(np.float64)
-        total += np.sum(nfac * wu * 16 * n + ksi * (2 * wu + 8) * 16 * n)
+    gk = np.ones(iters.shape, dtype=bool) if info is None else (np.asarray(info) & 8) == 0
+    total = (kl + ku + 1) * 16 * n + np.sum(np.where(gk, b_lu + iters * b_step, 0.0) + 16)
     return float(total)
+
+
+def bisection_flops(n, kl, ku, info):
+    """Floating-point operations of the bisection passes of one launch, counting every pass as
+    complete (a pass that meets a non-positive pivot stops early, so this is an upper bound).
+    Per row, with hb = kl + ku: forming H[i][i-e] for e = 0..hb takes (hb+1)(hb+2)/2 complex
+    multiply-adds (8 flops each); the factor row takes hb(hb-1)/2 more, plus per entry a scale
+    by 1/L_jj (2) and |l|^2 (3), and the pivot 3 (the subtraction, the bound, 1/sqrt)."""
+    hb = kl + ku
+    per_row = 8 * ((hb + 1) * (hb + 2) // 2 + hb * (hb - 1) // 2) + 5 * hb + 3
+    info = np.asarray(info, dtype=np.int64)
+    passes = np.where((info & 8) != 0, info >> 8, 0).astype(np.float64)
+    return float(np.sum(passes) * n * per_row)
 
 
 def _grid_points(grid):
@@ -347,8 +354,9 @@ def main():
             "iters_mean_full": float(it_full.mean()), "iters_max_full": int(it_full.max()),
             "iters_mean_mask": float(it_mask.mean()) if cnt_mask else 0.0,
             "maxiter_points_full": int(np.sum((info_full & 2) != 0)),
-            "shift_invert_points_full": int(si_full.sum()),
-            "shift_invert_steps_mean": float((info_full[si_full] >> 8).mean()) if si_full.any() else 0.0,
+            "bisection_points_full": int(si_full.sum()),
+            "bisection_passes_mean": float((info_full[si_full] >> 8).mean()) if si_full.any() else 0.0,
+            "bisection_flops_full": bisection_flops(band.n, band.kl, band.ku, info_full),
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded points of the full grid, one launch per shift (same kernel numerics and "

@@ -63,10 +63,11 @@ enum {
     PS_PT_SINGULAR = 1,   /* the LU met an exactly zero (or negligible) pivot: sigma_min = 0 */
     PS_PT_MAXITER = 2,    /* iteration cap reached: sigma is the best (upper) estimate        */
     PS_PT_UNDERFLOW = 4,  /* sigma_min below the smallest double: reported as 0               */
-    PS_PT_SHIFT_INVERT = 8 /* sigma came from the shift-and-invert phase; then bits 4..7 of
-                              info hold the number of factorisations of (zI-A)^H (zI-A) - s I
-                              it took (a shift found above sigma_min^2 is lowered and the
-                              factorisation repeated) and bits 8..31 its Lanczos steps      */
+    PS_PT_BISECT = 8      /* sigma came from the inertia bisection (sigma only, kl + ku >= 1):
+                             sigma_min^2 is the smallest eigenvalue of (zI-A)^H (zI-A), so
+                             t < sigma_min exactly when (zI-A)^H (zI-A) - t^2 I has a Cholesky
+                             factor; bits 8..31 of info hold the number of such tests (one
+                             pass over the band each), and no Golub-Kahan step was taken   */
 };
 
 /* Flags of ps_create_banded. */
@@ -95,12 +96,11 @@ typedef struct {
     int32_t slots;        /* 0: default                                       */
     int32_t check_shift;  /* Ritz-value checks every max(1, k >> check_shift)
                              Lanczos steps (0: default 5); set by ps_autotune  */
-    int32_t shift_invert; /* 0 (default): a shift whose Lanczos iteration is still
-                             running after 24 steps may switch to shift-and-invert
-                             Lanczos on ((zI-A)^H (zI-A) - s I)^{-1}, s just below
-                             the estimated sigma_min^2 (sigma only, kl + ku >= 1);
-                             k in 4..512: switch after k steps instead of 24;
-                             -1: never switch; set by ps_autotune              */
+    int32_t bisect;       /* 0 (default): a shift where the rounding of (zI-A)^H (zI-A),
+                             about 32 eps (|z| + ||A||)^2 / sigma in sigma, stays below an
+                             eighth of the target gets sigma_min by bisection on Cholesky
+                             tests instead of Lanczos steps (sigma only, kl + ku >= 1);
+                             -1: every shift takes the Golub-Kahan path                  */
 } ps_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -147,7 +147,8 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
  *              accumulates it, so vectors cost about twice the steps of sigma alone) and u
  *              one inverse-iteration step from it, u = (zI - A)^{-H} v / |(zI - A)^{-H} v|.
  *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL:
- *              Golub-Kahan (inverse Lanczos) steps; shift-and-invert steps are in info.
+ *              Golub-Kahan (inverse Lanczos) steps (0 for a shift flagged PS_PT_BISECT,
+ *              whose number of Cholesky tests is in info).
  * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
  */
 ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const ps_opts *o, void *ws_dev,
@@ -306,10 +307,10 @@ ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps
 
 /*
  * ps_autotune -- choose the plan for ps_eval_points / ps_eval_grid on this matrix: the number
- * of slots (shifts in flight), the Ritz-check schedule and the step at which slow shifts
- * switch to shift-and-invert (left off if o->shift_invert is -1).  Times each candidate on
+ * of slots (shifts in flight) and the Ritz-check schedule.  Times each candidate on
  * z_dev[0 .. npts) (a representative sample of the shifts to be evaluated, on the device)
- * with HIP events and writes the fastest into o->slots, o->check_shift and o->shift_invert.
+ * with HIP events and writes the fastest into o->slots and o->check_shift (o->bisect is
+ * kept as given).
  * Synchronous; allocates and frees its own workspace.  Results of the timed runs are
  * discarded.
  * Errors: PS_ERR_INVALID, PS_ERR_HIP.

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libps.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ps.h")
 
 PS_OK, PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP, PS_ERR_UNSUPPORTED = range(6)
-PS_PT_CONVERGED, PS_PT_SINGULAR, PS_PT_MAXITER, PS_PT_UNDERFLOW, PS_PT_SHIFT_INVERT = 0, 1, 2, 4, 8
+PS_PT_CONVERGED, PS_PT_SINGULAR, PS_PT_MAXITER, PS_PT_UNDERFLOW, PS_PT_BISECT = 0, 1, 2, 4, 8
 PS_DEVICE_PTR, PS_REAL_A = 1, 2
 
 STATUS_NAMES = {0: "PS_OK", 1: "PS_ERR_INVALID", 2: "PS_ERR_NONFINITE", 3: "PS_ERR_WORKSPACE", 4: "PS_ERR_HIP",
@@ -38,7 +38,7 @@ class ps_grid(ctypes.Structure):
 class ps_opts(ctypes.Structure):
     _fields_ = [("tol_norm", ctypes.c_double), ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("want_vectors", ctypes.c_int32), ("slots", ctypes.c_int32), ("check_shift", ctypes.c_int32),
-                ("shift_invert", ctypes.c_int32)]
+                ("bisect", ctypes.c_int32)]
 
 
 class PsError(RuntimeError):

@@ -31,11 +31,10 @@ def _stream_handle(stream=None) -> int:
 
 
 def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0, check_shift=0,
-              shift_invert=True):
+              bisect=True):
     return ps_opts_default(tol_norm=tol_norm, tol_rel=tol_rel, max_iter=max_iter,
                            want_vectors=int(bool(want_vectors)), slots=int(slots), check_shift=int(check_shift),
-                           shift_invert=(0 if shift_invert is True else -1 if shift_invert is False
-                                         else int(shift_invert)))
+                           bisect=0 if bisect else -1)
 
 
 class BandedMatrix:
@@ -94,13 +93,13 @@ class BandedBatch:
         except Exception:
             pass
 
-    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, shift_invert=True,
+    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
              device=None, stream=None, workspace: torch.Tensor | None = None):
         """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None.  Returns dict with
         the concatenated idx, sigma, info, iters, and counts [nmat]; matrix m owns offsets[m] onward."""
         dev = device or torch.device("cuda")
         nmat = len(self.mats)
-        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, shift_invert=shift_invert)
+        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect)
         keep = []
         mptr = 0
         if masks is not None:
@@ -129,12 +128,12 @@ class BandedBatch:
         out["_keep"] = keep
         return out
 
-    def label(self, eps: float, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, shift_invert=True,
+    def label(self, eps: float, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
               device=None, stream=None):
         """ps_label_batch: labels (sigma_min <= eps) of every grid point of every matrix, by exclusion
         regions.  Returns dict(label [total] uint8, sigma [total] (-1 where excluded), evals, offsets)."""
         dev = device or torch.device("cuda")
-        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, shift_invert=shift_invert)
+        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect)
         out = dict(label=torch.empty(self.total, dtype=torch.uint8, device=dev),
                    sigma=torch.empty(self.total, dtype=torch.float64, device=dev),
                    evals=torch.zeros(1, dtype=torch.int64, device=dev), offsets=list(self.offsets))
@@ -149,14 +148,14 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_norm=1e-10, tol_rel=1e-8,
-              max_iter=3000, slots=0, shift_invert=True, workspace: torch.Tensor | None = None, stream=None):
+              max_iter=3000, slots=0, bisect=True, workspace: torch.Tensor | None = None, stream=None):
     """sigma_min(z_p I - A) for every entry of the complex128 CUDA tensor z.  Returns a dict
     with ``sigma`` (float64), ``info`` and ``iters`` (int32), and ``u``, ``v`` ([npts, n]) if asked."""
     assert z.is_cuda and z.dtype == torch.complex128
     z = z.contiguous()
     npts = z.numel()
     dev = z.device
-    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, shift_invert=shift_invert)
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, bisect=bisect)
     out = dict(sigma=torch.empty(npts, dtype=torch.float64, device=dev),
                info=torch.empty(npts, dtype=torch.int32, device=dev),
                iters=torch.empty(npts, dtype=torch.int32, device=dev))
@@ -174,7 +173,7 @@ def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_nor
 
 
 def eval_grid(mat: BandedMatrix, grid, mask: torch.Tensor | None = None, *, eps=None, want_vectors=False,
-              tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, shift_invert=True, device=None, stream=None,
+              tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True, device=None, stream=None,
               workspace: torch.Tensor | None = None):
     """sigma_min on the grid (a, b, c, d, nx, ny) of Sec. 2.1, or on the points where ``mask`` (uint8
     [ny, nx] CUDA tensor) is nonzero.  Outputs are compacted: entry p belongs to flat grid index
@@ -182,7 +181,7 @@ def eval_grid(mat: BandedMatrix, grid, mask: torch.Tensor | None = None, *, eps=
     g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
     npts = g.nx * g.ny
     dev = mask.device if mask is not None else (device or torch.device("cuda"))
-    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, shift_invert=shift_invert)
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, bisect=bisect)
     out = dict(idx=torch.empty(npts, dtype=torch.int64, device=dev),
                count=torch.zeros(1, dtype=torch.int64, device=dev),
                sigma=torch.empty(npts, dtype=torch.float64, device=dev),
@@ -278,13 +277,13 @@ def contour_seeds(grid, sigma: torch.Tensor, eps: float, max_seeds: int | None =
 
 
 def label_grid(mat: BandedMatrix, grid, eps: float, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0,
-               shift_invert=True, device=None, stream=None):
+               bisect=True, device=None, stream=None):
     """ps_label_grid: the sensitive zone S_eps on the whole grid (label 1 iff sigma_min <= eps),
     evaluating sigma_min only outside the exclusion disks of points already evaluated.
     Returns dict(label [ny, nx] uint8, sigma [ny, nx] float64 (-1 where excluded), evals)."""
     g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
     dev = device or torch.device("cuda")
-    o = make_opts(tol_norm, tol_rel, max_iter, False, slots, shift_invert=shift_invert)
+    o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect)
     label = torch.empty((g.ny, g.nx), dtype=torch.uint8, device=dev)
     sigma = torch.empty((g.ny, g.nx), dtype=torch.float64, device=dev)
     evals = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -295,7 +294,7 @@ def label_grid(mat: BandedMatrix, grid, eps: float, *, tol_norm=1e-10, tol_rel=1
 
 
 def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):
-    """ps_autotune on the shifts z: returns the options (slots, check_shift, shift_invert) that ran fastest."""
+    """ps_autotune on the shifts z: returns the options (slots, check_shift; bisect as given) that ran fastest."""
     o = make_opts(**kw)
     ps_autotune(mat.handle, z.contiguous().data_ptr(), z.numel(), o, _stream_handle())
     return o

@@ -67,15 +67,14 @@ ps_status check_opts(const ps_opts &o) {
         return fail(PS_ERR_INVALID, "max_iter must be in [1, %d]", ps::kMaxIterCap);
     if (o.slots < 0) return fail(PS_ERR_INVALID, "slots must be >= 0");
     if (o.check_shift < 0 || o.check_shift > 12) return fail(PS_ERR_INVALID, "check_shift must be in [0, 12]");
-    if (o.shift_invert != 0 && o.shift_invert != -1 && (o.shift_invert < 4 || o.shift_invert > 512))
-        return fail(PS_ERR_INVALID, "shift_invert must be 0, -1 or in [4, 512]");
+    if (o.bisect != 0 && o.bisect != -1) return fail(PS_ERR_INVALID, "bisect must be 0 or -1");
     return PS_OK;
 }
 
 int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
 
-// Golub-Kahan steps before a slow shift may switch to shift-and-invert (0: never).
-int si_start_of(const ps_opts &o) { return o.shift_invert < 0 ? 0 : o.shift_invert > 0 ? o.shift_invert : 24; }
+// 1: shifts that qualify take the inertia bisection; 0: every shift takes Golub-Kahan.
+int bisect_of(const ps_opts &o) { return o.bisect < 0 ? 0 : 1; }
 
 int vec_of(const ps_opts &o) { return o.want_vectors ? 1 : 0; }
 
@@ -141,7 +140,7 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     a->arow = m->arow;
     a->normA = m->fro;
     a->norm2A = m->norm2;
-    a->si_start = si_start_of(o);
+    a->bisect = bisect_of(o);
     a->tol_norm = o.tol_norm;
     a->tol_rel = o.tol_rel;
     a->max_iter = o.max_iter;
@@ -166,7 +165,7 @@ void ps_opts_default(ps_opts *o) {
     o->want_vectors = 0;
     o->slots = 0;
     o->check_shift = 0;
-    o->shift_invert = 0;
+    o->bisect = 0;
 }
 
 const char *ps_last_error(void) { return g_err; }
@@ -588,10 +587,6 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     for (int64_t sl = s0; sl >= kSlotQuantum && slot_cands.size() < 3; sl = round_slots(sl / 2))
         slot_cands.push_back(sl);
     const int shift_cands[3] = {3, 4, 5};
-    // switch points of the shift-and-invert phase (unless the caller turned it off)
-    const int si_cands[3] = {base.shift_invert < 0 ? -1 : 12, base.shift_invert < 0 ? -1 : 24,
-                             base.shift_invert < 0 ? -1 : 48};
-    const int n_si = base.shift_invert < 0 ? 1 : 3;
     size_t wsb = 0;
     if ((st = ps_workspace_size(m, npts, &base, &wsb))) return st;
     void *ws = nullptr;
@@ -604,11 +599,10 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     float best = INFINITY;
     ps_opts pick = base;
     for (size_t i = 0; e == hipSuccess && i < slot_cands.size(); ++i) {
-        for (int c = 0; e == hipSuccess && c < 3 * n_si; ++c) {
+        for (int c = 0; e == hipSuccess && c < 3; ++c) {
             ps_opts t = base;
             t.slots = (int32_t)slot_cands[i];
-            t.check_shift = shift_cands[c % 3];
-            t.shift_invert = si_cands[c / 3];
+            t.check_shift = shift_cands[c];
             t.want_vectors = 0;
             if ((st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr, nullptr, stream)))
                 break;
@@ -635,7 +629,6 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     if (e != hipSuccess) return fail(PS_ERR_HIP, "autotune: %s", hipGetErrorString(e));
     o->slots = pick.slots;
     o->check_shift = pick.check_shift;
-    o->shift_invert = pick.shift_invert;
     return ok();
 }
 
@@ -780,7 +773,7 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
         a.tol_rel = r.tol_rel;
         a.max_iter = r.max_iter;
         a.check_shift = check_shift_of(r);
-        a.si_start = si_start_of(r);
+        a.bisect = bisect_of(r);
         a.want_vectors = 0;
         a.sigma = sigma_dev;
         a.info = info_dev;

@@ -237,15 +237,10 @@ struct Lane {
     double vnorm2;    // |v|^2 of the accumulated vector (known after its last step)
     double vamax;     // largest |v_i|^2 so far (first index on ties)
     cd vph;           // the entry that attains it
-    // Shift-and-invert phase (sigma only): phase 0 Golub-Kahan, 1 factorise
-    // M^H M - sh I next, 2 Lanczos on (M^H M - sh I)^{-1}.  In phases 1-2, k counts the
-    // shift-and-invert steps, theta / gmax / gopen / nchecks / next_check / rho_prev serve
-    // its Ritz checks, a_m = alpha_{k} and b_m = beta_{k} of its tridiagonal, bp = beta_{k-1}.
+    // Inertia bisection (sigma only): phase 1 while a lane bisects, 0 on the Golub-Kahan path.
     int phase;
-    int nfac;         // factorisations tried
-    int kgk;          // Golub-Kahan steps taken before the switch
-    double sh;        // the shift, below sigma_min^2
-    double sig_gk;    // the Golub-Kahan estimate of sigma_min at the switch (an upper bound)
+    int nbis;         // bisection passes so far
+    double blo, bhi;  // bracket: blo < sigma_min (tested), sigma_min <= bhi
     // batch mode: the matrix of the current shift
     int64_t n;
     const double2 *arow;
@@ -268,10 +263,9 @@ struct Kern {
         return BATCH ? ln.norm2A : a.norm2A;
     }
 
-    // Shift-and-invert is compiled for sigma-only kernels with kl + ku >= 1 (the
-    // half-bandwidth of M^H M); a lane uses it only while it is in phase 1 or 2.
-    static constexpr bool SI = !VEC && (KL + KU) >= 1;
-    static __device__ __forceinline__ bool gk(const Lane &ln) { return !SI || ln.phase == 0; }
+    // The bisection is compiled for sigma-only kernels with kl + ku >= 1 (its constants are
+    // defined with it, below); a lane is on the Golub-Kahan path unless it is in phase 1.
+    static __device__ __forceinline__ bool gk(const Lane &ln) { return ln.phase == 0; }
 
     // M[r][c] of M = zI - A from the row band (zero outside the matrix).
     static __device__ __forceinline__ cd mentry(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
@@ -875,271 +869,160 @@ struct Kern {
         eacc_out = Eacc;
     }
 
-    // ---------------------------------------------------------------- shift-and-invert phase
-    // Far from the spectrum the smallest singular values of M = zI - A cluster (relative gaps
-    // of 1e-5 and below), and the Lanczos process on (M^H M)^{-1} needs up to ~n/2 steps.
-    // Once the Golub-Kahan Ritz value gives sigma_est >= sigma_min with a few correct digits
-    // (after EvalArgs::si_start steps, 24 by default), such a lane switches to Lanczos on (H - sh I)^{-1}, H = M^H M, sh = sigma_est^2 (1 - delta)
-    // below sigma_min^2: the top eigenvalue mu = 1 / (sigma_min^2 - sh) stands out ~1/delta
-    // times further relative to the rest of the spectrum, and sigma_min^2 = sh + 1/mu needs mu
-    // only to a relative accuracy ~tol/delta.  H - sh I is positive definite exactly when
-    // sh < sigma_min^2: its banded Cholesky factor (half-bandwidth kl + ku) completes or meets a
-    // non-positive pivot, and then delta grows (2e-3, 1.6e-2, 0.128, then sh = 0) and the
-    // factorisation is repeated.  H is formed from the band inside the factorisation pass; its
-    // rounding (|dH| ~ eps |M|^2) moves sigma by ~eps |M|^2 / sigma, so a lane switches only
-    // where that is far below the tolerance.  With sigma_min bounded away from zero nothing
-    // overflows, so this phase keeps plain doubles (no block exponents).
-    static constexpr int kSiMaxFac = 4;
-    static constexpr int HB = KL + KU;       // half-bandwidth of H
-    // A shift found above sigma_min^2 costs one partial factorisation pass (it stops at the
-    // first non-positive pivot).  After 24 Golub-Kahan steps sigma_est is typically within a
-    // few 1e-4 of sigma_min, so a first delta of 2e-3 rarely fails (4e-4 fails almost always).
-    static __device__ __forceinline__ double si_delta(int nfac) {
-        return nfac == 0 ? 2e-3 : nfac == 1 ? 1.6e-2 : nfac == 2 ? 0.128 : 1.0;
-    }
+    // ---------------------------------------------------------------- inertia bisection
+    // sigma_min^2 is the smallest eigenvalue of H = M^H M, so for t >= 0, t < sigma_min exactly
+    // when H - t^2 I is positive definite, that is when its Cholesky factorisation meets no
+    // non-positive pivot (Sylvester's law of inertia).  One such test is one pass over the rows
+    // that reads only the band of A: H (half-bandwidth HB = kl + ku) is formed row by row from
+    // M = zI - A, and the HB previous rows of the factor stay in registers, so a pass moves no
+    // per-shift data through memory.  Bisection on t between a bound known to lie below
+    // sigma_min and one above it then gives sigma_min to any width above the rounding of the
+    // test, in about log2(sigma / target) passes.
+    //
+    // Rounding: forming H and factorising it perturb H by about eps |M|^2 (backward error),
+    // which moves the decision point sigma_min^2 by as much and sigma_min by eps |M|^2 /
+    // (2 sigma).  A shift uses the bisection only where 32 eps mn^2 (mn = |z| + sqrt(||A||_1
+    // ||A||_inf), at least the 2-norm of |M|) stays below an eighth of sigma * target(sigma),
+    // target(s) = tol_norm ||A||_F + tol_rel s: for sigma >= sigma_adm, the positive root of
+    // tol_rel s^2 + tol_norm ||A||_F s = 256 eps mn^2.  The first test, at t = sigma_adm, decides
+    // whether the shift qualifies; if H - sigma_adm^2 I is not positive definite the shift takes
+    // the Golub-Kahan path instead, which has no such limit (it never forms H).  With sigma_min
+    // above sigma_adm nothing overflows or underflows, so the passes use plain doubles.
+    static constexpr bool BIS = !VEC && (KL + KU) >= 1;
+    static constexpr int HB = KL + KU;          // half-bandwidth of H
+    static constexpr int kBisMaxPass = 128;     // far above the ~30-40 passes a shift needs
 
-    // M[r][c] (zero outside the matrix, including r < 0).
-    static __device__ __forceinline__ cd si_m(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
-        if (r < 0 || c < 0) return czero();
-        return mentry(a, ln, r, c);
-    }
+    // Rows per block of the pass: the M rows a block needs (PB + HB band rows) are loaded
+    // together before its rows are computed, so a pass waits for memory once per block, not
+    // once per row.  Narrower bands take longer blocks (the buffer is (PB + HB) x W entries).
+    static constexpr int PB = W <= 3 ? 8 : W <= 5 ? 4 : W <= 7 ? 2 : 1;
 
-    // Factorisation pass: H - sh I = L L^H with F[i][0] = 1 / L_ii (real) and F[i][e] = L[i][i-e]
-    // (e = 1..HB) stored in the U array; rows past n are identity rows.  The entries of the
-    // previous rows that row i needs are read back from the rows just written.  Returns
-    // false when a pivot is not positive (sh is not below sigma_min^2).
-    static __device__ bool si_factor(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln) {
-        const int64_t n = nn(a, ln), T = w.slots;
-        const int64_t npad = ((n + CH - 1) / CH) * CH;
-        const double sh = ln.sh;
-        bool ok = true;
-        for (int64_t i = 0; i < npad; ++i) {
-            cd li[HB + 1];
+    // One test: true when every pivot of the Cholesky factorisation of H - sh I is positive
+    // (checked at the end of each block: a lane whose pivot fails stops there).  A completed
+    // pass also returns hmin = min_i H[i][i] = min_i |M e_i|^2, an upper bound on sigma_min^2.
+    static __device__ bool pd_pass(const EvalArgs &a, const Lane &ln, double sh, double &hmin) {
+        const int64_t n = nn(a, ln);
+        const double2 *ab = band(a, ln);
+        const cd z = ln.z;
+        // The factor rows i-1 .. i-HB: P[e-1][f-1] = L[i-e][i-e-f] (f = 1 .. HB-e, the entries
+        // later rows still need) and R[e-1] = 1 / L[i-e][i-e]; rows before the first are zero.
+        constexpr int HA = HB > 0 ? HB : 1;   // (the pass is not compiled in for HB = 0)
+        cd P[HA][HA];
+        double R[HA];
 #pragma unroll
-            for (int e = 0; e <= HB; ++e) li[e] = czero();
-            double lii = 1.0;
-            if (i < n) {
-                // H[i][i-e] = sum_r conj(M[r][i]) M[r][i-e] over r in [i - ku, i - e + kl]
+        for (int e = 0; e < HA; ++e) {
+            R[e] = 0.0;
+#pragma unroll
+            for (int f = 0; f < HA; ++f) P[e][f] = czero();
+        }
+        double hm = 0x1p1000;
+        bool ok = true;
+        for (int64_t i0 = 0; i0 < n; i0 += PB) {
+            // Mb[q][d] = M[r][r + d - kl] for the rows r = i0 - ku + q (zero outside the matrix)
+            cd Mb[PB + HB][W];
+#pragma unroll
+            for (int q = 0; q < PB + HB; ++q) {
+                const int64_t r = i0 - KU + q;
+                const bool in = r >= 0 && r < n;
+                const int64_t rc = in ? r : 0;
+#pragma unroll
+                for (int d = 0; d < W; ++d) {
+                    const cd v = ab[rc * W + d];
+                    const cd m = d == KL ? C(z.x - v.x, z.y - v.y) : C(-v.x, -v.y);
+                    Mb[q][d] = in ? m : czero();
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                const bool row = i0 + p < n;   // rows past n are identity rows
+                // H[i][i-e] = sum_t conj(M[r][i]) M[r][i-e], r = i - ku + t, t = 0 .. HB - e
                 cd h[HB + 1];
 #pragma unroll
                 for (int e = 0; e <= HB; ++e) {
                     double hx = 0.0, hy = 0.0;
 #pragma unroll
                     for (int t = 0; t <= HB - e; ++t) {
-                        const int64_t r = i - KU + t;
-                        const cd mi = si_m(a, ln, r, i), mj = si_m(a, ln, r, i - e);
+                        const cd mi = Mb[p + t][HB - t], mj = Mb[p + t][HB - t - e];
                         hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
                         hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
                     }
-                    h[e] = C(hx, hy);
+                    h[e] = row ? C(hx, hy) : czero();
                 }
-                double dsq = h[0].x - sh;
+                if (row) hm = fmin(hm, h[0].x);
+                // L[i][j], j = i - e: (H[i][j] - sum_{m < j} L[i][m] conj(L[j][m])) / L[j][j]
+                double dsq = row ? h[0].x - sh : 1.0;
+                cd li[HB + 1];
 #pragma unroll
                 for (int e = HB; e >= 1; --e) {
-                    // L[i][j], j = i - e: (H[i][j] - sum_{m < j} L[i][m] conj(L[j][m])) / L[j][j]
-                    const int64_t j = i - e;
-                    if (j < 0) continue;
                     cd acc = h[e];
 #pragma unroll
-                    for (int e2 = HB; e2 > e; --e2)
-                        acc = cfnmac(w.U[(j * W + (e2 - e)) * T + s], li[e2], acc);   // L[j][i-e2]
-                    li[e] = cscale(acc, w.U[(j * W + 0) * T + s].x);                  // times 1 / L[j][j]
+                    for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[e - 1][e2 - e - 1], li[e2], acc);
+                    li[e] = cscale(acc, R[e - 1]);
                     dsq -= cabs2(li[e]);
                 }
-                if (!(dsq > 0.0)) {
-                    ok = false;
-                    break;            // sh is not below sigma_min^2: the factor is discarded
+                ok = ok && dsq > 0.0;
+#pragma unroll
+                for (int e = HB - 1; e >= 1; --e) {
+                    R[e] = R[e - 1];
+#pragma unroll
+                    for (int f = 0; f + e + 1 < HB; ++f) P[e][f] = P[e - 1][f];
                 }
-                lii = sqrt(dsq);
-            }
-            w.U[(i * W + 0) * T + s] = C(1.0 / lii, 0.0);
+                R[0] = rsqrt(dsq);             // not used once ok is false
 #pragma unroll
-            for (int e = 1; e <= HB; ++e) w.U[(i * W + e) * T + s] = li[e];
+                for (int f = 1; f < HB; ++f) P[0][f - 1] = li[f];
+            }
+            if (!ok) return false;
         }
-        return ok;
+        hmin = hm;
+        return true;
     }
 
-    // Forward pass of step k = ln.k + 1: r_k = Z - (alpha_{k-1} / beta_{k-1}) X with Z = w' of
-    // the previous step and X = r_{k-1}; r_k is stored over Z, y = L^{-1} r_k into vy.  Returns
-    // |r_k|^2.  The two vectors alternate between vu and vv with the parity of k.  Step 1 starts
-    // from the shift's random start vector h / |h| again: the last Golub-Kahan vector would be
-    // a poor start, being orthogonal to the Krylov space that holds the best approximation of
-    // the wanted singular vector.
-    static __device__ double si_fwd(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln) {
-        const int64_t n = nn(a, ln), T = w.slots;
-        const int64_t npad = ((n + CH - 1) / CH) * CH;
-        const int k = ln.k + 1;
-        double2 *Z = (k & 1) ? w.vv : w.vu;
-        const double2 *X = (k & 1) ? w.vu : w.vv;
-        const bool first = k == 1;
-        const double cx = first ? 0.0 : ln.a_m / ln.b_m;
-        cd yw[HB + 1];             // yw[d] = y_{i-d}
-#pragma unroll
-        for (int d = 0; d <= HB; ++d) yw[d] = czero();
-        double nr = 0.0;
-        for (int64_t q = 0; q < npad / CH; ++q) {
-            const int64_t i0 = q * CH;
-            cd Fr[CH][W], zr[CH], xr[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int64_t i = i0 + c;
-#pragma unroll
-                for (int d = 0; d < W; ++d) Fr[c][d] = w.U[(i * W + d) * T + s];
-                zr[c] = Z[i * T + s];
-                xr[c] = X[i * T + s];
-                if (first) zr[c] = i < n ? start_entry(a.seed, i) : czero();
-            }
-            const double fz = first ? 1.0 / sqrt(ln.nrm_h) : 1.0;
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const cd r = C(fma(-cx, xr[c].x, fz * zr[c].x), fma(-cx, xr[c].y, fz * zr[c].y));
-                cd acc = r;
-#pragma unroll
-                for (int d = 1; d <= HB; ++d) acc = cfnma(Fr[c][d], yw[d], acc);
-                const cd y = cscale(acc, Fr[c][0].x);
-                Z[(i0 + c) * T + s] = r;
-                w.vy[(i0 + c) * T + s] = y;
-                nr = fma(r.x, r.x, fma(r.y, r.y, nr));
-#pragma unroll
-                for (int d = HB; d >= 2; --d) yw[d] = yw[d - 1];
-                yw[1] = y;
-            }
-        }
-        return nr;
+    // A fresh shift: phase 1 (bisection) if it may qualify, with the bracket [sigma_adm, mn].
+    static __device__ void bis_begin(const EvalArgs &a, Lane &ln) {
+        ln.phase = 0;
+        ln.nbis = 0;
+        if (!BIS || !a.bisect) return;
+        const double mn = hypot(ln.z.x, ln.z.y) + nrm2(a, ln);
+        if (!(mn < 1e100)) return;
+        const double b = a.tol_norm * fro(a, ln), c = 256.0 * 0x1p-52 * mn * mn;
+        const double adm = 2.0 * c / (b + sqrt(b * b + 4.0 * a.tol_rel * c));   // inf if the target is 0
+        if (!(adm < mn)) return;
+        ln.phase = 1;
+        ln.blo = adm;
+        ln.bhi = mn;
     }
 
-    // Backward pass of step k = ln.k: x = L^{-H} y (= beta_k (H - sh I)^{-1} q_k), and
-    // w' = x / beta_k - (beta_k / beta_{k-1}) r_{k-1} stored over X.  Returns Re(r_k^H x)
-    // = alpha_k beta_k^2.
-    static __device__ double si_bwd(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln) {
-        const int64_t n = nn(a, ln), T = w.slots;
-        const int64_t npad = ((n + CH - 1) / CH) * CH;
-        const int k = ln.k;
-        const double2 *Z = (k & 1) ? w.vv : w.vu;    // r_k
-        double2 *X = (k & 1) ? w.vu : w.vv;          // r_{k-1}, then w'
-        const double ib = 1.0 / ln.b_m;
-        const double cx = k == 1 ? 0.0 : ln.b_m / ln.bp;
-        cd P[HB + 1];              // P[t]: sum of conj(L[j][i-t]) x_j over the rows j > i done so far
-#pragma unroll
-        for (int t = 0; t <= HB; ++t) P[t] = czero();
-        double al = 0.0;
-        for (int64_t q = npad / CH - 1; q >= 0; --q) {
-            const int64_t i0 = q * CH + CH - 1;
-            cd Fr[CH][W], yr[CH], zr[CH], xr[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int64_t i = i0 - c;
-#pragma unroll
-                for (int d = 0; d < W; ++d) Fr[c][d] = w.U[(i * W + d) * T + s];
-                yr[c] = w.vy[i * T + s];
-                zr[c] = Z[i * T + s];
-                xr[c] = X[i * T + s];
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const cd x = cscale(C(yr[c].x - P[0].x, yr[c].y - P[0].y), Fr[c][0].x);
-#pragma unroll
-                for (int t = 0; t < HB; ++t) {
-                    const cd f = Fr[c][t + 1];        // L[i][i-t-1]
-                    const cd base = t + 1 < HB ? P[t + 1] : czero();
-                    P[t] = C(base.x + f.x * x.x + f.y * x.y, base.y + f.x * x.y - f.y * x.x);
-                }
-                X[(i0 - c) * T + s] = C(fma(-cx, xr[c].x, x.x * ib), fma(-cx, xr[c].y, x.y * ib));
-                al = fma(zr[c].x, x.x, fma(zr[c].y, x.y, al));
-            }
-        }
-        return al;
-    }
-
-    // Ritz check of the shift-and-invert tridiagonal T_k (alpha_1..alpha_k, beta_2..beta_k)
-    // with the next beta known: mu is within r = beta_{k+1} |y_k| of theta, and
-    // sigma^2 = sh + 1/mu moves by at most r / theta^2, sigma by r / (2 sigma theta^2).
-    // That bound holds for the eigenvalue nearest theta.  When sigma_min has a neighbour
-    // within ~1e-7 (relative), a Ritz vector mixing the two still has a small residual
-    // (|r| ~ |c1 c2| (mu_1 - mu_2)) while theta sits nearer mu_2; so the residual must also
-    // fall below 2^-30 theta, small enough that the pair has separated, before a shift
-    // counts as converged.  These steps are cheap: the residual falls geometrically.  As in
-    // the Golub-Kahan phase, theta unchanged to 2^-44 over two checks also ends the phase
-    // (after convergence the residual estimate can stall once Ritz values repeat).
-    static __device__ bool si_check(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, int k,
-                                    double beta_next) {
-        TopEig te = top_eig(w.hist, w.slots, s, k, ln.theta, fmax(ln.gmax, ln.gopen));
-        const double th = te.theta;
-        if (!(th > 0.0)) return false;
-        const double sig = sqrt(ln.sh + 1.0 / th);
-        const double r = beta_next * sqrt(te.yk2);
-        const double target = a.tol_norm * fro(a, ln) + a.tol_rel * sig;
-        const double delta = fmax(th - ln.theta, 0.0);
-        const bool flat = ln.nchecks >= 1 && delta <= 0x1p-44 * th;
-        const bool flat_prev = ln.rho_prev > 0.0;
-        ln.rho_prev = flat ? 1.0 : 0.0;
-        ln.theta = th;
-        ln.nchecks += 1;
-        const bool sep = r <= 0x1p-30 * th;
-        return (r <= 2.0 * sig * th * th * target && sep) || (flat && flat_prev);
-    }
-
-    // One cycle of a lane in the shift-and-invert phase: the factorisation (phase 1), or one
-    // Lanczos step (phase 2).  Finishes the shift when converged.
-    static __device__ void si_cycle(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
-        const int64_t T = w.slots;
-        if (ln.phase == 1) {
-            const bool ok = si_factor(a, w, s, ln);
-            ln.nfac += 1;
-            if (ok) {
-                ln.phase = 2;
-                ln.k = 0;
-                ln.theta = 0.0;
-                ln.gmax = ln.gopen = 0.0;
-                ln.nchecks = 0;
-                ln.next_check = 1;
-                ln.rho_prev = 0.0;
-                ln.a_m = 0.0;
-                ln.b_m = 1.0;
-                ln.bp = 1.0;
-            } else if (ln.nfac < kSiMaxFac) {
-                ln.sh = ln.sig_gk * ln.sig_gk * (1.0 - si_delta(ln.nfac));
-            } else {
-                // M^H M is not numerically positive definite: report the Golub-Kahan estimate
-                ln.k = 0;
-                finish_si(a, ln, ln.sig_gk, 2);
-            }
+    // One bisection pass of a lane in phase 1.  The first pass tests sigma_adm; later passes
+    // split the bracket at its geometric mean while hi > 2 lo, then at its midpoint.  The
+    // result is the midpoint of the final bracket, whose width is at most target(lo).
+    static __device__ void bis_cycle(const EvalArgs &a, Lane &ln) {
+        const bool first = ln.nbis == 0;
+        const double lo = ln.blo, hi = ln.bhi;
+        const double t = first ? lo : hi > 2.0 * lo ? sqrt(lo * hi) : 0.5 * (lo + hi);
+        double hmin = 0.0;
+        const bool pd = pd_pass(a, ln, t * t, hmin);
+        ln.nbis += 1;
+        if (first && !pd) {           // sigma_min < sigma_adm: the Golub-Kahan path
+            ln.phase = 0;
             return;
         }
-        const int kn = ln.k + 1;                       // step whose vector is formed now
-        const double beta = sqrt(si_fwd(a, w, s, ln));
-        if (kn >= 2) {
-            w.hist[((int64_t)(kn - 2) * 2 + 1) * T + s] = beta * beta;
-            const int k = kn - 1;                      // T_k is complete
-            const bool cap = kn >= a.max_iter;
-            if (!(beta > 0.0) || k >= ln.next_check || cap) {
-                const bool conv = si_check(a, w, s, ln, k, beta) || !(beta > 0.0);
-                const int step = k >> 3;
-                ln.next_check = k + (step > 1 ? step : 1);
-                if (conv || cap) {
-                    // theta > 0 for the positive definite (H - sh I)^{-1}; otherwise keep the
-                    // Golub-Kahan bound
-                    const bool good = ln.theta > 0.0;
-                    finish_si(a, ln, good ? sqrt(ln.sh + 1.0 / ln.theta) : ln.sig_gk, conv && good ? 0 : 2);
-                    return;
-                }
-            }
-            ln.gmax = fmax(ln.gmax, ln.gopen + beta);
+        if (pd) {
+            ln.blo = t;
+            if (first) ln.bhi = fmin(hi, sqrt(hmin));
+        } else {
+            ln.bhi = t;
         }
-        ln.bp = ln.b_m;
-        ln.b_m = beta;
-        ln.k = kn;
-        const double al = si_bwd(a, w, s, ln) / (beta * beta);
-        w.hist[((int64_t)(kn - 1) * 2 + 0) * T + s] = al;
-        ln.a_m = al;
-        ln.gopen = fabs(al) + (kn >= 2 ? beta : 0.0);
+        const double target = a.tol_norm * fro(a, ln) + a.tol_rel * ln.blo;
+        const double mid = 0.5 * (ln.blo + ln.bhi);
+        const bool done = ln.bhi - ln.blo <= target || !(mid > ln.blo && mid < ln.bhi);
+        if (done || ln.nbis >= kBisMaxPass) finish_bis(a, ln, mid, done ? 0 : 2);
     }
 
-    static __device__ void finish_si(const EvalArgs &a, Lane &ln, double sigma, int flags) {
-        flags |= PS_PT_SHIFT_INVERT | ((ln.nfac < 15 ? ln.nfac : 15) << 4) | (ln.k << 8);
+    static __device__ void finish_bis(const EvalArgs &a, Lane &ln, double sigma, int flags) {
+        flags |= PS_PT_BISECT | (ln.nbis << 8);
         a.sigma[ln.pid] = sigma;
         if (a.info) a.info[ln.pid] = flags;
-        if (a.iters) a.iters[ln.pid] = ln.kgk;
+        if (a.iters) a.iters[ln.pid] = 0;
         if (a.sens) a.sens[ln.pid] = (uint8_t)(sigma <= a.eps);
         ln.active = false;
         ln.phase = 0;
@@ -1380,21 +1263,6 @@ struct Kern {
                 finish(a, w, s, ln, 0);
                 return;
             }
-            if (SI && a.si_start > 0 && ln.k >= a.si_start && ln.k < kcap) {
-                // switch to shift-and-invert where the rounding of M^H M (about
-                // 32 eps |M|^2 / sigma in sigma) stays below an eighth of the target
-                const double sig = ldexp(1.0 / sqrt(te.theta), -ln.E0);   // >= sigma_min
-                const double mn = hypot(ln.z.x, ln.z.y) + nrm2(a, ln);
-                const double target = a.tol_norm * fro(a, ln) + a.tol_rel * sig;
-                if (mn < 1e100 && sig < 1e100 && 32.0 * 0x1p-52 * mn * mn <= 0.125 * sig * target) {
-                    ln.phase = 1;
-                    ln.nfac = 0;
-                    ln.kgk = ln.k;
-                    ln.sig_gk = sig;
-                    ln.sh = sig * sig * (1.0 - si_delta(0));
-                    return;
-                }
-            }
         }
         if (ln.k >= kcap) {
             if (!checked) {
@@ -1403,6 +1271,46 @@ struct Kern {
             }
             finish(a, w, s, ln, 2);
         }
+    }
+
+    // In the kernels with kl = 4 the four sweeps are compiled as functions of their own.
+    // Inlined there, they put the kernel into heavy register spilling, and some of those
+    // builds returned wrong values for ku <= 2 on the Golub-Kahan path, although the same
+    // source is correct when its lane code runs on the CPU and when the sweeps are compiled
+    // separately: a code-generation problem, guarded by the all-band-shapes GPU test.  The
+    // other kernels keep the sweeps inline (separate sweeps cost about 2x in time there).
+    static constexpr bool kSplitSweeps = KL >= 4;
+    static __device__ __noinline__ void f1_sep(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        f1(a, w, s, ln);
+    }
+    static __device__ __noinline__ void b1_sep(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln,
+                                               double &acc, int &eacc) {
+        b1(a, w, s, ln, acc, eacc);
+    }
+    static __device__ __noinline__ void f2_sep(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        f2(a, w, s, ln);
+    }
+    static __device__ __noinline__ void b2_sep(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln,
+                                               double &acc, int &eacc) {
+        b2(a, w, s, ln, acc, eacc);
+    }
+    static __device__ __forceinline__ void sweep_f1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        if constexpr (kSplitSweeps) f1_sep(a, w, s, ln);
+        else f1(a, w, s, ln);
+    }
+    static __device__ __forceinline__ void sweep_b1(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln,
+                                                    double &acc, int &eacc) {
+        if constexpr (kSplitSweeps) b1_sep(a, w, s, ln, acc, eacc);
+        else b1(a, w, s, ln, acc, eacc);
+    }
+    static __device__ __forceinline__ void sweep_f2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        if constexpr (kSplitSweeps) f2_sep(a, w, s, ln);
+        else f2(a, w, s, ln);
+    }
+    static __device__ __forceinline__ void sweep_b2(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln,
+                                                    double &acc, int &eacc) {
+        if constexpr (kSplitSweeps) b2_sep(a, w, s, ln, acc, eacc);
+        else b2(a, w, s, ln, acc, eacc);
     }
 
     // The workspace is laid out [wavefront][row][component][lane]: the 64 lanes of a
@@ -1470,10 +1378,8 @@ struct Kern {
         ln.normA = a.normA;
         ln.norm2A = a.norm2A;
         ln.phase = 0;
-        ln.nfac = 0;
-        ln.kgk = 0;
-        ln.sh = 0.0;
-        ln.sig_gk = 0.0;
+        ln.nbis = 0;
+        ln.blo = ln.bhi = 0.0;
         while (true) {
             bool may_refill = !ln.active && !ln.exhausted;
             if (may_refill) {
@@ -1520,6 +1426,7 @@ struct Kern {
                         ln.pid = tile_flat((int64_t)id, a.nx, a.ny);   // full grid: output at the flat index
                         ln.z = grid_point(a, ln.pid);
                     }
+                    if (!VEC) bis_begin(a, ln);
                 }
             }
             if (__all(!ln.active && ln.exhausted)) break;
@@ -1528,20 +1435,20 @@ struct Kern {
             double acc;
             int eacc;
             if (!VEC) {
-                // Golub-Kahan lanes take the four sweeps; lanes in the shift-and-invert phase
-                // take one factorisation or step per cycle.  Each part runs only if a lane of
-                // the wavefront needs it.
-                if (__any(ln.active && gk(ln))) {
-                    f1(a, w, s, ln);
-                    if (ln.active && gk(ln) && ln.sing) finish(a, w, s, ln, 0);
-                    b1(a, w, s, ln, acc, eacc);
-                    if (ln.active && gk(ln)) after_b1(a, w, s, ln, acc, eacc);
-                    f2(a, w, s, ln);
-                    b2(a, w, s, ln, acc, eacc);
-                    if (ln.active && gk(ln)) after_b2(a, w, s, ln, acc, eacc, kcap);
+                // Lanes in the bisection take one pass per cycle (a fresh lane's first pass
+                // decides whether it stays there); Golub-Kahan lanes take the four sweeps.
+                // Each part runs only if a lane of the wavefront needs it.
+                if (BIS && __any(ln.active && !gk(ln))) {
+                    if (ln.active && !gk(ln)) bis_cycle(a, ln);
                 }
-                if (SI && __any(ln.active && !gk(ln))) {
-                    if (ln.active && !gk(ln)) si_cycle(a, w, s, ln);
+                if (__any(ln.active && gk(ln))) {
+                    sweep_f1(a, w, s, ln);
+                    if (ln.active && gk(ln) && ln.sing) finish(a, w, s, ln, 0);
+                    sweep_b1(a, w, s, ln, acc, eacc);
+                    if (ln.active && gk(ln)) after_b1(a, w, s, ln, acc, eacc);
+                    sweep_f2(a, w, s, ln);
+                    sweep_b2(a, w, s, ln, acc, eacc);
+                    if (ln.active && gk(ln)) after_b2(a, w, s, ln, acc, eacc, kcap);
                 }
                 continue;
             }
@@ -1550,9 +1457,9 @@ struct Kern {
             const bool act0 = ln.active;
             const bool fin = act0 && ln.stage == 2;        // only f2 and b2, from vacc
             if (fin) ln.active = false;
-            f1(a, w, s, ln);
+            sweep_f1(a, w, s, ln);
             if (ln.active && ln.sing) finish(a, w, s, ln, 0);
-            b1(a, w, s, ln, acc, eacc);
+            sweep_b1(a, w, s, ln, acc, eacc);
             const int st0 = ln.stage;
             if (ln.active) after_b1(a, w, s, ln, acc, eacc);
             const bool hold = ln.active && ln.stage != st0;   // entered the replay: starts next cycle
@@ -1562,10 +1469,10 @@ struct Kern {
                 ln.a_e = 0;
             }
             if (hold) ln.active = false;
-            f2(a, w, s, ln);
+            sweep_f2(a, w, s, ln);
             const bool endrep = ln.active && ln.stage == 1 && ln.k == ln.kfinal;   // vacc is complete
             if (endrep) ln.active = false;
-            b2(a, w, s, ln, acc, eacc);
+            sweep_b2(a, w, s, ln, acc, eacc);
             if (hold || endrep) ln.active = true;
             if (endrep) {
                 ln.stage = 2;

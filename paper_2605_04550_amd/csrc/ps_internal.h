@@ -74,8 +74,7 @@ struct EvalArgs {
     const double2 *arow = nullptr; // [n][kl+ku+1] row band, zero outside the matrix
     double normA = 0.0;            // ||A||_F
     double norm2A = 0.0;           // upper bound on ||A||_2 (sqrt(||A||_1 ||A||_inf))
-    int si_start = 24;             // Golub-Kahan steps before a slow shift may switch to
-                                   // shift-and-invert Lanczos (0: never)
+    int bisect = 1;                // 1: shifts that qualify take the inertia bisection
     int mode = kShiftList;
     const double2 *z = nullptr;
     const int64_t *idx = nullptr;

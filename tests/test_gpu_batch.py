@@ -82,7 +82,7 @@ def test_batch64_workload_runs_and_matches_stored_oracle_points():
     sel = np.concatenate([np.arange(o, o + 4915) for o in r["offsets"]])
     assert np.all(np.isfinite(sig[sel])) and np.all(sig[sel] >= 0)
     print("batch64: %d shifts in %.3f s = %.0f shifts/s (first call, with set-up); Golub-Kahan steps mean %.1f "
-          "max %d; shift-and-invert at %d shifts; MAXITER %d"
+          "max %d; bisection at %d shifts; MAXITER %d"
           % (len(sel), dt, len(sel) / dt, it[sel].mean(), it[sel].max(), np.sum((info[sel] & 8) != 0),
              np.sum((info[sel] & 2) != 0)), flush=True)
     g = golden("batch_pts")

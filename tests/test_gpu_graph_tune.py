@@ -89,11 +89,11 @@ def test_autotune_returns_a_valid_plan():
     z = torch.tensor(oracle.grid_points(w["grid"]), dtype=torch.complex128, device="cuda")
     o = api.autotune(mat, z)
     assert o.slots >= 256 and o.slots % 256 == 0 and o.check_shift in (3, 4, 5)
-    assert o.shift_invert in (12, 24, 48)
-    r = api.sigma_min(mat, z, slots=o.slots, shift_invert=o.shift_invert)
+    assert o.bisect == 0
+    r = api.sigma_min(mat, z, slots=o.slots, bisect=o.bisect == 0)
     gold = golden("grcar100_all")
     sig = r["sigma"].cpu().numpy()
     assert np.all(np.abs(sig - gold["sigma"]) <= tol(w["band"].fro, gold["sigma"]))
-    print("autotuned plan: slots %d, check_shift %d, shift_invert %d" % (o.slots, o.check_shift, o.shift_invert))
-    off = api.autotune(mat, z, shift_invert=False)
-    assert off.shift_invert == -1
+    print("autotuned plan: slots %d, check_shift %d" % (o.slots, o.check_shift))
+    off = api.autotune(mat, z, bisect=False)
+    assert off.bisect == -1

@@ -123,52 +123,60 @@ def test_random1000_grid_vs_oracle():
 
 
 def test_toeplitz2000_points_vs_oracle():
-    """Both ways of finishing a slow shift: the Golub-Kahan process alone, and the switch to
-    shift-and-invert Lanczos (which the far points of this workload take)."""
+    """Both ways of computing a shift: the Golub-Kahan process alone, and the inertia
+    bisection (which every point of this set with sigma well above the rounding of
+    (zI-A)^H (zI-A) takes)."""
     api = _api()
     import torch
     g = golden("toeplitz2000_pts")
     w = W.workload("toeplitz2000")
     mat = api.BandedMatrix.from_band(w["band"])
     z = torch.tensor(g["z"], dtype=torch.complex128, device="cuda")
-    for si in (False, True):
-        r = api.sigma_min(mat, z, shift_invert=si)
+    for bis in (False, True):
+        r = api.sigma_min(mat, z, bisect=bis)
         sig = r["sigma"].cpu().numpy()
         info = r["info"].cpu().numpy()
-        _check("toeplitz n=2000 (shift-invert %s)" % ("on" if si else "off"), sig, g["sigma"], w["band"].fro)
+        it = r["iters"].cpu().numpy()
+        _check("toeplitz n=2000 (bisection %s)" % ("on" if bis else "off"), sig, g["sigma"], w["band"].fro)
         assert np.all((info & 2) == 0)
         used = (info & 8) != 0
-        print("toeplitz: Golub-Kahan steps", r["iters"].cpu().numpy().tolist(), "shift-invert steps",
-              (info >> 8).tolist(), "factorisations", ((info >> 4) & 15).tolist())
-        if si:
-            assert used.sum() >= 4          # the far points switch
-            assert np.all(r["iters"].cpu().numpy()[used] >= 24)
+        print("toeplitz: Golub-Kahan steps", it.tolist(), "bisection passes", (info >> 8).tolist())
+        if bis:
+            assert used.sum() >= 4
+            assert np.all(it[used] == 0) and np.all((info[used] >> 8) >= 2)
+            # the shifts that do not qualify have sigma below the rounding limit
+            assert np.all(g["sigma"][~used] < 1e-3)
         else:
             assert not used.any()
 
 
-def test_shift_invert_across_band_shapes():
-    """Random banded matrices of every kl + ku in 1..4 at points far from the spectrum, where
-    the slow shifts switch: the same sigma as the Golub-Kahan-only path and the oracle."""
+def test_bisection_across_band_shapes():
+    """Random banded matrices of every half-bandwidth kl + ku of (zI-A)^H (zI-A) from 1 to 8,
+    at points far from the spectrum (bisection) and near it: the same sigma as the
+    Golub-Kahan-only path and the oracle."""
     api = _api()
     import torch
-    for k, (n, kl, ku) in enumerate([(400, 1, 0), (400, 0, 2), (350, 2, 1), (300, 1, 3), (250, 4, 0)]):
+    shapes = [(400, 1, 0), (400, 0, 2), (350, 2, 1), (300, 1, 3), (250, 4, 0), (230, 3, 3), (200, 4, 4)]
+    for k, (n, kl, ku) in enumerate(shapes):
         band = W.random_banded(n, kl, ku, seed=900 + k)
         rng = np.random.default_rng(90 + k)
         a, b, c, d = W.gershgorin_box(band)
         ang = rng.uniform(0, 2 * np.pi, 24)
-        rad = rng.uniform(0.6, 1.0, 24) * max(b - a, d - c)
+        rad = rng.uniform(0.05, 1.0, 24) * max(b - a, d - c)
         z = 0.5 * (a + b) + 0.5j * (c + d) + rad * np.exp(1j * ang)
         zt = torch.tensor(z, dtype=torch.complex128, device="cuda")
         mat = api.BandedMatrix.from_band(band)
         on = api.sigma_min(mat, zt)
-        off = api.sigma_min(mat, zt, shift_invert=False)
+        off = api.sigma_min(mat, zt, bisect=False)
         s_on, s_off = on["sigma"].cpu().numpy(), off["sigma"].cpu().numpy()
-        pick = np.arange(0, 24, 8)
+        info = on["info"].cpu().numpy()
+        assert np.all((info & 2) == 0)
+        pick = np.arange(0, 24, 4)
         ref = oracle.sigma_min(band, z[pick])["sigma"]
-        _check("n=%d kl=%d ku=%d shift-invert vs oracle" % (n, kl, ku), s_on[pick], ref, band.fro)
+        _check("n=%d kl=%d ku=%d bisection vs oracle" % (n, kl, ku), s_on[pick], ref, band.fro)
         bnd = tol(band.fro, s_off)
         assert np.all(np.abs(s_on - s_off) <= 2 * bnd)
-        print("kl=%d ku=%d: switched %d of 24; steps GK-only mean %.1f, with switch GK %.1f + SI %.1f"
-              % (kl, ku, int(np.sum((on["info"].cpu().numpy() & 8) != 0)), off["iters"].float().mean().item(),
-                 on["iters"].float().mean().item(), (on["info"].cpu().numpy() >> 8).mean()))
+        used = (info & 8) != 0
+        assert used.sum() >= 8
+        print("kl=%d ku=%d: bisection at %d of 24 (passes mean %.1f); Golub-Kahan steps mean %.1f (all points)"
+              % (kl, ku, used.sum(), (info[used] >> 8).mean(), off["iters"].float().mean().item()))
