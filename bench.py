@@ -18,16 +18,22 @@ stream, back to back).  value = shifts evaluated per second over the timed steps
                                               (writes profiles/toeplitz2000_traffic.json)
 
 Prints ONE JSON line.  The roofline object prices the dominant kernel (the persistent
-LU + inverse-Lanczos kernel, full-grid launch) by its algorithmic bytes: per shift
+eval kernel, full-grid launch).  Most shifts of this workload take the inertia bisection,
+whose passes read only the band of A (cached) and keep their state in registers: FP64
+arithmetic, so the roofline is "alu" against the FP64 vector peak (78.6 TFLOP/s).  Per row
+of a pass, with hb = kl + ku and kt test points per pass (3 for hb <= 2, 2 for hb <= 4,
+else 1):
+  F_row = 8 (hb+1)(hb+2)/2                      (H[i][i-e], e = 0..hb: complex multiply-adds)
+        + kt (8 hb(hb-1)/2 + 5 hb + 3)         (per test: the factor row, its scalings,
+                                                 |l|^2 terms and the pivot)
+and a launch performs F = F_row * n * (sum of the passes of its shifts, from the info word);
+every pass covers all n rows.  The shifts on the Golub-Kahan path move
   B_LU   = (w_L + w_U) 16 n + n                 (L, U, pivots written once)
   B_step = (2 (w_L + w_U) + 10) 16 n + 2 n      (factors read twice, ten vector passes,
                                                   pivots read twice) per Lanczos step
-  B_out  = 16
-plus, for a shift that switched to shift-and-invert Lanczos, w_U 16 n per factorisation of
-(zI-A)^H (zI-A) - s I and (2 w_U + 8) 16 n per step of it, plus the band of A
-(kl + ku + 1) 16 n once per launch, with w_L = kl, w_U = kl + ku + 1 and the step counts of
-each shift as returned by the kernel (iters and the info word).  Duration: HIP events on
-the stream the kernel runs on.  Peak: 8 TB/s (MI355X HBM3E).
+plus 16 bytes of output per shift and the band once (w_L = kl, w_U = kl + ku + 1); those
+bytes are reported beside the roofline.  Duration: HIP events on the stream the kernel
+runs on.
 """
 from __future__ import annotations
 
@@ -43,6 +49,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak
 EPS_ZONE = 1e-2
 CALIB_BYTES = 1 << 30          # the calibration copy: 1 GiB read, 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
@@ -124,14 +131,16 @@ def algorithmic_bytes(n, kl, ku, iters, info=None):
     return float(total)
 
 
-def bisection_flops(n, kl, ku, info):
-    """Floating-point operations of the bisection passes of one launch, counting every pass as
-    complete (a pass that meets a non-positive pivot stops early, so this is an upper bound).
-    Per row, with hb = kl + ku: forming H[i][i-e] for e = 0..hb takes (hb+1)(hb+2)/2 complex
-    multiply-adds (8 flops each); the factor row takes hb(hb-1)/2 more, plus per entry a scale
-    by 1/L_jj (2) and |l|^2 (3), and the pivot 3 (the subtraction, the bound, 1/sqrt)."""
+def test_points(kl, ku):
     hb = kl + ku
-    per_row = 8 * ((hb + 1) * (hb + 2) // 2 + hb * (hb - 1) // 2) + 5 * hb + 3
+    return 3 if hb <= 2 else 2 if hb <= 4 else 1
+
+
+def bisection_flops(n, kl, ku, info):
+    """Floating-point operations of the bisection passes of one launch (every pass covers
+    all n rows): F_row * n * total passes, F_row as in the module docstring."""
+    hb, kt = kl + ku, test_points(kl, ku)
+    per_row = 8 * (hb + 1) * (hb + 2) // 2 + kt * (8 * hb * (hb - 1) // 2 + 5 * hb + 3)
     info = np.asarray(info, dtype=np.int64)
     passes = np.where((info & 8) != 0, info >> 8, 0).astype(np.float64)
     return float(np.sum(passes) * n * per_row)
@@ -308,6 +317,8 @@ def main():
     achieved = bytes_full / dur_full / 1e9
     bytes_mask = algorithmic_bytes(band.n, band.kl, band.ku, it_mask, info_mask)
     si_full = (info_full & 8) != 0
+    flops_full = bisection_flops(band.n, band.kl, band.ku, info_full)
+    flops_mask = bisection_flops(band.n, band.kl, band.ku, info_mask)
 
     # plain per-shift GPU path (the speedup denominator): the same numerics and tolerance,
     # one launch per shift, no batching, on a seeded sample of the full grid
@@ -356,24 +367,26 @@ def main():
             "maxiter_points_full": int(np.sum((info_full & 2) != 0)),
             "bisection_points_full": int(si_full.sum()),
             "bisection_passes_mean": float((info_full[si_full] >> 8).mean()) if si_full.any() else 0.0,
-            "bisection_flops_full": bisection_flops(band.n, band.kl, band.ku, info_full),
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded points of the full grid, one launch per shift (same kernel numerics and "
                             "tolerance, no batching)" % args.plain_points},
         "speedup_vs_plain": value / plain_value,
         "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "bound": "alu",
+            "achieved": flops_full / dur_full / 1e12,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": flops_full / dur_full / 1e12 / FP64_PEAK_TFLOPS,
             "traffic": traffic,
             "kernel": "ps::k_eval<1,1,false,false> (full-grid launch)",
+            "algorithmic_flops_per_launch": flops_full,
+            # bytes of the Golub-Kahan shifts and of the outputs, and the HBM rate they make
             "algorithmic_bytes_per_launch": bytes_full,
+            "hbm_achieved_gbs": achieved,
             # both launches of a step (they overlap unless --serial) over the step time
-            "step_algorithmic_bytes": bytes_full + bytes_mask,
-            "step_achieved": (bytes_full + bytes_mask) / (ms_step / 1000.0) / 1e9,
+            "step_algorithmic_flops": flops_full + flops_mask,
+            "step_achieved": (flops_full + flops_mask) / (ms_step / 1000.0) / 1e12,
         },
     }
     if not args.no_cpu_baseline:

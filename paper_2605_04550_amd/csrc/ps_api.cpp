@@ -19,7 +19,8 @@ struct ps_matrix_s {
     uint32_t flags;
     double fro;
     double norm2;    // sqrt(||A||_1 ||A||_inf) >= ||A||_2
-    double2 *arow;   // device, [n][kl+ku+1]
+    double2 *arow;   // device, [n][kl+ku+1] rows 0 .. n-1 of the band
+    double2 *abase;  // the allocation: kBandPadTop zero rows, the band, kBandPadBottom zero rows
     int device;
 };
 
@@ -227,16 +228,22 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
     m->fro = sqrt(fro2);
     m->norm2 = sqrt(rowmax * colmax);
     m->arow = nullptr;
+    m->abase = nullptr;
     (void)hipGetDevice(&m->device);
-    hipError_t e = hipMalloc((void **)&m->arow, sizeof(double2) * rows.size());
+    // zero rows around the band: kernels may read rows -kBandPadTop .. n + kBandPadBottom - 1
+    const size_t padded = (size_t)(ps::kBandPadTop + n + ps::kBandPadBottom) * (size_t)w;
+    std::vector<double2> store(padded, make_double2(0.0, 0.0));
+    std::copy(rows.begin(), rows.end(), store.begin() + (size_t)ps::kBandPadTop * (size_t)w);
+    hipError_t e = hipMalloc((void **)&m->abase, sizeof(double2) * padded);
     if (e != hipSuccess) {
         delete m;
         return fail(PS_ERR_HIP, "hipMalloc of the band: %s", hipGetErrorString(e));
     }
-    e = hipMemcpyAsync(m->arow, rows.data(), sizeof(double2) * rows.size(), hipMemcpyHostToDevice, st);
+    m->arow = m->abase + (size_t)ps::kBandPadTop * (size_t)w;
+    e = hipMemcpyAsync(m->abase, store.data(), sizeof(double2) * padded, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        (void)hipFree(m->arow);
+        (void)hipFree(m->abase);
         delete m;
         return fail(PS_ERR_HIP, "band upload: %s", hipGetErrorString(e));
     }
@@ -246,7 +253,7 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
 
 ps_status ps_destroy(ps_matrix m) {
     if (!m) return ok();
-    if (m->arow) (void)hipFree(m->arow);
+    if (m->abase) (void)hipFree(m->abase);
     delete m;
     return ok();
 }

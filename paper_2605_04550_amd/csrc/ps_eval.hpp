@@ -892,89 +892,126 @@ struct Kern {
     static constexpr int HB = KL + KU;          // half-bandwidth of H
     static constexpr int kBisMaxPass = 128;     // far above the ~30-40 passes a shift needs
 
-    // Rows per block of the pass: the M rows a block needs (PB + HB band rows) are loaded
-    // together before its rows are computed, so a pass waits for memory once per block, not
-    // once per row.  Narrower bands take longer blocks (the buffer is (PB + HB) x W entries).
+    // Rows per block of the pass.  The M rows a block needs (PB + HB band rows) sit in
+    // registers; the PB rows the next block adds are loaded while the current block is
+    // computed, so the pass does not wait for memory.  Narrower bands take longer blocks.
+    // Reads past the ends of the matrix land in the zero rows stored around the band.
     static constexpr int PB = W <= 3 ? 8 : W <= 5 ? 4 : W <= 7 ? 2 : 1;
 
-    // One test: true when every pivot of the Cholesky factorisation of H - sh I is positive
-    // (checked at the end of each block: a lane whose pivot fails stops there).  A completed
-    // pass also returns hmin = min_i H[i][i] = min_i |M e_i|^2, an upper bound on sigma_min^2.
-    static __device__ bool pd_pass(const EvalArgs &a, const Lane &ln, double sh, double &hmin) {
+    // Test points per pass: one pass factorises H - sh_j I for KT shifts sh_1 < .. < sh_KT at
+    // once.  H is formed once per row for all of them, and the KT independent recurrences
+    // overlap one another's latency; the bracket shrinks by KT + 1 per pass instead of 2.
+    // Wider bands keep fewer (each recurrence holds HB (HB - 1) / 2 factor entries).
+    static constexpr int KT = HB <= 2 ? 3 : HB <= 4 ? 2 : 1;
+
+    // One pass: the number c of leading tests (sh_1 .. sh_c) for which every pivot of the
+    // Cholesky factorisation of H - sh_j I is positive.  A pass always runs over all n rows
+    // (a test that has failed computes on with meaningless values): the lanes of a wavefront
+    // run in step anyway, and every pass then costs the same known work.  The pass also
+    // returns hmin = min_i H[i][i] = min_i |M e_i|^2, an upper bound on sigma_min^2.
+    static __device__ int pd_pass(const EvalArgs &a, const Lane &ln, const double (&sh)[KT], double &hmin) {
         const int64_t n = nn(a, ln);
         const double2 *ab = band(a, ln);
         const cd z = ln.z;
-        // The factor rows i-1 .. i-HB: P[e-1][f-1] = L[i-e][i-e-f] (f = 1 .. HB-e, the entries
-        // later rows still need) and R[e-1] = 1 / L[i-e][i-e]; rows before the first are zero.
+        // Per test j, the factor rows i-1 .. i-HB: P[j][e-1][f-1] = L[i-e][i-e-f] (f = 1 ..
+        // HB-e, the entries later rows still need) and R[j][e-1] = 1 / L[i-e][i-e]; rows
+        // before the first are zero.
         constexpr int HA = HB > 0 ? HB : 1;   // (the pass is not compiled in for HB = 0)
-        cd P[HA][HA];
-        double R[HA];
+        cd P[KT][HA][HA];
+        double R[KT][HA];
+        bool ok[KT];
 #pragma unroll
-        for (int e = 0; e < HA; ++e) {
-            R[e] = 0.0;
+        for (int j = 0; j < KT; ++j) {
+            ok[j] = true;
 #pragma unroll
-            for (int f = 0; f < HA; ++f) P[e][f] = czero();
-        }
-        double hm = 0x1p1000;
-        bool ok = true;
-        for (int64_t i0 = 0; i0 < n; i0 += PB) {
-            // Mb[q][d] = M[r][r + d - kl] for the rows r = i0 - ku + q (zero outside the matrix)
-            cd Mb[PB + HB][W];
+            for (int e = 0; e < HA; ++e) {
+                R[j][e] = 0.0;
 #pragma unroll
-            for (int q = 0; q < PB + HB; ++q) {
-                const int64_t r = i0 - KU + q;
-                const bool in = r >= 0 && r < n;
-                const int64_t rc = in ? r : 0;
-#pragma unroll
-                for (int d = 0; d < W; ++d) {
-                    const cd v = ab[rc * W + d];
-                    const cd m = d == KL ? C(z.x - v.x, z.y - v.y) : C(-v.x, -v.y);
-                    Mb[q][d] = in ? m : czero();
-                }
+                for (int f = 0; f < HA; ++f) P[j][e][f] = czero();
             }
+        }
+        // M[r][r + d - kl] of band row r (zero outside the matrix)
+        auto mrow = [&](int64_t r, int d) -> cd {
+            const cd v = ab[r * W + d];
+            const bool diag = d == KL && r >= 0 && r < n;
+            return C(diag ? z.x - v.x : -v.x, diag ? z.y - v.y : -v.y);
+        };
+        // Mb[q][d] = M[r][r + d - kl] for the rows r = i0 - ku + q of the current block
+        cd Mb[PB + HB][W];
 #pragma unroll
-            for (int p = 0; p < PB; ++p) {
-                const bool row = i0 + p < n;   // rows past n are identity rows
-                // H[i][i-e] = sum_t conj(M[r][i]) M[r][i-e], r = i - ku + t, t = 0 .. HB - e
-                cd h[HB + 1];
+        for (int q = 0; q < PB + HB; ++q)
 #pragma unroll
-                for (int e = 0; e <= HB; ++e) {
-                    double hx = 0.0, hy = 0.0;
+            for (int d = 0; d < W; ++d) Mb[q][d] = mrow(q - KU, d);
+        double hm = 0x1p1000;
+        // one row of the factorisations (row = false: a row past n, which acts as an identity row)
+        auto do_row = [&](int p, bool row) {
+            // H[i][i-e] = sum_t conj(M[r][i]) M[r][i-e], r = i - ku + t, t = 0 .. HB - e
+            cd h[HB + 1];
 #pragma unroll
-                    for (int t = 0; t <= HB - e; ++t) {
-                        const cd mi = Mb[p + t][HB - t], mj = Mb[p + t][HB - t - e];
-                        hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
-                        hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
-                    }
-                    h[e] = row ? C(hx, hy) : czero();
+            for (int e = 0; e <= HB; ++e) {
+                double hx = 0.0, hy = 0.0;
+#pragma unroll
+                for (int t = 0; t <= HB - e; ++t) {
+                    const cd mi = Mb[p + t][HB - t], mj = Mb[p + t][HB - t - e];
+                    hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
+                    hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
                 }
-                if (row) hm = fmin(hm, h[0].x);
-                // L[i][j], j = i - e: (H[i][j] - sum_{m < j} L[i][m] conj(L[j][m])) / L[j][j]
-                double dsq = row ? h[0].x - sh : 1.0;
+                h[e] = row ? C(hx, hy) : czero();
+            }
+            if (row) hm = fmin(hm, h[0].x);
+#pragma unroll
+            for (int j = 0; j < KT; ++j) {
+                // L[i][m], m = i - e: (H[i][m] - sum_{l < m} L[i][l] conj(L[m][l])) / L[m][m]
+                double dsq = row ? h[0].x - sh[j] : 1.0;
                 cd li[HB + 1];
 #pragma unroll
                 for (int e = HB; e >= 1; --e) {
                     cd acc = h[e];
 #pragma unroll
-                    for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[e - 1][e2 - e - 1], li[e2], acc);
-                    li[e] = cscale(acc, R[e - 1]);
+                    for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[j][e - 1][e2 - e - 1], li[e2], acc);
+                    li[e] = cscale(acc, R[j][e - 1]);
                     dsq -= cabs2(li[e]);
                 }
-                ok = ok && dsq > 0.0;
+                ok[j] = ok[j] && dsq > 0.0;
 #pragma unroll
                 for (int e = HB - 1; e >= 1; --e) {
-                    R[e] = R[e - 1];
+                    R[j][e] = R[j][e - 1];
 #pragma unroll
-                    for (int f = 0; f + e + 1 < HB; ++f) P[e][f] = P[e - 1][f];
+                    for (int f = 0; f + e + 1 < HB; ++f) P[j][e][f] = P[j][e - 1][f];
                 }
-                R[0] = rsqrt(dsq);             // not used once ok is false
+                R[j][0] = rsqrt(dsq);          // not used once ok[j] is false
 #pragma unroll
-                for (int f = 1; f < HB; ++f) P[0][f - 1] = li[f];
+                for (int f = 1; f < HB; ++f) P[j][0][f - 1] = li[f];
             }
-            if (!ok) return false;
+        };
+        for (int64_t i0 = 0; i0 < n; i0 += PB) {
+            // the rows the next block adds: i0 + PB + kl .. i0 + 2 PB - 1 + kl
+            cd Nb[PB][W];
+#pragma unroll
+            for (int q = 0; q < PB; ++q)
+#pragma unroll
+                for (int d = 0; d < W; ++d) Nb[q][d] = mrow(i0 + PB + KL + q, d);
+            if (i0 + PB <= n) {
+#pragma unroll
+                for (int p = 0; p < PB; ++p) do_row(p, true);
+            } else {
+#pragma unroll
+                for (int p = 0; p < PB; ++p) do_row(p, i0 + p < n);
+            }
+#pragma unroll
+            for (int q = 0; q < HB; ++q)
+#pragma unroll
+                for (int d = 0; d < W; ++d) Mb[q][d] = Mb[q + PB][d];
+#pragma unroll
+            for (int q = 0; q < PB; ++q)
+#pragma unroll
+                for (int d = 0; d < W; ++d) Mb[HB + q][d] = Nb[q][d];
         }
         hmin = hm;
-        return true;
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < KT; ++j) c += (c == j && ok[j]) ? 1 : 0;
+        return c;
     }
 
     // A fresh shift: phase 1 (bisection) if it may qualify, with the bracket [sigma_adm, mn].
@@ -992,26 +1029,33 @@ struct Kern {
         ln.bhi = mn;
     }
 
-    // One bisection pass of a lane in phase 1.  The first pass tests sigma_adm; later passes
-    // split the bracket at its geometric mean while hi > 2 lo, then at its midpoint.  The
-    // result is the midpoint of the final bracket, whose width is at most target(lo).
+    // One pass of a lane in phase 1.  The first pass tests sigma_adm and KT - 1 points
+    // spread geometrically up to mn; later passes split the bracket into KT + 1 parts,
+    // geometrically while hi > 2 lo, then evenly.  The result is the midpoint of the final
+    // bracket, whose width is at most target(lo).
     static __device__ void bis_cycle(const EvalArgs &a, Lane &ln) {
         const bool first = ln.nbis == 0;
         const double lo = ln.blo, hi = ln.bhi;
-        const double t = first ? lo : hi > 2.0 * lo ? sqrt(lo * hi) : 0.5 * (lo + hi);
+        double t[KT], sh[KT];
+        const bool geo = first || hi > 2.0 * lo;
+        const double lr = geo ? log2(hi / lo) : 0.0;
+#pragma unroll
+        for (int j = 0; j < KT; ++j) {
+            const double f = first ? (double)j / KT : (double)(j + 1) / (KT + 1);
+            t[j] = geo ? (j == 0 && first ? lo : lo * exp2(f * lr)) : lo + (hi - lo) * f;
+            sh[j] = t[j] * t[j];
+        }
         double hmin = 0.0;
-        const bool pd = pd_pass(a, ln, t * t, hmin);
+        const int c = pd_pass(a, ln, sh, hmin);
         ln.nbis += 1;
-        if (first && !pd) {           // sigma_min < sigma_adm: the Golub-Kahan path
+        if (first && c == 0) {        // sigma_min < sigma_adm: the Golub-Kahan path
             ln.phase = 0;
             return;
         }
-        if (pd) {
-            ln.blo = t;
-            if (first) ln.bhi = fmin(hi, sqrt(hmin));
-        } else {
-            ln.bhi = t;
-        }
+        // tests are monotone in t: t_c < sigma_min <= t_{c+1}
+        if (c > 0) ln.blo = fmax(lo, t[c - 1]);
+        if (c < KT) ln.bhi = fmin(hi, t[c]);
+        if (first) ln.bhi = fmin(ln.bhi, sqrt(hmin));
         const double target = a.tol_norm * fro(a, ln) + a.tol_rel * ln.blo;
         const double mid = 0.5 * (ln.blo + ln.bhi);
         const bool done = ln.bhi - ln.blo <= target || !(mid > ln.blo && mid < ln.bhi);
@@ -1313,6 +1357,68 @@ struct Kern {
         else b2(a, w, s, ln, acc, eacc);
     }
 
+    // Shift position id -> output index (pid), shift z and, in batch mode, its matrix.
+    static __device__ void locate(const EvalArgs &a, int64_t id, Lane &ln) {
+        ln.pid = id;
+        if (BATCH) {
+            // matrix of position id: the last m with mfirst[m] <= id
+            int lo = 0, hi = a.nmat - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (a.mfirst[mid] <= id) lo = mid;
+                else hi = mid - 1;
+            }
+            const MatDesc d = a.mats[lo];
+            const int64_t q = id - a.mfirst[lo];
+            ln.n = d.n;
+            ln.arow = d.arow;
+            ln.normA = d.normA;
+            ln.norm2A = d.norm2A;
+            ln.pid = d.out_off + q;
+            const int64_t flat = a.idx[ln.pid];
+            const int64_t gi = flat / d.nx, gj = flat - gi * d.nx;
+            const double x = d.nx > 1 ? __dadd_rn(d.ga, __ddiv_rn(__dmul_rn(d.gb - d.ga, (double)gj),
+                                                                   (double)(d.nx - 1))) : d.ga;
+            const double y = d.ny > 1 ? __dadd_rn(d.gc, __ddiv_rn(__dmul_rn(d.gd - d.gc, (double)gi),
+                                                                   (double)(d.ny - 1))) : d.gc;
+            ln.z = C(x, y);
+        } else if (a.mode == kShiftList) {
+            ln.z = a.z[ln.pid];
+        } else if (a.idx) {
+            ln.z = grid_point(a, a.idx[ln.pid]);
+        } else {
+            ln.pid = tile_flat(id, a.nx, a.ny);   // full grid: output at the flat index
+            ln.z = grid_point(a, ln.pid);
+        }
+    }
+
+    // Classification pass (one thread per shift position, before the persistent launch):
+    // the first bisection pass of every shift that may qualify.  pcls[id] = 1: continue the
+    // bisection from the bracket stored in pbr; 2: finished already (outputs written);
+    // 0: the Golub-Kahan path.  Sorting the queue by this class gives wavefronts that run
+    // only one kind of work, instead of Golub-Kahan sweeps and bisection passes in turn.
+    static __device__ void classify(const EvalArgs &a, const Workspace &w) {
+        const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (id >= *a.count_dev) return;
+        Lane ln;
+        ln.n = a.n;
+        ln.arow = a.arow;
+        ln.normA = a.normA;
+        ln.norm2A = a.norm2A;
+        ln.active = true;
+        ln.blo = ln.bhi = 0.0;
+        locate(a, id, ln);
+        bis_begin(a, ln);
+        uint8_t c = 0;
+        if (ln.phase == 1) {
+            bis_cycle(a, ln);
+            c = !ln.active ? 2 : ln.phase == 1 ? 1 : 0;
+        }
+        w.pcls[id] = c;
+        w.pbr[2 * id] = ln.blo;
+        w.pbr[2 * id + 1] = ln.bhi;
+    }
+
     // The workspace is laid out [wavefront][row][component][lane]: the 64 lanes of a
     // wavefront touch one contiguous 1 KiB (complex) segment per access, and a chunk of
     // consecutive rows of one wavefront is contiguous as well.  Each lane works on a view
@@ -1383,12 +1489,18 @@ struct Kern {
         while (true) {
             bool may_refill = !ln.active && !ln.exhausted;
             if (may_refill) {
-                unsigned long long id = atomicAdd(w.queue, 1ull);
+                const unsigned long long id = atomicAdd(w.queue, 1ull);
                 if ((int64_t)id >= npts) {
                     ln.exhausted = true;
                 } else {
-                    ln.pid = (int64_t)id;
-                    ln.active = true;
+                    // queue position -> shift position (classified launches take the shifts in
+                    // the order bisection first, Golub-Kahan after)
+                    const int64_t qid = a.perm ? a.perm[id] : (int64_t)id;
+                    // -1: padding of a classified queue.  The lane retires instead of taking
+                    // the next position, which would put Golub-Kahan work into a wavefront of
+                    // bisection lanes.
+                    ln.active = qid >= 0;
+                    ln.exhausted = qid < 0;
                     ln.fresh = true;
                     ln.stage = 0;
                     ln.phase = 0;
@@ -1396,37 +1508,20 @@ struct Kern {
                     ln.k = 0;
                     ln.b_m = 0.0;
                     ln.b_e = 0;
-                    if (BATCH) {
-                        // matrix of queue position id: the last m with mfirst[m] <= id
-                        int lo = 0, hi = a.nmat - 1;
-                        while (lo < hi) {
-                            int mid = (lo + hi + 1) >> 1;
-                            if (a.mfirst[mid] <= (int64_t)id) lo = mid;
-                            else hi = mid - 1;
+                    locate(a, qid >= 0 ? qid : 0, ln);
+                    if (!VEC && ln.active) {
+                        if (a.perm) {
+                            // the classification pass already ran this shift's first test
+                            const uint8_t c = a.pcls[qid];
+                            ln.phase = c == 1 ? 1 : 0;
+                            ln.nbis = 1;
+                            ln.blo = a.pbr[2 * qid];
+                            ln.bhi = a.pbr[2 * qid + 1];
+                            if (c == 2) ln.active = false;   // finished by that pass
+                        } else {
+                            bis_begin(a, ln);
                         }
-                        const MatDesc d = a.mats[lo];
-                        const int64_t q = (int64_t)id - a.mfirst[lo];
-                        ln.n = d.n;
-                        ln.arow = d.arow;
-                        ln.normA = d.normA;
-                        ln.norm2A = d.norm2A;
-                        ln.pid = d.out_off + q;
-                        const int64_t flat = a.idx[ln.pid];
-                        const int64_t gi = flat / d.nx, gj = flat - gi * d.nx;
-                        const double x = d.nx > 1 ? __dadd_rn(d.ga, __ddiv_rn(__dmul_rn(d.gb - d.ga, (double)gj),
-                                                                               (double)(d.nx - 1))) : d.ga;
-                        const double y = d.ny > 1 ? __dadd_rn(d.gc, __ddiv_rn(__dmul_rn(d.gd - d.gc, (double)gi),
-                                                                               (double)(d.ny - 1))) : d.gc;
-                        ln.z = C(x, y);
-                    } else if (a.mode == kShiftList) {
-                        ln.z = a.z[ln.pid];
-                    } else if (a.idx) {
-                        ln.z = grid_point(a, a.idx[ln.pid]);
-                    } else {
-                        ln.pid = tile_flat((int64_t)id, a.nx, a.ny);   // full grid: output at the flat index
-                        ln.z = grid_point(a, ln.pid);
                     }
-                    if (!VEC) bis_begin(a, ln);
                 }
             }
             if (__all(!ln.active && ln.exhausted)) break;
@@ -1496,15 +1591,25 @@ __global__ void __launch_bounds__(kEvalBlock) k_eval(EvalArgs a, Workspace w) {
     Kern<KL, KU, VEC, BATCH>::run(a, w);
 }
 
+// Threads per block of the classification pass (plain data-parallel: one shift per thread).
+constexpr int kClassifyBlock = 256;
+
+template <int KL, int KU, bool BATCH>
+__global__ void __launch_bounds__(kClassifyBlock) k_classify(EvalArgs a, Workspace w) {
+    Kern<KL, KU, false, BATCH>::classify(a, w);
+}
+
 typedef void (*EvalKernel)(EvalArgs, Workspace);
 
-// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only
+// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only;
+// 3: classification pass of mode 0
 template <int KL, int KU>
 EvalKernel pick_mode(int mode) {
     switch (mode) {
     case 0: return k_eval<KL, KU, false, false>;
     case 1: return k_eval<KL, KU, true, false>;
     case 2: return k_eval<KL, KU, false, true>;
+    case 3: return k_classify<KL, KU, false>;
     }
     return nullptr;
 }

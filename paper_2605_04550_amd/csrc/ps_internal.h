@@ -17,6 +17,10 @@ constexpr int kMaxIterCap = 4096;
 // round_up(n, kChunk) + kChunk rows; rows past n hold zeros and make no contribution.
 constexpr int kChunk = 8;
 inline int64_t padded_rows(int64_t n) { return ((n + kChunk - 1) / kChunk) * kChunk + kChunk; }
+// Zero rows stored before and after the row band of A (so that blocked reads near the ends
+// of the matrix need no bounds checks): rows -kBandPadTop .. n + kBandPadBottom - 1 exist.
+constexpr int kBandPadTop = 8;
+constexpr int kBandPadBottom = 32;
 
 // Where the shifts of one evaluation come from.
 enum ShiftMode : int {
@@ -48,6 +52,13 @@ struct Workspace {
     unsigned long long *queue = nullptr;   // shift counter of the persistent launch
     int64_t *count = nullptr;      // number of shifts (device)
     int64_t *blocksums = nullptr;  // mask compaction scratch
+    // Classification of the shifts before a sigma-only launch (allocated when npts_max > 0):
+    uint8_t *pcls = nullptr;       // [npts_max] 0 Golub-Kahan, 1 bisection, 2 finished
+    double *pbr = nullptr;         // [npts_max][2] bisection bracket after the first pass
+    int64_t *perm = nullptr;       // [npts_max + 64] queue position -> shift position (-1: none)
+    int64_t *ptiles = nullptr;     // scan scratch of the partition
+    int64_t *pn1 = nullptr;        // [2] shifts of classes 1 and 2, length of the sorted queue
+    int64_t npts_max = 0;
     int kmax = 0;
     int vec = 0;                   // 1: singular vectors wanted
 };
@@ -75,6 +86,9 @@ struct EvalArgs {
     double normA = 0.0;            // ||A||_F
     double norm2A = 0.0;           // upper bound on ||A||_2 (sqrt(||A||_1 ||A||_inf))
     int bisect = 1;                // 1: shifts that qualify take the inertia bisection
+    const int64_t *perm = nullptr; // queue position -> shift position (classified launches)
+    const uint8_t *pcls = nullptr; // class of each shift position
+    const double *pbr = nullptr;   // bisection bracket of each shift position
     int mode = kShiftList;
     const double2 *z = nullptr;
     const int64_t *idx = nullptr;

@@ -511,9 +511,22 @@ void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int k
         w->vacc = nullptr;
         w->vmeta = nullptr;
     }
+    if (!vec && npts_max > 0) {
+        w->pcls = (uint8_t *)take((size_t)npts_max);
+        w->pbr = (double *)take(sizeof(double) * 2 * (size_t)npts_max);
+        w->perm = (int64_t *)take(sizeof(int64_t) * (size_t)(npts_max + 64));
+        w->pn1 = (int64_t *)take(2 * sizeof(int64_t));
+    } else {
+        w->pcls = nullptr;
+        w->pbr = nullptr;
+        w->perm = nullptr;
+        w->pn1 = nullptr;
+    }
+    w->npts_max = npts_max;
     w->blocksums = (int64_t *)take(8);
-    // blocksums extends to the end (sized by workspace_bytes)
-    (void)npts_max;
+    // blocksums extends to the end (sized by workspace_bytes); the partition of a classified
+    // launch reuses it after the mask compaction is done
+    w->ptiles = w->blocksums;
 }
 
 hipError_t launch_set_count(int64_t *count, int64_t value, unsigned long long *queue, hipStream_t st) {
@@ -548,9 +561,72 @@ static EvalKernel pick(int kl, int ku, int mode) {
     return nullptr;
 }
 
-hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st) {
+// Partition of a classified launch: perm[0 .. n1) = the shift positions of classes 1 and 2
+// in increasing order, then -1 up to the next multiple of 64 (so that no wavefront gets
+// shifts of both kinds), then the positions of class 0 (Golub-Kahan), also in order.
+// pn1[0] = n1, pn1[1] = the length of the queue.
+__global__ void __launch_bounds__(kScanBlock) k_part_count(const uint8_t *cls, const int64_t *count,
+                                                           int64_t *tilesums) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t npts = *count;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < npts && cls[base + q] != 0) ++c;
+    int64_t total;
+    block_scan(c, sh, total);
+    if (threadIdx.x == 0) tilesums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_part_scatter(const uint8_t *cls, const int64_t *count,
+                                                             const int64_t *tilesums, const int64_t *n1,
+                                                             int64_t *perm) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t npts = *count;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < npts && cls[base + q] != 0) ++c;
+    int64_t total;
+    const int64_t ex = block_scan(c, sh, total);
+    int64_t pos = tilesums[blockIdx.x] + ex;      // positions of classes 1-2 before base
+    const int64_t m = (*n1 + 63) & ~(int64_t)63;
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t id = base + q;
+        if (id >= npts) break;
+        if (cls[id] != 0) perm[pos++] = id;
+        else perm[m + id - pos] = id;
+    }
+}
+
+__global__ void k_part_pad(const int64_t *count, int64_t *n1, int64_t *perm) {
+    const int64_t a = n1[0], m = (a + 63) & ~(int64_t)63;
+    if (a + (int64_t)threadIdx.x < m) perm[a + threadIdx.x] = -1;
+    if (threadIdx.x == 0) n1[1] = m + (*count - a);
+}
+
+hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st) {
+    EvalArgs a = a0;
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
+    if (!a.want_vectors && a.bisect && a.kl + a.ku >= 1 && ws.perm && ws.npts_max > 0) {
+        // classification pass, then the queue sorted by class
+        EvalKernel kc = pick(a.kl, a.ku, 3);
+        if (!kc) return hipErrorInvalidValue;
+        const int64_t nb = (ws.npts_max + kClassifyBlock - 1) / kClassifyBlock;
+        hipLaunchKernelGGL(kc, dim3((unsigned)nb), dim3(kClassifyBlock), 0, st, a, ws);
+        const int64_t nt = (ws.npts_max + kScanTile - 1) / kScanTile;
+        hipLaunchKernelGGL(k_part_count, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev,
+                           ws.ptiles);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ws.ptiles, nt, ws.pn1, ws.queue);
+        hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev,
+                           ws.ptiles, ws.pn1, ws.perm);
+        hipLaunchKernelGGL(k_part_pad, dim3(1), dim3(64), 0, st, a.count_dev, ws.pn1, ws.perm);
+        a.count_dev = ws.pn1 + 1;
+        a.perm = ws.perm;
+        a.pcls = ws.pcls;
+        a.pbr = ws.pbr;
+    }
     int64_t blocks = ws.slots / kEvalBlock;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
