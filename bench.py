@@ -86,12 +86,19 @@ def summarize_counters(fetch_csv, write_csv):
     res = {}
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         rs = rows(path, counter)
-        calib = [v for _, k, v in rs if "copyBuffer" in k and v > 1000.0][0]
-        kern = [v for _, k, v in rs if KERNEL_TAG in k][0]
+        cid, calib = [(d, v) for d, k, v in rs if "copyBuffer" in k and v > 1000.0][0]
+        # every library kernel of the full-grid call (classification, partition, k_eval)
+        parts = {}
+        for d, k, v in rs:
+            if d > cid and "ps::" in k:
+                name = k.split("(")[0].replace("void ", "")
+                parts[name] = parts.get(name, 0.0) + v
+        kern = sum(parts.values())
         factor = (CALIB_BYTES / 1024.0) / calib
-        res[counter] = dict(kib=kern, calib_kib=calib, factor=factor, bytes=kern * 1024.0 * factor)
+        res[counter] = dict(kib=kern, calib_kib=calib, factor=factor, bytes=kern * 1024.0 * factor,
+                            per_kernel_kib=parts)
     traffic = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
-    doc = dict(kernel="ps::" + KERNEL_TAG + " (full-grid launch of toeplitz2000)",
+    doc = dict(kernel="full-grid call of toeplitz2000 (ps::k_classify, partition kernels, ps::" + KERNEL_TAG + ")",
                source_hash=source_hash(), traffic_bytes_per_launch=traffic,
                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
                commands=["timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch "
@@ -379,7 +386,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": flops_full / dur_full / 1e12 / FP64_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "ps::k_eval<1,1,false,false> (full-grid launch)",
+            "kernel": "full-grid call: ps::k_classify, partition kernels, ps::k_eval<1,1,false,false>",
             "algorithmic_flops_per_launch": flops_full,
             # bytes of the Golub-Kahan shifts and of the outputs, and the HBM rate they make
             "algorithmic_bytes_per_launch": bytes_full,
