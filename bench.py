@@ -22,10 +22,11 @@ eval kernel, full-grid launch).  Most shifts of this workload take the inertia b
 whose passes read only the band of A (cached) and keep their state in registers: FP64
 arithmetic, so the roofline is "alu" against the FP64 vector peak (78.6 TFLOP/s).  Per row
 of a pass, with hb = kl + ku and kt test points per pass (3 for hb <= 2, 2 for hb <= 4,
-else 1):
-  F_row = 8 (hb+1)(hb+2)/2                      (H[i][i-e], e = 0..hb: complex multiply-adds)
-        + kt (8 hb(hb-1)/2 + 5 hb + 3)         (per test: the factor row, its scalings,
-                                                 |l|^2 terms and the pivot)
+else 1), counting each FP64 add, multiply and fused multiply-add as executed (an FMA is 2):
+  F_row = 4 (hb+1) + 8 hb(hb+1)/2                (H[i][i], real, and H[i][i-e], e = 1..hb)
+        + kt (8 hb(hb-1)/2 + 6 hb + 10)         (per test: the factor row of L D L^H, the
+                                                 pivot, and 1/pivot: hardware reciprocal
+                                                 plus two Newton steps)
 and a launch performs F = F_row * n * (sum of the passes of its shifts, from the info word);
 every pass covers all n rows.  The shifts on the Golub-Kahan path move
   B_LU   = (w_L + w_U) 16 n + n                 (L, U, pivots written once)
@@ -147,7 +148,7 @@ def bisection_flops(n, kl, ku, info):
     """Floating-point operations of the bisection passes of one launch (every pass covers
     all n rows): F_row * n * total passes, F_row as in the module docstring."""
     hb, kt = kl + ku, test_points(kl, ku)
-    per_row = 8 * (hb + 1) * (hb + 2) // 2 + kt * (8 * hb * (hb - 1) // 2 + 5 * hb + 3)
+    per_row = 4 * (hb + 1) + 8 * hb * (hb + 1) // 2 + kt * (8 * hb * (hb - 1) // 2 + 6 * hb + 10)
     info = np.asarray(info, dtype=np.int64)
     passes = np.where((info & 8) != 0, info >> 8, 0).astype(np.float64)
     return float(np.sum(passes) * n * per_row)

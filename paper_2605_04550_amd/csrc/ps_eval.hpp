@@ -904,28 +904,38 @@ struct Kern {
     // Wider bands keep fewer (each recurrence holds HB (HB - 1) / 2 factor entries).
     static constexpr int KT = HB <= 2 ? 3 : HB <= 4 ? 2 : 1;
 
+    // 1 / d to full precision: the hardware reciprocal (about 24 correct bits) and two
+    // Newton steps (each doubles the correct bits), without the library's special-case paths
+    // (d is a positive normal number wherever the result is used).
+    static __device__ __forceinline__ double recip(double d) {
+        double r = __builtin_amdgcn_rcp(d);
+        r = fma(r, fma(-d, r, 1.0), r);
+        return fma(r, fma(-d, r, 1.0), r);
+    }
+
     // One pass: the number c of leading tests (sh_1 .. sh_c) for which every pivot of the
-    // Cholesky factorisation of H - sh_j I is positive.  A pass always runs over all n rows
-    // (a test that has failed computes on with meaningless values): the lanes of a wavefront
-    // run in step anyway, and every pass then costs the same known work.  The pass also
-    // returns hmin = min_i H[i][i] = min_i |M e_i|^2, an upper bound on sigma_min^2.
+    // factorisation H - sh_j I = L D L^H (L unit lower triangular) is positive.  A pass always
+    // runs over all n rows (a test that has failed computes on with meaningless values): the
+    // lanes of a wavefront run in step anyway, and every pass then costs the same known work.
+    // The pass also returns hmin = min_i H[i][i] = min_i |M e_i|^2, an upper bound on
+    // sigma_min^2.
     static __device__ int pd_pass(const EvalArgs &a, const Lane &ln, const double (&sh)[KT], double &hmin) {
         const int64_t n = nn(a, ln);
         const double2 *ab = band(a, ln);
         const cd z = ln.z;
         // Per test j, the factor rows i-1 .. i-HB: P[j][e-1][f-1] = L[i-e][i-e-f] (f = 1 ..
-        // HB-e, the entries later rows still need) and R[j][e-1] = 1 / L[i-e][i-e]; rows
-        // before the first are zero.
+        // HB-e, the entries later rows still need) and Q[j][e-1] = 1 / d[i-e]; rows before the
+        // first are zero.
         constexpr int HA = HB > 0 ? HB : 1;   // (the pass is not compiled in for HB = 0)
         cd P[KT][HA][HA];
-        double R[KT][HA];
+        double Q[KT][HA];
         bool ok[KT];
 #pragma unroll
         for (int j = 0; j < KT; ++j) {
             ok[j] = true;
 #pragma unroll
             for (int e = 0; e < HA; ++e) {
-                R[j][e] = 0.0;
+                Q[j][e] = 0.0;
 #pragma unroll
                 for (int f = 0; f < HA; ++f) P[j][e][f] = czero();
             }
@@ -954,34 +964,36 @@ struct Kern {
                 for (int t = 0; t <= HB - e; ++t) {
                     const cd mi = Mb[p + t][HB - t], mj = Mb[p + t][HB - t - e];
                     hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
-                    hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
+                    if (e > 0) hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
                 }
                 h[e] = row ? C(hx, hy) : czero();
             }
             if (row) hm = fmin(hm, h[0].x);
 #pragma unroll
             for (int j = 0; j < KT; ++j) {
-                // L[i][m], m = i - e: (H[i][m] - sum_{l < m} L[i][l] conj(L[m][l])) / L[m][m]
-                double dsq = row ? h[0].x - sh[j] : 1.0;
-                cd li[HB + 1];
+                // row i, m = i - e:  w_m = L[i][m] d[m] = H[i][m] - sum_{l < m} w_l conj(L[m][l]),
+                // L[i][m] = w_m / d[m],  d[i] = H[i][i] - sh - sum_m Re(w_m conj(L[i][m]))
+                double d = row ? h[0].x - sh[j] : 1.0;
+                cd wv[HB + 1], lv[HB + 1];
 #pragma unroll
                 for (int e = HB; e >= 1; --e) {
                     cd acc = h[e];
 #pragma unroll
-                    for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[j][e - 1][e2 - e - 1], li[e2], acc);
-                    li[e] = cscale(acc, R[j][e - 1]);
-                    dsq -= cabs2(li[e]);
+                    for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[j][e - 1][e2 - e - 1], wv[e2], acc);
+                    wv[e] = acc;
+                    lv[e] = cscale(acc, Q[j][e - 1]);
+                    d = fma(-acc.x, lv[e].x, fma(-acc.y, lv[e].y, d));
                 }
-                ok[j] = ok[j] && dsq > 0.0;
+                ok[j] = ok[j] && d > 0.0;
 #pragma unroll
                 for (int e = HB - 1; e >= 1; --e) {
-                    R[j][e] = R[j][e - 1];
+                    Q[j][e] = Q[j][e - 1];
 #pragma unroll
                     for (int f = 0; f + e + 1 < HB; ++f) P[j][e][f] = P[j][e - 1][f];
                 }
-                R[j][0] = rsqrt(dsq);          // not used once ok[j] is false
+                Q[j][0] = recip(d);            // not used once ok[j] is false
 #pragma unroll
-                for (int f = 1; f < HB; ++f) P[j][0][f - 1] = li[f];
+                for (int f = 1; f < HB; ++f) P[j][0][f - 1] = lv[f];
             }
         };
         for (int64_t i0 = 0; i0 < n; i0 += PB) {
@@ -1020,7 +1032,7 @@ struct Kern {
         ln.nbis = 0;
         if (!BIS || !a.bisect) return;
         const double mn = hypot(ln.z.x, ln.z.y) + nrm2(a, ln);
-        if (!(mn < 1e100)) return;
+        if (!(mn < 1e100 && mn > 1e-100)) return;   // H and its pivots stay far from over/underflow
         const double b = a.tol_norm * fro(a, ln), c = 256.0 * 0x1p-52 * mn * mn;
         const double adm = 2.0 * c / (b + sqrt(b * b + 4.0 * a.tol_rel * c));   // inf if the target is 0
         if (!(adm < mn)) return;
