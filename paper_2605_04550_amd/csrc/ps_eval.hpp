@@ -896,7 +896,7 @@ struct Kern {
     // registers; the PB rows the next block adds are loaded while the current block is
     // computed, so the pass does not wait for memory.  Narrower bands take longer blocks.
     // Reads past the ends of the matrix land in the zero rows stored around the band.
-    static constexpr int PB = W <= 3 ? 8 : W <= 5 ? 4 : W <= 7 ? 2 : 1;
+    static constexpr int PB = W <= 3 ? 4 : W <= 4 ? 2 : 1;
 
     // Test points per pass: one pass factorises H - sh_j I for KT shifts sh_1 < .. < sh_KT at
     // once.  H is formed once per row for all of them, and the KT independent recurrences
@@ -922,6 +922,10 @@ struct Kern {
     static __device__ int pd_pass(const EvalArgs &a, const Lane &ln, const double (&sh)[KT], double &hmin) {
         const int64_t n = nn(a, ln);
         const double2 *ab = band(a, ln);
+        // The band address is the same in every lane; held in vector registers it is read by
+        // vector loads into vector registers, instead of scalar loads whose values would
+        // overflow the scalar register file.
+        asm volatile("" : "+v"(ab));
         const cd z = ln.z;
         // Per test j, the factor rows i-1 .. i-HB: P[j][e-1][f-1] = L[i-e][i-e-f] (f = 1 ..
         // HB-e, the entries later rows still need) and Q[j][e-1] = 1 / d[i-e]; rows before the
