@@ -405,7 +405,7 @@ int64_t class_slots(const ps_batch_s::Cls &c, const ps_opts &o) {
     if (want < kSlotQuantum) want = kSlotQuantum;
     if (want > kMaxSlots) want = kMaxSlots;
     while (want > kSlotQuantum &&
-           (double)ps::workspace_bytes(c.nmax, c.kl, c.ku, want, o.max_iter, 0, 0) > kDefaultWsBudget)
+           (double)ps::workspace_bytes(c.nmax, c.kl, c.ku, want, o.max_iter, 0, c.npts) > kDefaultWsBudget)
         want -= kSlotQuantum;
     return want;
 }
@@ -742,7 +742,7 @@ ps_status ps_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes) {
     size_t mx = 0;
     for (const auto &c : b->classes) {
         int64_t sl = class_slots(c, r);
-        mx = std::max(mx, ps::workspace_bytes(c.nmax, c.kl, c.ku, sl, r.max_iter, 0, 0));
+        mx = std::max(mx, ps::workspace_bytes(c.nmax, c.kl, c.ku, sl, r.max_iter, 0, c.npts));
     }
     *bytes = batch_scratch_bytes(b) + mx;
     return ok();
@@ -764,7 +764,7 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
     for (const auto &c : b->classes) {
         ps::Workspace w;
         int64_t sl = class_slots(c, r);
-        ps::carve_workspace(evbase, c.nmax, c.kl, c.ku, sl, r.max_iter, 0, 0, &w);
+        ps::carve_workspace(evbase, c.nmax, c.kl, c.ku, sl, r.max_iter, 0, c.npts, &w);
         HIP_TRY(ps::launch_batch_prefix(b->desc_class + c.begin, counts_dev, c.count, mfirst + c.begin, w.count,
                                         w.queue, s));
         ps::EvalArgs a;

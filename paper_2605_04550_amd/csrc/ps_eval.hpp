@@ -1618,7 +1618,7 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(EvalArgs a, Workspa
 typedef void (*EvalKernel)(EvalArgs, Workspace);
 
 // mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only;
-// 3: classification pass of mode 0
+// 3: classification pass of mode 0; 4: classification pass of mode 2
 template <int KL, int KU>
 EvalKernel pick_mode(int mode) {
     switch (mode) {
@@ -1626,6 +1626,7 @@ EvalKernel pick_mode(int mode) {
     case 1: return k_eval<KL, KU, true, false>;
     case 2: return k_eval<KL, KU, false, true>;
     case 3: return k_classify<KL, KU, false>;
+    case 4: return k_classify<KL, KU, true>;
     }
     return nullptr;
 }

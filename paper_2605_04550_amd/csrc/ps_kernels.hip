@@ -605,36 +605,50 @@ __global__ void k_part_pad(const int64_t *count, int64_t *n1, int64_t *perm) {
     if (threadIdx.x == 0) n1[1] = m + (*count - a);
 }
 
+// Classification pass of a sigma-only launch and the queue sorted by class (see
+// Kern::classify); afterwards the launch reads its shifts through a.perm.
+static hipError_t classify_and_sort(EvalArgs &a, const Workspace &ws, EvalKernel kc, hipStream_t st) {
+    if (!kc) return hipErrorInvalidValue;
+    const int64_t nb = (ws.npts_max + kClassifyBlock - 1) / kClassifyBlock;
+    hipLaunchKernelGGL(kc, dim3((unsigned)nb), dim3(kClassifyBlock), 0, st, a, ws);
+    const int64_t nt = (ws.npts_max + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_part_count, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev, ws.ptiles);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ws.ptiles, nt, ws.pn1, ws.queue);
+    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev, ws.ptiles,
+                       ws.pn1, ws.perm);
+    hipLaunchKernelGGL(k_part_pad, dim3(1), dim3(64), 0, st, a.count_dev, ws.pn1, ws.perm);
+    a.count_dev = ws.pn1 + 1;
+    a.perm = ws.perm;
+    a.pcls = ws.pcls;
+    a.pbr = ws.pbr;
+    return hipGetLastError();
+}
+
+static bool classified(const EvalArgs &a, const Workspace &ws, int kl, int ku) {
+    return !a.want_vectors && a.bisect && kl + ku >= 1 && ws.perm && ws.npts_max > 0;
+}
+
 hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st) {
     EvalArgs a = a0;
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
-    if (!a.want_vectors && a.bisect && a.kl + a.ku >= 1 && ws.perm && ws.npts_max > 0) {
-        // classification pass, then the queue sorted by class
-        EvalKernel kc = pick(a.kl, a.ku, 3);
-        if (!kc) return hipErrorInvalidValue;
-        const int64_t nb = (ws.npts_max + kClassifyBlock - 1) / kClassifyBlock;
-        hipLaunchKernelGGL(kc, dim3((unsigned)nb), dim3(kClassifyBlock), 0, st, a, ws);
-        const int64_t nt = (ws.npts_max + kScanTile - 1) / kScanTile;
-        hipLaunchKernelGGL(k_part_count, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev,
-                           ws.ptiles);
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ws.ptiles, nt, ws.pn1, ws.queue);
-        hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev,
-                           ws.ptiles, ws.pn1, ws.perm);
-        hipLaunchKernelGGL(k_part_pad, dim3(1), dim3(64), 0, st, a.count_dev, ws.pn1, ws.perm);
-        a.count_dev = ws.pn1 + 1;
-        a.perm = ws.perm;
-        a.pcls = ws.pcls;
-        a.pbr = ws.pbr;
+    if (classified(a, ws, a.kl, a.ku)) {
+        const hipError_t e = classify_and_sort(a, ws, pick(a.kl, a.ku, 3), st);
+        if (e != hipSuccess) return e;
     }
     int64_t blocks = ws.slots / kEvalBlock;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_eval_batch(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st) {
+hipError_t launch_eval_batch(const EvalArgs &a0, const Workspace &ws, int kl, int ku, hipStream_t st) {
+    EvalArgs a = a0;
     EvalKernel k = pick(kl, ku, 2);
     if (!k) return hipErrorInvalidValue;
+    if (classified(a, ws, kl, ku)) {
+        const hipError_t e = classify_and_sort(a, ws, pick(kl, ku, 4), st);
+        if (e != hipSuccess) return e;
+    }
     int64_t blocks = ws.slots / kEvalBlock;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
