@@ -180,3 +180,41 @@ def test_bisection_across_band_shapes():
         assert used.sum() >= 8
         print("kl=%d ku=%d: bisection at %d of 24 (passes mean %.1f); Golub-Kahan steps mean %.1f (all points)"
               % (kl, ku, used.sum(), (info[used] >> 8).mean(), off["iters"].float().mean().item()))
+
+def test_classified_queue_edge_cases():
+    """The sorted queue of a sigma-only call (bisection shifts first, padding to a multiple of
+    64, then Golub-Kahan shifts): 1, 63, 64, 65 and 200 shifts, all of one kind or mixed, list,
+    mask and full-grid forms; every result equals the Golub-Kahan-only path to the bar."""
+    api = _api()
+    import torch
+    band = W.toeplitz(300, 0.25, 0.0, 1.0)
+    mat = api.BandedMatrix.from_band(band)
+    rng = np.random.default_rng(77)
+    inside = 0.6 * np.exp(2j * np.pi * rng.uniform(0, 1, 200)) * rng.uniform(0.2, 1.0, 200)   # sigma ~ 0
+    outside = (1.8 + rng.uniform(0, 1, 200)) * np.exp(2j * np.pi * rng.uniform(0, 1, 200))  # bisection
+    mixed = np.where(rng.uniform(size=200) < 0.5, inside, outside)
+    for name, z in (("one", outside[:1]), ("one-gk", inside[:1]), ("63", mixed[:63]), ("64", mixed[:64]),
+                    ("65", mixed[:65]), ("200-in", inside), ("200-out", outside), ("200-mixed", mixed)):
+        zt = torch.tensor(z, dtype=torch.complex128, device="cuda")
+        on = api.sigma_min(mat, zt)
+        off = api.sigma_min(mat, zt, bisect=False)
+        s_on, s_off = on["sigma"].cpu().numpy(), off["sigma"].cpu().numpy()
+        info = on["info"].cpu().numpy()
+        assert np.all(np.abs(s_on - s_off) <= 2 * tol(band.fro, s_off)), name
+        assert np.all((info & 2) == 0), name
+        print("%s: %d shifts, %d by bisection" % (name, len(z), int(np.sum((info & 8) != 0))))
+    pick = np.arange(0, 200, 25)
+    ref = oracle.sigma_min(band, mixed[pick])["sigma"]
+    r = api.sigma_min(mat, torch.tensor(mixed[pick], dtype=torch.complex128, device="cuda"))
+    _check("toeplitz n=300 mixed", r["sigma"].cpu().numpy(), ref, band.fro)
+    # mask and full grid of a grid that straddles the spectrum
+    g = W.Grid(-2.5, 2.5, -2.5, 2.5, 23, 19)
+    full = api.eval_grid(mat, g)
+    full_off = api.eval_grid(mat, g, bisect=False)
+    a, b = full["sigma"].cpu().numpy(), full_off["sigma"].cpu().numpy()
+    assert np.all(np.abs(a - b) <= 2 * tol(band.fro, b))
+    m = torch.tensor((rng.uniform(size=(19, 23)) < 0.37).astype(np.uint8), device="cuda")
+    rm = api.eval_grid(mat, g, m)
+    c = int(rm["count"].item())
+    idx = rm["idx"][:c].cpu().numpy()
+    assert np.array_equal(rm["sigma"][:c].cpu().numpy(), a[idx])
