@@ -211,6 +211,40 @@ def label_bench(args):
         "labels_equal_to_plain": agree, "points": npts}), flush=True)
 
 
+def trace_bench(args):
+    """Contour tracing on the measured workload: args.trace seeds taken evenly from the
+    eps = 1e-2 seeds of the full toeplitz2000 grid, traced inside the grid box with h = the
+    grid spacing, 2 Newton steps per point, at most 64 points per tracer."""
+    import torch
+    import workloads as W
+    from paper_2605_04550_amd import api
+    w = W.workload("toeplitz2000")
+    mat = api.BandedMatrix.from_band(w["band"])
+    g = w["grid"]
+    eps = EPS_ZONE
+    r = api.eval_grid(mat, g)
+    seeds, count = api.contour_seeds(g, r["sigma"], eps)
+    pick = seeds[:: max(1, count // args.trace)][: args.trace].contiguous()
+    h = (g.b - g.a) / (g.nx - 1)
+    box = (g.a, g.b, g.c, g.d)
+    api.trace_contour(mat, pick[:4], eps, h, 4, box=box)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = api.trace_contour(mat, pick, eps, h, 64, box=box)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    npts = int(tr["count"].sum().item())
+    fl = tr["flags"].cpu().numpy()
+    print(json.dumps({
+        "metric": "eps-contour points traced per second (predictor + 2 Newton steps, FP64)", "value": npts / dt,
+        "unit": "points/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "toeplitz2000 eps=1e-2: %d seeds from the full-grid contour seeds, h = grid spacing, "
+                               "<= 64 points each" % len(pick), "seeds": len(pick)},
+        "seconds": dt, "points": npts,
+        "flags": {"closed": int(np.sum(fl & 1 != 0)), "left_box": int(np.sum(fl & 2 != 0)),
+                  "newton_failed": int(np.sum(fl & 4 != 0)), "max_points": int(np.sum(fl & 8 != 0))}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +258,8 @@ def main():
     ap.add_argument("--counter-pass", action="store_true",
                     help="calibration copy + one full-grid launch, for rocprofv3 --pmc")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--trace", type=int, default=0, metavar="NSEED",
+                    help="instead of the headline: trace the eps = 1e-2 contour of the workload from NSEED seeds")
     ap.add_argument("--labels", type=int, default=0, metavar="NMAT",
                     help="instead of the headline: label NMAT matrices of the Sec. 3.2 workload by exclusion "
                          "regions and by the plain method, one JSON line")
@@ -246,6 +282,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.labels:
         label_bench(args)
+        return
+    if args.trace:
+        trace_bench(args)
         return
     w = W.workload("toeplitz2000")
     band, grid = w["band"], w["grid"]

@@ -261,6 +261,41 @@ ps_status ps_newton_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, 
 ps_status ps_newton_contour(ps_matrix m, ps_c128 *z_dev, int64_t npts, double eps, int32_t steps, const ps_opts *o,
                             void *ws_dev, size_t ws_bytes, double *sigma_dev, int32_t *info_dev, void *stream);
 
+/* Stop flags of ps_trace_contour (flags_dev[p]). */
+enum {
+    PS_TRACE_CLOSED = 1,         /* point k >= 3 came within h of point 0: the curve closed    */
+    PS_TRACE_LEFT_BOX = 2,       /* the last stored point lies outside the box                */
+    PS_TRACE_NEWTON_FAILED = 4,  /* a corrected point missed the curve (|ln(sigma/eps)| >
+                                    1e-6); it is not stored                                   */
+    PS_TRACE_MAX_POINTS = 8      /* max_points points were stored                             */
+};
+
+/*
+ * ps_trace_contour -- follow the eps-level curve sigma_min(zI - A) = eps (the boundary of the
+ * eps-pseudospectrum, drawn as the level curve log10 eps in Sec. 2.1) from each seed, by
+ * predictor-corrector steps: with g = conj(u^H v) the gradient of sigma_min at the current
+ * point, the next point is the current one plus h i g / |g| (a step of length h along the
+ * curve's tangent, counterclockwise around the region sigma < eps), corrected by
+ * newton_steps Newton steps z <- z - sigma ln(sigma / eps) g / |g|^2 (as ps_newton_contour).
+ * Point 0 is the seed after 2 newton_steps + 2 Newton steps.  Each Newton step and each
+ * accepted point evaluates sigma_min with its singular vectors at every tracer.
+ *   seeds_dev  device ps_c128[nseed] (e.g. from ps_contour_seeds).  nseed >= 0.
+ *   eps > 0, h > 0 finite, max_points >= 1, newton_steps >= 1.
+ *   box        host ps_grid whose a, b, c, d bound the tracing region (nx, ny unused), or NULL.
+ *   points_dev device ps_c128[nseed][max_points]: the points of tracer p in order; entries
+ *              past count_dev[p] are left as they were.
+ *   count_dev  device int32[nseed]: points stored.  flags_dev: device int32[nseed], PS_TRACE_*.
+ *   ws_dev / ws_bytes >= ps_trace_workspace_size(m, nseed, o) (vectors are implied in o).
+ * Synchronous: every 8 points the call waits for the stream to learn whether any tracer is
+ * still active, and returns when none is (so it cannot be captured in a graph).
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_trace_workspace_size(ps_matrix m, int64_t nseed, const ps_opts *o, size_t *bytes);
+ps_status ps_trace_contour(ps_matrix m, const ps_c128 *seeds_dev, int64_t nseed, double eps, double h,
+                           int32_t max_points, int32_t newton_steps, const ps_grid *box, const ps_opts *o,
+                           void *ws_dev, size_t ws_bytes, ps_c128 *points_dev, int32_t *count_dev,
+                           int32_t *flags_dev, void *stream);
+
 /*
  * ps_contour_seeds -- starting points for ps_newton_contour on the eps-level curve of sigma_min
  * (the boundary of the eps-pseudospectrum, drawn as the level curve log10 eps in Sec. 2.1):

@@ -20,6 +20,9 @@ Contents (each function names the passage of the paper it follows):
   * ``count_below``    -- number of singular values of zI - A below t, by the inertia of a
                           banded Hermitian augmented matrix (``inertia.c``); certifies
                           sigma_min at sizes where a dense SVD per shift is too slow.
+  * ``trace_contour``  -- points along the eps-level curve from seeds: a step along the
+                          tangent, then Newton steps back onto the curve (Sec. 2.1 level
+                          curve; the paper does not say how to follow it).
 Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
 closed forms, invariants, brute force and the paper's Jordan example.
 """
@@ -214,3 +217,67 @@ def contour_seeds(grid, sigma, eps) -> np.ndarray:
         out.append(z1 + tau * (z2 - z1))
     return np.concatenate(out)
 
+
+
+TRACE_CLOSED, TRACE_LEFT_BOX, TRACE_NEWTON_FAILED, TRACE_MAX_POINTS = 1, 2, 4, 8
+
+
+def trace_contour(band, seeds, eps, h, max_points, newton_steps=2, box=None):
+    """Follow the eps-level curve sigma_min(zI - A) = eps (the boundary of the
+    eps-pseudospectrum that Sec. 2.1 draws as the level curve log10 eps) from each seed.
+
+    With g = grad sigma_min (conjugate-Wirtinger, from the singular pair, ``adjoint``) the
+    curve's tangent is i g / |g|.  A tracer first takes 2 newton_steps + 2 Newton steps
+    (``newton_step``) from its seed onto the curve (a seed may lie a grid spacing away): that
+    is point 0.  Point k then comes from
+    point k-1 by a step of length h along the tangent (computed at point k-1) followed by
+    ``newton_steps`` Newton steps; at every point sigma and g are evaluated once more.  A
+    tracer stops, with the flag set, when a corrected point misses the curve
+    (|ln(sigma/eps)| > 1e-6: TRACE_NEWTON_FAILED, the point is not stored), when a point lies
+    outside the box (a, b, c, d) (TRACE_LEFT_BOX, stored), when point k >= 3 lies within h of
+    point 0 (TRACE_CLOSED, stored), or after max_points points (TRACE_MAX_POINTS).
+    Returns points [nseed, max_points] (unused entries 0), count [nseed], flags [nseed]."""
+    seeds = np.atleast_1d(np.asarray(seeds, dtype=np.complex128))
+    m = len(seeds)
+
+    def evaluate(z):
+        r = sigma_min(band, z, want_vectors=True)
+        g, _ = adjoint(band, r["u"], r["v"], np.ones(len(z)))
+        return r["sigma"], g
+
+    def correct(z, steps):
+        for _ in range(steps):
+            s, g = evaluate(z)
+            z = newton_step(z, s, g, eps)
+        s, g = evaluate(z)
+        return z, s, g
+
+    pts = np.zeros((m, max_points), dtype=np.complex128)
+    count = np.zeros(m, dtype=np.int32)
+    flags = np.zeros(m, dtype=np.int32)
+    for t in range(m):
+        z = np.array([seeds[t]])
+        z0 = None
+        g = None
+        for k in range(max_points):
+            if k > 0:
+                z = z + h * 1j * g / np.abs(g)
+            z, s, g = correct(z, newton_steps if k > 0 else 2 * newton_steps + 2)
+            if not (np.isfinite(s[0]) and s[0] > 0 and abs(np.log(s[0] / eps)) <= 1e-6):
+                flags[t] |= TRACE_NEWTON_FAILED
+                break
+            pts[t, k] = z[0]
+            count[t] = k + 1
+            if k == 0:
+                z0 = z[0]
+            if box is not None:
+                a, b, c, d = box
+                if not (a <= z[0].real <= b and c <= z[0].imag <= d):
+                    flags[t] |= TRACE_LEFT_BOX
+                    break
+            if k >= 3 and abs(z[0] - z0) < h:
+                flags[t] |= TRACE_CLOSED
+                break
+            if k == max_points - 1:
+                flags[t] |= TRACE_MAX_POINTS
+    return pts, count, flags

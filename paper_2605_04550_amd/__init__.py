@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ps.h")
 
 PS_OK, PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP, PS_ERR_UNSUPPORTED = range(6)
 PS_PT_CONVERGED, PS_PT_SINGULAR, PS_PT_MAXITER, PS_PT_UNDERFLOW, PS_PT_BISECT = 0, 1, 2, 4, 8
+PS_TRACE_CLOSED, PS_TRACE_LEFT_BOX, PS_TRACE_NEWTON_FAILED, PS_TRACE_MAX_POINTS = 1, 2, 4, 8
 PS_DEVICE_PTR, PS_REAL_A = 1, 2
 
 STATUS_NAMES = {0: "PS_OK", 1: "PS_ERR_INVALID", 2: "PS_ERR_NONFINITE", 3: "PS_ERR_WORKSPACE", 4: "PS_ERR_HIP",
@@ -70,6 +71,10 @@ _SIGNATURES = {
     "ps_newton_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "ps_newton_contour": (ctypes.c_int, [_P, _P, _I64, ctypes.c_double, _I32, ctypes.POINTER(ps_opts), _P,
                                          ctypes.c_size_t, _P, _P, _P]),
+    "ps_trace_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_trace_contour": (ctypes.c_int, [_P, _P, _I64, ctypes.c_double, ctypes.c_double, _I32, _I32,
+                                        ctypes.POINTER(ps_grid), ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P,
+                                        _P, _P]),
     "ps_label_batch_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "ps_label_batch": (ctypes.c_int, [_P, ctypes.c_double, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P, _P,
                                       _P]),
@@ -190,6 +195,21 @@ def ps_newton_contour(handle, z_ptr, npts, eps, steps, opts, ws_ptr, ws_bytes, s
     _check(lib().ps_newton_contour(_P(handle), _P(z_ptr), npts, float(eps), int(steps),
                                    ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
                                    _P(sigma_ptr), _P(info_ptr), _P(stream)))
+
+
+def ps_trace_workspace_size(handle: int, nseed: int, opts: ps_opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_trace_workspace_size(_P(handle), nseed, ctypes.byref(opts) if opts is not None else None,
+                                         ctypes.byref(b)))
+    return b.value
+
+
+def ps_trace_contour(handle, seeds_ptr, nseed, eps, h, max_points, newton_steps, box, opts, ws_ptr, ws_bytes,
+                     points_ptr, count_ptr, flags_ptr, stream=0) -> None:
+    _check(lib().ps_trace_contour(_P(handle), _P(seeds_ptr), nseed, float(eps), float(h), int(max_points),
+                                  int(newton_steps), ctypes.byref(box) if box is not None else None,
+                                  ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
+                                  _P(points_ptr), _P(count_ptr), _P(flags_ptr), _P(stream)))
 
 
 def ps_label_batch_workspace_size(handle, opts: ps_opts | None = None) -> int:

@@ -20,7 +20,7 @@ from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_w
                ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
                ps_newton_workspace_size, ps_opts_default, ps_workspace_size, ps_contour_seeds,
                ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size, ps_label_batch,
-               ps_label_batch_workspace_size)
+               ps_label_batch_workspace_size, ps_trace_contour, ps_trace_workspace_size)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
 
@@ -256,6 +256,25 @@ def newton_contour(mat: BandedMatrix, z0: torch.Tensor, eps: float, steps: int =
     ps_newton_contour(mat.handle, z.data_ptr(), npts, eps, steps, o, ws.data_ptr(), ws.numel(), sig.data_ptr(),
                       info.data_ptr(), _stream_handle(stream))
     return z, sig
+
+
+def trace_contour(mat: BandedMatrix, seeds: torch.Tensor, eps: float, h: float, max_points: int,
+                  newton_steps: int = 2, box=None, tol_rel=1e-12, tol_norm=1e-14, stream=None):
+    """ps_trace_contour: follow the eps-level curve from each seed (tangent step of length h,
+    then Newton corrections).  box: (a, b, c, d) or None.  Returns dict(points [nseed,
+    max_points] complex128, count [nseed] int32, flags [nseed] int32, PS_TRACE_* bits)."""
+    z = seeds.detach().to(torch.complex128).contiguous()
+    m = z.numel()
+    dev = z.device
+    o = make_opts(tol_norm, tol_rel, 3000, True, 0)
+    pts = torch.zeros((m, max_points), dtype=torch.complex128, device=dev)
+    count = torch.zeros(m, dtype=torch.int32, device=dev)
+    flags = torch.zeros(m, dtype=torch.int32, device=dev)
+    g = None if box is None else ps_grid(float(box[0]), float(box[1]), float(box[2]), float(box[3]), 1, 1)
+    ws = _workspace(ps_trace_workspace_size(mat.handle, m, o), dev)
+    ps_trace_contour(mat.handle, z.data_ptr(), m, eps, h, max_points, newton_steps, g, o, ws.data_ptr(), ws.numel(),
+                     pts.data_ptr(), count.data_ptr(), flags.data_ptr(), _stream_handle(stream))
+    return dict(points=pts, count=count, flags=flags)
 
 
 def contour_seeds(grid, sigma: torch.Tensor, eps: float, max_seeds: int | None = None, stream=None):

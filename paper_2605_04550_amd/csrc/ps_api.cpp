@@ -581,6 +581,101 @@ ps_status ps_newton_contour(ps_matrix m, ps_c128 *z_dev, int64_t npts, double ep
     return ok();
 }
 
+// Workspace of ps_trace_contour: the evaluation workspace (with vectors) for nseed shifts,
+// u and v, then per tracer the gradient, trial point, current point, its gradient, point 0,
+// sigma, the active flag, and the active count.
+ps_status ps_trace_workspace_size(ps_matrix m, int64_t nseed, const ps_opts *o, size_t *bytes) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (nseed < 0) return fail(PS_ERR_INVALID, "nseed must be >= 0");
+    ps_opts r = resolve(o);
+    r.want_vectors = 1;
+    if ((st = check_opts(r))) return st;
+    size_t ev = 0;
+    if ((st = ps_workspace_size(m, nseed, &r, &ev))) return st;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t k = (size_t)nseed;
+    *bytes = al(ev) + 2 * al(sizeof(ps_c128) * k * (size_t)m->n) + 5 * al(sizeof(ps_c128) * k) +
+             al(sizeof(double) * k) + al(sizeof(int32_t) * k) + 256;
+    return ok();
+}
+
+ps_status ps_trace_contour(ps_matrix m, const ps_c128 *seeds_dev, int64_t nseed, double eps, double h,
+                           int32_t max_points, int32_t newton_steps, const ps_grid *box, const ps_opts *o,
+                           void *ws_dev, size_t ws_bytes, ps_c128 *points_dev, int32_t *count_dev,
+                           int32_t *flags_dev, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (nseed < 0) return fail(PS_ERR_INVALID, "nseed must be >= 0");
+    if (!(eps > 0.0) || !isfinite(eps)) return fail(PS_ERR_INVALID, "eps must be finite and > 0");
+    if (!(h > 0.0) || !isfinite(h)) return fail(PS_ERR_INVALID, "h must be finite and > 0");
+    if (max_points < 1 || newton_steps < 1) return fail(PS_ERR_INVALID, "need max_points >= 1 and newton_steps >= 1");
+    if (box && (!isfinite(box->a) || !isfinite(box->b) || !isfinite(box->c) || !isfinite(box->d)))
+        return fail(PS_ERR_NONFINITE, "non-finite box");
+    if (nseed == 0) return ok();
+    if (!seeds_dev || !points_dev || !count_dev || !flags_dev)
+        return fail(PS_ERR_INVALID, "seeds, points, count and flags are required");
+    ps_opts rv = resolve(o);
+    rv.want_vectors = 1;
+    if ((st = check_opts(rv))) return st;
+    size_t need = 0;
+    if ((st = ps_trace_workspace_size(m, nseed, &rv, &need))) return st;
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "trace workspace needs %zu bytes", need);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t ev = 0;
+    ps_workspace_size(m, nseed, &rv, &ev);
+    ev = al(ev);
+    const size_t k = (size_t)nseed;
+    char *p = (char *)ws_dev + ev;
+    auto take = [&](size_t bytes) -> char * {
+        char *q = p;
+        p += al(bytes);
+        return q;
+    };
+    ps_c128 *u = (ps_c128 *)take(sizeof(ps_c128) * k * (size_t)m->n);
+    ps_c128 *v = (ps_c128 *)take(sizeof(ps_c128) * k * (size_t)m->n);
+    double2 *gz = (double2 *)take(sizeof(ps_c128) * k);
+    double2 *zt = (double2 *)take(sizeof(ps_c128) * k);
+    double2 *zc = (double2 *)take(sizeof(ps_c128) * k);
+    double2 *gc = (double2 *)take(sizeof(ps_c128) * k);
+    double2 *z0 = (double2 *)take(sizeof(ps_c128) * k);
+    double *sig = (double *)take(sizeof(double) * k);
+    int32_t *active = (int32_t *)take(sizeof(int32_t) * k);
+    int32_t *n_active = (int32_t *)take(sizeof(int32_t));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ps::launch_trace_init(nseed, (const double2 *)seeds_dev, zt, active, count_dev, flags_dev, s));
+    auto evaluate = [&]() -> ps_status {
+        ps_status e = ps_eval_points(m, (const ps_c128 *)zt, nseed, &rv, ws_dev, ev, sig, u, v, nullptr, nullptr,
+                                     stream);
+        if (e) return e;
+        HIP_TRY(ps::launch_backward(m->n, m->kl, m->ku, nseed, nullptr, (const double2 *)u, (const double2 *)v, gz,
+                                    nullptr, nullptr, 0, s));
+        return PS_OK;
+    };
+    for (int32_t kp = 0; kp < max_points; ++kp) {
+        if (kp > 0) HIP_TRY(ps::launch_trace_predict(nseed, active, zc, gc, h, zt, s));
+        const int32_t steps = kp == 0 ? 2 * newton_steps + 2 : newton_steps;
+        for (int32_t it = 0; it < steps; ++it) {
+            if ((st = evaluate())) return st;
+            HIP_TRY(ps::launch_trace_newton(nseed, active, zt, sig, gz, eps, s));
+        }
+        if ((st = evaluate())) return st;
+        HIP_TRY(ps::launch_trace_accept(nseed, kp, max_points, eps, h, box, zt, sig, gz, active, zc, gc, z0,
+                                        (double2 *)points_dev, count_dev, flags_dev, s));
+        if ((kp & 7) == 7 && kp + 1 < max_points) {
+            int32_t h_active = 0;
+            HIP_TRY(ps::launch_count_active(nseed, active, n_active, s));
+            HIP_TRY(hipMemcpyAsync(&h_active, n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (h_active == 0) break;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return ok();
+}
+
 ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *o, void *stream) {
     ps_status st = check_handle(m);
     if (st) return st;

@@ -137,6 +137,17 @@ hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double
 int64_t backward_partial_rows(int64_t npts);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 int64_t contour_edge_tiles(int64_t nx, int64_t ny);
+hipError_t launch_trace_init(int64_t m, const double2 *seeds, double2 *zt, int32_t *active, int32_t *count,
+                             int32_t *flags, hipStream_t st);
+hipError_t launch_trace_predict(int64_t m, const int32_t *active, const double2 *zc, const double2 *gc, double h,
+                                double2 *zt, hipStream_t st);
+hipError_t launch_trace_newton(int64_t m, const int32_t *active, double2 *zt, const double *sigma, const double2 *g,
+                               double eps, hipStream_t st);
+hipError_t launch_trace_accept(int64_t m, int32_t k, int32_t max_points, double eps, double h, const ps_grid *box,
+                               const double2 *zt, const double *sigma, const double2 *g, int32_t *active, double2 *zc,
+                               double2 *gc, double2 *z0, double2 *pts, int32_t *count, int32_t *flags,
+                               hipStream_t st);
+hipError_t launch_count_active(int64_t m, const int32_t *active, int32_t *n_active, hipStream_t st);
 hipError_t launch_label_init(uint8_t *status, double *sig_out, int64_t npts, int64_t *evals, hipStream_t st);
 hipError_t launch_label_mask(const uint8_t *status, int64_t nx, int64_t npts, int stride, uint8_t *mask,
                              hipStream_t st);

@@ -770,6 +770,122 @@ __global__ void k_newton_update(int64_t npts, double2 *z, const double *sigma, c
     z[p] = make_double2(z[p].x - f * gp.x, z[p].y - f * gp.y);
 }
 
+// ------------------------------------------------------------------------ contour tracing
+// One thread per tracer.  zc: current point on the curve, gc: the gradient there, zt: the
+// point being corrected, z0: point 0 (closure test).
+
+__global__ void k_trace_init(int64_t m, const double2 *seeds, double2 *zt, int32_t *active, int32_t *count,
+                             int32_t *flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    zt[p] = seeds[p];
+    active[p] = 1;
+    count[p] = 0;
+    flags[p] = 0;
+}
+
+// Predictor: a step of length h along the tangent i g / |g| (active tracers only).
+__global__ void k_trace_predict(int64_t m, const int32_t *active, const double2 *zc, const double2 *gc, double h,
+                                double2 *zt) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m || !active[p]) return;
+    const double2 g = gc[p];
+    const double f = h / sqrt(fma(g.x, g.x, g.y * g.y));
+    zt[p] = make_double2(zc[p].x - f * g.y, zc[p].y + f * g.x);
+}
+
+// Corrector: one Newton step on ln(sigma / eps) along g (active tracers only).
+__global__ void k_trace_newton(int64_t m, const int32_t *active, double2 *zt, const double *sigma, const double2 *g,
+                               double eps) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m || !active[p]) return;
+    const double s = sigma[p];
+    const double2 gp = g[p];
+    const double g2 = fma(gp.x, gp.x, gp.y * gp.y);
+    if (!(s > 0.0) || !(g2 > 0.0)) return;
+    const double f = s * log(s / eps) / g2;
+    zt[p] = make_double2(zt[p].x - f * gp.x, zt[p].y - f * gp.y);
+}
+
+// Acceptance of point k: store it and set the stop flags (bits as PS_TRACE_*).
+__global__ void k_trace_accept(int64_t m, int32_t k, int32_t max_points, double eps, double h, int use_box,
+                               double ba, double bb, double bc, double bd, const double2 *zt, const double *sigma,
+                               const double2 *g, int32_t *active, double2 *zc, double2 *gc, double2 *z0,
+                               double2 *pts, int32_t *count, int32_t *flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m || !active[p]) return;
+    const double s = sigma[p];
+    if (!(s > 0.0) || !(fabs(log(s / eps)) <= 1e-6)) {
+        flags[p] |= PS_TRACE_NEWTON_FAILED;
+        active[p] = 0;
+        return;
+    }
+    const double2 z = zt[p];
+    pts[p * max_points + k] = z;
+    count[p] = k + 1;
+    zc[p] = z;
+    gc[p] = g[p];
+    if (k == 0) z0[p] = z;
+    int stop = 0;
+    if (use_box && !(z.x >= ba && z.x <= bb && z.y >= bc && z.y <= bd)) stop |= PS_TRACE_LEFT_BOX;
+    const double2 o = k == 0 ? z : z0[p];
+    if (k >= 3 && hypot(z.x - o.x, z.y - o.y) < h) stop |= PS_TRACE_CLOSED;
+    if (!stop && k == max_points - 1) stop |= PS_TRACE_MAX_POINTS;
+    if (stop) {
+        flags[p] |= stop;
+        active[p] = 0;
+    }
+}
+
+__global__ void k_count_active(int64_t m, const int32_t *active, int32_t *n_active) {
+    __shared__ int32_t sh[256];
+    int32_t c = 0;
+    for (int64_t p = threadIdx.x; p < m; p += 256) c += active[p] != 0;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_active = sh[0];
+}
+
+static dim3 grid_for(int64_t m) { return dim3((unsigned)((m + 255) / 256)); }
+
+hipError_t launch_trace_init(int64_t m, const double2 *seeds, double2 *zt, int32_t *active, int32_t *count,
+                             int32_t *flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_trace_init, grid_for(m), dim3(256), 0, st, m, seeds, zt, active, count, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_predict(int64_t m, const int32_t *active, const double2 *zc, const double2 *gc, double h,
+                                double2 *zt, hipStream_t st) {
+    hipLaunchKernelGGL(k_trace_predict, grid_for(m), dim3(256), 0, st, m, active, zc, gc, h, zt);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_newton(int64_t m, const int32_t *active, double2 *zt, const double *sigma, const double2 *g,
+                               double eps, hipStream_t st) {
+    hipLaunchKernelGGL(k_trace_newton, grid_for(m), dim3(256), 0, st, m, active, zt, sigma, g, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_accept(int64_t m, int32_t k, int32_t max_points, double eps, double h, const ps_grid *box,
+                               const double2 *zt, const double *sigma, const double2 *g, int32_t *active, double2 *zc,
+                               double2 *gc, double2 *z0, double2 *pts, int32_t *count, int32_t *flags,
+                               hipStream_t st) {
+    const int use_box = box != nullptr;
+    const double ba = box ? box->a : 0.0, bb = box ? box->b : 0.0, bc = box ? box->c : 0.0, bd = box ? box->d : 0.0;
+    hipLaunchKernelGGL(k_trace_accept, grid_for(m), dim3(256), 0, st, m, k, max_points, eps, h, use_box, ba, bb, bc,
+                       bd, zt, sigma, g, active, zc, gc, z0, pts, count, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_active(int64_t m, const int32_t *active, int32_t *n_active, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, st, m, active, n_active);
+    return hipGetLastError();
+}
+
 hipError_t launch_newton_update(int64_t npts, double2 *z, const double *sigma, const double2 *grad_z, double eps,
                                 hipStream_t st) {
     if (npts > 0)

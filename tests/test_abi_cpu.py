@@ -132,3 +132,18 @@ def test_label_argument_checks():
     with pytest.raises(P.PsError) as e:
         P.ps_label_grid(0, g, 0.01, None, fake, 1 << 30, fake)
     assert e.value.status == P.PS_ERR_INVALID
+
+
+def test_trace_argument_checks():
+    _lib()
+    o = P.ps_opts_default()
+    fake = 256
+    for bad in ((0.0, 1e-3, 10, 2), (1e-2, 0.0, 10, 2), (1e-2, float("nan"), 10, 2), (1e-2, 1e-3, 0, 2),
+                (1e-2, 1e-3, 10, 0)):
+        with pytest.raises(P.PsError) as e:
+            P.ps_trace_contour(fake, fake, 4, bad[0], bad[1], bad[2], bad[3], None, o, fake, 1 << 20, fake, fake,
+                               fake)
+        assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:
+        P.ps_trace_contour(0, fake, 4, 1e-2, 1e-3, 10, 2, None, o, fake, 1 << 20, fake, fake, fake)
+    assert e.value.status == P.PS_ERR_INVALID

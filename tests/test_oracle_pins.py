@@ -426,6 +426,50 @@ def test_contour_seeds_on_a_circle():
     np.testing.assert_allclose(np.sort(sd.real), [-0.5, 0.5], atol=1e-15)
 
 
+def test_trace_contour_circles():
+    # normal A: sigma_min(z) = dist(z, spectrum), so near an isolated eigenvalue a the
+    # eps-level curve is the circle |z - a| = eps (Sec. 2, resolvent-norm definition)
+    a = np.array([0.4 + 0.1j, -0.3 - 0.2j, 5.0])
+    band = W.diagonal(a)
+    eps, h = 1e-2, 1e-3
+    pts, cnt, fl = oracle.trace_contour(band, [a[0] + 1.2e-2, a[1] - 0.9e-2j], eps, h, max_points=200)
+    assert list(fl) == [oracle.TRACE_CLOSED, oracle.TRACE_CLOSED]
+    for t in range(2):
+        p = pts[t, :cnt[t]]
+        assert np.all(np.abs(np.abs(p - a[t]) - eps) < 1e-10)
+        # a tangent step of length h, then a radial correction: each step turns by
+        # atan(h / eps), so consecutive points are 2 eps sin(atan(h / eps) / 2) apart and a full
+        # turn takes 2 pi / atan(h / eps) steps
+        th = np.arctan(h / eps)
+        np.testing.assert_allclose(np.abs(np.diff(p)), 2 * eps * np.sin(th / 2), rtol=1e-6)
+        assert abs(cnt[t] - 2 * np.pi / th) <= 2
+        # counterclockwise around the region sigma < eps
+        ang = np.unwrap(np.angle(p - a[t]))
+        assert np.all(np.diff(ang) > 0)
+    # the box stops a tracer at the first point outside it, which is stored
+    pts, cnt, fl = oracle.trace_contour(band, [a[0] + 1.2e-2], eps, h, max_points=200,
+                                        box=(a[0].real - 1.0, a[0].real + 1.0, a[0].imag - 1.0, a[0].imag + 0.005))
+    assert fl[0] == oracle.TRACE_LEFT_BOX and pts[0, cnt[0] - 1].imag > a[0].imag + 0.005
+    assert np.all(pts[0, :cnt[0] - 1].imag <= a[0].imag + 0.005)
+    pts, cnt, fl = oracle.trace_contour(band, [a[0] + 1.2e-2], eps, h, max_points=10)
+    assert fl[0] == oracle.TRACE_MAX_POINTS and cnt[0] == 10
+
+
+def test_trace_contour_nonnormal_points_lie_on_the_curve():
+    # Grcar n = 40: every traced point has sigma_min = eps by LAPACK's SVD (an opinion
+    # independent of the Jacobi SVD the tracer uses), and consecutive points are about h apart
+    band = W.grcar(40)
+    A = W.to_dense(band)
+    eps, h = 1e-2, 0.02
+    pts, cnt, fl = oracle.trace_contour(band, [0.3 + 1.9j], eps, h, max_points=25)
+    p = pts[0, :cnt[0]]
+    assert cnt[0] == 25 and fl[0] == oracle.TRACE_MAX_POINTS
+    s = np.array([np.linalg.svd(z * np.eye(40) - A, compute_uv=False)[-1] for z in p])
+    assert np.all(np.abs(s / eps - 1) < 1e-6)
+    d = np.abs(np.diff(p))
+    assert np.all((d > 0.9 * h) & (d < 1.1 * h))
+
+
 # ----------------------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
