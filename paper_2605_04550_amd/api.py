@@ -259,7 +259,7 @@ def newton_contour(mat: BandedMatrix, z0: torch.Tensor, eps: float, steps: int =
 
 
 def trace_contour(mat: BandedMatrix, seeds: torch.Tensor, eps: float, h: float, max_points: int,
-                  newton_steps: int = 2, box=None, tol_rel=1e-12, tol_norm=1e-14, stream=None):
+                  newton_steps: int = 2, box=None, tol_rel=1e-8, tol_norm=1e-10, stream=None):
     """ps_trace_contour: follow the eps-level curve from each seed (tangent step of length h,
     then Newton corrections).  box: (a, b, c, d) or None.  Returns dict(points [nseed,
     max_points] complex128, count [nseed] int32, flags [nseed] int32, PS_TRACE_* bits)."""

@@ -241,6 +241,9 @@ struct Lane {
     int phase;
     int nbis;         // bisection passes so far
     double blo, bhi;  // bracket: blo < sigma_min (tested), sigma_min <= bhi
+    // vectors after the bisection (phase 2): the step, sigma and flags to report, |x|^2
+    int vit, vflags;
+    double vsig, vx2;
     // batch mode: the matrix of the current shift
     int64_t n;
     const double2 *arow;
@@ -611,7 +614,8 @@ struct Kern {
         // replay: vacc[r] (+)= p_k u_k[r]; the last replayed step also yields |v|^2 and the
         // first entry of largest modulus (for the phase convention)
         const bool first = rep && ln.k == 1, lastk = rep && ln.k == ln.kfinal;
-        const double cf = rep ? w.vmeta[((int64_t)(ln.k - 1) * 4 + 3) * T + s] : 0.0;
+        // (a lane held out of this sweep can be in the replay with k = 0: no read then)
+        const double cf = act && rep && ln.k >= 1 ? w.vmeta[((int64_t)(ln.k - 1) * 4 + 3) * T + s] : 0.0;
         double vn = 0.0, vam = -1.0;
         cd vph = C(1.0, 0.0);
         auto accum = [&](int64_t r, cd un) {
@@ -888,7 +892,7 @@ struct Kern {
     // whether the shift qualifies; if H - sigma_adm^2 I is not positive definite the shift takes
     // the Golub-Kahan path instead, which has no such limit (it never forms H).  With sigma_min
     // above sigma_adm nothing overflows or underflows, so the passes use plain doubles.
-    static constexpr bool BIS = !VEC && (KL + KU) >= 1;
+    static constexpr bool BIS = (KL + KU) >= 1;
     static constexpr int HB = KL + KU;          // half-bandwidth of H
     static constexpr int kBisMaxPass = 128;     // far above the ~30-40 passes a shift needs
 
@@ -1080,12 +1084,191 @@ struct Kern {
 
     static __device__ void finish_bis(const EvalArgs &a, Lane &ln, double sigma, int flags) {
         flags |= PS_PT_BISECT | (ln.nbis << 8);
+        if (VEC) {                    // the singular pair follows (vec_cycle)
+            ln.phase = 2;
+            ln.vit = 0;
+            ln.vsig = sigma;
+            ln.vflags = flags;
+            return;
+        }
         a.sigma[ln.pid] = sigma;
         if (a.info) a.info[ln.pid] = flags;
         if (a.iters) a.iters[ln.pid] = 0;
         if (a.sens) a.sens[ln.pid] = (uint8_t)(sigma <= a.eps);
         ln.active = false;
         ln.phase = 0;
+    }
+
+    // ---------------------------------------------------------------- vectors after the bisection
+    // With vectors wanted, a bisection shift ends with lo < sigma_min <= hi, hi - lo <= target.
+    // Its singular pair then comes from inverse iteration on H - lo^2 I = L D L^H (the test at
+    // lo passed, so this factorisation exists): the top eigenvalue 1 / (sigma_min^2 - lo^2) of
+    // (H - lo^2 I)^{-1} exceeds the next one by the factor (sigma_2^2 - lo^2) / (sigma_min^2 -
+    // lo^2), the gap to sigma_2 over the bracket width (1e3 and more where sigma_2 / sigma_min
+    // - 1 > 1e-5), so kInvIter steps from the start vector h give v; then u = M v / |M v|.  The
+    // factor is stored in the U array (U[i][0].x = 1/d_i, U[i][e] = L[i][i-e]), x in vv, the
+    // solves' middle vector in vy.  Phase convention as on the Golub-Kahan path.  One cycle of
+    // the lane does one unit: the factorisation, one step, or the output.
+    static constexpr int kInvIter = 4;
+
+    // M[r][c] of M = zI - A (zero outside the matrix).
+    static __device__ __forceinline__ cd mval(const EvalArgs &a, const Lane &ln, int64_t r, int64_t c) {
+        const int64_t n = nn(a, ln);
+        if (r < 0 || r >= n || c < 0 || c >= n) return czero();
+        const int64_t d = c - r + KL;
+        if (d < 0 || d >= W) return czero();
+        const cd v = band(a, ln)[r * W + d];
+        return r == c ? C(ln.z.x - v.x, ln.z.y - v.y) : C(-v.x, -v.y);
+    }
+
+    // Factorisation of H - sh I stored in U; x = h (the start vector) into vv; returns |h|^2.
+    static __device__ double vec_factor(const EvalArgs &a, const Workspace &w, int64_t s, const Lane &ln, double sh) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        constexpr int HA = HB > 0 ? HB : 1;
+        cd P[HA][HA];
+        double Q[HA];
+#pragma unroll
+        for (int e = 0; e < HA; ++e) {
+            Q[e] = 0.0;
+#pragma unroll
+            for (int f = 0; f < HA; ++f) P[e][f] = czero();
+        }
+        double h2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            cd h[HB + 1];
+#pragma unroll
+            for (int e = 0; e <= HB; ++e) {
+                double hx = 0.0, hy = 0.0;
+#pragma unroll
+                for (int t = 0; t <= HB - e; ++t) {
+                    const int64_t r = i - KU + t;
+                    const cd mi = mval(a, ln, r, i), mj = mval(a, ln, r, i - e);
+                    hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
+                    hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
+                }
+                h[e] = C(hx, e > 0 ? hy : 0.0);
+            }
+            double d = h[0].x - sh;
+            cd wv[HB + 1], lv[HB + 1];
+#pragma unroll
+            for (int e = HB; e >= 1; --e) {
+                cd acc = h[e];
+#pragma unroll
+                for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[e - 1][e2 - e - 1], wv[e2], acc);
+                wv[e] = acc;
+                lv[e] = cscale(acc, Q[e - 1]);
+                d = fma(-acc.x, lv[e].x, fma(-acc.y, lv[e].y, d));
+            }
+#pragma unroll
+            for (int e = HB - 1; e >= 1; --e) {
+                Q[e] = Q[e - 1];
+#pragma unroll
+                for (int f = 0; f + e + 1 < HB; ++f) P[e][f] = P[e - 1][f];
+            }
+            Q[0] = recip(d);
+#pragma unroll
+            for (int f = 1; f < HB; ++f) P[0][f - 1] = lv[f];
+            w.U[(i * W + 0) * T + s] = C(Q[0], 0.0);
+#pragma unroll
+            for (int e = 1; e <= HB; ++e) w.U[(i * W + e) * T + s] = lv[e];
+            const cd x = start_entry(a.seed, i);
+            w.vv[i * T + s] = x;
+            h2 += cabs2(x);
+        }
+        return h2;
+    }
+
+    // One step x <- (H - sh I)^{-1} (x / |x|) (forward L solve and the 1/d scaling into vy, then
+    // the backward L^H solve into vv); returns the new |x|^2 and records in vamax / vph the first
+    // entry of largest modulus.
+    static __device__ double vec_step(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double scale) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        constexpr int HA = HB > 0 ? HB : 1;
+        cd y[HA];
+#pragma unroll
+        for (int e = 0; e < HA; ++e) y[e] = czero();   // y[e-1] = y_{i-e}
+        for (int64_t i = 0; i < n; ++i) {
+            cd acc = cscale(w.vv[i * T + s], scale);
+#pragma unroll
+            for (int e = 1; e <= HB; ++e) acc = cfnma(w.U[(i * W + e) * T + s], y[e - 1], acc);
+#pragma unroll
+            for (int e = HB - 1; e >= 1; --e) y[e] = y[e - 1];
+            y[0] = acc;
+            w.vy[i * T + s] = cscale(acc, w.U[(i * W + 0) * T + s].x);
+        }
+        cd x[HA];
+#pragma unroll
+        for (int e = 0; e < HA; ++e) x[e] = czero();   // x[e-1] = x_{i+e}
+        double x2 = 0.0, am = -1.0;
+        cd ph = C(1.0, 0.0);
+        for (int64_t i = n - 1; i >= 0; --i) {
+            cd acc = w.vy[i * T + s];
+#pragma unroll
+            for (int e = 1; e <= HB; ++e)
+                if (i + e < n) acc = cfnmac(w.U[((i + e) * W + e) * T + s], x[e - 1], acc);
+#pragma unroll
+            for (int e = HB - 1; e >= 1; --e) x[e] = x[e - 1];
+            x[0] = acc;
+            w.vv[i * T + s] = acc;
+            const double m = cabs2(acc);
+            x2 += m;
+            if (m >= am) {             // going backward, >= keeps the first index on ties
+                am = m;
+                ph = acc;
+            }
+        }
+        ln.vamax = am;
+        ln.vph = ph;
+        return x2;
+    }
+
+    // v = x / |x| with the phase convention, u = M v / |M v|, then sigma and flags.
+    static __device__ void vec_output(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        const int64_t n = nn(a, ln), T = w.slots;
+        const double am = sqrt(ln.vamax);
+        const cd ph = am > 0.0 ? C(ln.vph.x / am, -ln.vph.y / am) : C(1.0, 0.0);
+        const double rv = 1.0 / sqrt(ln.vx2);
+        double2 *vout = a.v + ln.pid * n;
+        double2 *uout = a.u + ln.pid * n;
+        for (int64_t i = 0; i < n; ++i) {
+            const cd v = cscale(cmul(w.vv[i * T + s], ph), rv);
+            w.vv[i * T + s] = v;
+            vout[i] = v;
+        }
+        double u2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            cd acc = czero();
+#pragma unroll
+            for (int d = 0; d < W; ++d) {
+                const int64_t c = i - KL + d;
+                if (c >= 0 && c < n) {
+                    const cd m = mval(a, ln, i, c), v = w.vv[c * T + s];
+                    acc = C(fma(m.x, v.x, fma(-m.y, v.y, acc.x)), fma(m.x, v.y, fma(m.y, v.x, acc.y)));
+                }
+            }
+            w.vy[i * T + s] = acc;
+            u2 += cabs2(acc);
+        }
+        const double ru = 1.0 / sqrt(u2);
+        for (int64_t i = 0; i < n; ++i) uout[i] = cscale(w.vy[i * T + s], ru);
+        a.sigma[ln.pid] = ln.vsig;
+        if (a.info) a.info[ln.pid] = ln.vflags;
+        if (a.iters) a.iters[ln.pid] = 0;
+        if (a.sens) a.sens[ln.pid] = (uint8_t)(ln.vsig <= a.eps);
+        ln.active = false;
+        ln.phase = 0;
+    }
+
+    static __device__ void vec_cycle(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
+        if (ln.vit == 0) {
+            ln.vx2 = vec_factor(a, w, s, ln, ln.blo * ln.blo);
+        } else if (ln.vit <= kInvIter) {
+            ln.vx2 = vec_step(a, w, s, ln, 1.0 / sqrt(ln.vx2));
+        } else {
+            vec_output(a, w, s, ln);
+            return;
+        }
+        ln.vit += 1;
     }
 
     // ---------------------------------------------------------------- singular vectors
@@ -1502,6 +1685,8 @@ struct Kern {
         ln.phase = 0;
         ln.nbis = 0;
         ln.blo = ln.bhi = 0.0;
+        ln.vit = ln.vflags = 0;
+        ln.vsig = ln.vx2 = 0.0;
         while (true) {
             bool may_refill = !ln.active && !ln.exhausted;
             if (may_refill) {
@@ -1525,8 +1710,8 @@ struct Kern {
                     ln.b_m = 0.0;
                     ln.b_e = 0;
                     locate(a, qid >= 0 ? qid : 0, ln);
-                    if (!VEC && ln.active) {
-                        if (a.perm) {
+                    if (ln.active) {
+                        if (!VEC && a.perm) {
                             // the classification pass already ran this shift's first test
                             const uint8_t c = a.pcls[qid];
                             ln.phase = c == 1 ? 1 : 0;
@@ -1563,6 +1748,13 @@ struct Kern {
                 }
                 continue;
             }
+            // Lanes in the bisection, or computing their vectors after it, take one unit of
+            // that work per cycle.
+            if (BIS && __any(ln.active && !gk(ln))) {
+                if (ln.active && ln.phase == 1) bis_cycle(a, ln);
+                else if (ln.active && ln.phase == 2) vec_cycle(a, w, s, ln);
+            }
+            if (!__any(ln.active && gk(ln))) continue;
             // With vectors a cycle serves lanes in all three stages; lanes sit out the sweeps
             // their stage does not need (ln.active is cleared around those calls).
             const bool act0 = ln.active;
@@ -1572,7 +1764,7 @@ struct Kern {
             if (ln.active && ln.sing) finish(a, w, s, ln, 0);
             sweep_b1(a, w, s, ln, acc, eacc);
             const int st0 = ln.stage;
-            if (ln.active) after_b1(a, w, s, ln, acc, eacc);
+            if (ln.active && gk(ln)) after_b1(a, w, s, ln, acc, eacc);
             const bool hold = ln.active && ln.stage != st0;   // entered the replay: starts next cycle
             if (fin) {
                 ln.active = true;
@@ -1590,7 +1782,7 @@ struct Kern {
             } else if (fin) {
                 write_vectors(a, w, s, ln, acc, eacc);
                 ln.active = false;
-            } else if (ln.active && !hold) {
+            } else if (ln.active && !hold && gk(ln)) {
                 after_b2(a, w, s, ln, acc, eacc, kcap);
             }
         }

@@ -5,8 +5,8 @@ against the 8-row chunks) and 16 seeded shifts in its Gershgorin box, from near 
 spectrum to the box edge.  Every evaluation mode is compared with the oracle to the parity
 bar |sigma - sigma_oracle| <= 1e-10 ||A||_F + 1e-8 sigma_oracle:
   the Golub-Kahan path alone (bisection off), the default (inertia bisection where it
-  applies), the vector kernel (sigma only), and the batch kernel on a 4 x 4 grid with and
-  without bisection.
+  applies), the vector kernel (sigma, and the residual of the singular pair), and the batch
+  kernel on a 4 x 4 grid with and without bisection.
 The shapes share one source but are 75 separately compiled kernels (plus 25 batch
 kernels), so this is also the check that each compiled kernel computes what the source
 says."""
@@ -53,8 +53,16 @@ def test_every_mode_matches_oracle(kl, ku):
         assert np.all((info & 2) == 0), tag
         if tag == "default":
             used_bisection = int(np.sum((info & 8) != 0))
-        else:
+        elif tag == "golub-kahan":
             assert not np.any(info & 8), tag
+        else:
+            # the singular pair: unit vectors with (zI - A) v = sigma u to the accuracy of sigma
+            A = W.to_dense(band)
+            u, v = r["u"].cpu().numpy(), r["v"].cpu().numpy()
+            for p in range(len(z)):
+                res = np.linalg.norm((z[p] * np.eye(band.n) - A) @ v[p] - s[p] * u[p])
+                assert abs(np.linalg.norm(u[p]) - 1) < 1e-12 and abs(np.linalg.norm(v[p]) - 1) < 1e-12
+                assert res <= 4 * bnd[p] + 1e-12 * band.fro, (kl, ku, p, res, bnd[p])
     if kl + ku >= 1:
         assert used_bisection >= 8         # the far half of the shifts qualifies
     refg = oracle.sigma_min(band, oracle.grid_points(grid))["sigma"]
