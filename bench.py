@@ -57,16 +57,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
 KERNEL_TAG = "k_eval<1, 1, false, false>"
 
 
+# The sources of the measured launch: the kernels (classification, partition, k_eval at
+# kl = ku = 1), their workspace carving and launchers, and the constants they share.  The
+# host-side plan for this workload (one slot per shift) lives in ps_api.cpp.
+EVAL_SOURCES = ("ps_eval.hpp", "ps_eval_kl1.hip", "ps_kernels.hip", "ps_internal.h")
+
+
 def source_hash():
     """Hash of everything that decides the measured kernel's traffic on this workload (the
-    HIP sources and the input generator); a stored traffic figure is used only while it
-    matches."""
+    eval kernel's sources and the input generator); a stored traffic figure is used only
+    while it matches."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_04550_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in EVAL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     h.update(open(os.path.join(ROOT, "workloads", "gen.py"), "rb").read())
     return h.hexdigest()[:16]
 
