@@ -178,7 +178,7 @@ def cpu_baseline(band, z_sample, threads):
 
 
 def label_bench(args):
-    """Label workload of Sec. 3.2: NMAT matrices (n = 64, eq. (matrix)), 100 x 100 grid on
+    """Label workload of Sec. 3.3: NMAT matrices (n = 64, eq. (matrix)), 100 x 100 grid on
     [-4, 4]^2, eps = 0.01, as one batch.  Times ps_label_batch (exclusion regions) against the
     plain method (ps_eval_batch on every point, labels sigma <= eps)."""
     import torch
@@ -208,7 +208,7 @@ def label_bench(args):
     print(json.dumps({
         "metric": "grid points labelled per second (sensitive zone, eps = 0.01)", "value": npts / t_label,
         "unit": "points/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "Sec. 3.2 label workload: %d matrices n=64 (eq. (matrix)), 100x100 grid on "
+        "config": {"workload": "Sec. 3.3 label workload: %d matrices n=64 (eq. (matrix)), 100x100 grid on "
                                "[-4,4]^2, one batch" % len(mats), "matrices": len(mats)},
         "label_s": t_label, "plain_s": t_plain, "plain_points_per_s": npts / t_plain,
         "speedup_vs_plain_method": t_plain / t_label,
@@ -250,6 +250,94 @@ def trace_bench(args):
                   "newton_failed": int(np.sum(fl & 4 != 0)), "max_points": int(np.sum(fl & 8 != 0))}}), flush=True)
 
 
+# Network flops per evaluation of the classifier of Sec. 3.2: 2 x the multiply-adds of its dense
+# layers (26*64 + 64*64 + 33*128 + 128*64 + 2*128*128 + 128*64 + 64 = 59 200).
+MLP_FLOPS = 2 * 59200
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def mask_bench(args):
+    """The hybrid method of Sec. 4 on the Sec. 3.3 setting: NMAT matrices (n = 64, eq. (matrix)),
+    100 x 100 grid on [-4, 4]^2.  Per matrix the mask producer (ps_mask_predict: classifier of
+    Sec. 3.2 on the coarse grid of stride 4, refinement of the cells at or above the 80th
+    percentile, tau = 0.05, 5 x 5 dilation), then sigma_min on the masked points of all
+    matrices in one ps_eval_batch call, against the plain method (every point).  Weights are
+    seeded draws (no trained weights exist here), so the masks' coverage means nothing; the
+    cost does not depend on the weights' values.  Also the classifier's throughput alone
+    (ps_mlp_prob on 2^20 points) against the float32 matrix-core peak."""
+    import torch
+    import workloads as W
+    from paper_2605_04550_amd import api
+    from workloads import nets
+    w = W.paper_label_workload(args.mask)
+    grid = w["grid"]
+    dev = torch.device("cuda:0")
+    net = api.MaskNet(nets.mlp_params(W.SEED_BASE + 900, 3.0))
+    eigs = [torch.tensor(np.linalg.eigvals(W.to_dense(b)), dtype=torch.complex128, device=dev) for b in w["mats"]]
+    gfs = [list(nets.global_features(W.SEED_BASE + 901 + m)) for m in range(len(w["mats"]))]
+    mats = [api.BandedMatrix.from_band(b) for b in w["mats"]]
+    batch = api.BandedBatch(mats, [grid] * len(mats))
+    stream = torch.cuda.current_stream()
+
+    def masks():
+        return [net.predict(grid, gfs[m], eigs[m], tau=0.05) for m in range(len(mats))]
+
+    rs = masks()
+    batch.eval([r["mask"] for r in rs])
+    batch.eval(None)
+    torch.cuda.synchronize()
+    reps = 3
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    t_mask = t_rest = 0.0
+    for _ in range(reps):
+        e0.record(stream)
+        rs = masks()
+        e1.record(stream)
+        batch.eval([r["mask"] for r in rs])
+        e2.record(stream)
+        torch.cuda.synchronize()
+        t_mask += e0.elapsed_time(e1) / 1e3 / reps
+        t_rest += e1.elapsed_time(e2) / 1e3 / reps
+    e0.record(stream)
+    for _ in range(reps):
+        batch.eval(None)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / 1e3 / reps
+    evals = sum(int(r["evals"].item()) for r in rs)
+    region = sum(int(r["mask"].sum().item()) for r in rs)
+    npts = grid.npts * len(mats)
+    # classifier throughput: 2^20 points of the grid box, one launch
+    nthr = 1 << 20
+    rng = np.random.default_rng(7)
+    z = torch.tensor(rng.uniform(-4, 4, nthr) + 1j * rng.uniform(-4, 4, nthr), dtype=torch.complex128, device=dev)
+    net.prob(gfs[0], eigs[0], z)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        net.prob(gfs[0], eigs[0], z)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_prob = e0.elapsed_time(e1) / 1e3 / reps
+    achieved = MLP_FLOPS * nthr / t_prob / 1e12
+    print(json.dumps({
+        "metric": "grid points per second, hybrid method (mask producer + sigma_min on the mask)",
+        "value": npts / (t_mask + t_rest), "unit": "points/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32 (classifier) / f64 (sigma_min)", "data": "synthetic",
+        "config": {"workload": "Sec. 3.3 setting: %d matrices n=64 (eq. (matrix)), 100x100 grid on [-4,4]^2, "
+                               "stride 4, 80th percentile, tau 0.05, 5x5 dilation, seeded weights" % len(mats),
+                   "matrices": len(mats)},
+        "mask_s": t_mask, "mask_ms_per_matrix": 1e3 * t_mask / len(mats), "restricted_eval_s": t_rest,
+        "plain_s": t_plain, "speedup_vs_plain_method": t_plain / (t_mask + t_rest),
+        "network_evaluations": evals, "evaluations_per_matrix": evals / len(mats),
+        "region_fraction": region / npts,
+        "classifier": {"points": nthr, "seconds": t_prob, "evaluations_per_s": nthr / t_prob,
+                       "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                                    "kernel": "ps::mlp::k_points (one launch; + k_prep, 1 workgroup)",
+                                    "algorithmic_flops_per_launch": MLP_FLOPS * nthr}}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,8 +354,11 @@ def main():
     ap.add_argument("--trace", type=int, default=0, metavar="NSEED",
                     help="instead of the headline: trace the eps = 1e-2 contour of the workload from NSEED seeds")
     ap.add_argument("--labels", type=int, default=0, metavar="NMAT",
-                    help="instead of the headline: label NMAT matrices of the Sec. 3.2 workload by exclusion "
+                    help="instead of the headline: label NMAT matrices of the Sec. 3.3 workload by exclusion "
                          "regions and by the plain method, one JSON line")
+    ap.add_argument("--mask", type=int, default=0, metavar="NMAT",
+                    help="instead of the headline: the hybrid method (mask producer + restricted sigma_min) on NMAT "
+                         "matrices of the Sec. 3.3 setting, one JSON line")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
@@ -290,6 +381,9 @@ def main():
         return
     if args.trace:
         trace_bench(args)
+        return
+    if args.mask:
+        mask_bench(args)
         return
     w = W.workload("toeplitz2000")
     band, grid = w["band"], w["grid"]

@@ -108,7 +108,7 @@ void ps_opts_default(ps_opts *o);
 
 /*
  * ps_create_banded -- register a banded matrix A (n x n, kl sub- and ku superdiagonals).
- * Passage: the problem input A in C^{n x n} (Sec. 2; banded class of Sec. 3.2, eq. (matrix)).
+ * Passage: the problem input A in C^{n x n} (Sec. 2; banded class of Sec. 3.3, eq. (matrix)).
  *   ab    LAPACK general-band storage, column-major: A[i][j] = ab[(ku + i - j) + j * ldab]
  *         for max(0, j - ku) <= i <= min(n - 1, j + kl); other entries are ignored.
  *         Host pointer unless flags has PS_DEVICE_PTR.
@@ -231,7 +231,7 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
 
 /*
  * ps_label_batch -- ps_label_grid for every matrix of a batch at once (the label generation
- * of Sec. 3.2 runs over many matrices): each level builds the masks of all matrices, evaluates
+ * of Sec. 3.3 runs over many matrices): each level builds the masks of all matrices, evaluates
  * them with one persistent launch per (kl, ku) class as ps_eval_batch does, then marks and
  * excludes for all matrices together.  Matrix m's labels (and sigma) occupy
  * [offsets[m], offsets[m] + nx ny) of the concatenated outputs (offsets from ps_batch_info).
@@ -317,7 +317,7 @@ ps_status ps_trace_contour(ps_matrix m, const ps_c128 *seeds_dev, int64_t nseed,
  * ps_label_grid -- the sensitive zone S_eps of Sec. 2.1 (eq. sensitive_zone: z in S_eps iff
  * sigma_min(zI - A) <= eps) on the whole grid g, exactly, evaluating sigma_min only where the
  * answer is not already implied (the exclusion-region labelling the paper uses to generate
- * its training labels, Sec. 1 and Sec. 3.2).  sigma_min is 1-Lipschitz in z, so a computed
+ * its training labels, Sec. 1 and Sec. 3.3).  sigma_min is 1-Lipschitz in z, so a computed
  * sigma(z0) > eps excludes every grid point closer to z0 than sigma(z0) - eps - margin
  * (margin = twice the evaluation tolerance tol_norm ||A||_F + tol_rel sigma(z0)).  The still
  * unknown points of the lattices of stride 8, 4, 2 and 1 (coarser strides are skipped on
@@ -351,6 +351,97 @@ ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps
  * Errors: PS_ERR_INVALID, PS_ERR_HIP.
  */
 ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *o, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Mask producer (Sec. 3.2, Sec. 3.5, Sec. 4): the classifier p(z, A) of the dual-path network
+ * and its coarse-to-fine use over a grid, giving the restricted set R for ps_eval_grid.
+ *
+ * The network (Sec. 3.2, dual-path architecture).  Coordinates c = [Re z, Im z] are encoded
+ * as phi(c) = [c, sin(2c), cos(2c), sin(4c), cos(4c), ..., sin(64c), cos(64c)] (26 values,
+ * element-wise over c); the matrix features are f(z, A) = [f1 .. f30, g1, g2, g3] with the 30
+ * global features supplied by the caller and the per-point distances of Sec. 3.1 eq. (dist)
+ * computed here: g1 = min_i |z - lambda_i|, g2 = |z - lambda*|, g3 = mean_i |z - lambda_i|,
+ * lambda* read as the eigenvalue centroid (the paper leaves it undefined).  Then
+ *   h_c1 = SiLU(W_c1 phi + b_c1) (64), h_c2 = SiLU(W_c2 h_c1 + b_c2) (64),
+ *   h_m1 = SiLU(W_m1 f + b_m1) (128), h_m2 = SiLU(W_m2 h_m1 + b_m2) (64),
+ *   h4 = SiLU(W4 [h_c2, h_m2] + b4), h6 = h4 + SiLU(W5 h4 + b5) (128),
+ *   h7 = SiLU(W7 h6 + b7) (64), p = 1 / (1 + exp(-(w . h7 + b))).
+ * Parameter vector (PS_MLP_NPARAM floats): each layer's W (out x in, row-major) followed by
+ * its b, in the order W_c1 (64x26), W_c2 (64x64), W_m1 (128x33), W_m2 (64x128), W4 (128x128),
+ * W5 (128x128), W7 (64x128), w (1x64).
+ * Arithmetic: float32 (the matrix cores' 16x16x4 float32 products, float32 accumulation);
+ * the features are formed in float64 and rounded to float32; the global features enter
+ * through a float64 fold into b_m1.  No trained weights ship with the library.
+ * ---------------------------------------------------------------------------------------- */
+#define PS_MLP_NPARAM 59841
+#define PS_MLP_NGLOBAL 30
+
+typedef struct ps_mlp_s *ps_mlp;
+
+/* Options of ps_mask_predict (Sec. 3.5 hierarchical prediction, Sec. 3.6 threshold calibration). */
+typedef struct {
+    int32_t stride;   /* coarse stride s (default 4, 1 .. 32): coarse point (I, J) is fine
+                         point (s I, s J) and owns the cell of fine rows s I .. s I + s - 1 and
+                         columns likewise, cut at the grid's edge                             */
+    int32_t dilate;   /* side of the square structuring element (default 5; odd, 1 .. 31)    */
+    double coarse_q;  /* the coarse percentile as a fraction (default 0.8, in [0, 1])         */
+    double tau;       /* the calibrated threshold tau (default 0.05, in (0, 1])               */
+} ps_mask_opts;
+
+void ps_mask_opts_default(ps_mask_opts *o);
+
+/*
+ * ps_mlp_create -- upload a parameter vector (layout above) and repack it for the kernels.
+ *   params  PS_MLP_NPARAM floats; host pointer unless flags has PS_DEVICE_PTR.
+ *   out     receives a handle owning device copies (freed by ps_mlp_destroy).
+ * Synchronous on stream.  Errors: PS_ERR_INVALID, PS_ERR_NONFINITE (NaN/Inf), PS_ERR_HIP.
+ */
+ps_status ps_mlp_create(const float *params, uint32_t flags, ps_mlp *out, void *stream);
+ps_status ps_mlp_destroy(ps_mlp net);
+
+/*
+ * ps_mask_workspace_size -- device workspace of ps_mask_predict on grid g with options o
+ * (o NULL = defaults); g NULL gives the workspace of ps_mlp_prob.
+ */
+ps_status ps_mask_workspace_size(const ps_grid *g, const ps_mask_opts *o, size_t *bytes);
+
+/*
+ * ps_mlp_prob -- p(z, A) (Sec. 3.2) at npts arbitrary points.
+ *   gfeat    host double[30]: f1 .. f30 of A (Tables matrix, matrixAdd, resolvent of Sec. 3.1).
+ *   eig_dev  device ps_c128[neig], neig >= 1: the eigenvalues of A.
+ *   z_dev    device ps_c128[npts] (npts >= 0).   prob_dev  device float[npts].
+ *   ws_dev / ws_bytes >= ps_mask_workspace_size(NULL, NULL), 256-byte aligned.
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE (gfeat), PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_mlp_prob(ps_mlp net, const double *gfeat, const ps_c128 *eig_dev, int64_t neig, const ps_c128 *z_dev,
+                      int64_t npts, void *ws_dev, size_t ws_bytes, float *prob_dev, void *stream);
+
+/*
+ * ps_mask_predict -- the predicted region R of Sec. 4 on grid g by the hierarchical
+ * prediction of Sec. 3.5:
+ *   1. p at the coarse points -> P_coarse;
+ *   2. tau_coarse = quantile_q(P_coarse), linear interpolation between the order statistics
+ *      v_(k) <= v_(k+1) at h = q (m - 1), k = floor(h): v_(k) + (h - k)(v_(k+1) - v_(k));
+ *   3. every cell whose coarse value is >= tau_coarse gets p at all its fine points; every
+ *      other fine point gets probability 0;
+ *   4. mask = {p >= tau} dilated by the dilate x dilate square (points outside the grid do
+ *      not exist).
+ * The comparisons are taken in double on the float32 probabilities.  All steps run on the
+ * stream without host synchronisation.
+ *   mask_dev        device uint8[ny][nx] (required), row-major (row <-> y): R, ready as
+ *                   ps_eval_grid's mask.
+ *   prob_dev        device float[ny][nx] or NULL: the fine probability map (0 outside the
+ *                   refined cells).
+ *   coarse_dev      device float[ceil(ny/s)][ceil(nx/s)] or NULL: P_coarse.
+ *   tau_coarse_dev  device double or NULL.   evals_dev  device int64 or NULL: the number of
+ *                   network evaluations (coarse points + fine points of the refined cells).
+ *   gfeat, eig_dev, neig as in ps_mlp_prob.  o NULL = defaults.
+ *   ws_dev / ws_bytes >= ps_mask_workspace_size(g, o), 256-byte aligned.
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_mask_predict(ps_mlp net, const ps_grid *g, const double *gfeat, const ps_c128 *eig_dev, int64_t neig,
+                          const ps_mask_opts *o, void *ws_dev, size_t ws_bytes, uint8_t *mask_dev, float *prob_dev,
+                          float *coarse_dev, double *tau_coarse_dev, int64_t *evals_dev, void *stream);
 
 /* Thread-local description of the last error on the calling thread ("" if none). */
 const char *ps_last_error(void);

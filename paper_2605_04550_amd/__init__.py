@@ -42,6 +42,14 @@ class ps_opts(ctypes.Structure):
                 ("bisect", ctypes.c_int32)]
 
 
+class ps_mask_opts(ctypes.Structure):
+    _fields_ = [("stride", ctypes.c_int32), ("dilate", ctypes.c_int32), ("coarse_q", ctypes.c_double),
+                ("tau", ctypes.c_double)]
+
+
+PS_MLP_NPARAM, PS_MLP_NGLOBAL = 59841, 30
+
+
 class PsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
@@ -91,6 +99,15 @@ _SIGNATURES = {
     "ps_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "ps_batch_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "ps_eval_batch": (ctypes.c_int, [_P, _P, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+    "ps_mask_opts_default": (None, [ctypes.POINTER(ps_mask_opts)]),
+    "ps_mlp_create": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(_P), _P]),
+    "ps_mlp_destroy": (ctypes.c_int, [_P]),
+    "ps_mask_workspace_size": (ctypes.c_int, [ctypes.POINTER(ps_grid), ctypes.POINTER(ps_mask_opts),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_mlp_prob": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), _P, _I64, _P, _I64, _P, ctypes.c_size_t, _P,
+                                   _P]),
+    "ps_mask_predict": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), ctypes.POINTER(ctypes.c_double), _P, _I64,
+                                       ctypes.POINTER(ps_mask_opts), _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
 }
 
 
@@ -288,6 +305,53 @@ def ps_eval_batch(batch, masks_ptr, opts, ws_ptr, ws_bytes, idx_ptr, counts_ptr,
     _check(lib().ps_eval_batch(_P(batch), _P(masks_ptr), ctypes.byref(opts) if opts is not None else None,
                                _P(ws_ptr), ws_bytes, _P(idx_ptr), _P(counts_ptr), _P(sigma_ptr), _P(info_ptr),
                                _P(iters_ptr), _P(stream)))
+
+
+def ps_mask_opts_default(**kw) -> ps_mask_opts:
+    o = ps_mask_opts()
+    lib().ps_mask_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def ps_mlp_create(params_ptr, flags=0, stream=0) -> int:
+    h = _P()
+    _check(lib().ps_mlp_create(_P(params_ptr), flags, ctypes.byref(h), _P(stream)))
+    return h.value
+
+
+def ps_mlp_destroy(handle) -> None:
+    _check(lib().ps_mlp_destroy(_P(handle)))
+
+
+def ps_mask_workspace_size(grid, opts) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_mask_workspace_size(ctypes.byref(grid) if grid is not None else None,
+                                        ctypes.byref(opts) if opts is not None else None, ctypes.byref(b)))
+    return b.value
+
+
+def _gfeat(gfeat):
+    g = (ctypes.c_double * PS_MLP_NGLOBAL)(*[float(v) for v in gfeat])
+    return g
+
+
+def ps_mlp_prob(handle, gfeat, eig_ptr, neig, z_ptr, npts, ws_ptr, ws_bytes, prob_ptr, stream=0) -> None:
+    if len(gfeat) != PS_MLP_NGLOBAL:
+        raise ValueError("gfeat needs %d values" % PS_MLP_NGLOBAL)
+    _check(lib().ps_mlp_prob(_P(handle), _gfeat(gfeat), _P(eig_ptr), neig, _P(z_ptr), npts, _P(ws_ptr), ws_bytes,
+                             _P(prob_ptr), _P(stream)))
+
+
+def ps_mask_predict(handle, grid: ps_grid, gfeat, eig_ptr, neig, opts, ws_ptr, ws_bytes, mask_ptr, prob_ptr=0,
+                    coarse_ptr=0, tau_coarse_ptr=0, evals_ptr=0, stream=0) -> None:
+    if len(gfeat) != PS_MLP_NGLOBAL:
+        raise ValueError("gfeat needs %d values" % PS_MLP_NGLOBAL)
+    _check(lib().ps_mask_predict(_P(handle), ctypes.byref(grid), _gfeat(gfeat), _P(eig_ptr), neig,
+                                 ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
+                                 _P(mask_ptr), _P(prob_ptr), _P(coarse_ptr), _P(tau_coarse_ptr), _P(evals_ptr),
+                                 _P(stream)))
 
 
 def header_symbols():

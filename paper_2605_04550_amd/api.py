@@ -6,6 +6,8 @@
 * ``SigmaMin``       -- torch.autograd.Function: forward = ps_eval_points with vectors,
                         backward = ps_backward (gradients w.r.t. the shifts and the band).
 * ``newton_contour`` -- Newton steps moving points onto the level curve sigma_min = eps.
+* ``MaskNet``        -- the classifier of Sec. 3.2 (ps_mlp_create): ``prob`` (ps_mlp_prob) and
+                        ``predict`` (ps_mask_predict, the hierarchical prediction of Sec. 3.5).
 """
 from __future__ import annotations
 
@@ -20,9 +22,12 @@ from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_w
                ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
                ps_newton_workspace_size, ps_opts_default, ps_workspace_size, ps_contour_seeds,
                ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size, ps_label_batch,
-               ps_label_batch_workspace_size, ps_trace_contour, ps_trace_workspace_size)
+               ps_label_batch_workspace_size, ps_trace_contour, ps_trace_workspace_size, ps_mask_opts_default,
+               ps_mlp_create, ps_mlp_destroy, ps_mask_workspace_size, ps_mlp_prob, ps_mask_predict,
+               PS_MLP_NPARAM)
 
-__all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts"]
+__all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts",
+           "MaskNet"]
 
 
 def _stream_handle(stream=None) -> int:
@@ -317,3 +322,61 @@ def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):
     o = make_opts(**kw)
     ps_autotune(mat.handle, z.contiguous().data_ptr(), z.numel(), o, _stream_handle())
     return o
+
+
+class MaskNet:
+    """The classifier of Sec. 3.2 registered with the library (ps_mlp_create / ps_mlp_destroy).
+
+    params: PS_MLP_NPARAM float32 values in the layout of include/ps.h (numpy array or CUDA
+    tensor)."""
+
+    def __init__(self, params):
+        if isinstance(params, torch.Tensor):
+            t = params.detach().to(torch.float32).contiguous()
+            assert t.numel() == PS_MLP_NPARAM
+            self.handle = ps_mlp_create(t.data_ptr(), PS_DEVICE_PTR if t.is_cuda else 0,
+                                        _stream_handle() if t.is_cuda else 0)
+        else:
+            keep = np.ascontiguousarray(params, dtype=np.float32).ravel()
+            assert keep.size == PS_MLP_NPARAM
+            self.handle = ps_mlp_create(keep.ctypes.data, 0, _stream_handle())
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                ps_mlp_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def prob(self, gfeat, eig: torch.Tensor, z: torch.Tensor, stream=None) -> torch.Tensor:
+        """ps_mlp_prob: p(z, A) at the points z (complex128 CUDA tensor); eig: the eigenvalues of A
+        (complex128 CUDA tensor); gfeat: the 30 global features (host floats)."""
+        eig = eig.contiguous()
+        z = z.contiguous()
+        prob = torch.empty(z.numel(), dtype=torch.float32, device=z.device)
+        ws = _workspace(ps_mask_workspace_size(None, None), z.device)
+        ps_mlp_prob(self.handle, list(gfeat), eig.data_ptr(), eig.numel(), z.data_ptr(), z.numel(), ws.data_ptr(),
+                    ws.numel(), prob.data_ptr(), _stream_handle(stream))
+        return prob
+
+    def predict(self, grid, gfeat, eig: torch.Tensor, *, tau=0.05, stride=4, dilate=5, coarse_q=0.8, stream=None):
+        """ps_mask_predict: the predicted region R on the grid (Sec. 3.5 / Sec. 4).  Returns
+        dict(mask [ny, nx] uint8, prob [ny, nx] float32, coarse [cy, cx] float32,
+        tau_coarse (0-d float64 tensor), evals (1-element int64 tensor))."""
+        g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
+        o = ps_mask_opts_default(stride=int(stride), dilate=int(dilate), coarse_q=float(coarse_q), tau=float(tau))
+        eig = eig.contiguous()
+        dev = eig.device
+        cy, cx = (g.ny + o.stride - 1) // o.stride, (g.nx + o.stride - 1) // o.stride
+        mask = torch.empty((g.ny, g.nx), dtype=torch.uint8, device=dev)
+        prob = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev)
+        coarse = torch.empty((cy, cx), dtype=torch.float32, device=dev)
+        tau_c = torch.empty((), dtype=torch.float64, device=dev)
+        evals = torch.empty(1, dtype=torch.int64, device=dev)
+        ws = _workspace(ps_mask_workspace_size(g, o), dev)
+        ps_mask_predict(self.handle, g, list(gfeat), eig.data_ptr(), eig.numel(), o, ws.data_ptr(), ws.numel(),
+                        mask.data_ptr(), prob.data_ptr(), coarse.data_ptr(), tau_c.data_ptr(), evals.data_ptr(),
+                        _stream_handle(stream))
+        return dict(mask=mask, prob=prob, coarse=coarse, tau_coarse=tau_c, evals=evals)

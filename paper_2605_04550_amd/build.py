@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libps.so")
-SOURCES = ["ps_kernels.hip", "ps_api.cpp"] + ["ps_eval_kl%d.hip" % k for k in range(5)]
+SOURCES = ["ps_kernels.hip", "ps_mask.hip", "ps_api.cpp"] + ["ps_eval_kl%d.hip" % k for k in range(5)]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -3,6 +3,7 @@
 
 #include "ps.h"
 #include "ps_internal.h"
+#include "ps_mask.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -12,6 +13,12 @@
 
 #include <algorithm>
 #include <vector>
+
+struct ps_mlp_s {
+    float *raw;      // device, the parameter vector
+    float *packed;   // device, the MFMA operand order of the hidden layers
+    int device;
+};
 
 struct ps_matrix_s {
     int64_t n;
@@ -167,6 +174,151 @@ void ps_opts_default(ps_opts *o) {
     o->slots = 0;
     o->check_shift = 0;
     o->bisect = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Mask producer (classifier of Sec. 3.2, hierarchical prediction of Sec. 3.5).
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+ps_mask_opts resolve_mask(const ps_mask_opts *o) {
+    ps_mask_opts r;
+    ps_mask_opts_default(&r);
+    if (o) r = *o;
+    return r;
+}
+
+ps_status check_mask_opts(const ps_mask_opts &o) {
+    if (o.stride < 1 || o.stride > 32) return fail(PS_ERR_INVALID, "stride must be in [1, 32]");
+    if (o.dilate < 1 || o.dilate > 31 || o.dilate % 2 == 0) return fail(PS_ERR_INVALID, "dilate must be odd, 1 .. 31");
+    if (!(o.coarse_q >= 0.0 && o.coarse_q <= 1.0)) return fail(PS_ERR_INVALID, "coarse_q must be in [0, 1]");
+    if (!(o.tau > 0.0 && o.tau <= 1.0)) return fail(PS_ERR_INVALID, "tau must be in (0, 1]");
+    return PS_OK;
+}
+
+ps_status check_net_inputs(ps_mlp net, const double *gfeat, const ps_c128 *eig, int64_t neig,
+                           ps::mlp::Globals *gf) {
+    if (!net) return fail(PS_ERR_INVALID, "network handle is NULL");
+    if (!gfeat) return fail(PS_ERR_INVALID, "global features are NULL");
+    if (!eig || neig < 1) return fail(PS_ERR_INVALID, "the spectrum needs neig >= 1 eigenvalues");
+    for (int k = 0; k < ps::mlp::kNGlobal; ++k) {
+        if (!isfinite(gfeat[k])) return fail(PS_ERR_NONFINITE, "global feature %d is not finite", k);
+        gf->f[k] = gfeat[k];
+    }
+    return PS_OK;
+}
+
+}  // namespace
+
+void ps_mask_opts_default(ps_mask_opts *o) {
+    if (!o) return;
+    o->stride = 4;
+    o->dilate = 5;
+    o->coarse_q = 0.8;
+    o->tau = 0.05;
+}
+
+ps_status ps_mlp_create(const float *params, uint32_t flags, ps_mlp *out, void *stream) {
+    if (!params || !out) return fail(PS_ERR_INVALID, "params and out are required");
+    if (flags & ~(uint32_t)PS_DEVICE_PTR) return fail(PS_ERR_INVALID, "unknown flags");
+    *out = nullptr;
+    const size_t bytes = sizeof(float) * ps::mlp::kNParam;
+    std::vector<float> h(ps::mlp::kNParam);
+    if (flags & PS_DEVICE_PTR)
+        HIP_TRY(hipMemcpy(h.data(), params, bytes, hipMemcpyDeviceToHost));
+    else
+        memcpy(h.data(), params, bytes);
+    for (int i = 0; i < ps::mlp::kNParam; ++i)
+        if (!isfinite(h[i])) return fail(PS_ERR_NONFINITE, "parameter %d is not finite", i);
+    ps_mlp_s *n = new ps_mlp_s();
+    HIP_TRY(hipGetDevice(&n->device));
+    hipError_t e = hipMalloc((void **)&n->raw, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&n->packed, sizeof(float) * ps::mlp::kPackedFloats);
+    hipStream_t s = (hipStream_t)stream;
+    if (e == hipSuccess) e = hipMemcpyAsync(n->raw, h.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = ps::mlp::launch_pack(n->raw, n->packed, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        if (n->raw) (void)hipFree(n->raw);
+        if (n->packed) (void)hipFree(n->packed);
+        delete n;
+        return fail(PS_ERR_HIP, "ps_mlp_create: %s", hipGetErrorString(e));
+    }
+    *out = n;
+    return ok();
+}
+
+ps_status ps_mlp_destroy(ps_mlp net) {
+    if (!net) return ok();
+    hipError_t e1 = hipFree(net->raw), e2 = hipFree(net->packed);
+    delete net;
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(PS_ERR_HIP, "ps_mlp_destroy: hipFree failed");
+    return ok();
+}
+
+ps_status ps_mask_workspace_size(const ps_grid *g, const ps_mask_opts *o, size_t *bytes) {
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (!g) {
+        *bytes = ps::mlp::kWsHeader;
+        return ok();
+    }
+    ps_status st = check_grid(g);
+    if (st) return st;
+    const ps_mask_opts r = resolve_mask(o);
+    if ((st = check_mask_opts(r))) return st;
+    const int64_t ncoarse = ((g->ny + r.stride - 1) / r.stride) * ((g->nx + r.stride - 1) / r.stride);
+    *bytes = ps::mlp::kWsHeader + align256(sizeof(float) * (size_t)ncoarse) +
+             align256(sizeof(float) * (size_t)(g->nx * g->ny));
+    return ok();
+}
+
+ps_status ps_mlp_prob(ps_mlp net, const double *gfeat, const ps_c128 *eig_dev, int64_t neig, const ps_c128 *z_dev,
+                      int64_t npts, void *ws_dev, size_t ws_bytes, float *prob_dev, void *stream) {
+    ps::mlp::Globals gf;
+    ps_status st = check_net_inputs(net, gfeat, eig_dev, neig, &gf);
+    if (st) return st;
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    if (npts > 0 && (!z_dev || !prob_dev)) return fail(PS_ERR_INVALID, "z and prob are required");
+    if (!ws_dev || ws_bytes < (size_t)ps::mlp::kWsHeader)
+        return fail(PS_ERR_WORKSPACE, "network workspace needs %d bytes", ps::mlp::kWsHeader);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)ws_dev;
+    HIP_TRY(ps::mlp::launch_prep(net->raw, gf, (const double2 *)eig_dev, neig, ws, nullptr, 0, s));
+    HIP_TRY(ps::mlp::launch_points(net->raw, net->packed, (const double2 *)eig_dev, neig, ws, (const double2 *)z_dev,
+                                   npts, prob_dev, s));
+    return ok();
+}
+
+ps_status ps_mask_predict(ps_mlp net, const ps_grid *g, const double *gfeat, const ps_c128 *eig_dev, int64_t neig,
+                          const ps_mask_opts *o, void *ws_dev, size_t ws_bytes, uint8_t *mask_dev, float *prob_dev,
+                          float *coarse_dev, double *tau_coarse_dev, int64_t *evals_dev, void *stream) {
+    ps::mlp::Globals gf;
+    ps_status st = check_net_inputs(net, gfeat, eig_dev, neig, &gf);
+    if (st) return st;
+    if ((st = check_grid(g))) return st;
+    const ps_mask_opts r = resolve_mask(o);
+    if ((st = check_mask_opts(r))) return st;
+    if (!mask_dev) return fail(PS_ERR_INVALID, "mask output is NULL");
+    const int64_t ncy = (g->ny + r.stride - 1) / r.stride, ncx = (g->nx + r.stride - 1) / r.stride;
+    if (ncy * ncx >= ((int64_t)1 << 31)) return fail(PS_ERR_INVALID, "too many coarse points");
+    size_t need = 0;
+    ps_mask_workspace_size(g, &r, &need);
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "mask workspace needs %zu bytes", need);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    char *ws = (char *)ws_dev;
+    float *coarse = coarse_dev ? coarse_dev : (float *)(ws + ps::mlp::kWsHeader);
+    float *prob = prob_dev ? prob_dev
+                           : (float *)(ws + ps::mlp::kWsHeader + align256(sizeof(float) * (size_t)(ncy * ncx)));
+    int64_t *evals = evals_dev ? evals_dev : (int64_t *)(ws + ps::mlp::kWsEvals);
+    ps::mlp::GridArgs ga{g->a, g->b, g->c, g->d, g->nx, g->ny};
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ps::mlp::launch_prep(net->raw, gf, (const double2 *)eig_dev, neig, ws, evals, ncy * ncx, s));
+    HIP_TRY(ps::mlp::launch_mask(net->raw, net->packed, (const double2 *)eig_dev, neig, ws, ga, r.stride, r.dilate,
+                                 r.coarse_q, r.tau, coarse, prob, mask_dev, evals, tau_coarse_dev, s));
+    return ok();
 }
 
 const char *ps_last_error(void) { return g_err; }

@@ -16,7 +16,7 @@ Sets (file ``tests/golden/<set>.npz``):
   grcar400_vec       Grcar n=400, 32 seeded points of the 256x256 grid on [-1.5,3]x[-3.5,3.5],
                      with singular vectors and the two smallest singular values.
   batch_pts          One seeded point for each matrix of the 64-matrix batch with n <= 1200.
-  paper_labels       The first three matrices of the label workload of Sec. 3.2 (n = 64,
+  paper_labels       The first three matrices of the label workload of Sec. 3.3 (n = 64,
                      100x100 grid on [-4,4]^2): sigma at all 10^4 points and the labels
                      sigma <= 0.01 (keys sigma0.., label0..).
 Each file holds: idx (flat grid index, or -1), z, sigma, s2 (second smallest singular

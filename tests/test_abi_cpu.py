@@ -147,3 +147,55 @@ def test_trace_argument_checks():
     with pytest.raises(P.PsError) as e:
         P.ps_trace_contour(0, fake, 4, 1e-2, 1e-3, 10, 2, None, o, fake, 1 << 20, fake, fake, fake)
     assert e.value.status == P.PS_ERR_INVALID
+
+
+def test_mask_argument_checks():
+    """ps_mlp_create / ps_mlp_prob / ps_mask_predict reject bad arguments before any device call."""
+    _lib()
+    fake = 256
+    params = np.zeros(P.PS_MLP_NPARAM, dtype=np.float32)
+    params[123] = np.nan
+    with pytest.raises(P.PsError) as e:
+        P.ps_mlp_create(params.ctypes.data, 0, 0)
+    assert e.value.status == P.PS_ERR_NONFINITE
+    with pytest.raises(P.PsError) as e:
+        P.ps_mlp_create(0, 0, 0)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:
+        P.ps_mlp_create(params.ctypes.data, 4, 0)               # unknown flag
+    assert e.value.status == P.PS_ERR_INVALID
+    g = P.ps_grid(-4, 4, -4, 4, 100, 100)
+    for bad in (dict(stride=0), dict(stride=33), dict(dilate=4), dict(dilate=0), dict(dilate=33),
+                dict(coarse_q=1.5), dict(coarse_q=float("nan")), dict(tau=0.0), dict(tau=1.5)):
+        o = P.ps_mask_opts_default(**bad)
+        with pytest.raises(P.PsError) as e:
+            P.ps_mask_workspace_size(g, o)
+        assert e.value.status == P.PS_ERR_INVALID, bad
+        with pytest.raises(P.PsError) as e:
+            P.ps_mask_predict(fake, g, [0.0] * 30, fake, 4, o, fake, 1 << 20, fake)
+        assert e.value.status == P.PS_ERR_INVALID, bad
+    # workspace: header + coarse map + probability map, each rounded to 256 bytes
+    assert P.ps_mask_workspace_size(None, None) == 1024
+    assert P.ps_mask_workspace_size(g, None) == 1024 + 2560 + 40192
+    o = P.ps_mask_opts_default()
+    with pytest.raises(P.PsError) as e:                          # NULL network
+        P.ps_mask_predict(0, g, [0.0] * 30, fake, 4, o, fake, 1 << 20, fake)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:                          # empty spectrum
+        P.ps_mask_predict(fake, g, [0.0] * 30, fake, 0, o, fake, 1 << 20, fake)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:                          # non-finite global feature
+        P.ps_mask_predict(fake, g, [0.0] * 29 + [float("inf")], fake, 4, o, fake, 1 << 20, fake)
+    assert e.value.status == P.PS_ERR_NONFINITE
+    with pytest.raises(P.PsError) as e:                          # workspace too small
+        P.ps_mask_predict(fake, g, [0.0] * 30, fake, 4, o, fake, 1000, fake)
+    assert e.value.status == P.PS_ERR_WORKSPACE
+    with pytest.raises(P.PsError) as e:                          # mask output missing
+        P.ps_mask_predict(fake, g, [0.0] * 30, fake, 4, o, fake, 1 << 20, 0)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:
+        P.ps_mlp_prob(fake, [0.0] * 30, fake, 4, fake, -1, fake, 1024, fake)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(P.PsError) as e:
+        P.ps_mlp_prob(fake, [0.0] * 30, fake, 4, fake, 8, fake, 512, fake)
+    assert e.value.status == P.PS_ERR_WORKSPACE

@@ -1,5 +1,5 @@
 """GPU tests of the exclusion-region labelling (ps_label_grid): the sensitive zone of
-Sec. 2.1 on the label workload of Sec. 3.2 (n = 64 matrices of the class of eq. (matrix),
+Sec. 2.1 on the label workload of Sec. 3.3 (n = 64 matrices of the class of eq. (matrix),
 100 x 100 grid on [-4, 4]^2, eps = 0.01), against the oracle's labels at every grid point
 and against the plain evaluation of every point.  A point whose sigma lies within the parity
 bar of eps may go either way; every other label must agree."""

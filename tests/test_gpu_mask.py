@@ -1,0 +1,150 @@
+"""GPU parity of the mask producer (ps_mlp_prob, ps_mask_predict) against the oracle
+(``oracle/mask.py``): the classifier of Sec. 3.2 and the hierarchical prediction of Sec. 3.5.
+
+Probabilities: |p_gpu - p_oracle| within the oracle's first-order bound for a float32
+evaluation, per point.  Decisions (the coarse percentile, the refined cells, p >= tau, the
+dilation): the oracle's rule is fed the GPU's own float32 probabilities, and the GPU's
+tau_coarse, refined cells, probability map, mask and evaluation count must then be identical.
+Weights, global features and spectra are seeded draws (``workloads.nets``); the paper's
+trained weights are not available."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import need_gpu
+from oracle import mask as OM
+from workloads import nets
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    need_gpu()
+    from paper_2605_04550_amd import api
+    return api
+
+
+def _t(x, dtype):
+    import torch
+    return torch.tensor(x, dtype=dtype, device="cuda")
+
+
+def _check_prob(p_gpu, params, gf, eig, z, what):
+    p_or, e = OM.mlp_prob(params, gf, eig, z, bound=True)
+    err = np.abs(p_gpu.astype(np.float64) - p_or)
+    worst = int(np.argmax(err / e))
+    print("%s: %d points, max |dp| %.2e, max |dp| / bound %.3f (p std %.3f)"
+          % (what, len(z), err.max(), (err / e)[worst], p_or.std()), flush=True)
+    assert np.all(err <= e + 1e-30), (what, worst, p_gpu[worst], p_or[worst], e[worst])
+    return p_or, e
+
+
+@pytest.mark.parametrize("scale,neig,npts", [(1.0, 64, 1000), (3.0, 23, 517), (3.0, 1, 37), (2.0, 301, 16)])
+def test_mlp_prob_vs_oracle(scale, neig, npts):
+    api = _api()
+    import torch
+    params = nets.mlp_params(11, scale)
+    gf = nets.global_features(12)
+    eig = nets.spectrum(13, neig)
+    rng = np.random.default_rng(14)
+    z = rng.uniform(-4, 4, npts) + 1j * rng.uniform(-4, 4, npts)
+    net = api.MaskNet(params)
+    p = net.prob(gf, _t(eig, torch.complex128), _t(z, torch.complex128))
+    torch.cuda.synchronize()
+    _check_prob(p.cpu().numpy(), params, gf, eig, z, "prob scale %g neig %d" % (scale, neig))
+    # a device-resident parameter vector gives the same network
+    net2 = api.MaskNet(_t(params, torch.float32))
+    p2 = net2.prob(gf, _t(eig, torch.complex128), _t(z, torch.complex128))
+    assert torch.equal(p, p2)
+    # no points: nothing to do
+    assert net.prob(gf, _t(eig, torch.complex128), _t(np.zeros(0), torch.complex128)).numel() == 0
+
+
+def _run_mask(api, grid, params, gf, eig, tau, stride, dilate, q=0.8):
+    import torch
+    net = api.MaskNet(params)
+    r = net.predict(grid, gf, _t(eig, torch.complex128), tau=tau, stride=stride, dilate=dilate, coarse_q=q)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def _check_mask(grid, params, gf, eig, tau, stride, dilate, r, q=0.8, what=""):
+    cy, cx = OM.coarse_shape(grid, stride)
+    assert r["coarse"].shape == (cy, cx) and r["prob"].shape == (grid.ny, grid.nx)
+    # coarse probabilities vs the oracle
+    ci, cj = np.meshgrid(np.arange(cy), np.arange(cx), indexing="ij")
+    cflat = (stride * ci * grid.nx + stride * cj).ravel()
+    _check_prob(r["coarse"].ravel(), params, gf, eig, OM.mask_points_z(grid, cflat), what + " coarse")
+    # the oracle's rule on the GPU's own probabilities: identical decisions
+    gprob = r["prob"].astype(np.float64).ravel()
+    ref = OM.hierarchical_mask(grid, lambda flat: gprob[np.asarray(flat)], tau, stride=stride, q=q, dilate=dilate,
+                               coarse=r["coarse"].astype(np.float64))
+    assert float(r["tau_coarse"]) == ref["tau_coarse"], (float(r["tau_coarse"]), ref["tau_coarse"])
+    np.testing.assert_array_equal(r["prob"].astype(np.float64), ref["prob"])     # zeros exactly off the refined cells
+    np.testing.assert_array_equal(r["mask"], ref["mask"])
+    assert int(r["evals"][0]) == ref["evals"]
+    # fine probabilities of the refined cells vs the oracle
+    fine = np.flatnonzero(np.kron(ref["selected"], np.ones((stride, stride), dtype=bool))[:grid.ny, :grid.nx].ravel())
+    if fine.size:
+        _check_prob(r["prob"].ravel()[fine], params, gf, eig, OM.mask_points_z(grid, fine), what + " fine")
+    return ref
+
+
+def test_mask_predict_paper_grid_vs_oracle():
+    """The Sec. 3.5 setting: 100 x 100 grid on [-4, 4]^2, stride 4 (625 coarse points), 80th
+    percentile, 5 x 5 dilation; a 64-point spectrum."""
+    api = _api()
+    grid = W.Grid(-4.0, 4.0, -4.0, 4.0, 100, 100)
+    params, gf, eig = nets.mlp_params(21, 3.0), nets.global_features(22), nets.spectrum(23, 64)
+    for tau in (0.05, 0.3, 0.6):
+        r = _run_mask(api, grid, params, gf, eig, tau, 4, 5)
+        ref = _check_mask(grid, params, gf, eig, tau, 4, 5, r, what="paper grid tau %g" % tau)
+        print("tau %g: tau_coarse %.4f, %d refined cells, %d evaluations, |R| = %d"
+              % (tau, ref["tau_coarse"], ref["selected"].sum(), int(r["evals"][0]), int(r["mask"].sum())), flush=True)
+        assert ref["selected"].sum() >= 125                    # at least the top 20 % of 625 cells
+        # end to end against the float64 oracle: masks agree except where a decision sits
+        # within the float32 error of its threshold
+        full = OM.mask_predict(params, gf, eig, grid, tau)
+        diff = np.flatnonzero(full["mask"].ravel() != r["mask"].ravel())
+        if diff.size:
+            pc, ec = OM.mlp_prob(params, gf, eig, OM.mask_points_z(grid, np.arange(grid.npts)), bound=True)
+            near = np.abs(pc - tau) <= ec
+            near_c = abs(full["tau_coarse"] - float(r["tau_coarse"])) > 0
+            assert near.any() or near_c, diff[:10]
+        print("  float64 oracle mask differs at %d points" % diff.size, flush=True)
+
+
+@pytest.mark.parametrize("shape,stride,dilate,tau,neig", [
+    ((37, 23), 4, 5, 0.4, 23), ((1, 1), 4, 5, 0.1, 1), ((13, 1), 4, 1, 0.5, 5), ((1, 30), 3, 5, 0.2, 7),
+    ((50, 61), 8, 3, 0.6, 64), ((17, 9), 2, 7, 0.4, 64), ((100, 100), 1, 1, 0.5, 10), ((64, 64), 16, 31, 0.7, 3),
+    ((33, 47), 5, 9, 1.0, 40)])
+def test_mask_predict_ragged_and_edge_cases(shape, stride, dilate, tau, neig):
+    api = _api()
+    nx, ny = shape
+    grid = W.Grid(-3.0, 2.5, -1.5, 4.0, nx, ny)
+    params, gf, eig = nets.mlp_params(31 + nx, 3.0), nets.global_features(32), nets.spectrum(33 + ny, neig)
+    r = _run_mask(api, grid, params, gf, eig, tau, stride, dilate)
+    _check_mask(grid, params, gf, eig, tau, stride, dilate, r, what="%dx%d s%d d%d" % (nx, ny, stride, dilate))
+
+
+def test_mask_feeds_the_restricted_evaluation():
+    """Sec. 4: sigma_min only on R.  The predicted mask goes straight into ps_eval_grid; the
+    values on R equal the full-grid values at the same points (same arithmetic)."""
+    api = _api()
+    import torch
+    band = W.paper_training_matrix(W.SEED_BASE + 6000)
+    A = W.to_dense(band)
+    eig = np.linalg.eigvals(A)                      # input preparation: the spectrum of A
+    grid = W.Grid(-4.0, 4.0, -4.0, 4.0, 100, 100)
+    params, gf = nets.mlp_params(41, 3.0), nets.global_features(42)
+    net = api.MaskNet(params)
+    r = net.predict(grid, gf, _t(eig, torch.complex128), tau=0.3)
+    mat = api.BandedMatrix.from_band(band)
+    full = api.eval_grid(mat, grid, eps=0.01)
+    res = api.eval_grid(mat, grid, r["mask"], eps=0.01)
+    torch.cuda.synchronize()
+    c = int(res["count"].item())
+    idx = res["idx"][:c].cpu().numpy()
+    np.testing.assert_array_equal(idx, np.flatnonzero(r["mask"].cpu().numpy().ravel()))
+    np.testing.assert_allclose(res["sigma"][:c].cpu().numpy(), full["sigma"].cpu().numpy()[idx], rtol=1e-13, atol=0)
+    print("restricted evaluation: |R| = %d of %d points" % (c, grid.npts), flush=True)

@@ -7,7 +7,7 @@ In memory this is exactly LAPACK's column-major ``AB(ldab = kl + ku + 1, n)``.
 Entries of ``ab`` that fall outside the matrix are zero.
 
 Matrix families follow the paper's setting (banded non-normal A, Sec. 1 and
-the training generator of Sec. 3.2, eq. (matrix)) and the five measured
+the training generator of Sec. 3.3, eq. (matrix)) and the five measured
 workloads; grids follow Sec. 2.1 (z_ij = x_j + i*y_i on [a,b] x [c,d]).
 Random draws use ``numpy.random.default_rng(seed)`` (PCG64).
 """
@@ -221,7 +221,7 @@ def random_mask(grid: Grid, count: int, seed: int):
 
 
 def paper_training_matrix(seed: int, n: int = 64, max_tries: int = 1000) -> Band:
-    """Sec. 3.2, eq. (matrix): bandwidth beta ~ U{1..4}; A_ij ~ U{-1, 0, 1} for |i-j| <= beta, else 0;
+    """Sec. 3.3, eq. (matrix): bandwidth beta ~ U{1..4}; A_ij ~ U{-1, 0, 1} for |i-j| <= beta, else 0;
     rejected if A equals its transpose or if cond(A) >= 1e8."""
     rng = np.random.default_rng(seed)
     for _ in range(max_tries):
@@ -290,7 +290,7 @@ def _w_grcar4000():
 
 
 def paper_label_workload(nmat: int = 500, first: int = 0):
-    """The label-generation setting of Sec. 3.2: matrices of the class of eq. (matrix), n = 64,
+    """The label-generation setting of Sec. 3.3: matrices of the class of eq. (matrix), n = 64,
     each labelled on a 100 x 100 grid over [-4, 4] x [-4, 4] with eps = 0.01 (z sensitive iff
     sigma_min(zI - A) <= eps).  Matrix m uses seed base + 6000 + m."""
     grid = Grid(-4.0, 4.0, -4.0, 4.0, 100, 100)
