@@ -23,8 +23,8 @@ Contents (each function names the passage of the paper it follows):
   * ``trace_contour``  -- points along the eps-level curve from seeds: a step along the
                           tangent, then Newton steps back onto the curve (Sec. 2.1 level
                           curve; the paper does not say how to follow it).
-  * ``mask``           -- submodule: the classifier of Sec. 3.3 and its hierarchical use over a
-                          grid (Sec. 3.6), the producer of the restricted set R (Sec. 4).
+  * ``mask``           -- submodule: the classifier of Sec. 3.2 and its hierarchical use over a
+                          grid (Sec. 3.5), the producer of the restricted set R (Sec. 4).
 Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
 closed forms, invariants, brute force and the paper's Jordan example; the ``mask``
 submodule in ``tests/test_oracle_mask_pins.py``.

@@ -7,14 +7,14 @@ library; the two meet only through the seeded inputs of ``workloads``.  Arithmet
 float64 throughout (the network's weights are float32 numbers, used exactly).
 
 Contents, each following the passage named in its docstring:
-  * ``unpack``             -- the parameter vector split into the layers of Sec. 3.3.
-  * ``fourier_features``   -- phi(c) of Sec. 3.3 (Fourier feature encoding), 26 values.
-  * ``point_features``     -- g1, g2, g3 of Sec. 3.2, eq. (dist).
-  * ``mlp_prob``           -- p(z, A) of Sec. 3.3 (dual-path network), with an optional
+  * ``unpack``             -- the parameter vector split into the layers of Sec. 3.2.
+  * ``fourier_features``   -- phi(c) of Sec. 3.2 (Fourier feature encoding), 26 values.
+  * ``point_features``     -- g1, g2, g3 of Sec. 3.1, eq. (dist).
+  * ``mlp_prob``           -- p(z, A) of Sec. 3.2 (dual-path network), with an optional
                               a-priori bound on the error of a float32 evaluation.
-  * ``quantile_linear``    -- the 80th-percentile threshold of Sec. 3.6 (hierarchical
+  * ``quantile_linear``    -- the 80th-percentile threshold of Sec. 3.5 (hierarchical
                               prediction), linear interpolation between order statistics.
-  * ``hierarchical_mask``  -- Sec. 3.6 and Sec. 4: coarse grid of stride s, refinement of
+  * ``hierarchical_mask``  -- Sec. 3.5 and Sec. 4: coarse grid of stride s, refinement of
                               the cells at or above the percentile, threshold tau, square
                               dilation.
   * ``mask_predict``       -- ``hierarchical_mask`` with the network as the probability.
@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-# Layer shapes of Sec. 3.3 (out, in), in the order the parameter vector stores them; each
+# Layer shapes of Sec. 3.2 (out, in), in the order the parameter vector stores them; each
 # layer is its weight matrix W (out x in, row-major, y = W h + b) followed by its bias b.
 LAYERS = (
     ("c1", 64, 26),    # coordinate path, on phi(c)
@@ -45,7 +45,7 @@ U32 = 2.0 ** -24                                  # unit roundoff of float32
 
 
 def unpack(params):
-    """Split the flat parameter vector into {name: (W, b)} (float64 copies), Sec. 3.3."""
+    """Split the flat parameter vector into {name: (W, b)} (float64 copies), Sec. 3.2."""
     p = np.asarray(params, dtype=np.float64).ravel()
     if p.size != NPARAM:
         raise ValueError("expected %d parameters, got %d" % (NPARAM, p.size))
@@ -60,7 +60,7 @@ def unpack(params):
 
 
 def fourier_features(x, y):
-    """Sec. 3.3, Fourier feature encoding: phi(c) = [c, sin(2c), cos(2c), sin(4c), cos(4c), ...,
+    """Sec. 3.2, Fourier feature encoding: phi(c) = [c, sin(2c), cos(2c), sin(4c), cos(4c), ...,
     sin(64c), cos(64c)] for c = [x, y], element-wise over c; 2 + 6 * 4 = 26 values per point."""
     x = np.atleast_1d(np.asarray(x, dtype=np.float64))
     y = np.atleast_1d(np.asarray(y, dtype=np.float64))
@@ -72,7 +72,7 @@ def fourier_features(x, y):
 
 
 def point_features(z, eig):
-    """Sec. 3.2, eq. (dist): g1 = min_i |z - lambda_i|, g2 = |z - lambda*|, g3 = mean_i |z - lambda_i|.
+    """Sec. 3.1, eq. (dist): g1 = min_i |z - lambda_i|, g2 = |z - lambda*|, g3 = mean_i |z - lambda_i|.
 
     lambda* is not defined in the paper; it is read as the eigenvalue centroid (the mean of
     the eigenvalues, the point the resolvent features of the same section are taken around)."""
@@ -113,7 +113,7 @@ def _act_err(y):
 
 
 def mlp_prob(params, gfeat, eig, z, bound=False):
-    """Sec. 3.3: p(z, A) = sigmoid(w^T h7 + b) of the dual-path network, for points z.
+    """Sec. 3.2: p(z, A) = sigmoid(w^T h7 + b) of the dual-path network, for points z.
 
     gfeat: the 30 global matrix features f1 .. f30 (computed by the caller); eig: the
     eigenvalues of A (for g1 .. g3).  Coordinates c = [Re z, Im z].
@@ -195,7 +195,7 @@ def mlp_prob(params, gfeat, eig, z, bound=False):
 
 
 def quantile_linear(values, q):
-    """Sec. 3.6: tau_coarse = quantile_q(P_coarse), read as linear interpolation between the
+    """Sec. 3.5: tau_coarse = quantile_q(P_coarse), read as linear interpolation between the
     order statistics v_(0) <= ... <= v_(m-1) at position h = q (m - 1):
     tau = v_(k) + (h - k) (v_(k+1) - v_(k)), k = floor(h) (v_(k+1) = v_(k) when k = m - 1)."""
     v = np.sort(np.asarray(values, dtype=np.float64).ravel())
@@ -211,7 +211,7 @@ def quantile_linear(values, q):
 
 
 def coarse_shape(grid, stride):
-    """Sec. 3.6: the coarse grid takes every stride-th point in both directions, starting at the
+    """Sec. 3.5: the coarse grid takes every stride-th point in both directions, starting at the
     first; coarse point (I, J) is fine point (stride I, stride J) and owns the cell of fine rows
     stride I .. stride I + stride - 1 and columns likewise (cut at the grid's edge)."""
     return (grid.ny + stride - 1) // stride, (grid.nx + stride - 1) // stride
@@ -224,7 +224,7 @@ def _grid_z(grid, rows, cols):
 
 
 def hierarchical_mask(grid, prob_at, tau, stride=4, q=0.8, dilate=5, coarse=None):
-    """Sec. 3.6 (hierarchical prediction) and Sec. 4 (the predicted region R):
+    """Sec. 3.5 (hierarchical prediction) and Sec. 4 (the predicted region R):
 
     1. p on the coarse points (stride in both directions) -> P_coarse;
     2. tau_coarse = quantile_q(P_coarse) (``quantile_linear``);
@@ -266,7 +266,7 @@ def hierarchical_mask(grid, prob_at, tau, stride=4, q=0.8, dilate=5, coarse=None
 
 
 def mask_predict(params, gfeat, eig, grid, tau, stride=4, q=0.8, dilate=5):
-    """Sec. 3.6 / Sec. 4 with the network of Sec. 3.3 as the probability (float64)."""
+    """Sec. 3.5 / Sec. 4 with the network of Sec. 3.2 as the probability (float64)."""
     nx = grid.nx
 
     def prob_at(flat):

@@ -1,4 +1,4 @@
-"""Pins for the mask-producer oracle (``oracle/mask.py``, Sec. 3.3 and Sec. 3.6).
+"""Pins for the mask-producer oracle (``oracle/mask.py``, Sec. 3.2 and Sec. 3.5).
 
 Each pin is independent of the oracle's own code: closed forms of the Fourier features and of
 the eigenvalue-distance features, brute force, the network rebuilt from torch.nn layers (a
@@ -72,7 +72,7 @@ def test_point_features():
 # ----------------------------------------------------------------------------- the network
 
 def _torch_prob(params, gfeat, eig, z):
-    """The dual-path network of Sec. 3.3 assembled from torch.nn.Linear layers (float64)."""
+    """The dual-path network of Sec. 3.2 assembled from torch.nn.Linear layers (float64)."""
     import torch
     import torch.nn as nn
     p = torch.tensor(np.asarray(params, dtype=np.float64))
@@ -229,7 +229,7 @@ def test_error_bound_covers_float32():
 
 
 def test_parameter_count_is_the_paper_shapes():
-    # Sec. 3.3 layer shapes: 1728 + 4160 + 4352 + 8256 + 2 * 16512 + 8256 + 65
+    # Sec. 3.2 layer shapes: 1728 + 4160 + 4352 + 8256 + 2 * 16512 + 8256 + 65
     assert M0.NPARAM == nets.NPARAM == 59841
     assert tuple((o, i) for _, o, i in M0.LAYERS) == nets.LAYER_SHAPES
 
@@ -286,7 +286,7 @@ def test_hierarchy_vs_kron_and_scipy():
 
 
 def test_paper_grid_evaluation_count():
-    # Sec. 3.6: 100 x 100 grid, stride 4 -> 625 coarse points; the 80th percentile keeps
+    # Sec. 3.5: 100 x 100 grid, stride 4 -> 625 coarse points; the 80th percentile keeps
     # 125 cells (distinct values) -> 625 + 16 * 125 = 2625 evaluations
     g = W.Grid(-4, 4, -4, 4, 100, 100)
     prob_at, _ = _hashed_prob(g, 3)

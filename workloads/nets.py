@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs of the mask producer (the classifier of Sec. 3.3): parameter
+"""Seeded synthetic inputs of the mask producer (the classifier of Sec. 3.2): parameter
 vectors, global feature vectors and spectra.  Inputs only: no network arithmetic.
 
 The paper's trained weights are not available; parameters are drawn like a freshly
