@@ -443,6 +443,28 @@ ps_status ps_mask_predict(ps_mlp net, const ps_grid *g, const double *gfeat, con
                           const ps_mask_opts *o, void *ws_dev, size_t ws_bytes, uint8_t *mask_dev, float *prob_dev,
                           float *coarse_dev, double *tau_coarse_dev, int64_t *evals_dev, void *stream);
 
+/*
+ * ps_mask_predict_batch -- ps_mask_predict for nmat matrices on one grid g, every step one launch
+ * for all matrices (the setting of Sec. 3.3 and Sec. 5: many matrices, one grid).
+ *   nmat            1 .. 65535.
+ *   gfeat           host double[nmat][30]: the global features of each matrix.
+ *   eig_dev         device ps_c128[eig_off[nmat]]: the eigenvalues of all matrices, matrix m's at
+ *                   eig_off[m] .. eig_off[m+1] - 1.
+ *   eig_off         host int64[nmat + 1]: eig_off[0] = 0, every matrix with at least one
+ *                   eigenvalue.  gfeat and eig_off are copied to the workspace on the stream
+ *                   before the call returns (host memory may be reused afterwards).
+ *   mask_dev        device uint8[nmat][ny][nx] (required); prob_dev float[nmat][ny][nx],
+ *                   coarse_dev float[nmat][ceil(ny/s)][ceil(nx/s)], tau_coarse_dev double[nmat],
+ *                   evals_dev int64[nmat]: optional (NULL), as in ps_mask_predict, per matrix.
+ *   ws_dev / ws_bytes >= ps_mask_batch_workspace_size(nmat, g, o), 256-byte aligned.
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+ps_status ps_mask_batch_workspace_size(int32_t nmat, const ps_grid *g, const ps_mask_opts *o, size_t *bytes);
+ps_status ps_mask_predict_batch(ps_mlp net, int32_t nmat, const ps_grid *g, const double *gfeat,
+                                const ps_c128 *eig_dev, const int64_t *eig_off, const ps_mask_opts *o, void *ws_dev,
+                                size_t ws_bytes, uint8_t *mask_dev, float *prob_dev, float *coarse_dev,
+                                double *tau_coarse_dev, int64_t *evals_dev, void *stream);
+
 /* Thread-local description of the last error on the calling thread ("" if none). */
 const char *ps_last_error(void);
 

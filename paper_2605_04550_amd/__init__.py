@@ -108,6 +108,11 @@ _SIGNATURES = {
                                    _P]),
     "ps_mask_predict": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), ctypes.POINTER(ctypes.c_double), _P, _I64,
                                        ctypes.POINTER(ps_mask_opts), _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+    "ps_mask_batch_workspace_size": (ctypes.c_int, [_I32, ctypes.POINTER(ps_grid), ctypes.POINTER(ps_mask_opts),
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_mask_predict_batch": (ctypes.c_int, [_P, _I32, ctypes.POINTER(ps_grid), ctypes.POINTER(ctypes.c_double), _P,
+                                             ctypes.POINTER(_I64), ctypes.POINTER(ps_mask_opts), _P, ctypes.c_size_t,
+                                             _P, _P, _P, _P, _P, _P]),
 }
 
 
@@ -352,6 +357,29 @@ def ps_mask_predict(handle, grid: ps_grid, gfeat, eig_ptr, neig, opts, ws_ptr, w
                                  ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
                                  _P(mask_ptr), _P(prob_ptr), _P(coarse_ptr), _P(tau_coarse_ptr), _P(evals_ptr),
                                  _P(stream)))
+
+
+def ps_mask_batch_workspace_size(nmat, grid, opts) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_mask_batch_workspace_size(int(nmat), ctypes.byref(grid),
+                                              ctypes.byref(opts) if opts is not None else None, ctypes.byref(b)))
+    return b.value
+
+
+def ps_mask_predict_batch(handle, nmat, grid: ps_grid, gfeat, eig_ptr, eig_off, opts, ws_ptr, ws_bytes, mask_ptr,
+                          prob_ptr=0, coarse_ptr=0, tau_coarse_ptr=0, evals_ptr=0, stream=0) -> None:
+    """gfeat: nmat * 30 floats (flat or nested); eig_off: nmat + 1 integers (host)."""
+    import numpy as _np
+    gf = _np.ascontiguousarray(_np.asarray(gfeat, dtype=_np.float64).ravel())
+    off = _np.ascontiguousarray(_np.asarray(eig_off, dtype=_np.int64).ravel())
+    if gf.size != PS_MLP_NGLOBAL * nmat or off.size != nmat + 1:
+        raise ValueError("gfeat needs nmat * %d values and eig_off nmat + 1" % PS_MLP_NGLOBAL)
+    _check(lib().ps_mask_predict_batch(_P(handle), int(nmat), ctypes.byref(grid),
+                                       gf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _P(eig_ptr),
+                                       off.ctypes.data_as(ctypes.POINTER(_I64)),
+                                       ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
+                                       _P(mask_ptr), _P(prob_ptr), _P(coarse_ptr), _P(tau_coarse_ptr), _P(evals_ptr),
+                                       _P(stream)))
 
 
 def header_symbols():

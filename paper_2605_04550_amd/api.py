@@ -24,7 +24,7 @@ from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_w
                ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size, ps_label_batch,
                ps_label_batch_workspace_size, ps_trace_contour, ps_trace_workspace_size, ps_mask_opts_default,
                ps_mlp_create, ps_mlp_destroy, ps_mask_workspace_size, ps_mlp_prob, ps_mask_predict,
-               PS_MLP_NPARAM)
+               ps_mask_batch_workspace_size, ps_mask_predict_batch, PS_MLP_NPARAM)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts",
            "MaskNet"]
@@ -379,4 +379,26 @@ class MaskNet:
         ps_mask_predict(self.handle, g, list(gfeat), eig.data_ptr(), eig.numel(), o, ws.data_ptr(), ws.numel(),
                         mask.data_ptr(), prob.data_ptr(), coarse.data_ptr(), tau_c.data_ptr(), evals.data_ptr(),
                         _stream_handle(stream))
+        return dict(mask=mask, prob=prob, coarse=coarse, tau_coarse=tau_c, evals=evals)
+
+    def predict_batch(self, grid, gfeats, eigs, *, tau=0.05, stride=4, dilate=5, coarse_q=0.8, stream=None):
+        """ps_mask_predict_batch: ``predict`` for several matrices on one grid in one set of launches.
+        gfeats: nmat x 30 host values; eigs: list of complex128 CUDA tensors (one spectrum per matrix).
+        Returns the same dict as ``predict`` with a leading matrix axis."""
+        g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
+        o = ps_mask_opts_default(stride=int(stride), dilate=int(dilate), coarse_q=float(coarse_q), tau=float(tau))
+        nmat = len(eigs)
+        dev = eigs[0].device
+        eig = torch.cat([e.reshape(-1) for e in eigs]).contiguous()
+        off = np.concatenate([[0], np.cumsum([e.numel() for e in eigs])]).astype(np.int64)
+        cy, cx = (g.ny + o.stride - 1) // o.stride, (g.nx + o.stride - 1) // o.stride
+        mask = torch.empty((nmat, g.ny, g.nx), dtype=torch.uint8, device=dev)
+        prob = torch.empty((nmat, g.ny, g.nx), dtype=torch.float32, device=dev)
+        coarse = torch.empty((nmat, cy, cx), dtype=torch.float32, device=dev)
+        tau_c = torch.empty(nmat, dtype=torch.float64, device=dev)
+        evals = torch.empty(nmat, dtype=torch.int64, device=dev)
+        ws = _workspace(ps_mask_batch_workspace_size(nmat, g, o), dev)
+        ps_mask_predict_batch(self.handle, nmat, g, np.asarray(gfeats, dtype=np.float64), eig.data_ptr(), off, o,
+                              ws.data_ptr(), ws.numel(), mask.data_ptr(), prob.data_ptr(), coarse.data_ptr(),
+                              tau_c.data_ptr(), evals.data_ptr(), _stream_handle(stream))
         return dict(mask=mask, prob=prob, coarse=coarse, tau_coarse=tau_c, evals=evals)

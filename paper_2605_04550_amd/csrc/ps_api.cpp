@@ -286,7 +286,9 @@ ps_status ps_mlp_prob(ps_mlp net, const double *gfeat, const ps_c128 *eig_dev, i
     if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)ws_dev;
-    HIP_TRY(ps::mlp::launch_prep(net->raw, gf, (const double2 *)eig_dev, neig, ws, nullptr, 0, s));
+    const ps::mlp::Batch none{nullptr, nullptr};
+    HIP_TRY(ps::mlp::launch_prep(net->raw, gf, none, 1, (const double2 *)eig_dev, neig, ws,
+                                 (int64_t *)(ws + ps::mlp::kWsEvals), 0, s));
     HIP_TRY(ps::mlp::launch_points(net->raw, net->packed, (const double2 *)eig_dev, neig, ws, (const double2 *)z_dev,
                                    npts, prob_dev, s));
     return ok();
@@ -315,9 +317,82 @@ ps_status ps_mask_predict(ps_mlp net, const ps_grid *g, const double *gfeat, con
     int64_t *evals = evals_dev ? evals_dev : (int64_t *)(ws + ps::mlp::kWsEvals);
     ps::mlp::GridArgs ga{g->a, g->b, g->c, g->d, g->nx, g->ny};
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(ps::mlp::launch_prep(net->raw, gf, (const double2 *)eig_dev, neig, ws, evals, ncy * ncx, s));
-    HIP_TRY(ps::mlp::launch_mask(net->raw, net->packed, (const double2 *)eig_dev, neig, ws, ga, r.stride, r.dilate,
-                                 r.coarse_q, r.tau, coarse, prob, mask_dev, evals, tau_coarse_dev, s));
+    const ps::mlp::Batch none{nullptr, nullptr};
+    HIP_TRY(ps::mlp::launch_prep(net->raw, gf, none, 1, (const double2 *)eig_dev, neig, ws, evals, ncy * ncx, s));
+    HIP_TRY(ps::mlp::launch_mask(net->raw, net->packed, none, 1, (const double2 *)eig_dev, neig, ws, ga, r.stride,
+                                 r.dilate, r.coarse_q, r.tau, coarse, prob, mask_dev, evals, tau_coarse_dev, s));
+    return ok();
+}
+
+namespace {
+
+// Workspace of a batched call: the per-matrix headers, the uploaded tables (global features,
+// eigenvalue offsets), the coarse and the probability maps.
+struct MaskBatchLayout {
+    size_t headers, gfeat, eig_off, coarse, prob, total;
+};
+
+MaskBatchLayout mask_batch_layout(int32_t nmat, const ps_grid *g, const ps_mask_opts &r) {
+    const int64_t ncoarse = ((g->ny + r.stride - 1) / r.stride) * ((g->nx + r.stride - 1) / r.stride);
+    MaskBatchLayout L;
+    L.headers = 0;
+    L.gfeat = L.headers + (size_t)nmat * ps::mlp::kWsHeader;
+    L.eig_off = L.gfeat + align256(sizeof(double) * ps::mlp::kNGlobal * (size_t)nmat);
+    L.coarse = L.eig_off + align256(sizeof(int64_t) * ((size_t)nmat + 1));
+    L.prob = L.coarse + align256(sizeof(float) * (size_t)ncoarse * (size_t)nmat);
+    L.total = L.prob + align256(sizeof(float) * (size_t)(g->nx * g->ny) * (size_t)nmat);
+    return L;
+}
+
+}  // namespace
+
+ps_status ps_mask_batch_workspace_size(int32_t nmat, const ps_grid *g, const ps_mask_opts *o, size_t *bytes) {
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (nmat < 1 || nmat > 65535) return fail(PS_ERR_INVALID, "nmat must be in [1, 65535]");
+    ps_status st = check_grid(g);
+    if (st) return st;
+    const ps_mask_opts r = resolve_mask(o);
+    if ((st = check_mask_opts(r))) return st;
+    *bytes = mask_batch_layout(nmat, g, r).total;
+    return ok();
+}
+
+ps_status ps_mask_predict_batch(ps_mlp net, int32_t nmat, const ps_grid *g, const double *gfeat,
+                                const ps_c128 *eig_dev, const int64_t *eig_off, const ps_mask_opts *o, void *ws_dev,
+                                size_t ws_bytes, uint8_t *mask_dev, float *prob_dev, float *coarse_dev,
+                                double *tau_coarse_dev, int64_t *evals_dev, void *stream) {
+    if (!net) return fail(PS_ERR_INVALID, "network handle is NULL");
+    if (nmat < 1 || nmat > 65535) return fail(PS_ERR_INVALID, "nmat must be in [1, 65535]");
+    if (!gfeat || !eig_off || !eig_dev) return fail(PS_ERR_INVALID, "gfeat, eig and eig_off are required");
+    ps_status st = check_grid(g);
+    if (st) return st;
+    const ps_mask_opts r = resolve_mask(o);
+    if ((st = check_mask_opts(r))) return st;
+    if (!mask_dev) return fail(PS_ERR_INVALID, "mask output is NULL");
+    if (eig_off[0] != 0) return fail(PS_ERR_INVALID, "eig_off[0] must be 0");
+    for (int32_t m = 0; m < nmat; ++m)
+        if (eig_off[m + 1] - eig_off[m] < 1) return fail(PS_ERR_INVALID, "matrix %d has no eigenvalues", m);
+    for (size_t k = 0; k < (size_t)nmat * ps::mlp::kNGlobal; ++k)
+        if (!isfinite(gfeat[k])) return fail(PS_ERR_NONFINITE, "global feature %zu is not finite", k);
+    const int64_t ncy = (g->ny + r.stride - 1) / r.stride, ncx = (g->nx + r.stride - 1) / r.stride;
+    if (ncy * ncx >= ((int64_t)1 << 31)) return fail(PS_ERR_INVALID, "too many coarse points");
+    const MaskBatchLayout L = mask_batch_layout(nmat, g, r);
+    if (!ws_dev || ws_bytes < L.total) return fail(PS_ERR_WORKSPACE, "mask batch workspace needs %zu bytes", L.total);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    char *ws = (char *)ws_dev;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(ws + L.gfeat, gfeat, sizeof(double) * ps::mlp::kNGlobal * (size_t)nmat,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + L.eig_off, eig_off, sizeof(int64_t) * ((size_t)nmat + 1), hipMemcpyHostToDevice, s));
+    const ps::mlp::Batch bt{(const double *)(ws + L.gfeat), (const int64_t *)(ws + L.eig_off)};
+    float *coarse = coarse_dev ? coarse_dev : (float *)(ws + L.coarse);
+    float *prob = prob_dev ? prob_dev : (float *)(ws + L.prob);
+    ps::mlp::GridArgs ga{g->a, g->b, g->c, g->d, g->nx, g->ny};
+    ps::mlp::Globals unused{};
+    HIP_TRY(ps::mlp::launch_prep(net->raw, unused, bt, nmat, (const double2 *)eig_dev, 0, ws, evals_dev, ncy * ncx,
+                                 s));
+    HIP_TRY(ps::mlp::launch_mask(net->raw, net->packed, bt, nmat, (const double2 *)eig_dev, 0, ws, ga, r.stride,
+                                 r.dilate, r.coarse_q, r.tau, coarse, prob, mask_dev, evals_dev, tau_coarse_dev, s));
     return ok();
 }
 

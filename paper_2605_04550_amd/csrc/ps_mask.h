@@ -50,6 +50,12 @@ struct Globals {
     double f[kNGlobal];
 };
 
+// Device tables of a batched call (nmat matrices on one grid); all NULL for a single matrix.
+struct Batch {
+    const double *gfeat;      // [nmat][30]
+    const int64_t *eig_off;   // [nmat + 1]: matrix m's eigenvalues are eig[eig_off[m] .. eig_off[m+1])
+};
+
 struct GridArgs {
     double a, b, c, d;
     int64_t nx, ny;
@@ -57,19 +63,22 @@ struct GridArgs {
 
 hipError_t launch_pack(const float *raw, float *packed, hipStream_t s);
 
-// Folded bias and centroid into the workspace header; evals (if not NULL) set to evals0.
-hipError_t launch_prep(const float *raw, const Globals &gf, const double2 *eig, int64_t neig, char *ws,
-                       int64_t *evals, int64_t evals0, hipStream_t s);
+// Folded bias and centroid into each matrix's workspace header (matrix m's at ws + m * kWsHeader);
+// the evaluation counters (evals[m], or the header's when evals is NULL) set to evals0.
+hipError_t launch_prep(const float *raw, const Globals &gf, const Batch &bt, int nmat, const double2 *eig,
+                       int64_t neig, char *ws, int64_t *evals, int64_t evals0, hipStream_t s);
 
-// p at arbitrary points z[npts].
+// p at arbitrary points z[npts] (one matrix; launch_prep with nmat = 1 first).
 hipError_t launch_points(const float *raw, const float *packed, const double2 *eig, int64_t neig, const char *ws,
                          const double2 *z, int64_t npts, float *prob, hipStream_t s);
 
-// The hierarchical chain after launch_prep: coarse probabilities, tau_coarse, the refined cells,
-// the thresholded and dilated mask.
-hipError_t launch_mask(const float *raw, const float *packed, const double2 *eig, int64_t neig, char *ws,
-                       const GridArgs &g, int stride, int dilate, double coarse_q, double tau, float *coarse,
-                       float *prob, uint8_t *mask, int64_t *evals, double *tau_coarse_out, hipStream_t s);
+// The hierarchical chain after launch_prep, for nmat matrices on one grid: coarse probabilities,
+// tau_coarse, the refined cells, the thresholded and dilated mask.  Per-matrix outputs are
+// consecutive: coarse [nmat][ncoarse], prob and mask [nmat][ny][nx], evals and tau [nmat].
+hipError_t launch_mask(const float *raw, const float *packed, const Batch &bt, int nmat, const double2 *eig,
+                       int64_t neig, char *ws, const GridArgs &g, int stride, int dilate, double coarse_q, double tau,
+                       float *coarse, float *prob, uint8_t *mask, int64_t *evals, double *tau_coarse_out,
+                       hipStream_t s);
 
 }  // namespace mlp
 }  // namespace ps

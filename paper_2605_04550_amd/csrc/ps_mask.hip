@@ -202,14 +202,38 @@ __global__ void __launch_bounds__(kBlock) k_pack(const float *__restrict__ raw, 
     packed[t] = (o < O && k < K) ? raw[woff + o * ld + col0 + k] : 0.0f;
 }
 
-__global__ void __launch_bounds__(kBlock) k_prep(const float *__restrict__ raw, Globals gf,
+// Per-matrix view of a (possibly batched) call: matrix m = blockIdx.y.  A single-matrix call
+// has no device tables (gfeat / eig_off NULL) and one matrix.
+struct Mat {
+    const double2 *eig;
+    int64_t neig;
+    char *ws;          // this matrix's header (kWsHeader bytes)
+};
+
+__device__ __forceinline__ Mat mat_of(const Batch &b, const double2 *eig, int64_t neig, char *ws) {
+    const int m = blockIdx.y;
+    Mat r;
+    if (b.eig_off) {
+        const int64_t o0 = b.eig_off[m], o1 = b.eig_off[m + 1];
+        r.eig = eig + o0;
+        r.neig = o1 - o0;
+    } else {
+        r.eig = eig;
+        r.neig = neig;
+    }
+    r.ws = ws + (int64_t)m * kWsHeader;
+    return r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_prep(const float *__restrict__ raw, Globals gf, Batch bt,
                                                  const double2 *__restrict__ eig, int64_t neig, char *ws,
                                                  int64_t *evals, int64_t evals0) {
     __shared__ double sx[kBlock], sy[kBlock];
+    const Mat mt = mat_of(bt, eig, neig, ws);
     double ax = 0.0, ay = 0.0;
-    for (int64_t e = threadIdx.x; e < neig; e += kBlock) {
-        ax += eig[e].x;
-        ay += eig[e].y;
+    for (int64_t e = threadIdx.x; e < mt.neig; e += kBlock) {
+        ax += mt.eig[e].x;
+        ay += mt.eig[e].y;
     }
     sx[threadIdx.x] = ax;
     sy[threadIdx.x] = ay;
@@ -222,14 +246,16 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float *__restrict__ raw, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        *(double2 *)(ws + kWsCent) = make_double2(sx[0] / (double)neig, sy[0] / (double)neig);
-        if (evals) *evals = evals0;
+        *(double2 *)(mt.ws + kWsCent) = make_double2(sx[0] / (double)mt.neig, sy[0] / (double)mt.neig);
+        int64_t *ev = evals ? evals + blockIdx.y : (int64_t *)(mt.ws + kWsEvals);
+        *ev = evals0;
     }
     if (threadIdx.x < 128) {
         const int o = threadIdx.x;
+        const double *f = bt.gfeat ? bt.gfeat + (int64_t)blockIdx.y * kNGlobal : gf.f;
         double acc = raw[kBm1 + o];
-        for (int k = 0; k < kNGlobal; ++k) acc += (double)raw[kWm1 + o * 33 + k] * gf.f[k];
-        ((float *)(ws + kWsBfold))[o] = (float)acc;
+        for (int k = 0; k < kNGlobal; ++k) acc += (double)raw[kWm1 + o * 33 + k] * f[k];
+        ((float *)(mt.ws + kWsBfold))[o] = (float)acc;
     }
 }
 
@@ -248,18 +274,19 @@ __global__ void __launch_bounds__(kBlock) k_points(const float *__restrict__ raw
 }
 
 __global__ void __launch_bounds__(kBlock) k_coarse(const float *__restrict__ raw, const float *__restrict__ packed,
-                                                   const double2 *__restrict__ eig, int64_t neig, const char *ws,
+                                                   Batch bt, const double2 *__restrict__ eig, int64_t neig, char *ws,
                                                    GridArgs g, int stride, int64_t ncx, int64_t ncoarse,
                                                    float *coarse) {
     const int lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (tile * 16 >= ncoarse) return;
-    const Net net = make_net(raw, packed, eig, neig, ws);
+    const Mat mt = mat_of(bt, eig, neig, ws);
+    const Net net = make_net(raw, packed, mt.eig, mt.neig, mt.ws);
     const int64_t c = tile * 16 + (lane & 15);
     const int64_t cc = c < ncoarse ? c : ncoarse - 1;
     const int64_t I = cc / ncx, J = cc - I * ncx;
     const float p = eval_tile(net, grid_x(g, (int64_t)stride * J), grid_y(g, (int64_t)stride * I), lane);
-    if (lane < 16 && c < ncoarse) coarse[c] = p;
+    if (lane < 16 && c < ncoarse) coarse[(int64_t)blockIdx.y * ncoarse + c] = p;
 }
 
 // Order statistic of rank k of m floats by radix selection on order-preserving keys (one
@@ -302,23 +329,58 @@ __device__ float select_rank(const float *__restrict__ v, int64_t m, int64_t k, 
     return value_of(prefix);
 }
 
+// Bitonic sort of the m <= kSortMax order-preserving keys of one matrix in LDS (padded with the
+// largest key), for the quantile.
+constexpr int kSortMax = 8192;
+
+__device__ void bitonic_sort(unsigned *key, int n) {
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned a = key[lo], b = key[hi];
+                if ((a > b) == up) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // tau_coarse = v_(k) + (h - k)(v_(k+1) - v_(k)), h = q (m - 1), k = floor(h): the quantile of
 // Sec. 3.5 by linear interpolation between order statistics (no fused multiply-add, so the
-// value is the one the plain formula gives).
-__global__ void __launch_bounds__(kBlock) k_quantile(const float *__restrict__ v, int64_t m, double q, char *ws,
+// value is the one the plain formula gives).  One workgroup per matrix.
+__global__ void __launch_bounds__(kBlock) k_quantile(const float *__restrict__ coarse, int64_t m, double q, char *ws,
                                                      double *tau_out) {
+    __shared__ unsigned keys[kSortMax];
     __shared__ unsigned hist[256];
     __shared__ int64_t sk;
     __shared__ unsigned sprefix;
+    const float *v = coarse + (int64_t)blockIdx.x * m;
     const double h = __dmul_rn(q, (double)(m - 1));
     const int64_t k0 = (int64_t)floor(h);
     const double g = __dsub_rn(h, (double)k0);
-    const float v0 = select_rank(v, m, k0, hist, &sk, &sprefix);
-    const float v1 = k0 + 1 < m ? select_rank(v, m, k0 + 1, hist, &sk, &sprefix) : v0;
+    float v0, v1;
+    if (m <= kSortMax) {
+        int n = 2;
+        while (n < m) n <<= 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = i < m ? key_of(v[i]) : 0xffffffffu;
+        __syncthreads();
+        bitonic_sort(keys, n);
+        v0 = value_of(keys[k0]);
+        v1 = k0 + 1 < m ? value_of(keys[k0 + 1]) : v0;
+    } else {
+        v0 = select_rank(v, m, k0, hist, &sk, &sprefix);
+        v1 = k0 + 1 < m ? select_rank(v, m, k0 + 1, hist, &sk, &sprefix) : v0;
+    }
     if (threadIdx.x == 0) {
         const double tau = __dadd_rn((double)v0, __dmul_rn(g, __dsub_rn((double)v1, (double)v0)));
-        *(double *)(ws + kWsTau) = tau;
-        if (tau_out) *tau_out = tau;
+        *(double *)(ws + (int64_t)blockIdx.x * kWsHeader + kWsTau) = tau;
+        if (tau_out) tau_out[blockIdx.x] = tau;
     }
 }
 
@@ -327,7 +389,7 @@ __global__ void __launch_bounds__(kBlock) k_quantile(const float *__restrict__ v
 // 0 there.  (No loop over tiles inside a wavefront: the weight loads are the same for every
 // tile, and a loop would invite the compiler to hoist all of them into registers.)
 __global__ void __launch_bounds__(kBlock) k_fine(const float *__restrict__ raw, const float *__restrict__ packed,
-                                                 const double2 *__restrict__ eig, int64_t neig, const char *ws,
+                                                 Batch bt, const double2 *__restrict__ eig, int64_t neig, char *ws,
                                                  GridArgs g, int stride, int64_t ncx, int64_t ncells, int tpc,
                                                  const float *__restrict__ coarse, float *prob, int64_t *evals) {
     const int lane = threadIdx.x & 63;
@@ -341,18 +403,23 @@ __global__ void __launch_bounds__(kBlock) k_fine(const float *__restrict__ raw, 
     const int w = (int)(c0 + stride <= g.nx ? stride : g.nx - c0);
     const int cnt = h * w;
     if (t0 >= cnt) return;                               // a tile past a cut cell's points
-    const bool sel = (double)coarse[cell] >= *(const double *)(ws + kWsTau);
+    const Mat mt = mat_of(bt, eig, neig, ws);
+    float *pm = prob + (int64_t)blockIdx.y * g.nx * g.ny;
+    const bool sel = (double)coarse[(int64_t)blockIdx.y * ncells + cell] >= *(const double *)(mt.ws + kWsTau);
     const int li = t0 + (lane & 15);
     const int lc = li < cnt ? li : cnt - 1;
     const int64_t i = r0 + lc / w, j = c0 + lc % w;
     if (!sel) {
-        if (lane < 16 && li < cnt) prob[i * g.nx + j] = 0.0f;
+        if (lane < 16 && li < cnt) pm[i * g.nx + j] = 0.0f;
         return;
     }
-    if (lane == 0 && evals) atomicAdd((unsigned long long *)evals, (unsigned long long)(cnt - t0 < 16 ? cnt - t0 : 16));
-    const Net net = make_net(raw, packed, eig, neig, ws);
+    if (lane == 0) {
+        int64_t *ev = evals ? evals + blockIdx.y : (int64_t *)(mt.ws + kWsEvals);
+        atomicAdd((unsigned long long *)ev, (unsigned long long)(cnt - t0 < 16 ? cnt - t0 : 16));
+    }
+    const Net net = make_net(raw, packed, mt.eig, mt.neig, mt.ws);
     const float p = eval_tile(net, grid_x(g, j), grid_y(g, i), lane);
-    if (lane < 16 && li < cnt) prob[i * g.nx + j] = p;
+    if (lane < 16 && li < cnt) pm[i * g.nx + j] = p;
 }
 
 // mask = the points within the (2r+1) x (2r+1) square of a point with p >= tau.
@@ -360,17 +427,18 @@ __global__ void __launch_bounds__(kBlock) k_dilate(const float *__restrict__ pro
                                                    int r, uint8_t *mask) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nx * ny) return;
+    const float *pm = prob + (int64_t)blockIdx.y * nx * ny;
     const int64_t i = t / nx, j = t - i * nx;
     const int64_t i0 = i - r > 0 ? i - r : 0, i1 = i + r < ny - 1 ? i + r : ny - 1;
     const int64_t j0 = j - r > 0 ? j - r : 0, j1 = j + r < nx - 1 ? j + r : nx - 1;
     uint8_t hit = 0;
     for (int64_t a = i0; a <= i1 && !hit; ++a)
         for (int64_t b = j0; b <= j1; ++b)
-            if ((double)prob[a * nx + b] >= tau) {
+            if ((double)pm[a * nx + b] >= tau) {
                 hit = 1;
                 break;
             }
-    mask[t] = hit;
+    mask[(int64_t)blockIdx.y * nx * ny + t] = hit;
 }
 
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
@@ -382,9 +450,9 @@ hipError_t launch_pack(const float *raw, float *packed, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const float *raw, const Globals &gf, const double2 *eig, int64_t neig, char *ws,
-                       int64_t *evals, int64_t evals0, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(kBlock), 0, s, raw, gf, eig, neig, ws, evals, evals0);
+hipError_t launch_prep(const float *raw, const Globals &gf, const Batch &bt, int nmat, const double2 *eig,
+                       int64_t neig, char *ws, int64_t *evals, int64_t evals0, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3(1, nmat), dim3(kBlock), 0, s, raw, gf, bt, eig, neig, ws, evals, evals0);
     return hipGetLastError();
 }
 
@@ -397,19 +465,20 @@ hipError_t launch_points(const float *raw, const float *packed, const double2 *e
     return hipGetLastError();
 }
 
-hipError_t launch_mask(const float *raw, const float *packed, const double2 *eig, int64_t neig, char *ws,
-                       const GridArgs &g, int stride, int dilate, double coarse_q, double tau, float *coarse,
-                       float *prob, uint8_t *mask, int64_t *evals, double *tau_coarse_out, hipStream_t s) {
+hipError_t launch_mask(const float *raw, const float *packed, const Batch &bt, int nmat, const double2 *eig,
+                       int64_t neig, char *ws, const GridArgs &g, int stride, int dilate, double coarse_q, double tau,
+                       float *coarse, float *prob, uint8_t *mask, int64_t *evals, double *tau_coarse_out,
+                       hipStream_t s) {
     const int64_t ncy = (g.ny + stride - 1) / stride, ncx = (g.nx + stride - 1) / stride;
     const int64_t ncoarse = ncy * ncx;
-    hipLaunchKernelGGL(k_coarse, dim3((unsigned)blocks_for(blocks_for(ncoarse, 16), kBlock / 64)), dim3(kBlock), 0, s,
-                       raw, packed, eig, neig, ws, g, stride, ncx, ncoarse, coarse);
-    hipLaunchKernelGGL(k_quantile, dim3(1), dim3(kBlock), 0, s, coarse, ncoarse, coarse_q, ws, tau_coarse_out);
+    hipLaunchKernelGGL(k_coarse, dim3((unsigned)blocks_for(blocks_for(ncoarse, 16), kBlock / 64), nmat), dim3(kBlock),
+                       0, s, raw, packed, bt, eig, neig, ws, g, stride, ncx, ncoarse, coarse);
+    hipLaunchKernelGGL(k_quantile, dim3(nmat), dim3(kBlock), 0, s, coarse, ncoarse, coarse_q, ws, tau_coarse_out);
     const int tpc = (stride * stride + 15) / 16;
-    hipLaunchKernelGGL(k_fine, dim3((unsigned)blocks_for(ncoarse * tpc, kBlock / 64)), dim3(kBlock), 0, s, raw, packed,
-                       eig, neig, ws, g, stride, ncx, ncoarse, tpc, coarse, prob, evals);
-    hipLaunchKernelGGL(k_dilate, dim3((unsigned)blocks_for(g.nx * g.ny, kBlock)), dim3(kBlock), 0, s, prob, g.nx, g.ny,
-                       tau, (dilate - 1) / 2, mask);
+    hipLaunchKernelGGL(k_fine, dim3((unsigned)blocks_for(ncoarse * tpc, kBlock / 64), nmat), dim3(kBlock), 0, s, raw,
+                       packed, bt, eig, neig, ws, g, stride, ncx, ncoarse, tpc, coarse, prob, evals);
+    hipLaunchKernelGGL(k_dilate, dim3((unsigned)blocks_for(g.nx * g.ny, kBlock), nmat), dim3(kBlock), 0, s, prob, g.nx,
+                       g.ny, tau, (dilate - 1) / 2, mask);
     return hipGetLastError();
 }
 

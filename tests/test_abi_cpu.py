@@ -199,3 +199,36 @@ def test_mask_argument_checks():
     with pytest.raises(P.PsError) as e:
         P.ps_mlp_prob(fake, [0.0] * 30, fake, 4, fake, 8, fake, 512, fake)
     assert e.value.status == P.PS_ERR_WORKSPACE
+
+
+def test_mask_batch_argument_checks():
+    _lib()
+    fake = 256
+    g = P.ps_grid(-4, 4, -4, 4, 100, 100)
+    o = P.ps_mask_opts_default()
+    gf = np.zeros((3, 30))
+    off = np.array([0, 4, 8, 12])
+    for nmat in (0, 70000):
+        with pytest.raises(P.PsError) as e:
+            P.ps_mask_batch_workspace_size(nmat, g, o)
+        assert e.value.status == P.PS_ERR_INVALID
+    # headers 3 * 1024, gfeat 720 -> 768, offsets 32 -> 256, coarse 3 * 625 * 4 -> 7680, prob 120000
+    assert P.ps_mask_batch_workspace_size(3, g, o) == 3072 + 768 + 256 + 7680 + 120064
+    bad_off = [np.array([1, 4, 8, 12]), np.array([0, 4, 4, 12]), np.array([0, 4, 8, 7])]
+    for b in bad_off:
+        with pytest.raises(P.PsError) as e:
+            P.ps_mask_predict_batch(fake, 3, g, gf, fake, b, o, fake, 1 << 30, fake)
+        assert e.value.status == P.PS_ERR_INVALID, b
+    gbad = gf.copy()
+    gbad[2, 7] = np.nan
+    with pytest.raises(P.PsError) as e:
+        P.ps_mask_predict_batch(fake, 3, g, gbad, fake, off, o, fake, 1 << 30, fake)
+    assert e.value.status == P.PS_ERR_NONFINITE
+    with pytest.raises(P.PsError) as e:
+        P.ps_mask_predict_batch(fake, 3, g, gf, fake, off, o, fake, 1000, fake)
+    assert e.value.status == P.PS_ERR_WORKSPACE
+    with pytest.raises(P.PsError) as e:
+        P.ps_mask_predict_batch(0, 3, g, gf, fake, off, o, fake, 1 << 30, fake)
+    assert e.value.status == P.PS_ERR_INVALID
+    with pytest.raises(ValueError):
+        P.ps_mask_predict_batch(fake, 3, g, gf[:2], fake, off, o, fake, 1 << 30, fake)

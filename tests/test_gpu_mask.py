@@ -148,3 +148,32 @@ def test_mask_feeds_the_restricted_evaluation():
     np.testing.assert_array_equal(idx, np.flatnonzero(r["mask"].cpu().numpy().ravel()))
     np.testing.assert_allclose(res["sigma"][:c].cpu().numpy(), full["sigma"].cpu().numpy()[idx], rtol=1e-13, atol=0)
     print("restricted evaluation: |R| = %d of %d points" % (c, grid.npts), flush=True)
+
+
+@pytest.mark.parametrize("shape,stride,dilate,tau", [((37, 23), 4, 5, 0.4), ((100, 100), 4, 5, 0.05),
+                                                     ((33, 47), 5, 9, 0.5)])
+def test_mask_predict_batch_equals_single_calls(shape, stride, dilate, tau):
+    """ps_mask_predict_batch runs the single call's kernels with a matrix index: every output of
+    every matrix is identical to the single call's; one matrix also against the oracle."""
+    api = _api()
+    import torch
+    nx, ny = shape
+    grid = W.Grid(-4.0, 4.0, -3.0, 3.5, nx, ny)
+    sizes = [1, 5, 64, 64, 23, 300, 2]
+    params = nets.mlp_params(51, 3.0)
+    gfs = np.stack([nets.global_features(60 + m) for m in range(len(sizes))])
+    eigs = [nets.spectrum(70 + m, n) for m, n in enumerate(sizes)]
+    net = api.MaskNet(params)
+    teigs = [_t(e, torch.complex128) for e in eigs]
+    rb = net.predict_batch(grid, gfs, teigs, tau=tau, stride=stride, dilate=dilate)
+    torch.cuda.synchronize()
+    for m in range(len(sizes)):
+        r1 = net.predict(grid, gfs[m], teigs[m], tau=tau, stride=stride, dilate=dilate)
+        torch.cuda.synchronize()
+        for k in ("mask", "prob", "coarse"):
+            assert torch.equal(rb[k][m], r1[k]), (m, k)
+        assert float(rb["tau_coarse"][m]) == float(r1["tau_coarse"]), m
+        assert int(rb["evals"][m]) == int(r1["evals"][0]), m
+    r = {k: v[4].cpu().numpy() for k, v in rb.items()}
+    r["evals"] = np.array([r["evals"]])
+    _check_mask(grid, params, gfs[4], eigs[4], tau, stride, dilate, r, what="batch matrix 4")
