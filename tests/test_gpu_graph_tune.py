@@ -97,3 +97,36 @@ def test_autotune_returns_a_valid_plan():
     print("autotuned plan: slots %d, check_shift %d" % (o.slots, o.check_shift))
     off = api.autotune(mat, z, bisect=False)
     assert off.bisect == -1
+
+
+def test_graph_capture_of_mask_predict():
+    """ps_mask_predict captured in a HIP graph (kernels only, no memset or copy): every replay,
+    with eager work in between, equals the eager result."""
+    api = _api()
+    import torch
+    from workloads import nets
+    grid = W.Grid(-4.0, 4.0, -4.0, 4.0, 61, 47)
+    net = api.MaskNet(nets.mlp_params(81, 3.0))
+    gf = nets.global_features(82)
+    eig = torch.tensor(nets.spectrum(83, 40), dtype=torch.complex128, device="cuda")
+    eager = net.predict(grid, gf, eig, tau=0.4)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        net.predict(grid, gf, eig, tau=0.4)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        got = net.predict(grid, gf, eig, tau=0.4)
+    for rep in range(3):
+        got["mask"].fill_(7)
+        got["prob"].fill_(-1.0)
+        got["evals"].fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        net.predict(W.Grid(0.0, 1.0, 0.0, 1.0, 9, 5), gf, eig, tau=0.2)      # eager work between replays
+        torch.cuda.synchronize()
+        for k in ("mask", "prob", "coarse", "tau_coarse", "evals"):
+            assert torch.equal(got[k], eager[k]), (rep, k)
