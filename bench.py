@@ -374,7 +374,7 @@ def main():
         summarize_counters(*args.summarize_counters)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(shifts are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
         sys.exit(2)
 
