@@ -205,6 +205,18 @@ def label_bench(args):
     npts = grid.npts * len(mats)
     plain_lab = (p["sigma"] <= eps).to(torch.uint8)
     agree = int((plain_lab == r["label"]).sum().item())
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = oracle.default_threads()
+        zs = oracle.grid_points(grid)[:2000]
+        t0 = time.perf_counter()
+        oracle.sigma_min(w["mats"][0], zs, nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=len(zs) / dt, unit="points/s", cores=threads, kind="oracle",
+                   sample="the plain method on the first 2000 grid points of matrix 0 (n=64): dense one-sided "
+                          "Jacobi per point, points over %d threads; %.1f s" % (threads, dt))
     print(json.dumps({
         "metric": "grid points labelled per second (sensitive zone, eps = 0.01)", "value": npts / t_label,
         "unit": "points/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
@@ -213,7 +225,7 @@ def label_bench(args):
         "label_s": t_label, "plain_s": t_plain, "plain_points_per_s": npts / t_plain,
         "speedup_vs_plain_method": t_plain / t_label,
         "evaluated_fraction": int(r["evals"].item()) / npts,
-        "labels_equal_to_plain": agree, "points": npts}), flush=True)
+        "labels_equal_to_plain": agree, "points": npts, "cpu_baseline": cpu}), flush=True)
 
 
 def trace_bench(args):
@@ -273,7 +285,8 @@ def mask_bench(args):
     w = W.paper_label_workload(args.mask)
     grid = w["grid"]
     dev = torch.device("cuda:0")
-    net = api.MaskNet(nets.mlp_params(W.SEED_BASE + 900, 3.0))
+    net_params = nets.mlp_params(W.SEED_BASE + 900, 3.0)
+    net = api.MaskNet(net_params)
     eigs = [torch.tensor(np.linalg.eigvals(W.to_dense(b)), dtype=torch.complex128, device=dev) for b in w["mats"]]
     gfs = [list(nets.global_features(W.SEED_BASE + 901 + m)) for m in range(len(w["mats"]))]
     mats = [api.BandedMatrix.from_band(b) for b in w["mats"]]
@@ -329,6 +342,22 @@ def mask_bench(args):
     torch.cuda.synchronize()
     t_prob = e0.elapsed_time(e1) / 1e3 / reps
     achieved = MLP_FLOPS * nthr / t_prob / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's hybrid method on matrix 0 (same weights, features and spectrum)
+        import oracle
+        from oracle import mask as OM
+        oracle.build(force=False)
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        om = OM.mask_predict(net_params, gfs[0], eigs[0].cpu().numpy(), grid, 0.05)
+        region0 = np.flatnonzero(om["mask"].ravel())
+        oracle.sigma_min(w["mats"][0], oracle.grid_points(grid)[region0], nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=grid.npts / dt, unit="points/s", cores=threads, kind="oracle",
+                   sample="matrix 0: the oracle's mask (float64 network, %d evaluations) and dense Jacobi "
+                          "sigma_min on its %d region points over %d threads; %.1f s"
+                          % (om["evals"], len(region0), threads, dt))
     print(json.dumps({
         "metric": "grid points per second, hybrid method (mask producer + sigma_min on the mask)",
         "value": npts / (t_mask + t_rest), "unit": "points/s", "n_gpus": 1, "higher_is_better": True,
@@ -345,7 +374,8 @@ def mask_bench(args):
                        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
                                     "kernel": "ps::mlp::k_points (one launch; + k_prep, 1 workgroup)",
-                                    "algorithmic_flops_per_launch": MLP_FLOPS * nthr}}}), flush=True)
+                                    "algorithmic_flops_per_launch": MLP_FLOPS * nthr}},
+        "cpu_baseline": cpu}), flush=True)
 
 
 def main():
