@@ -18,6 +18,9 @@ Contents, each following the passage named in its docstring:
                               the cells at or above the percentile, threshold tau, square
                               dilation.
   * ``mask_predict``       -- ``hierarchical_mask`` with the network as the probability.
+  * ``calibrate_tau``      -- the threshold calibration of Sec. 3.6: recall of the dilated
+                              predictions against the dilated labels, the smallest candidate
+                              whose median and 10th-percentile recall reach their bounds.
 Pins: ``tests/test_oracle_mask_pins.py`` (closed forms, torch.nn layers as an independent
 implementation of the network, numpy's quantile, scipy's dilation, brute force).
 """
@@ -281,3 +284,49 @@ def mask_points_z(grid, flat):
     """Grid points z at flat row-major indices (Sec. 2.1 grid, inclusive end points)."""
     flat = np.asarray(flat, dtype=np.int64)
     return _grid_z(grid, (flat // grid.nx).astype(np.float64), (flat % grid.nx).astype(np.float64))
+
+
+def dilate(binary, side):
+    """Morphological dilation of a 2-D boolean map by a side x side square centred on each point
+    (side odd; neighbours outside the map do not exist)."""
+    b = np.asarray(binary, dtype=bool)
+    r = (side - 1) // 2
+    out = np.zeros_like(b)
+    for i, j in zip(*np.nonzero(b)):
+        out[max(0, i - r):i + r + 1, max(0, j - r):j + r + 1] = True
+    return out
+
+
+def calibrate_tau(prob, labels, taus, pred_dilate=5, label_dilate=3, median_min=0.90, p10_min=0.75):
+    """Sec. 3.6, threshold calibration on a validation set of matrices (one probability map and
+    one ground-truth label map per matrix, same grid):
+
+    for each candidate tau (ascending): S_hat = {p >= tau} dilated by a pred_dilate square, the
+    labels dilated by a label_dilate square, recall = |S_hat_dil & S_dil| / |S_dil| per matrix
+    (1 when S_dil is empty); a candidate qualifies when median(recall) >= median_min and
+    P10(recall) >= p10_min, both quantiles by ``quantile_linear`` (q = 0.5 and 0.1).  tau* is
+    the smallest qualifying candidate, as the paper writes it; recall cannot rise with tau, so
+    that is the first candidate whenever any qualifies.  The largest qualifying candidate (the
+    one that predicts the fewest points within the same recall bounds) is returned too.
+
+    Returns dict(recall [nval, ntau], median [ntau], p10 [ntau], index, index_max (-1 if no
+    candidate qualifies))."""
+    prob = np.asarray(prob, dtype=np.float64)
+    labels = np.asarray(labels)
+    nval = prob.shape[0]
+    taus = np.asarray(taus, dtype=np.float64)
+    recall = np.zeros((nval, len(taus)))
+    for m in range(nval):
+        lab = dilate(labels[m] != 0, label_dilate)
+        nlab = int(lab.sum())
+        for k, tau in enumerate(taus):
+            if nlab == 0:
+                recall[m, k] = 1.0
+                continue
+            hit = int((dilate(prob[m] >= tau, pred_dilate) & lab).sum())
+            recall[m, k] = hit / nlab
+    med = np.array([quantile_linear(recall[:, k], 0.5) for k in range(len(taus))])
+    p10 = np.array([quantile_linear(recall[:, k], 0.1) for k in range(len(taus))])
+    ok = np.flatnonzero((med >= median_min) & (p10 >= p10_min))
+    return dict(recall=recall, median=med, p10=p10, index=int(ok[0]) if ok.size else -1,
+                index_max=int(ok[-1]) if ok.size else -1)

@@ -308,10 +308,52 @@ def test_mask_predict_is_the_network_through_the_hierarchy():
     np.testing.assert_allclose(z.reshape(g.ny, g.nx)[3, 7], complex(-4 + 8 * 7 / 29, -4 + 8 * 3 / 25), atol=1e-15)
 
 
+def pin_calibration(M):
+    from scipy import ndimage
+    rng = np.random.default_rng(17)
+    nval, ny, nx = 9, 23, 31
+    prob = rng.uniform(size=(nval, ny, nx)) ** 13                  # mostly small, a few near 1
+    labels = (rng.uniform(size=(nval, ny, nx)) < 0.03).astype(np.uint8)
+    labels[4] = 0                                                   # a matrix with no sensitive point
+    taus = np.round(np.arange(0.05, 0.95, 0.01), 2)
+    r = M.calibrate_tau(prob, labels, taus)
+    for m in range(nval):
+        lab = ndimage.binary_dilation(labels[m] != 0, structure=np.ones((3, 3)))
+        for k in (0, 10, 45, 89):
+            if lab.sum() == 0:
+                assert r["recall"][m, k] == 1.0
+                continue
+            pred = ndimage.binary_dilation(prob[m] >= taus[k], structure=np.ones((5, 5)))
+            assert r["recall"][m, k] == (pred & lab).sum() / lab.sum()
+    np.testing.assert_allclose(r["median"], np.median(r["recall"], axis=0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(r["p10"], np.percentile(r["recall"], 10, axis=0), rtol=0, atol=1e-15)
+    ok = (np.median(r["recall"], axis=0) >= 0.9) & (np.percentile(r["recall"], 10, axis=0) >= 0.75)
+    assert r["index"] == (int(np.argmax(ok)) if ok.any() else -1) == 0
+    assert r["index_max"] == len(taus) - 1 - int(np.argmax(ok[::-1]))
+    assert 0 < r["index_max"] < len(taus) - 1                      # the draws put it inside the range
+    assert ok[:r["index_max"] + 1].all() and not ok[r["index_max"] + 1:].any()
+    # recall falls as tau rises (fewer predicted points)
+    assert np.all(np.diff(r["recall"], axis=1) <= 0)
+    # closed form: one label point, one predicted point at Chebyshev distance d: the dilated
+    # sets (radii 2 and 1) meet the 3 x 3 label square in (4 - d) columns when d <= 3
+    for d in range(0, 5):
+        p = np.zeros((1, 15, 15))
+        lb = np.zeros((1, 15, 15), dtype=np.uint8)
+        lb[0, 7, 7] = 1
+        p[0, 7, 7 + d] = 0.5
+        rr = M.calibrate_tau(p, lb, [0.5, 0.6])
+        assert rr["recall"][0, 0] == max(0, min(3, 4 - d)) * 3 / 9, d
+        assert rr["recall"][0, 1] == 0.0
+
+
+def test_calibration():
+    pin_calibration(M0)
+
+
 # ----------------------------------------------------------------------------- mutants
 
 PINS = [pin_fourier_closed_form, pin_point_features, pin_network_vs_torch, pin_network_constant,
-        pin_error_bound, pin_bound_vs_autograd, pin_quantile, pin_hierarchy]
+        pin_error_bound, pin_bound_vs_autograd, pin_quantile, pin_hierarchy, pin_calibration]
 
 MUTANTS = [
     ("sin/cos order", "cols += [np.sin(f * x), np.sin(f * y), np.cos(f * x), np.cos(f * y)]",
@@ -327,6 +369,10 @@ MUTANTS = [
     ("strict selection", "selected = coarse >= tau_c", "selected = coarse > tau_c"),
     ("dilation radius", "r = (dilate - 1) // 2", "r = (dilate + 1) // 2"),
     ("bound without the dense layers", "np.abs(g_y5) * local(\"r5\", h4)", "0.0 * local(\"r5\", h4)"),
+    ("recall without the label dilation", "lab = dilate(labels[m] != 0, label_dilate)", "lab = labels[m] != 0"),
+    ("recall of an empty label set", "                recall[m, k] = 1.0\n", "                recall[m, k] = 0.0\n"),
+    ("tau* as the largest", "index=int(ok[0]) if ok.size", "index=int(ok[-1]) if ok.size"),
+    ("median for P10", "p10 = np.array([quantile_linear(recall[:, k], 0.1)", "p10 = np.array([quantile_linear(recall[:, k], 0.5)"),
     ("bound without the inputs", "e += np.sum(np.abs(g_x) * 1.01 * U32 * np.abs(x), axis=1)", "pass"),
 ]
 
