@@ -465,6 +465,37 @@ ps_status ps_mask_predict_batch(ps_mlp net, int32_t nmat, const ps_grid *g, cons
                                 size_t ws_bytes, uint8_t *mask_dev, float *prob_dev, float *coarse_dev,
                                 double *tau_coarse_dev, int64_t *evals_dev, void *stream);
 
+/*
+ * ps_mask_calibrate -- the threshold calibration of Sec. 3.6 on a validation set of nval matrices
+ * sharing grid g: for each candidate tau_k (ascending), the prediction {p >= tau_k} dilated by a
+ * pred_dilate square is compared with the labels dilated by a label_dilate square; per matrix
+ * recall = |both| / |dilated labels| (1 when a matrix has no labelled point).  Candidate k
+ * qualifies when the median of the nval recalls is >= median_min and their 10th percentile is
+ * >= p10_min (both by linear interpolation between order statistics, as for tau_coarse).  The
+ * paper's tau* is the smallest qualifying candidate (recall cannot rise with tau, so it is the
+ * first candidate whenever any qualifies); the largest qualifying candidate is the one that
+ * predicts the fewest points within the same bounds.  Paper values: candidates 0.05, 0.06, ...,
+ * 0.94, dilations 5 and 3, bounds 0.90 and 0.75, 30 validation matrices.
+ *   prob_dev      device float[nval][ny][nx]: probability maps (e.g. ps_mask_predict_batch's).
+ *   label_dev     device uint8[nval][ny][nx]: ground truth, nonzero = sensitive (e.g.
+ *                 ps_label_batch's labels of the same matrices on the same grid).
+ *   taus          host double[ntau], strictly ascending, 1 <= ntau <= PS_CAL_MAX_TAU.
+ *   nval          1 .. PS_CAL_MAX_VAL.   pred_dilate, label_dilate: odd, 1 .. 31.
+ *   index_dev     device int32[2] (required): the smallest and the largest qualifying candidate
+ *                 index, -1 when none qualifies.
+ *   recall_dev    device double[nval][ntau], median_dev / p10_dev double[ntau]: optional.
+ *   ws_dev / ws_bytes >= ps_mask_calibrate_workspace_size(nval, ntau), 256-byte aligned.
+ * Runs on the stream without host synchronisation; the candidates travel as kernel arguments.
+ * Errors: PS_ERR_INVALID, PS_ERR_NONFINITE, PS_ERR_WORKSPACE, PS_ERR_HIP.
+ */
+#define PS_CAL_MAX_TAU 128
+#define PS_CAL_MAX_VAL 256
+ps_status ps_mask_calibrate_workspace_size(int32_t nval, int32_t ntau, size_t *bytes);
+ps_status ps_mask_calibrate(int32_t nval, const ps_grid *g, const float *prob_dev, const uint8_t *label_dev,
+                            const double *taus, int32_t ntau, int32_t pred_dilate, int32_t label_dilate,
+                            double median_min, double p10_min, void *ws_dev, size_t ws_bytes, int32_t *index_dev,
+                            double *recall_dev, double *median_dev, double *p10_dev, void *stream);
+
 /* Thread-local description of the last error on the calling thread ("" if none). */
 const char *ps_last_error(void);
 

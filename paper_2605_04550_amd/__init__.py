@@ -108,6 +108,10 @@ _SIGNATURES = {
                                    _P]),
     "ps_mask_predict": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), ctypes.POINTER(ctypes.c_double), _P, _I64,
                                        ctypes.POINTER(ps_mask_opts), _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+    "ps_mask_calibrate_workspace_size": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(ctypes.c_size_t)]),
+    "ps_mask_calibrate": (ctypes.c_int, [_I32, ctypes.POINTER(ps_grid), _P, _P, ctypes.POINTER(ctypes.c_double), _I32,
+                                         _I32, _I32, ctypes.c_double, ctypes.c_double, _P, ctypes.c_size_t, _P, _P, _P,
+                                         _P, _P]),
     "ps_mask_batch_workspace_size": (ctypes.c_int, [_I32, ctypes.POINTER(ps_grid), ctypes.POINTER(ps_mask_opts),
                                                     ctypes.POINTER(ctypes.c_size_t)]),
     "ps_mask_predict_batch": (ctypes.c_int, [_P, _I32, ctypes.POINTER(ps_grid), ctypes.POINTER(ctypes.c_double), _P,
@@ -380,6 +384,21 @@ def ps_mask_predict_batch(handle, nmat, grid: ps_grid, gfeat, eig_ptr, eig_off, 
                                        ctypes.byref(opts) if opts is not None else None, _P(ws_ptr), ws_bytes,
                                        _P(mask_ptr), _P(prob_ptr), _P(coarse_ptr), _P(tau_coarse_ptr), _P(evals_ptr),
                                        _P(stream)))
+
+
+def ps_mask_calibrate_workspace_size(nval, ntau) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().ps_mask_calibrate_workspace_size(int(nval), int(ntau), ctypes.byref(b)))
+    return b.value
+
+
+def ps_mask_calibrate(nval, grid: ps_grid, prob_ptr, label_ptr, taus, pred_dilate, label_dilate, median_min, p10_min,
+                      ws_ptr, ws_bytes, index_ptr, recall_ptr=0, median_ptr=0, p10_ptr=0, stream=0) -> None:
+    t = (ctypes.c_double * max(len(taus), 1))(*[float(v) for v in taus])
+    _check(lib().ps_mask_calibrate(int(nval), ctypes.byref(grid), _P(prob_ptr), _P(label_ptr), t, len(taus),
+                                   int(pred_dilate), int(label_dilate), float(median_min), float(p10_min),
+                                   _P(ws_ptr), ws_bytes, _P(index_ptr), _P(recall_ptr), _P(median_ptr),
+                                   _P(p10_ptr), _P(stream)))
 
 
 def header_symbols():

@@ -8,6 +8,7 @@
 * ``newton_contour`` -- Newton steps moving points onto the level curve sigma_min = eps.
 * ``MaskNet``        -- the classifier of Sec. 3.2 (ps_mlp_create): ``prob`` (ps_mlp_prob) and
                         ``predict`` (ps_mask_predict, the hierarchical prediction of Sec. 3.5).
+* ``calibrate_tau``  -- ps_mask_calibrate, the threshold calibration of Sec. 3.6.
 """
 from __future__ import annotations
 
@@ -24,10 +25,11 @@ from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_w
                ps_contour_seeds_workspace_size, ps_label_grid, ps_label_workspace_size, ps_label_batch,
                ps_label_batch_workspace_size, ps_trace_contour, ps_trace_workspace_size, ps_mask_opts_default,
                ps_mlp_create, ps_mlp_destroy, ps_mask_workspace_size, ps_mlp_prob, ps_mask_predict,
-               ps_mask_batch_workspace_size, ps_mask_predict_batch, PS_MLP_NPARAM)
+               ps_mask_batch_workspace_size, ps_mask_predict_batch, ps_mask_calibrate,
+               ps_mask_calibrate_workspace_size, PS_MLP_NPARAM)
 
 __all__ = ["BandedMatrix", "BandedBatch", "sigma_min", "eval_grid", "SigmaMin", "newton_contour", "make_opts",
-           "MaskNet"]
+           "MaskNet", "calibrate_tau"]
 
 
 def _stream_handle(stream=None) -> int:
@@ -322,6 +324,34 @@ def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):
     o = make_opts(**kw)
     ps_autotune(mat.handle, z.contiguous().data_ptr(), z.numel(), o, _stream_handle())
     return o
+
+
+def calibrate_tau(grid, prob: torch.Tensor, labels: torch.Tensor, taus=None, *, pred_dilate=5, label_dilate=3,
+                  median_min=0.90, p10_min=0.75, stream=None):
+    """ps_mask_calibrate on probability maps prob [nval, ny, nx] (float32) and labels [nval, ny, nx]
+    (uint8), both CUDA tensors.  taus defaults to 0.05, 0.06, ..., 0.94.  Returns dict(index
+    (smallest qualifying candidate, -1 if none), index_max, taus, recall [nval, ntau],
+    median [ntau], p10 [ntau])."""
+    if taus is None:
+        taus = [round(0.05 + 0.01 * k, 2) for k in range(90)]
+    g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
+    nval = prob.shape[0]
+    assert prob.dtype == torch.float32 and labels.dtype == torch.uint8 and prob.numel() == labels.numel()
+    assert prob.numel() == nval * g.nx * g.ny
+    dev = prob.device
+    prob = prob.contiguous()
+    labels = labels.contiguous()
+    ntau = len(taus)
+    idx = torch.empty(2, dtype=torch.int32, device=dev)
+    recall = torch.empty((nval, ntau), dtype=torch.float64, device=dev)
+    med = torch.empty(ntau, dtype=torch.float64, device=dev)
+    p10 = torch.empty(ntau, dtype=torch.float64, device=dev)
+    ws = _workspace(ps_mask_calibrate_workspace_size(nval, ntau), dev)
+    ps_mask_calibrate(nval, g, prob.data_ptr(), labels.data_ptr(), taus, pred_dilate, label_dilate, median_min,
+                      p10_min, ws.data_ptr(), ws.numel(), idx.data_ptr(), recall.data_ptr(), med.data_ptr(),
+                      p10.data_ptr(), _stream_handle(stream))
+    i = idx.cpu().tolist()
+    return dict(index=i[0], index_max=i[1], taus=list(taus), recall=recall, median=med, p10=p10)
 
 
 class MaskNet:

@@ -396,6 +396,40 @@ ps_status ps_mask_predict_batch(ps_mlp net, int32_t nmat, const ps_grid *g, cons
     return ok();
 }
 
+ps_status ps_mask_calibrate_workspace_size(int32_t nval, int32_t ntau, size_t *bytes) {
+    if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
+    if (nval < 1 || nval > ps::mlp::kCalMaxVal) return fail(PS_ERR_INVALID, "nval must be in [1, %d]", ps::mlp::kCalMaxVal);
+    if (ntau < 1 || ntau > ps::mlp::kCalMaxTau) return fail(PS_ERR_INVALID, "ntau must be in [1, %d]", ps::mlp::kCalMaxTau);
+    *bytes = align256(sizeof(int64_t) * (size_t)nval * ((size_t)ntau + 1));
+    return ok();
+}
+
+ps_status ps_mask_calibrate(int32_t nval, const ps_grid *g, const float *prob_dev, const uint8_t *label_dev,
+                            const double *taus, int32_t ntau, int32_t pred_dilate, int32_t label_dilate,
+                            double median_min, double p10_min, void *ws_dev, size_t ws_bytes, int32_t *index_dev,
+                            double *recall_dev, double *median_dev, double *p10_dev, void *stream) {
+    size_t need = 0;
+    ps_status st = ps_mask_calibrate_workspace_size(nval, ntau, &need);
+    if (st) return st;
+    if ((st = check_grid(g))) return st;
+    if (!prob_dev || !label_dev || !index_dev || !taus) return fail(PS_ERR_INVALID, "prob, label, taus and index are required");
+    for (int32_t k = 0; k < ntau; ++k) {
+        if (!isfinite(taus[k])) return fail(PS_ERR_NONFINITE, "tau %d is not finite", k);
+        if (k > 0 && !(taus[k] > taus[k - 1])) return fail(PS_ERR_INVALID, "taus must be strictly ascending");
+    }
+    for (int32_t d : {pred_dilate, label_dilate})
+        if (d < 1 || d > 31 || d % 2 == 0) return fail(PS_ERR_INVALID, "dilation sides must be odd, 1 .. 31");
+    if (!isfinite(median_min) || !isfinite(p10_min)) return fail(PS_ERR_NONFINITE, "recall bounds must be finite");
+    if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "calibration workspace needs %zu bytes", need);
+    if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    ps::mlp::Taus tv{};
+    for (int32_t k = 0; k < ntau; ++k) tv.t[k] = taus[k];
+    HIP_TRY(ps::mlp::launch_calibrate(prob_dev, label_dev, nval, g->nx, g->ny, (pred_dilate - 1) / 2,
+                                      (label_dilate - 1) / 2, tv, ntau, median_min, p10_min, (int64_t *)ws_dev,
+                                      recall_dev, median_dev, p10_dev, index_dev, (hipStream_t)stream));
+    return ok();
+}
+
 const char *ps_last_error(void) { return g_err; }
 
 const char *ps_version(void) { return "ps-mi355x 0.1 (gfx950, fp64)"; }

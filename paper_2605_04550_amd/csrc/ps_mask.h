@@ -80,5 +80,16 @@ hipError_t launch_mask(const float *raw, const float *packed, const Batch &bt, i
                        float *coarse, float *prob, uint8_t *mask, int64_t *evals, double *tau_coarse_out,
                        hipStream_t s);
 
+// Threshold calibration (Sec. 3.6): candidates by value (ascending), counts in the workspace
+// (nval * (ntau + 1) int64: labelled points per matrix, then the per-candidate bins).
+constexpr int kCalMaxTau = 128;
+constexpr int kCalMaxVal = 256;
+struct Taus {
+    double t[kCalMaxTau];
+};
+hipError_t launch_calibrate(const float *prob, const uint8_t *label, int nval, int64_t nx, int64_t ny, int rp, int rl,
+                            const Taus &taus, int ntau, double median_min, double p10_min, int64_t *counts,
+                            double *recall, double *median, double *p10, int32_t *index, hipStream_t s);
+
 }  // namespace mlp
 }  // namespace ps

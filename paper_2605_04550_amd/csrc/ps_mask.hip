@@ -352,18 +352,20 @@ __device__ void bitonic_sort(unsigned *key, int n) {
 }
 
 // tau_coarse = v_(k) + (h - k)(v_(k+1) - v_(k)), h = q (m - 1), k = floor(h): the quantile of
-// Sec. 3.5 by linear interpolation between order statistics (no fused multiply-add, so the
-// value is the one the plain formula gives).  One workgroup per matrix.
+// Sec. 3.5 by linear interpolation between order statistics, with contraction into fused
+// multiply-adds switched off for the operators written here, so the value is the one the plain
+// formula gives.  One workgroup per matrix.
 __global__ void __launch_bounds__(kBlock) k_quantile(const float *__restrict__ coarse, int64_t m, double q, char *ws,
                                                      double *tau_out) {
+#pragma clang fp contract(off)
     __shared__ unsigned keys[kSortMax];
     __shared__ unsigned hist[256];
     __shared__ int64_t sk;
     __shared__ unsigned sprefix;
     const float *v = coarse + (int64_t)blockIdx.x * m;
-    const double h = __dmul_rn(q, (double)(m - 1));
+    const double h = q * (double)(m - 1);
     const int64_t k0 = (int64_t)floor(h);
-    const double g = __dsub_rn(h, (double)k0);
+    const double g = h - (double)k0;
     float v0, v1;
     if (m <= kSortMax) {
         int n = 2;
@@ -378,7 +380,7 @@ __global__ void __launch_bounds__(kBlock) k_quantile(const float *__restrict__ c
         v1 = k0 + 1 < m ? select_rank(v, m, k0 + 1, hist, &sk, &sprefix) : v0;
     }
     if (threadIdx.x == 0) {
-        const double tau = __dadd_rn((double)v0, __dmul_rn(g, __dsub_rn((double)v1, (double)v0)));
+        const double tau = (double)v0 + g * ((double)v1 - (double)v0);
         *(double *)(ws + (int64_t)blockIdx.x * kWsHeader + kWsTau) = tau;
         if (tau_out) tau_out[blockIdx.x] = tau;
     }
@@ -441,6 +443,97 @@ __global__ void __launch_bounds__(kBlock) k_dilate(const float *__restrict__ pro
     mask[(int64_t)blockIdx.y * nx * ny + t] = hit;
 }
 
+// ------------------------------------------------------------------ threshold calibration
+// Sec. 3.6: per validation matrix and candidate tau, recall of the prediction {p >= tau} dilated
+// by a square of radius rp against the labels dilated by a square of radius rl.  A point lies
+// in the dilated prediction at tau exactly when the maximum of p over its (2 rp + 1)^2 window
+// is >= tau, so one pass per point bins the labelled points by how many candidates they pass.
+
+__global__ void __launch_bounds__(kBlock) k_cal_zero(int64_t *cnt, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) cnt[t] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cal_count(const float *__restrict__ prob,
+                                                      const uint8_t *__restrict__ label, int64_t nx, int64_t ny,
+                                                      int rp, int rl, Taus taus, int ntau, int64_t *nlab,
+                                                      int64_t *hist) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nx * ny) return;
+    const int m = blockIdx.y;
+    const uint8_t *L = label + (int64_t)m * nx * ny;
+    const float *P = prob + (int64_t)m * nx * ny;
+    const int64_t i = t / nx, j = t - i * nx;
+    bool lab = false;
+    for (int64_t a = (i - rl > 0 ? i - rl : 0); a <= (i + rl < ny - 1 ? i + rl : ny - 1) && !lab; ++a)
+        for (int64_t b = (j - rl > 0 ? j - rl : 0); b <= (j + rl < nx - 1 ? j + rl : nx - 1); ++b)
+            if (L[a * nx + b]) {
+                lab = true;
+                break;
+            }
+    if (!lab) return;
+    atomicAdd((unsigned long long *)(nlab + m), 1ull);
+    float pmax = -INFINITY;
+    for (int64_t a = (i - rp > 0 ? i - rp : 0); a <= (i + rp < ny - 1 ? i + rp : ny - 1); ++a)
+        for (int64_t b = (j - rp > 0 ? j - rp : 0); b <= (j + rp < nx - 1 ? j + rp : nx - 1); ++b)
+            pmax = fmaxf(pmax, P[a * nx + b]);
+    const double pm = (double)pmax;
+    int k = 0;
+    while (k < ntau && taus.t[k] <= pm) ++k;
+    if (k > 0) atomicAdd((unsigned long long *)(hist + (int64_t)m * ntau + (k - 1)), 1ull);
+}
+
+// v_(k) + (h - k)(v_(k+1) - v_(k)) at h = q (n - 1) on sorted v (no fused multiply-add).
+__device__ double quantile_sorted(const double *v, int n, double q) {
+#pragma clang fp contract(off)
+    const double h = q * (double)(n - 1);
+    const int k = (int)floor(h);
+    const double g = h - (double)k;
+    const double v0 = v[k], v1 = k + 1 < n ? v[k + 1] : v0;
+    return v0 + g * (v1 - v0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cal_select(const int64_t *__restrict__ nlab,
+                                                       const int64_t *__restrict__ hist, int nval, int ntau,
+                                                       double median_min, double p10_min, double *recall_out,
+                                                       double *median_out, double *p10_out, int32_t *index_out) {
+    __shared__ double rec[kCalMaxVal];
+    __shared__ double srt[kCalMaxVal];
+    __shared__ int first, last;
+    if (threadIdx.x == 0) first = last = -1;
+    for (int k = 0; k < ntau; ++k) {
+        for (int m = threadIdx.x; m < nval; m += blockDim.x) {
+            int64_t hit = 0;
+            for (int i = k; i < ntau; ++i) hit += hist[(int64_t)m * ntau + i];
+            const int64_t nl = nlab[m];
+            const double r = nl > 0 ? (double)hit / (double)nl : 1.0;
+            rec[m] = r;
+            if (recall_out) recall_out[(int64_t)m * ntau + k] = r;
+        }
+        __syncthreads();
+        for (int m = threadIdx.x; m < nval; m += blockDim.x) {
+            int r = 0;
+            for (int j = 0; j < nval; ++j) r += (rec[j] < rec[m]) || (rec[j] == rec[m] && j < m);
+            srt[r] = rec[m];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double med = quantile_sorted(srt, nval, 0.5), p10 = quantile_sorted(srt, nval, 0.1);
+            if (median_out) median_out[k] = med;
+            if (p10_out) p10_out[k] = p10;
+            if (med >= median_min && p10 >= p10_min) {
+                if (first < 0) first = k;
+                last = k;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        index_out[0] = first;
+        index_out[1] = last;
+    }
+}
+
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 
 }  // namespace
@@ -479,6 +572,19 @@ hipError_t launch_mask(const float *raw, const float *packed, const Batch &bt, i
                        packed, bt, eig, neig, ws, g, stride, ncx, ncoarse, tpc, coarse, prob, evals);
     hipLaunchKernelGGL(k_dilate, dim3((unsigned)blocks_for(g.nx * g.ny, kBlock), nmat), dim3(kBlock), 0, s, prob, g.nx,
                        g.ny, tau, (dilate - 1) / 2, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_calibrate(const float *prob, const uint8_t *label, int nval, int64_t nx, int64_t ny, int rp, int rl,
+                            const Taus &taus, int ntau, double median_min, double p10_min, int64_t *counts,
+                            double *recall, double *median, double *p10, int32_t *index, hipStream_t s) {
+    const int64_t ncnt = (int64_t)nval * (ntau + 1);
+    int64_t *nlab = counts, *hist = counts + nval;
+    hipLaunchKernelGGL(k_cal_zero, dim3((unsigned)blocks_for(ncnt, kBlock)), dim3(kBlock), 0, s, counts, ncnt);
+    hipLaunchKernelGGL(k_cal_count, dim3((unsigned)blocks_for(nx * ny, kBlock), nval), dim3(kBlock), 0, s, prob, label,
+                       nx, ny, rp, rl, taus, ntau, nlab, hist);
+    hipLaunchKernelGGL(k_cal_select, dim3(1), dim3(kBlock), 0, s, nlab, hist, nval, ntau, median_min, p10_min, recall,
+                       median, p10, index);
     return hipGetLastError();
 }
 

@@ -232,3 +232,30 @@ def test_mask_batch_argument_checks():
     assert e.value.status == P.PS_ERR_INVALID
     with pytest.raises(ValueError):
         P.ps_mask_predict_batch(fake, 3, g, gf[:2], fake, off, o, fake, 1 << 30, fake)
+
+
+def test_mask_calibrate_argument_checks():
+    _lib()
+    fake = 256
+    g = P.ps_grid(-4, 4, -4, 4, 100, 100)
+    taus = [0.05, 0.1, 0.2]
+    assert P.ps_mask_calibrate_workspace_size(30, 90) == 30 * 91 * 8 // 256 * 256 + 256 * ((30 * 91 * 8) % 256 > 0)
+    for nval, ntau in ((0, 3), (257, 3), (3, 0), (3, 129)):
+        with pytest.raises(P.PsError) as e:
+            P.ps_mask_calibrate_workspace_size(nval, ntau)
+        assert e.value.status == P.PS_ERR_INVALID
+    bad = [dict(taus=[0.1, 0.1]), dict(taus=[0.2, 0.1]), dict(pred_dilate=4), dict(label_dilate=0),
+           dict(index=0), dict(prob=0)]
+    for b in bad:
+        kw = dict(taus=taus, pred_dilate=5, label_dilate=3, index=fake, prob=fake)
+        kw.update(b)
+        with pytest.raises(P.PsError) as e:
+            P.ps_mask_calibrate(3, g, kw["prob"], fake, kw["taus"], kw["pred_dilate"], kw["label_dilate"], 0.9, 0.75,
+                                fake, 1 << 20, kw["index"])
+        assert e.value.status == P.PS_ERR_INVALID, b
+    with pytest.raises(P.PsError) as e:
+        P.ps_mask_calibrate(3, g, fake, fake, [0.1, float("nan")], 5, 3, 0.9, 0.75, fake, 1 << 20, fake)
+    assert e.value.status == P.PS_ERR_NONFINITE
+    with pytest.raises(P.PsError) as e:
+        P.ps_mask_calibrate(3, g, fake, fake, taus, 5, 3, 0.9, 0.75, fake, 16, fake)
+    assert e.value.status == P.PS_ERR_WORKSPACE

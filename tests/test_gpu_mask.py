@@ -177,3 +177,60 @@ def test_mask_predict_batch_equals_single_calls(shape, stride, dilate, tau):
     r = {k: v[4].cpu().numpy() for k, v in rb.items()}
     r["evals"] = np.array([r["evals"]])
     _check_mask(grid, params, gfs[4], eigs[4], tau, stride, dilate, r, what="batch matrix 4")
+
+
+def _check_calibration(api, grid, prob, labels, taus, **kw):
+    import torch
+    r = api.calibrate_tau(grid, _t(prob, torch.float32), _t(labels, torch.uint8), taus, **kw)
+    torch.cuda.synchronize()
+    o = OM.calibrate_tau(prob.astype(np.float32).astype(np.float64), labels, taus,
+                         **{k: v for k, v in kw.items()})
+    np.testing.assert_array_equal(r["recall"].cpu().numpy(), o["recall"])
+    np.testing.assert_array_equal(r["median"].cpu().numpy(), o["median"])
+    np.testing.assert_array_equal(r["p10"].cpu().numpy(), o["p10"])
+    assert (r["index"], r["index_max"]) == (o["index"], o["index_max"])
+    return r
+
+
+def test_calibration_vs_oracle():
+    """ps_mask_calibrate against the oracle on the same maps: recalls (ratios of counts), their
+    median and 10th percentile, and both qualifying indices, all identical."""
+    api = _api()
+    rng = np.random.default_rng(17)
+    nval, ny, nx = 9, 23, 31
+    grid = W.Grid(0.0, 1.0, 0.0, 1.0, nx, ny)
+    prob = (rng.uniform(size=(nval, ny, nx)) ** 13).astype(np.float32)
+    labels = (rng.uniform(size=(nval, ny, nx)) < 0.03).astype(np.uint8)
+    labels[4] = 0
+    taus = [round(0.05 + 0.01 * k, 2) for k in range(90)]
+    r = _check_calibration(api, grid, prob, labels, taus)
+    assert r["index"] == 0 and 0 < r["index_max"] < 89
+    # other dilations and bounds; no candidate qualifies; a single matrix and candidate
+    _check_calibration(api, grid, prob, labels, taus, pred_dilate=3, label_dilate=1, median_min=0.8, p10_min=0.5)
+    r = _check_calibration(api, grid, prob, labels, taus, median_min=1.01)
+    assert (r["index"], r["index_max"]) == (-1, -1)
+    _check_calibration(api, grid, prob[:1], labels[:1], [0.3])
+    r = _check_calibration(api, grid, prob, np.zeros_like(labels), taus)
+    assert (r["index"], r["index_max"]) == (0, 89)
+
+
+def test_calibration_on_predicted_maps_and_exact_labels():
+    """The Sec. 3.6 procedure end to end on the GPU: 30 validation matrices of the Sec. 3.3 class,
+    probability maps from ps_mask_predict_batch, labels from ps_label_batch (exact, eps = 0.01);
+    the oracle's calibration on the same two arrays gives the same answer."""
+    api = _api()
+    import torch
+    w = W.paper_label_workload(30)
+    grid = w["grid"]
+    mats = [api.BandedMatrix.from_band(b) for b in w["mats"]]
+    batch = api.BandedBatch(mats, [grid] * len(mats))
+    lab = batch.label(w["eps"])["label"].reshape(30, grid.ny, grid.nx)
+    net = api.MaskNet(nets.mlp_params(91, 3.0))
+    eigs = [_t(np.linalg.eigvals(W.to_dense(b)), torch.complex128) for b in w["mats"]]
+    gfs = np.stack([nets.global_features(92 + m) for m in range(30)])
+    pr = net.predict_batch(grid, gfs, eigs, tau=0.05)["prob"]
+    torch.cuda.synchronize()
+    taus = [round(0.05 + 0.01 * k, 2) for k in range(90)]
+    r = _check_calibration(api, grid, pr.cpu().numpy(), lab.cpu().numpy(), taus)
+    print("calibration on 30 matrices: tau* index %d, largest qualifying %d, median recall at 0.05 %.3f"
+          % (r["index"], r["index_max"], float(r["median"][0])), flush=True)
