@@ -87,7 +87,12 @@ def test_trace_from_grid_seeds_grcar100():
     assert np.all(cnt >= 1) and np.all(fl != 0)
     pts = np.concatenate([tr["points"][t, :cnt[t]].cpu().numpy() for t in range(len(cnt))])
     s_gpu = api.sigma_min(mat, torch.tensor(pts, dtype=torch.complex128, device="cuda"))["sigma"].cpu().numpy()
-    assert np.all(np.abs(np.log(s_gpu / eps)) <= 1e-6 + 1e-8)
+    # accepted at |ln(sigma / eps)| <= 1e-6 by the tracer's own evaluation; a second evaluation
+    # may differ from it by the evaluation tolerance twice (each within tol of the truth)
+    worst = float(np.max(np.abs(s_gpu - eps)))
+    print("grcar100: max |sigma - eps| of the stored points %.3e (bound %.3e)"
+          % (worst, 1e-6 * eps + 2 * tol(w["band"].fro, eps)), flush=True)
+    assert np.all(np.abs(s_gpu - eps) <= 1e-6 * eps + 2 * tol(w["band"].fro, eps))
     sel = np.arange(0, len(pts), max(1, len(pts) // 12))
     s_or = oracle.sigma_min(w["band"], pts[sel])["sigma"]
     assert np.all(np.abs(s_or - eps) <= tol(w["band"].fro, eps) + 1e-6 * eps)
