@@ -372,7 +372,7 @@ def mask_bench(args):
         "region_fraction": region / npts,
         "classifier": {"points": nthr, "seconds": t_prob, "evaluations_per_s": nthr / t_prob,
                        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
-                                    "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
                                     "kernel": "ps::mlp::k_points (one launch; + k_prep, 1 workgroup)",
                                     "algorithmic_flops_per_launch": MLP_FLOPS * nthr}},
         "cpu_baseline": cpu}), flush=True)
