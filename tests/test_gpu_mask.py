@@ -234,3 +234,29 @@ def test_calibration_on_predicted_maps_and_exact_labels():
     r = _check_calibration(api, grid, pr.cpu().numpy(), lab.cpu().numpy(), taus)
     print("calibration on 30 matrices: tau* index %d, largest qualifying %d, median recall at 0.05 %.3f"
           % (r["index"], r["index_max"], float(r["median"][0])), flush=True)
+
+
+def test_mask_batch_at_the_benchmarked_size():
+    """The launch the mask benchmark times: 500 matrices of the Sec. 3.3 class, the 100 x 100
+    grid, the same weights and features.  Sampled matrices equal their single calls exactly,
+    and one of them matches the oracle (probabilities within the bound, decisions identical)."""
+    api = _api()
+    import torch
+    w = W.paper_label_workload(500)
+    grid = w["grid"]
+    params = nets.mlp_params(W.SEED_BASE + 900, 3.0)
+    net = api.MaskNet(params)
+    eig_np = [np.linalg.eigvals(W.to_dense(b)) for b in w["mats"]]
+    eigs = [_t(e, torch.complex128) for e in eig_np]
+    gfs = np.stack([nets.global_features(W.SEED_BASE + 901 + m) for m in range(500)])
+    rb = net.predict_batch(grid, gfs, eigs, tau=0.05)
+    torch.cuda.synchronize()
+    assert int(rb["evals"].min()) >= 2625
+    for m in (0, 137, 311, 499):
+        r1 = net.predict(grid, gfs[m], eigs[m], tau=0.05)
+        torch.cuda.synchronize()
+        for k in ("mask", "prob", "coarse"):
+            assert torch.equal(rb[k][m], r1[k]), (m, k)
+    r = {k: v[311].cpu().numpy() for k, v in rb.items()}
+    r["evals"] = np.array([r["evals"]])
+    _check_mask(grid, params, gfs[311], eig_np[311], 0.05, 4, 5, r, what="benchmarked batch, matrix 311")
