@@ -110,3 +110,32 @@ def test_batched_labels_match_single_matrix_and_oracle():
     npts = sum(gr.npts for gr in grids)
     print("batched labels: %d matrices, %d of %d shifts evaluated (%.1f %%)"
           % (len(bands), total_evals, npts, 100.0 * total_evals / npts), flush=True)
+
+
+def test_label_batch_at_the_benchmarked_size():
+    """The launch the label benchmark times: all 500 matrices of the workload in one
+    ps_label_batch.  Every label equals the plain method's (sigma_min <= eps from ps_eval_batch on
+    every point) wherever sigma is further than twice the tolerance from eps, and the first
+    three matrices match the oracle's stored labels."""
+    api = _api()
+    import torch
+    g = golden("paper_labels")
+    w = W.paper_label_workload(500)
+    grid, eps = w["grid"], w["eps"]
+    mats = [api.BandedMatrix.from_band(b) for b in w["mats"]]
+    batch = api.BandedBatch(mats, [grid] * len(mats))
+    r = batch.label(eps)
+    p = batch.eval(None)
+    torch.cuda.synchronize()
+    lab = r["label"].cpu().numpy()
+    sp = p["sigma"].cpu().numpy()
+    fro = np.repeat([b.fro for b in w["mats"]], grid.npts)
+    sure = np.abs(sp - eps) > 2 * tol(fro, sp)
+    assert np.array_equal(lab[sure], (sp[sure] <= eps).astype(np.uint8))
+    for m in range(3):
+        off = r["offsets"][m]
+        s_or, l_or = g["sigma%d" % m], g["label%d" % m]
+        sure_o = np.abs(s_or - eps) > 2 * tol(w["mats"][m].fro, s_or)
+        assert np.array_equal(lab[off:off + grid.npts][sure_o], l_or[sure_o]), m
+    print("label batch of 500: %d of %d labels decided away from eps, %d evaluations"
+          % (int(sure.sum()), len(sp), int(r["evals"].item())), flush=True)
