@@ -97,3 +97,31 @@ def test_trace_from_grid_seeds_grcar100():
     s_or = oracle.sigma_min(w["band"], pts[sel])["sigma"]
     assert np.all(np.abs(s_or - eps) <= tol(w["band"].fro, eps) + 1e-6 * eps)
     print("grcar100: %d tracers, %d points, flags %s" % (len(cnt), len(pts), fl.tolist()))
+
+
+def test_trace_at_the_benchmarked_size_certified():
+    """The launch the tracing benchmark times: toeplitz n = 2000, 256 seeds from the eps = 1e-2
+    contour seeds of the full 256 x 256 grid, h = the grid spacing, 64 points each.  Sampled
+    stored points are certified by the oracle's inertia count: no singular value of zI - A
+    below eps - d and at least one below eps + d, d = 1e-6 eps + 2 tol (the acceptance bound
+    and the evaluation tolerance)."""
+    api = _api()
+    w = W.workload("toeplitz2000")
+    band, g = w["band"], w["grid"]
+    mat = api.BandedMatrix.from_band(band)
+    eps = 1e-2
+    r = api.eval_grid(mat, g)
+    seeds, count = api.contour_seeds(g, r["sigma"], eps)
+    pick = seeds[:: max(1, count // 256)][:256].contiguous()
+    h = (g.b - g.a) / (g.nx - 1)
+    tr = api.trace_contour(mat, pick, eps, h, 64, box=(g.a, g.b, g.c, g.d))
+    cnt = tr["count"].cpu().numpy()
+    assert len(cnt) == 256 and np.all(cnt >= 1)
+    pts = np.concatenate([tr["points"][t, :cnt[t]].cpu().numpy() for t in range(len(cnt))])
+    sel = pts[np.linspace(0, len(pts) - 1, 12).astype(int)]
+    d = 1e-6 * eps + 2 * tol(band.fro, eps)
+    below = oracle.count_below(band, sel, eps - d)
+    above = oracle.count_below(band, sel, eps + d)
+    print("toeplitz2000 trace: %d tracers, %d points; certified %d sampled points within %.2e of eps"
+          % (len(cnt), len(pts), len(sel), d), flush=True)
+    assert np.all(below == 0) and np.all(above >= 1), (below, above)
