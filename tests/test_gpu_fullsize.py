@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import need_gpu, tol
+from gpu_util import golden, need_gpu, tol
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -226,3 +226,44 @@ def _fd_grad_z(api, mat, z, h=1e-6):
     def sg(zz):
         return api.sigma_min(mat, torch.tensor(zz, dtype=torch.complex128, device="cuda"), **tight)["sigma"].cpu().numpy()
     return ((sg(z + h) - sg(z - h)) + 1j * (sg(z + 1j * h) - sg(z - 1j * h))) / (2 * h)
+
+
+def test_toeplitz2000_benchmarked_launch():
+    """The two calls the headline benchmark times, as it makes them: the full 256 x 256 grid
+    (eps = 1e-2 flags) and the annulus mask.  Stored oracle values at 16 grid points (read
+    from the full-grid output), restricted == full at every masked point, 1-Lipschitz on every
+    neighbouring pair, sigma <= dist(z, spectrum) with the exact spectrum cos(k pi / 2001), and
+    the flags equal sigma <= eps."""
+    api = _api()
+    import torch
+    g = golden("toeplitz2000_pts")
+    w = W.workload("toeplitz2000")
+    band, grid = w["band"], w["grid"]
+    mat = api.BandedMatrix.from_band(band)
+    eps = 1e-2
+    full = api.eval_grid(mat, grid, eps=eps)
+    mask = torch.tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    rest = api.eval_grid(mat, grid, mask, eps=eps)
+    torch.cuda.synchronize()
+    sig = full["sigma"].cpu().numpy()
+    assert np.all((full["info"].cpu().numpy() & 2) == 0)
+    b = tol(band.fro, g["sigma"])
+    assert np.all(np.abs(sig[g["idx"]] - g["sigma"]) <= b), np.max(np.abs(sig[g["idx"]] - g["sigma"]) / b)
+    c = int(rest["count"].item())
+    idx = rest["idx"][:c].cpu().numpy()
+    assert np.array_equal(idx, np.flatnonzero(w["mask"].ravel()))
+    np.testing.assert_allclose(rest["sigma"][:c].cpu().numpy(), sig[idx], rtol=1e-13, atol=0)
+    z = oracle.grid_points(grid).reshape(grid.ny, grid.nx)
+    s2 = sig.reshape(grid.ny, grid.nx)
+    slack = 2 * tol(band.fro, np.maximum(s2[:, 1:], s2[:, :-1]))
+    assert np.all(np.abs(s2[:, 1:] - s2[:, :-1]) <= np.abs(z[:, 1:] - z[:, :-1]) + slack)
+    slack = 2 * tol(band.fro, np.maximum(s2[1:], s2[:-1]))
+    assert np.all(np.abs(s2[1:] - s2[:-1]) <= np.abs(z[1:] - z[:-1]) + slack)
+    lam = np.sort(np.cos(np.arange(1, 2001) * np.pi / 2001))      # real: nearest by binary search
+    zr = z.ravel()
+    k = np.clip(np.searchsorted(lam, zr.real), 1, len(lam) - 1)
+    dist = np.minimum(np.abs(zr - lam[k - 1]), np.abs(zr - lam[k]))
+    assert np.all(sig <= dist + tol(band.fro, dist))
+    assert np.array_equal(full["sens"].cpu().numpy(), (sig <= eps).astype(np.uint8))
+    print("toeplitz2000 benchmarked launch: %d + %d shifts, stored points max err/bound %.3f"
+          % (sig.size, c, float(np.max(np.abs(sig[g["idx"]] - g["sigma"]) / b))), flush=True)
