@@ -44,24 +44,35 @@ __device__ __forceinline__ v4f silu4(v4f y) {
     return r;
 }
 
-// y[oc] = W h + b for O outputs over KC groups of 16 inputs (see the layout note above).
+// y[oc] = W h + b for O outputs over KC groups of 16 inputs (see the layout note above).  The
+// A operands stream through a two-deep register queue: the load for step s + 2 is issued before
+// the four MFMAs of step s (a scheduling barrier keeps it there), so each operand has two
+// steps of matrix-core work to arrive from L2.
 template <int O, int KC>
 __device__ __forceinline__ void dense(const float4 *__restrict__ P, const float *__restrict__ bias, const v4f *h,
                                       v4f *y, int lane) {
+    constexpr int N = (O / 16) * KC;
     const int q = lane >> 4;
+    float4 q0 = P[lane];
+    float4 q1 = N > 1 ? P[64 + lane] : q0;
+    v4f acc;
 #pragma unroll
-    for (int oc = 0; oc < O / 16; ++oc) {
-        const float4 bb = *(const float4 *)(bias + 16 * oc + 4 * q);
-        v4f acc = {bb.x, bb.y, bb.z, bb.w};
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const float4 a = P[(oc * KC + kc) * 64 + lane];
-            acc = mfma(a.x, h[kc][0], acc);
-            acc = mfma(a.y, h[kc][1], acc);
-            acc = mfma(a.z, h[kc][2], acc);
-            acc = mfma(a.w, h[kc][3], acc);
+    for (int s = 0; s < N; ++s) {
+        const int oc = s / KC, kc = s % KC;
+        float4 nxt = q1;
+        if (s + 2 < N) nxt = P[(s + 2) * 64 + lane];
+        __builtin_amdgcn_sched_barrier(0);
+        if (kc == 0) {
+            const float4 bb = *(const float4 *)(bias + 16 * oc + 4 * q);
+            acc = v4f{bb.x, bb.y, bb.z, bb.w};
         }
-        y[oc] = acc;
+        acc = mfma(q0.x, h[kc][0], acc);
+        acc = mfma(q0.y, h[kc][1], acc);
+        acc = mfma(q0.z, h[kc][2], acc);
+        acc = mfma(q0.w, h[kc][3], acc);
+        if (kc == KC - 1) y[oc] = acc;
+        q0 = q1;
+        q1 = nxt;
     }
 }
 
