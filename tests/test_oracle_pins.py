@@ -470,6 +470,41 @@ def test_trace_contour_nonnormal_points_lie_on_the_curve():
     assert np.all((d > 0.9 * h) & (d < 1.1 * h))
 
 
+# ----------------------------------------------------------------------------- pair orders
+
+@pytest.mark.parametrize("n", [7, 8, 13, 40, 41, 64])
+def test_round_robin_order_small(n):
+    """The round-robin (tournament) pair order reaches the same singular values as the cyclic
+    order and as LAPACK, at even and odd n (odd n: one dummy player sits out each round)."""
+    band = W.random_banded(n, 2, 3, seed=70 + n)
+    z = np.array([0.3 - 0.2j, 1.7 + 0.9j])
+    rr = oracle.sigma_min(band, z, all_sv=True, parallel_pairs=True, nthreads=4)
+    cy = oracle.sigma_min(band, z, all_sv=True, parallel_pairs=False)
+    A = W.to_dense(band)
+    for k, zz in enumerate(z):
+        ref = np.sort(np.linalg.svd(zz * np.eye(n) - A, compute_uv=False))
+        t = _tol(band, ref[-1])
+        assert np.max(np.abs(np.sort(rr["sall"][k]) - ref)) <= t
+        assert np.max(np.abs(np.sort(rr["sall"][k]) - np.sort(cy["sall"][k]))) <= t
+        assert abs(rr["sigma"][k] - ref[0]) <= _tol(band, ref[0])
+
+
+@pytest.mark.parametrize("n", [512, 513])
+def test_round_robin_order_large(n):
+    """At n >= 512 (where the round-robin order is the default for few shifts) against LAPACK
+    and, for a normal matrix, against the closed form dist(z, spectrum)."""
+    band = W.random_banded(n, 1, 2, seed=n)
+    z = np.array([0.4 + 0.1j])
+    rr = oracle.sigma_min(band, z, all_sv=True, nthreads=8)        # default order at this size
+    ref = np.sort(np.linalg.svd(z[0] * np.eye(n) - W.to_dense(band), compute_uv=False))
+    assert np.max(np.abs(np.sort(rr["sall"][0]) - ref)) <= _tol(band, ref[-1])
+    H = W.hermitian_toeplitz_tridiag(n, 0.1, 0.6 - 0.3j)
+    lam = 0.1 + 2 * abs(0.6 - 0.3j) * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    zz = np.array([0.05 + 0.02j, 1.5 - 0.4j])
+    s = oracle.sigma_min(H, zz, parallel_pairs=True, nthreads=8)["sigma"]
+    assert np.allclose(s, np.min(np.abs(zz[:, None] - lam[None]), axis=1), atol=_tol(H), rtol=0)
+
+
 # ----------------------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
@@ -484,6 +519,12 @@ MUTANTS = {
     "gamma_unconjugated": ("gamma += conj(mp[i]) * mq[i];", "gamma += mp[i] * mq[i];"),
     "u_unnormalised": ("u[r] = (smin > 0.0) ? M[r + imin * n] * ph / smin : 0.0;",
                        "u[r] = (smin > 0.0) ? M[r + imin * n] * ph : 0.0;"),
+    # the round-robin pair order: a dropped slot, a wrong rotation modulus, a real player
+    # treated as the dummy, a round missing
+    "rr_slot0_dropped": ("for (int64_t k = 0; k < m / 2; ++k) {", "for (int64_t k = 1; k < m / 2; ++k) {"),
+    "rr_mod_m": ("x = 1 + ((r + k) % (m - 1));", "x = 1 + ((r + k) % m);"),
+    "rr_last_player_skipped": ("if (b >= n)", "if (b >= n - 1)"),
+    "rr_round_missing": ("for (int64_t r = 0; r < m - 1; ++r) {", "for (int64_t r = 0; r < m - 2; ++r) {"),
 }
 
 
@@ -493,7 +534,7 @@ def _pin_suite_passes(lib):
     i64 = ctypes.c_int64
     lib.oracle_sigma_min.argtypes = [i64, i64, i64, P, i64, i64, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int]
 
-    def smin(band, z, vec=False):
+    def smin(band, z, vec=False, rr=0, sall=None):
         z = np.ascontiguousarray(np.asarray(z, dtype=complex))
         s = np.empty(z.size)
         u = np.empty((z.size, band.n), complex) if vec else None
@@ -502,7 +543,7 @@ def _pin_suite_passes(lib):
         ab = np.ascontiguousarray(band.ab)
         p = lambda a: None if a is None else a.ctypes.data_as(P)
         st = lib.oracle_sigma_min(band.n, band.kl, band.ku, p(ab), band.kl + band.ku + 1, z.size, p(z), p(s),
-                                  None, p(u), p(v), p(sw), 2, 0)
+                                  p(sall), p(u), p(v), p(sw), 2, rr)
         return st, s, u, v
 
     try:
@@ -529,6 +570,18 @@ def _pin_suite_passes(lib):
                 return False
             if np.linalg.norm(M @ v[k] - s[k] * u[k]) > 1e-10 or abs(np.linalg.norm(u[k]) - 1) > 1e-10:
                 return False
+        # the round-robin order, even and odd n: every singular value against LAPACK
+        for n in (10, 11):
+            band = W.random_banded(n, 1, 2, seed=n)
+            A = W.to_dense(band)
+            sall = np.empty((z.size, n))
+            st, s, _, _ = smin(band, z, rr=1, sall=sall)
+            if st:
+                return False
+            for k, zz in enumerate(z):
+                ref = np.sort(np.linalg.svd(zz * np.eye(n) - A, compute_uv=False))
+                if np.max(np.abs(np.sort(sall[k]) - ref)) > 1e-11 or abs(s[k] - ref[0]) > 1e-11:
+                    return False
         return True
     except Exception:
         return False
