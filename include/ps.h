@@ -99,8 +99,15 @@ typedef struct {
     int32_t bisect;       /* 0 (default): a shift where the rounding of (zI-A)^H (zI-A),
                              about 32 eps (|z| + ||A||)^2 / sigma in sigma, stays below an
                              eighth of the target gets sigma_min by bisection on Cholesky
-                             tests instead of Lanczos steps (sigma only, kl + ku >= 1);
+                             tests instead of Lanczos steps (kl + ku >= 1);
                              -1: every shift takes the Golub-Kahan path                  */
+    int32_t lanes;        /* sigma only: lanes of a wavefront that share one shift's
+                             bisection (0 = default 1; 1, 2, 4, or 64 = one wavefront per
+                             shift, the plain per-shift form; 64 is refused in batch mode) */
+    int32_t tests;        /* sigma only: tests per lane and bisection pass (0 = default 2;
+                             1: one; 2: three for kl + ku <= 2, two for <= 4, one above;
+                             3: two for kl + ku <= 6, one above).  A pass splits the bracket
+                             into lanes * tests + 1 parts.  Set by ps_autotune.            */
 } ps_opts;
 
 /* Fills *o with the defaults listed above. */

@@ -39,7 +39,7 @@ class ps_grid(ctypes.Structure):
 class ps_opts(ctypes.Structure):
     _fields_ = [("tol_norm", ctypes.c_double), ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("want_vectors", ctypes.c_int32), ("slots", ctypes.c_int32), ("check_shift", ctypes.c_int32),
-                ("bisect", ctypes.c_int32)]
+                ("bisect", ctypes.c_int32), ("lanes", ctypes.c_int32), ("tests", ctypes.c_int32)]
 
 
 class ps_mask_opts(ctypes.Structure):

@@ -38,10 +38,10 @@ def _stream_handle(stream=None) -> int:
 
 
 def make_opts(tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, want_vectors=False, slots=0, check_shift=0,
-              bisect=True):
+              bisect=True, lanes=0, tests=0):
     return ps_opts_default(tol_norm=tol_norm, tol_rel=tol_rel, max_iter=max_iter,
                            want_vectors=int(bool(want_vectors)), slots=int(slots), check_shift=int(check_shift),
-                           bisect=0 if bisect else -1)
+                           bisect=0 if bisect else -1, lanes=int(lanes), tests=int(tests))
 
 
 class BandedMatrix:
@@ -101,12 +101,12 @@ class BandedBatch:
             pass
 
     def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
-             device=None, stream=None, workspace: torch.Tensor | None = None):
+             device=None, stream=None, workspace: torch.Tensor | None = None, lanes=0, tests=0):
         """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None.  Returns dict with
         the concatenated idx, sigma, info, iters, and counts [nmat]; matrix m owns offsets[m] onward."""
         dev = device or torch.device("cuda")
         nmat = len(self.mats)
-        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect)
+        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect, lanes=lanes, tests=tests)
         keep = []
         mptr = 0
         if masks is not None:
@@ -155,14 +155,15 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_norm=1e-10, tol_rel=1e-8,
-              max_iter=3000, slots=0, bisect=True, workspace: torch.Tensor | None = None, stream=None):
+              max_iter=3000, slots=0, bisect=True, workspace: torch.Tensor | None = None, stream=None, lanes=0,
+              tests=0):
     """sigma_min(z_p I - A) for every entry of the complex128 CUDA tensor z.  Returns a dict
     with ``sigma`` (float64), ``info`` and ``iters`` (int32), and ``u``, ``v`` ([npts, n]) if asked."""
     assert z.is_cuda and z.dtype == torch.complex128
     z = z.contiguous()
     npts = z.numel()
     dev = z.device
-    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, bisect=bisect)
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, bisect=bisect, lanes=lanes, tests=tests)
     out = dict(sigma=torch.empty(npts, dtype=torch.float64, device=dev),
                info=torch.empty(npts, dtype=torch.int32, device=dev),
                iters=torch.empty(npts, dtype=torch.int32, device=dev))
@@ -181,14 +182,14 @@ def sigma_min(mat: BandedMatrix, z: torch.Tensor, *, want_vectors=False, tol_nor
 
 def eval_grid(mat: BandedMatrix, grid, mask: torch.Tensor | None = None, *, eps=None, want_vectors=False,
               tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True, device=None, stream=None,
-              workspace: torch.Tensor | None = None):
+              workspace: torch.Tensor | None = None, lanes=0, tests=0):
     """sigma_min on the grid (a, b, c, d, nx, ny) of Sec. 2.1, or on the points where ``mask`` (uint8
     [ny, nx] CUDA tensor) is nonzero.  Outputs are compacted: entry p belongs to flat grid index
     ``idx[p]``, for p < ``count``."""
     g = ps_grid(float(grid.a), float(grid.b), float(grid.c), float(grid.d), int(grid.nx), int(grid.ny))
     npts = g.nx * g.ny
     dev = mask.device if mask is not None else (device or torch.device("cuda"))
-    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, bisect=bisect)
+    o = make_opts(tol_norm, tol_rel, max_iter, want_vectors, slots, bisect=bisect, lanes=lanes, tests=tests)
     out = dict(idx=torch.empty(npts, dtype=torch.int64, device=dev),
                count=torch.zeros(1, dtype=torch.int64, device=dev),
                sigma=torch.empty(npts, dtype=torch.float64, device=dev),

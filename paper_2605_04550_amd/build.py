@@ -12,11 +12,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libps.so")
-SOURCES = ["ps_kernels.hip", "ps_mask.hip", "ps_api.cpp"] + ["ps_eval_kl%d.hip" % k for k in range(5)]
+SOURCES = (["ps_kernels.hip", "ps_mask.hip", "ps_api.cpp", "ps_bisect.hip"] + ["ps_eval_kl%d.hip" % k for k in range(5)]
+           + ["ps_bis_h%d.hip" % h for h in range(1, 9)])
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
-    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=" + ARCH, "-O3", "-std=c++20", "-fPIC",
     # no packed-FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),

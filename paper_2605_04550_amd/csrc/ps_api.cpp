@@ -28,6 +28,8 @@ struct ps_matrix_s {
     double norm2;    // sqrt(||A||_1 ||A||_inf) >= ||A||_2
     double2 *arow;   // device, [n][kl+ku+1] rows 0 .. n-1 of the band
     double2 *abase;  // the allocation: kBandPadTop zero rows, the band, kBandPadBottom zero rows
+    double *gram;    // device, the Gram band read by the bisection kernel (kl + ku >= 1)
+    ps::SideStream side;   // second stream for the Golub-Kahan launch beside the bisection
     int device;
 };
 
@@ -76,10 +78,19 @@ ps_status check_opts(const ps_opts &o) {
     if (o.slots < 0) return fail(PS_ERR_INVALID, "slots must be >= 0");
     if (o.check_shift < 0 || o.check_shift > 12) return fail(PS_ERR_INVALID, "check_shift must be in [0, 12]");
     if (o.bisect != 0 && o.bisect != -1) return fail(PS_ERR_INVALID, "bisect must be 0 or -1");
+    if (o.lanes != 0 && o.lanes != 1 && o.lanes != 2 && o.lanes != 4 && o.lanes != 64)
+        return fail(PS_ERR_INVALID, "lanes must be 0, 1, 2, 4 or 64");
+    if (o.tests < 0 || o.tests > 3) return fail(PS_ERR_INVALID, "tests must be in [0, 3]");
     return PS_OK;
 }
 
 int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
+
+// Lanes per shift of the bisection kernel (default 1) and its test-count mode: tests 1 -> one
+// test per lane and pass; 0 and 2 -> three for kl + ku <= 2, two for <= 4, one above; 3 -> two
+// for kl + ku <= 6, one above.
+int lanes_of(const ps_opts &o) { return o.lanes > 0 ? o.lanes : 1; }
+int ktm_of(const ps_opts &o) { return o.tests == 1 ? 0 : o.tests == 3 ? 2 : 1; }
 
 // 1: shifts that qualify take the inertia bisection; 0: every shift takes Golub-Kahan.
 int bisect_of(const ps_opts &o) { return o.bisect < 0 ? 0 : 1; }
@@ -116,6 +127,22 @@ int64_t slots_for(const ps_matrix_s *m, int64_t npts, const ps_opts &o, size_t w
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// A non-blocking stream at the default priority and its fork and join events (no timing).
+hipError_t create_side(ps::SideStream *s) {
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+    return e;
+}
+
+void destroy_side(ps::SideStream *s) {
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->fork) (void)hipEventDestroy(s->fork);
+    if (s->join) (void)hipEventDestroy(s->join);
+    s->stream = nullptr;
+    s->fork = s->join = nullptr;
+}
+
 ps_status check_grid(const ps_grid *g) {
     if (!g) return fail(PS_ERR_INVALID, "grid is NULL");
     if (g->nx < 1 || g->ny < 1) return fail(PS_ERR_INVALID, "grid needs nx, ny >= 1");
@@ -149,6 +176,9 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     a->normA = m->fro;
     a->norm2A = m->norm2;
     a->bisect = bisect_of(o);
+    a->gram = m->gram;
+    a->lanes = lanes_of(o);
+    a->ktm = ktm_of(o);
     a->tol_norm = o.tol_norm;
     a->tol_rel = o.tol_rel;
     a->max_iter = o.max_iter;
@@ -174,6 +204,8 @@ void ps_opts_default(ps_opts *o) {
     o->slots = 0;
     o->check_shift = 0;
     o->bisect = 0;
+    o->lanes = 0;
+    o->tests = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -490,6 +522,8 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
     m->norm2 = sqrt(rowmax * colmax);
     m->arow = nullptr;
     m->abase = nullptr;
+    m->gram = nullptr;
+    m->side = ps::SideStream();
     (void)hipGetDevice(&m->device);
     // zero rows around the band: kernels may read rows -kBandPadTop .. n + kBandPadBottom - 1
     const size_t padded = (size_t)(ps::kBandPadTop + n + ps::kBandPadBottom) * (size_t)w;
@@ -502,9 +536,17 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
     }
     m->arow = m->abase + (size_t)ps::kBandPadTop * (size_t)w;
     e = hipMemcpyAsync(m->abase, store.data(), sizeof(double2) * padded, hipMemcpyHostToDevice, st);
+    // the Gram band of the bisection kernel (computed on the device from the uploaded band)
+    if (e == hipSuccess && kl + ku >= 1) {
+        e = hipMalloc((void **)&m->gram, ps::gram_bytes(n, kl, ku));
+        if (e == hipSuccess) e = ps::launch_gram_band(m->arow, n, kl, ku, m->gram, st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = create_side(&m->side);
     if (e != hipSuccess) {
         (void)hipFree(m->abase);
+        if (m->gram) (void)hipFree(m->gram);
+        destroy_side(&m->side);
         delete m;
         return fail(PS_ERR_HIP, "band upload: %s", hipGetErrorString(e));
     }
@@ -515,6 +557,8 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
 ps_status ps_destroy(ps_matrix m) {
     if (!m) return ok();
     if (m->abase) (void)hipFree(m->abase);
+    if (m->gram) (void)hipFree(m->gram);
+    destroy_side(&m->side);
     delete m;
     return ok();
 }
@@ -560,7 +604,7 @@ ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const 
     a.iters = iters_dev;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
-    HIP_TRY(ps::launch_eval(a, w, s));
+    HIP_TRY(ps::launch_eval(a, w, s, &m->side));
     return ok();
 }
 
@@ -601,7 +645,7 @@ ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, c
     }
     a.count_dev = w.count;
     HIP_TRY(hipMemcpyAsync(count_dev, w.count, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(ps::launch_eval(a, w, s));
+    HIP_TRY(ps::launch_eval(a, w, s, &m->side));
     return ok();
 }
 
@@ -651,35 +695,81 @@ struct ps_batch_s {
     int64_t max_npts = 0;
     ps::MatDesc *desc_caller = nullptr;   // device, caller order
     ps::MatDesc *desc_class = nullptr;    // device, grouped by (kl, ku), larger n first
+    ps::MatDesc *desc_lpt = nullptr;      // device, longest-first by predicted bisection cost
+    static constexpr int kSides = 4;      // streams for the per-class Golub-Kahan launches
+    ps::SideStream side[kSides];
+    int max_hb = 0;                       // largest kl + ku
+    int64_t lpt_chunks[3] = {0, 0, 0};    // chunks of 64, 32, 16 shifts over the full grids
     struct Cls {
         int kl, ku, begin, count;
         int64_t nmax, npts;
+        int64_t gkbase;   // offset of the class's Golub-Kahan list in the batch scratch
     };
     std::vector<Cls> classes;
 };
 
 namespace {
 
-int64_t class_slots(const ps_batch_s::Cls &c, const ps_opts &o) {
-    int64_t want = ((c.npts + kSlotQuantum - 1) / kSlotQuantum) * kSlotQuantum;
+// Slots of one class's Golub-Kahan launch.  The classes run concurrently, so each has its own
+// workspace within an equal share of the default budget.  A class that bisects hands only the
+// shifts below the bisection's rounding limit to this launch (a few per cent on the measured
+// workloads): an eighth of its shifts, at least 256, get a slot of their own; lanes take
+// further shifts as they finish.
+int64_t class_slots(const ps_batch_s::Cls &c, const ps_opts &o, bool bis, size_t nclass) {
+    int64_t need = bis && c.kl + c.ku >= 1 ? (c.npts + 7) / 8 : c.npts;
+    int64_t want = ((need + kSlotQuantum - 1) / kSlotQuantum) * kSlotQuantum;
     if (o.slots > 0) want = round_slots(o.slots);
     if (want < kSlotQuantum) want = kSlotQuantum;
     if (want > kMaxSlots) want = kMaxSlots;
+    const double budget = kDefaultWsBudget / (double)(nclass > 0 ? nclass : 1);
     while (want > kSlotQuantum &&
-           (double)ps::workspace_bytes(c.nmax, c.kl, c.ku, want, o.max_iter, 0, c.npts) > kDefaultWsBudget)
+           (double)ps::workspace_bytes(c.nmax, c.kl, c.ku, want, o.max_iter, 0, 0) > budget)
         want -= kSlotQuantum;
     return want;
 }
 
-size_t batch_scratch_bytes(const ps_batch_s *b) {
+size_t class_ws_bytes(const ps_batch_s::Cls &c, const ps_opts &o, bool bis, size_t nclass) {
+    const size_t b = ps::workspace_bytes(c.nmax, c.kl, c.ku, class_slots(c, o, bis, nclass), o.max_iter, 0, 0);
+    return (b + 255) & ~(size_t)255;
+}
+
+// Batch scratch, 256-byte aligned pieces: compaction tile sums [tiles * nmat], then
+// mfirst, pfx, chunkfirst [nmat], ctotal, gk_count [classes], the chunk total, and the
+// Golub-Kahan lists [total points].
+struct BatchScratch {
+    int64_t *tilesums, *mfirst, *pfx, *chunkfirst, *ctotal, *gk_count, *total_chunks, *gk_list;
+    double *st_lo, *st_hi;
+    int32_t *st_np;
+    size_t bytes;
+};
+
+BatchScratch batch_scratch(const ps_batch_s *b, char *base) {
     int64_t nt = ps::batch_tiles(b->max_npts);
     if (nt < 1) nt = 1;
-    size_t a = sizeof(int64_t) * (size_t)(nt * b->nmat);
-    a = (a + 255) & ~(size_t)255;
-    size_t f = sizeof(int64_t) * (size_t)b->nmat;
-    f = (f + 255) & ~(size_t)255;
-    return a + f;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> int64_t * {
+        int64_t *p = (int64_t *)(base + off);
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const size_t nm = sizeof(int64_t) * (size_t)b->nmat, nc = sizeof(int64_t) * b->classes.size();
+    BatchScratch r;
+    r.tilesums = take(sizeof(int64_t) * (size_t)(nt * b->nmat));
+    r.mfirst = take(nm);
+    r.pfx = take(nm);
+    r.chunkfirst = take(nm);
+    r.ctotal = take(nc);
+    r.gk_count = take(nc);
+    r.total_chunks = take(sizeof(int64_t));
+    r.gk_list = take(sizeof(int64_t) * (size_t)b->total);
+    r.st_lo = (double *)take(sizeof(double) * (size_t)b->total);
+    r.st_hi = (double *)take(sizeof(double) * (size_t)b->total);
+    r.st_np = (int32_t *)take(sizeof(int32_t) * (size_t)b->total);
+    r.bytes = off;
+    return r;
 }
+
+size_t batch_scratch_bytes(const ps_batch_s *b) { return batch_scratch(b, nullptr).bytes; }
 
 }  // namespace
 
@@ -751,7 +841,7 @@ ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts
         const int64_t lattice = ((g->ny + stride - 1) / stride) * ((g->nx + stride - 1) / stride);
         HIP_TRY(ps::launch_label_mask(status, g->nx, npts, stride, mask, s));
         HIP_TRY(ps::launch_compact_mask(mask, npts, idx, w.count, w.blocksums, w.queue, s));
-        HIP_TRY(ps::launch_eval(a, w, s));
+        HIP_TRY(ps::launch_eval(a, w, s, &m->side));
         HIP_TRY(ps::launch_label_update(g->a, g->b, g->c, g->d, g->nx, g->ny, idx, w.count, lattice, sig_c, eps,
                                         r.tol_norm * m->fro, r.tol_rel, status, sigma_dev, evals, s));
     }
@@ -1016,6 +1106,7 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         }
         ps::MatDesc d;
         d.arow = a->arow;
+        d.gram = a->gram;
         d.n = a->n;
         d.normA = a->fro;
         d.norm2A = a->norm2;
@@ -1029,8 +1120,12 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         d.kl = a->kl;
         d.ku = a->ku;
         d.cidx = m;
-        d.pad = 0;
+        d.cls = 0;
+        d.cpos = 0;
+        d.cfirst = 0;
+        d.gkbase = 0;
         dc[(size_t)m] = d;
+        b->max_hb = std::max(b->max_hb, a->kl + a->ku);
         b->grids.push_back(g);
         b->off.push_back(b->total);
         b->npts.push_back(g.nx * g.ny);
@@ -1059,12 +1154,45 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         }
         b->classes.push_back(c);
     }
+    // class of every matrix, its class-sorted position, the first matrix of its class, and the
+    // offset of its class's Golub-Kahan list (classes in order, each sized by its grid points)
+    int64_t gkbase = 0;
+    for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+        auto &c = b->classes[ci];
+        c.gkbase = gkbase;
+        for (int p = c.begin; p < c.begin + c.count; ++p) {
+            dk[(size_t)p].cls = (int32_t)ci;
+            dk[(size_t)p].cpos = p;
+            dk[(size_t)p].cfirst = c.begin;
+            dk[(size_t)p].gkbase = gkbase;
+            dc[(size_t)dk[(size_t)p].cidx] = dk[(size_t)p];
+        }
+        gkbase += c.npts;
+    }
+    // longest-first order of the bisection chunks: predicted cost per shift ~ n times the work
+    // of one row of a pass (forming the row of H and one test)
+    std::vector<ps::MatDesc> dl = dk;
+    auto cost = [](const ps::MatDesc &x) {
+        const double hb = (double)(x.kl + x.ku);
+        return (double)x.n * (2.0 * hb * hb + 8.0 * hb + 8.0);
+    };
+    std::stable_sort(dl.begin(), dl.end(),
+                     [&](const ps::MatDesc &x, const ps::MatDesc &y) { return cost(x) > cost(y); });
+    for (int k = 0; k < 3; ++k) {
+        const int64_t spw = 64 >> k;
+        for (const auto &d : dl) b->lpt_chunks[k] += (d.nx * d.ny + spw - 1) / spw;
+    }
     hipError_t e = hipMalloc((void **)&b->desc_caller, sizeof(ps::MatDesc) * (size_t)nmat);
     if (e == hipSuccess) e = hipMalloc((void **)&b->desc_class, sizeof(ps::MatDesc) * (size_t)nmat);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->desc_lpt, sizeof(ps::MatDesc) * (size_t)nmat);
     if (e == hipSuccess)
         e = hipMemcpy(b->desc_caller, dc.data(), sizeof(ps::MatDesc) * (size_t)nmat, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->desc_class, dk.data(), sizeof(ps::MatDesc) * (size_t)nmat, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->desc_lpt, dl.data(), sizeof(ps::MatDesc) * (size_t)nmat, hipMemcpyHostToDevice);
+    for (auto &sd : b->side)
+        if (e == hipSuccess) e = create_side(&sd);
     if (e != hipSuccess) {
         ps_destroy_batch(b);
         return fail(PS_ERR_HIP, "batch descriptors: %s", hipGetErrorString(e));
@@ -1077,6 +1205,8 @@ ps_status ps_destroy_batch(ps_batch b) {
     if (!b) return ok();
     if (b->desc_caller) (void)hipFree(b->desc_caller);
     if (b->desc_class) (void)hipFree(b->desc_class);
+    if (b->desc_lpt) (void)hipFree(b->desc_lpt);
+    for (auto &sd : b->side) destroy_side(&sd);
     delete b;
     return ok();
 }
@@ -1095,34 +1225,87 @@ ps_status ps_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes) {
     ps_opts r = resolve(o);
     ps_status st;
     if ((st = check_opts(r))) return st;
-    size_t mx = 0;
-    for (const auto &c : b->classes) {
-        int64_t sl = class_slots(c, r);
-        mx = std::max(mx, ps::workspace_bytes(c.nmax, c.kl, c.ku, sl, r.max_iter, 0, c.npts));
-    }
-    *bytes = batch_scratch_bytes(b) + mx;
+    const bool bis = bisect_of(r) && b->max_hb >= 1;
+    size_t sum = 0;
+    for (const auto &c : b->classes) sum += class_ws_bytes(c, r, bis, b->classes.size());
+    *bytes = batch_scratch_bytes(b) + sum;
     return ok();
 }
 
-// Compaction of the masks and one persistent launch per (kl, ku) class; evbase holds the
-// evaluation workspace (past the batch scratch).
+// Compaction of the masks, the plan (queue positions per (kl, ku) class, longest-first chunk
+// order), the bisection's first pass over every shift of every matrix, then at once: the
+// bisection resumed on the caller's stream, and one Golub-Kahan launch per class over the
+// shifts the first pass handed over (all shifts of a class that does not bisect) on the side
+// streams, longest classes first, each class with its own workspace past the batch scratch.
 static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, const ps_opts &r, char *base,
                                  int64_t *idx_dev, int64_t *counts_dev, double *sigma_dev, int32_t *info_dev,
                                  int32_t *iters_dev, hipStream_t s) {
-    int64_t nt = ps::batch_tiles(b->max_npts);
-    if (nt < 1) nt = 1;
-    int64_t *tilesums = (int64_t *)base;
-    size_t a0 = ((sizeof(int64_t) * (size_t)(nt * b->nmat)) + 255) & ~(size_t)255;
-    int64_t *mfirst = (int64_t *)(base + a0);
-    char *evbase = base + batch_scratch_bytes(b);
-    HIP_TRY(ps::launch_batch_compact(b->desc_caller, b->nmat, b->max_npts, masks_dev, idx_dev, counts_dev, tilesums,
-                                     s));
-    for (const auto &c : b->classes) {
+    const BatchScratch bs = batch_scratch(b, base);
+    const int lanes = lanes_of(r);
+    const bool bis = bisect_of(r) && b->max_hb >= 1;
+    const size_t ncls = b->classes.size();
+    HIP_TRY(ps::launch_batch_compact(b->desc_caller, b->nmat, b->max_npts, masks_dev, idx_dev, counts_dev,
+                                     bs.tilesums, s));
+    HIP_TRY(ps::launch_bis_plan(b->desc_class, b->desc_lpt, b->nmat, (int)ncls, counts_dev, 64 / lanes, bs.pfx,
+                                bs.mfirst, bs.ctotal, bs.chunkfirst, bs.total_chunks, bs.gk_count, s));
+    ps::BisArgs ba;
+    const int64_t chunks = b->lpt_chunks[lanes == 1 ? 0 : lanes == 2 ? 1 : 2];
+    if (bis) {
+        ba.batch = 1;
+        ba.mats = b->desc_lpt;
+        ba.nmat = b->nmat;
+        ba.chunkfirst = bs.chunkfirst;
+        ba.total_chunks = bs.total_chunks;
+        ba.counts = counts_dev;
+        ba.mfirst = bs.mfirst;
+        ba.idx = idx_dev;
+        ba.tol_norm = r.tol_norm;
+        ba.tol_rel = r.tol_rel;
+        ba.sigma = sigma_dev;
+        ba.info = info_dev;
+        ba.iters = iters_dev;
+        ba.gk_list = bs.gk_list;
+        ba.gk_count = bs.gk_count;
+        ba.st_lo = bs.st_lo;
+        ba.st_hi = bs.st_hi;
+        ba.st_np = bs.st_np;
+        ba.phase = 1;
+        HIP_TRY(ps::launch_bis(ba, b->max_hb, ktm_of(r), lanes, chunks, s));
+    }
+    // the class launches: largest predicted Golub-Kahan time first, each on the side stream
+    // that has the least predicted work so far
+    std::vector<size_t> order(ncls);
+    std::vector<double> est(ncls);
+    for (size_t ci = 0; ci < ncls; ++ci) {
+        const auto &c = b->classes[ci];
+        order[ci] = ci;
+        est[ci] = (double)c.nmax * (double)((c.kl + 1) * (c.kl + c.ku + 1)) * (double)c.count;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return est[x] > est[y]; });
+    double load[ps_batch_s::kSides] = {0.0, 0.0, 0.0, 0.0};
+    bool used[ps_batch_s::kSides] = {false, false, false, false};
+    HIP_TRY(hipEventRecord(b->side[0].fork, s));
+    std::vector<size_t> wsoff(ncls);
+    size_t off = bs.bytes;
+    for (size_t ci = 0; ci < ncls; ++ci) {
+        wsoff[ci] = off;
+        off += class_ws_bytes(b->classes[ci], r, bis, ncls);
+    }
+    for (size_t oi = 0; oi < ncls; ++oi) {
+        const size_t ci = order[oi];
+        const auto &c = b->classes[ci];
+        int q = 0;
+        for (int k = 1; k < ps_batch_s::kSides; ++k)
+            if (load[k] < load[q]) q = k;
+        load[q] += est[ci];
+        hipStream_t sq = b->side[q].stream;
+        if (!used[q]) {
+            HIP_TRY(hipStreamWaitEvent(sq, b->side[0].fork, 0));
+            used[q] = true;
+        }
         ps::Workspace w;
-        int64_t sl = class_slots(c, r);
-        ps::carve_workspace(evbase, c.nmax, c.kl, c.ku, sl, r.max_iter, 0, c.npts, &w);
-        HIP_TRY(ps::launch_batch_prefix(b->desc_class + c.begin, counts_dev, c.count, mfirst + c.begin, w.count,
-                                        w.queue, s));
+        ps::carve_workspace(base + wsoff[ci], c.nmax, c.kl, c.ku, class_slots(c, r, bis, ncls), r.max_iter, 0, 0,
+                            &w);
         ps::EvalArgs a;
         a.n = c.nmax;
         a.kl = c.kl;
@@ -1131,20 +1314,31 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
         a.normA = 0.0;
         a.mode = ps::kShiftGrid;
         a.idx = idx_dev;
-        a.count_dev = w.count;
+        const bool handed = bis && c.kl + c.ku >= 1;
+        a.perm = handed ? bs.gk_list + c.gkbase : nullptr;
+        a.count_dev = handed ? bs.gk_count + ci : bs.ctotal + ci;
         a.tol_norm = r.tol_norm;
         a.tol_rel = r.tol_rel;
         a.max_iter = r.max_iter;
         a.check_shift = check_shift_of(r);
-        a.bisect = bisect_of(r);
+        a.bisect = 0;
         a.want_vectors = 0;
         a.sigma = sigma_dev;
         a.info = info_dev;
         a.iters = iters_dev;
         a.mats = b->desc_class + c.begin;
         a.nmat = c.count;
-        a.mfirst = mfirst + c.begin;
-        HIP_TRY(ps::launch_eval_batch(a, w, c.kl, c.ku, s));
+        a.mfirst = bs.mfirst + c.begin;
+        HIP_TRY(ps::launch_eval_batch_gk(a, w, c.kl, c.ku, sq));
+    }
+    if (bis) {
+        ba.phase = 2;
+        HIP_TRY(ps::launch_bis(ba, b->max_hb, ktm_of(r), lanes, chunks, s));
+    }
+    for (int q = 0; q < ps_batch_s::kSides; ++q) {
+        if (!used[q]) continue;
+        HIP_TRY(hipEventRecord(b->side[q].join, b->side[q].stream));
+        HIP_TRY(hipStreamWaitEvent(s, b->side[q].join, 0));
     }
     return ok();
 }

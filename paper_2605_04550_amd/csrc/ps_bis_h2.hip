@@ -1,0 +1,36 @@
+// Inertia-bisection kernel instantiations for half-bandwidth 2 (one matrix), and for batches
+// whose largest half-bandwidth is 2 (even bounds only); one file per bound so that they
+// compile in parallel.
+#include "ps_bisect.hpp"
+
+namespace ps {
+
+namespace {
+
+template <int LO, int HI, bool SINGLE>
+BisKernel pick_range(int ktm, int lanes) {
+    switch (ktm * 100 + lanes) {
+    case 1: return bis::k_bis<LO, HI, 0, 1>;
+    case 2: return bis::k_bis<LO, HI, 0, 2>;
+    case 4: return bis::k_bis<LO, HI, 0, 4>;
+    case 101: return bis::k_bis<LO, HI, 1, 1>;
+    case 102: return bis::k_bis<LO, HI, 1, 2>;
+    case 104: return bis::k_bis<LO, HI, 1, 4>;
+    case 201: return bis::k_bis<LO, HI, 2, 1>;
+    case 202: return bis::k_bis<LO, HI, 2, 2>;
+    case 204: return bis::k_bis<LO, HI, 2, 4>;
+    case 64:
+        if constexpr (SINGLE) return bis::k_bis<LO, HI, 0, 64>;
+        return nullptr;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+BisKernel pick_bis_h2(bool batch, int ktm, int lanes) {
+    if (batch) return pick_range<1, 2, false>(ktm, lanes);
+    return pick_range<2, 2, true>(ktm, lanes);
+}
+
+}  // namespace ps

@@ -892,7 +892,9 @@ struct Kern {
     // whether the shift qualifies; if H - sigma_adm^2 I is not positive definite the shift takes
     // the Golub-Kahan path instead, which has no such limit (it never forms H).  With sigma_min
     // above sigma_adm nothing overflows or underflows, so the passes use plain doubles.
-    static constexpr bool BIS = (KL + KU) >= 1;
+    // Sigma-only calls bisect in their own kernel (ps_bisect.hpp); this one keeps the
+    // bisection for calls with singular vectors, which need its factor afterwards.
+    static constexpr bool BIS = VEC && (KL + KU) >= 1;
     static constexpr int HB = KL + KU;          // half-bandwidth of H
     static constexpr int kBisMaxPass = 128;     // far above the ~30-40 passes a shift needs
 
@@ -1591,33 +1593,6 @@ struct Kern {
         }
     }
 
-    // Classification pass (one thread per shift position, before the persistent launch):
-    // the first bisection pass of every shift that may qualify.  pcls[id] = 1: continue the
-    // bisection from the bracket stored in pbr; 2: finished already (outputs written);
-    // 0: the Golub-Kahan path.  Sorting the queue by this class gives wavefronts that run
-    // only one kind of work, instead of Golub-Kahan sweeps and bisection passes in turn.
-    static __device__ void classify(const EvalArgs &a, const Workspace &w) {
-        const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (id >= *a.count_dev) return;
-        Lane ln;
-        ln.n = a.n;
-        ln.arow = a.arow;
-        ln.normA = a.normA;
-        ln.norm2A = a.norm2A;
-        ln.active = true;
-        ln.blo = ln.bhi = 0.0;
-        locate(a, id, ln);
-        bis_begin(a, ln);
-        uint8_t c = 0;
-        if (ln.phase == 1) {
-            bis_cycle(a, ln);
-            c = !ln.active ? 2 : ln.phase == 1 ? 1 : 0;
-        }
-        w.pcls[id] = c;
-        w.pbr[2 * id] = ln.blo;
-        w.pbr[2 * id + 1] = ln.bhi;
-    }
-
     // The workspace is laid out [wavefront][row][component][lane]: the 64 lanes of a
     // wavefront touch one contiguous 1 KiB (complex) segment per access, and a chunk of
     // consecutive rows of one wavefront is contiguous as well.  Each lane works on a view
@@ -1694,12 +1669,8 @@ struct Kern {
                 if ((int64_t)id >= npts) {
                     ln.exhausted = true;
                 } else {
-                    // queue position -> shift position (classified launches take the shifts in
-                    // the order bisection first, Golub-Kahan after)
+                    // queue position (the shifts the bisection kernel handed over, or all)
                     const int64_t qid = a.perm ? a.perm[id] : (int64_t)id;
-                    // -1: padding of a classified queue.  The lane retires instead of taking
-                    // the next position, which would put Golub-Kahan work into a wavefront of
-                    // bisection lanes.
                     ln.active = qid >= 0;
                     ln.exhausted = qid < 0;
                     ln.fresh = true;
@@ -1710,19 +1681,7 @@ struct Kern {
                     ln.b_m = 0.0;
                     ln.b_e = 0;
                     locate(a, qid >= 0 ? qid : 0, ln);
-                    if (ln.active) {
-                        if (!VEC && a.perm) {
-                            // the classification pass already ran this shift's first test
-                            const uint8_t c = a.pcls[qid];
-                            ln.phase = c == 1 ? 1 : 0;
-                            ln.nbis = 1;
-                            ln.blo = a.pbr[2 * qid];
-                            ln.bhi = a.pbr[2 * qid + 1];
-                            if (c == 2) ln.active = false;   // finished by that pass
-                        } else {
-                            bis_begin(a, ln);
-                        }
-                    }
+                    if (ln.active) bis_begin(a, ln);   // (sigma only: the Golub-Kahan path)
                 }
             }
             if (__all(!ln.active && ln.exhausted)) break;
@@ -1731,13 +1690,8 @@ struct Kern {
             double acc;
             int eacc;
             if (!VEC) {
-                // Lanes in the bisection take one pass per cycle (a fresh lane's first pass
-                // decides whether it stays there); Golub-Kahan lanes take the four sweeps.
-                // Each part runs only if a lane of the wavefront needs it.
-                if (BIS && __any(ln.active && !gk(ln))) {
-                    if (ln.active && !gk(ln)) bis_cycle(a, ln);
-                }
-                if (__any(ln.active && gk(ln))) {
+                // Sigma only: every lane is on the Golub-Kahan path (four sweeps per cycle).
+                if (__any(ln.active)) {
                     sweep_f1(a, w, s, ln);
                     if (ln.active && gk(ln) && ln.sing) finish(a, w, s, ln, 0);
                     sweep_b1(a, w, s, ln, acc, eacc);
@@ -1799,26 +1753,15 @@ __global__ void __launch_bounds__(kEvalBlock) k_eval(EvalArgs a, Workspace w) {
     Kern<KL, KU, VEC, BATCH>::run(a, w);
 }
 
-// Threads per block of the classification pass (plain data-parallel: one shift per thread).
-constexpr int kClassifyBlock = 256;
-
-template <int KL, int KU, bool BATCH>
-__global__ void __launch_bounds__(kClassifyBlock) k_classify(EvalArgs a, Workspace w) {
-    Kern<KL, KU, false, BATCH>::classify(a, w);
-}
-
 typedef void (*EvalKernel)(EvalArgs, Workspace);
 
-// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only;
-// 3: classification pass of mode 0; 4: classification pass of mode 2
+// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only
 template <int KL, int KU>
 EvalKernel pick_mode(int mode) {
     switch (mode) {
     case 0: return k_eval<KL, KU, false, false>;
     case 1: return k_eval<KL, KU, true, false>;
     case 2: return k_eval<KL, KU, false, true>;
-    case 3: return k_classify<KL, KU, false>;
-    case 4: return k_classify<KL, KU, true>;
     }
     return nullptr;
 }

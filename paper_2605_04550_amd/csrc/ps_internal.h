@@ -52,12 +52,13 @@ struct Workspace {
     unsigned long long *queue = nullptr;   // shift counter of the persistent launch
     int64_t *count = nullptr;      // number of shifts (device)
     int64_t *blocksums = nullptr;  // mask compaction scratch
-    // Classification of the shifts before a sigma-only launch (allocated when npts_max > 0):
-    uint8_t *pcls = nullptr;       // [npts_max] 0 Golub-Kahan, 1 bisection, 2 finished
-    double *pbr = nullptr;         // [npts_max][2] bisection bracket after the first pass
-    int64_t *perm = nullptr;       // [npts_max + 64] queue position -> shift position (-1: none)
-    int64_t *ptiles = nullptr;     // scan scratch of the partition
-    int64_t *pn1 = nullptr;        // [2] shifts of classes 1 and 2, length of the sorted queue
+    // Sigma-only calls: the queue positions the inertia bisection hands to the Golub-Kahan
+    // kernel (allocated when npts_max > 0 and no vectors are wanted).
+    int64_t *gk_list = nullptr;    // [npts_max]
+    int64_t *gk_count = nullptr;   // [1]
+    double *st_lo = nullptr;       // [npts_max] brackets saved between the two bisection launches
+    double *st_hi = nullptr;
+    int32_t *st_np = nullptr;
     int64_t npts_max = 0;
     int kmax = 0;
     int vec = 0;                   // 1: singular vectors wanted
@@ -68,6 +69,7 @@ struct Workspace {
 // concatenated output arrays.
 struct MatDesc {
     const double2 *arow;
+    const double *gram;   // Gram band of the matrix (see the bisection kernel)
     int64_t n;
     double normA;
     double norm2A;    // upper bound on ||A||_2
@@ -76,7 +78,10 @@ struct MatDesc {
     int64_t out_off;
     int32_t kl, ku;
     int32_t cidx;     // position of the matrix in the caller's order
-    int32_t pad;
+    int32_t cls;      // its (kl, ku) class
+    int64_t cpos;     // its position in the class-sorted order
+    int64_t cfirst;   // class-sorted position of the first matrix of its class
+    int64_t gkbase;   // offset of its class's Golub-Kahan list
 };
 
 struct EvalArgs {
@@ -86,9 +91,10 @@ struct EvalArgs {
     double normA = 0.0;            // ||A||_F
     double norm2A = 0.0;           // upper bound on ||A||_2 (sqrt(||A||_1 ||A||_inf))
     int bisect = 1;                // 1: shifts that qualify take the inertia bisection
-    const int64_t *perm = nullptr; // queue position -> shift position (classified launches)
-    const uint8_t *pcls = nullptr; // class of each shift position
-    const double *pbr = nullptr;   // bisection bracket of each shift position
+    const double *gram = nullptr;  // Gram band (sigma-only bisection)
+    int lanes = 1;                 // lanes per shift of the bisection kernel (1, 2, 4, 64)
+    int ktm = 1;                   // its test-count mode (tests_per_lane)
+    const int64_t *perm = nullptr; // queue position -> shift position (the bisection's hand-off)
     int mode = kShiftList;
     const double2 *z = nullptr;
     const int64_t *idx = nullptr;
@@ -113,6 +119,51 @@ struct EvalArgs {
     const int64_t *mfirst = nullptr;   // device: first queue position of each matrix
 };
 
+// Arguments of the inertia-bisection kernel (sigma only): one matrix (batch == 0) or the
+// chunks of a batch in longest-first order.
+struct BisArgs {
+    int batch = 0;
+    const double *gram = nullptr;
+    int64_t n = 0;
+    int hb = 0;
+    double normA = 0.0, norm2A = 0.0;
+    int mode = kShiftList;
+    const double2 *z = nullptr;
+    const int64_t *idx = nullptr;
+    double ga = 0, gb = 0, gc = 0, gd = 0;
+    int64_t nx = 1, ny = 1;
+    const int64_t *count_dev = nullptr;
+    const MatDesc *mats = nullptr;          // batch: longest-first order
+    int nmat = 0;
+    const int64_t *chunkfirst = nullptr;    // [nmat] first chunk of each matrix
+    const int64_t *total_chunks = nullptr;
+    const int64_t *counts = nullptr;        // [nmat] shifts per matrix (caller order)
+    const int64_t *mfirst = nullptr;        // [nmat] class-relative queue position (class order)
+    double tol_norm = 1e-10, tol_rel = 1e-8;
+    double *sigma = nullptr;
+    int32_t *info = nullptr;
+    int32_t *iters = nullptr;
+    double eps = 0.0;
+    uint8_t *sens = nullptr;
+    int64_t *gk_list = nullptr;             // batch: base of all class lists
+    int64_t *gk_count = nullptr;            // batch: one per class
+    // 0: every pass in one launch; 1: first pass only, saving the bracket of every shift that
+    // goes on (and handing over or finishing the others); 2: resume from the saved brackets
+    int phase = 0;
+    double *st_lo = nullptr, *st_hi = nullptr;   // saved brackets (queue position, or output
+    int32_t *st_np = nullptr;                    // position in a batch); passes, -1 = settled
+};
+
+size_t gram_bytes(int64_t n, int kl, int ku);
+hipError_t launch_gram_band(const double2 *arow, int64_t n, int kl, int ku, double *gram, hipStream_t st);
+hipError_t launch_bis(const BisArgs &a, int hb, int ktm, int lanes, int64_t chunks, hipStream_t st);
+hipError_t launch_bis_plan(const MatDesc *cls_order, const MatDesc *lpt_order, int nmat, int nclass,
+                           const int64_t *counts, int spw, int64_t *pfx, int64_t *mfirst, int64_t *ctotal,
+                           int64_t *chunkfirst, int64_t *total, int64_t *gk_count, hipStream_t st);
+// Golub-Kahan launch of one class of a batch over count_dev queue positions, taken from perm
+// when it is not NULL.
+hipError_t launch_eval_batch_gk(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st);
+
 size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max);
 void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max,
                      Workspace *ws);
@@ -122,14 +173,18 @@ hipError_t launch_iota(int64_t *idx, int64_t npts, hipStream_t st);
 hipError_t launch_set_count(int64_t *count, int64_t value, unsigned long long *queue, hipStream_t st);
 hipError_t launch_compact_mask(const uint8_t *mask, int64_t npts, int64_t *idx, int64_t *count, int64_t *blocksums,
                                unsigned long long *queue, hipStream_t st);
-hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st);
+// A second stream of a handle and the two events that fork work onto it and join it back.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+// side: if not NULL (and the call bisects), the Golub-Kahan launch runs on side->stream beside
+// the bisection's second launch.
+hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st, const SideStream *side);
 // Batch: masks compaction for all matrices at once (masks: device array of nmat device
-// pointers, NULL entries = full grid), then per class the queue prefix and the launch.
+// pointers, NULL entries = full grid).
 hipError_t launch_batch_compact(const MatDesc *mats, int nmat, int64_t max_npts, const uint8_t *const *masks,
                                 int64_t *idx, int64_t *counts, int64_t *tilesums, hipStream_t st);
-hipError_t launch_batch_prefix(const MatDesc *mats_cls, const int64_t *counts, int nmat, int64_t *mfirst,
-                               int64_t *total, unsigned long long *queue, hipStream_t st);
-hipError_t launch_eval_batch(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st);
 int64_t batch_tiles(int64_t max_npts);
 hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double *g, const double2 *u,
                            const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,

@@ -512,21 +512,19 @@ void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int k
         w->vmeta = nullptr;
     }
     if (!vec && npts_max > 0) {
-        w->pcls = (uint8_t *)take((size_t)npts_max);
-        w->pbr = (double *)take(sizeof(double) * 2 * (size_t)npts_max);
-        w->perm = (int64_t *)take(sizeof(int64_t) * (size_t)(npts_max + 64));
-        w->pn1 = (int64_t *)take(2 * sizeof(int64_t));
+        w->gk_list = (int64_t *)take(sizeof(int64_t) * (size_t)npts_max);
+        w->gk_count = (int64_t *)take(sizeof(int64_t));
+        w->st_lo = (double *)take(sizeof(double) * (size_t)npts_max);
+        w->st_hi = (double *)take(sizeof(double) * (size_t)npts_max);
+        w->st_np = (int32_t *)take(sizeof(int32_t) * (size_t)npts_max);
     } else {
-        w->pcls = nullptr;
-        w->pbr = nullptr;
-        w->perm = nullptr;
-        w->pn1 = nullptr;
+        w->gk_list = nullptr;
+        w->gk_count = nullptr;
+        w->st_lo = w->st_hi = nullptr;
+        w->st_np = nullptr;
     }
     w->npts_max = npts_max;
-    w->blocksums = (int64_t *)take(8);
-    // blocksums extends to the end (sized by workspace_bytes); the partition of a classified
-    // launch reuses it after the mask compaction is done
-    w->ptiles = w->blocksums;
+    w->blocksums = (int64_t *)take(8);   // extends to the end (sized by workspace_bytes)
 }
 
 hipError_t launch_set_count(int64_t *count, int64_t value, unsigned long long *queue, hipStream_t st) {
@@ -561,94 +559,82 @@ static EvalKernel pick(int kl, int ku, int mode) {
     return nullptr;
 }
 
-// Partition of a classified launch: perm[0 .. n1) = the shift positions of classes 1 and 2
-// in increasing order, then -1 up to the next multiple of 64 (so that no wavefront gets
-// shifts of both kinds), then the positions of class 0 (Golub-Kahan), also in order.
-// pn1[0] = n1, pn1[1] = the length of the queue.
-__global__ void __launch_bounds__(kScanBlock) k_part_count(const uint8_t *cls, const int64_t *count,
-                                                           int64_t *tilesums) {
-    __shared__ int64_t sh[kScanBlock];
-    const int64_t npts = *count;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t c = 0;
-    for (int q = 0; q < kScanItems; ++q)
-        if (base + q < npts && cls[base + q] != 0) ++c;
-    int64_t total;
-    block_scan(c, sh, total);
-    if (threadIdx.x == 0) tilesums[blockIdx.x] = total;
+// Sigma-only calls with the bisection on (kl + ku >= 1): the bisection kernel evaluates
+// every shift it can and lists the others (sigma_min below its rounding limit) for the
+// Golub-Kahan kernel, which then takes only those.
+static bool bisects(const EvalArgs &a, const Workspace &ws) {
+    return !a.want_vectors && a.bisect && a.kl + a.ku >= 1 && a.gram && ws.gk_list && ws.npts_max > 0;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_part_scatter(const uint8_t *cls, const int64_t *count,
-                                                             const int64_t *tilesums, const int64_t *n1,
-                                                             int64_t *perm) {
-    __shared__ int64_t sh[kScanBlock];
-    const int64_t npts = *count;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t c = 0;
-    for (int q = 0; q < kScanItems; ++q)
-        if (base + q < npts && cls[base + q] != 0) ++c;
-    int64_t total;
-    const int64_t ex = block_scan(c, sh, total);
-    int64_t pos = tilesums[blockIdx.x] + ex;      // positions of classes 1-2 before base
-    const int64_t m = (*n1 + 63) & ~(int64_t)63;
-    for (int q = 0; q < kScanItems; ++q) {
-        const int64_t id = base + q;
-        if (id >= npts) break;
-        if (cls[id] != 0) perm[pos++] = id;
-        else perm[m + id - pos] = id;
-    }
-}
-
-__global__ void k_part_pad(const int64_t *count, int64_t *n1, int64_t *perm) {
-    const int64_t a = n1[0], m = (a + 63) & ~(int64_t)63;
-    if (a + (int64_t)threadIdx.x < m) perm[a + threadIdx.x] = -1;
-    if (threadIdx.x == 0) n1[1] = m + (*count - a);
-}
-
-// Classification pass of a sigma-only launch and the queue sorted by class (see
-// Kern::classify); afterwards the launch reads its shifts through a.perm.
-static hipError_t classify_and_sort(EvalArgs &a, const Workspace &ws, EvalKernel kc, hipStream_t st) {
-    if (!kc) return hipErrorInvalidValue;
-    const int64_t nb = (ws.npts_max + kClassifyBlock - 1) / kClassifyBlock;
-    hipLaunchKernelGGL(kc, dim3((unsigned)nb), dim3(kClassifyBlock), 0, st, a, ws);
-    const int64_t nt = (ws.npts_max + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_part_count, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev, ws.ptiles);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ws.ptiles, nt, ws.pn1, ws.queue);
-    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nt), dim3(kScanBlock), 0, st, ws.pcls, a.count_dev, ws.ptiles,
-                       ws.pn1, ws.perm);
-    hipLaunchKernelGGL(k_part_pad, dim3(1), dim3(64), 0, st, a.count_dev, ws.pn1, ws.perm);
-    a.count_dev = ws.pn1 + 1;
-    a.perm = ws.perm;
-    a.pcls = ws.pcls;
-    a.pbr = ws.pbr;
-    return hipGetLastError();
-}
-
-static bool classified(const EvalArgs &a, const Workspace &ws, int kl, int ku) {
-    return !a.want_vectors && a.bisect && kl + ku >= 1 && ws.perm && ws.npts_max > 0;
-}
-
-hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st) {
+hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, const SideStream *side) {
     EvalArgs a = a0;
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
-    if (classified(a, ws, a.kl, a.ku)) {
-        const hipError_t e = classify_and_sort(a, ws, pick(a.kl, a.ku, 3), st);
+    const int64_t blocks = ws.slots / kEvalBlock;
+    if (bisects(a, ws)) {
+        BisArgs b;
+        b.gram = a.gram;
+        b.n = a.n;
+        b.hb = a.kl + a.ku;
+        b.normA = a.normA;
+        b.norm2A = a.norm2A;
+        b.mode = a.mode;
+        b.z = a.z;
+        b.idx = a.idx;
+        b.ga = a.ga;
+        b.gb = a.gb;
+        b.gc = a.gc;
+        b.gd = a.gd;
+        b.nx = a.nx;
+        b.ny = a.ny;
+        b.count_dev = a.count_dev;
+        b.tol_norm = a.tol_norm;
+        b.tol_rel = a.tol_rel;
+        b.sigma = a.sigma;
+        b.info = a.info;
+        b.iters = a.iters;
+        b.eps = a.eps;
+        b.sens = a.sens;
+        b.gk_list = ws.gk_list;
+        b.gk_count = ws.gk_count;
+        b.st_lo = ws.st_lo;
+        b.st_hi = ws.st_hi;
+        b.st_np = ws.st_np;
+        hipError_t e = launch_zero(ws.gk_count, sizeof(int64_t), st);
         if (e != hipSuccess) return e;
+        const int64_t spw = 64 / a.lanes;
+        const int64_t chunks = (ws.npts_max + spw - 1) / spw;
+        a.perm = ws.gk_list;
+        a.count_dev = ws.gk_count;
+        if (!side || !side->stream) {
+            b.phase = 0;
+            e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
+            return hipGetLastError();
+        }
+        // first pass of every shift; then the Golub-Kahan launch over the shifts it handed
+        // over runs on the side stream while the bisection resumes on this one
+        b.phase = 1;
+        if ((e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st)) != hipSuccess) return e;
+        if ((e = hipEventRecord(side->fork, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, side->stream, a, ws);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess) return e;
+        b.phase = 2;
+        if ((e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st)) != hipSuccess) return e;
+        return hipStreamWaitEvent(st, side->join, 0);
     }
-    int64_t blocks = ws.slots / kEvalBlock;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_eval_batch(const EvalArgs &a0, const Workspace &ws, int kl, int ku, hipStream_t st) {
-    EvalArgs a = a0;
+hipError_t launch_eval_batch_gk(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st) {
     EvalKernel k = pick(kl, ku, 2);
     if (!k) return hipErrorInvalidValue;
-    if (classified(a, ws, kl, ku)) {
-        const hipError_t e = classify_and_sort(a, ws, pick(kl, ku, 4), st);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = launch_zero(ws.queue, sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
     int64_t blocks = ws.slots / kEvalBlock;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
@@ -709,19 +695,6 @@ __global__ void __launch_bounds__(kScanBlock) k_bmask_scatter(const MatDesc *mat
         if (base + q < npts && (!mask || mask[base + q])) out[pos++] = base + q;
 }
 
-// Queue positions of one class: mfirst[m] = sum of counts before m; total -> *total.
-__global__ void k_batch_prefix(const MatDesc *mats, const int64_t *counts, int nmat, int64_t *mfirst,
-                               int64_t *total, unsigned long long *queue) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int64_t acc = 0;
-        for (int m = 0; m < nmat; ++m) {
-            mfirst[m] = acc;
-            acc += counts[mats[m].cidx];
-        }
-        *total = acc;
-        *queue = 0ull;
-    }
-}
 
 hipError_t launch_batch_compact(const MatDesc *mats, int nmat, int64_t max_npts, const uint8_t *const *masks,
                                 int64_t *idx, int64_t *counts, int64_t *tilesums, hipStream_t st) {
@@ -735,11 +708,6 @@ hipError_t launch_batch_compact(const MatDesc *mats, int nmat, int64_t max_npts,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_prefix(const MatDesc *mats_cls, const int64_t *counts, int nmat, int64_t *mfirst,
-                               int64_t *total, unsigned long long *queue, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(64), 0, st, mats_cls, counts, nmat, mfirst, total, queue);
-    return hipGetLastError();
-}
 
 int64_t backward_partial_rows(int64_t npts) { return (npts + kBwdRows - 1) / kBwdRows; }
 
