@@ -144,19 +144,29 @@ def algorithmic_bytes(n, kl, ku, iters, info=None):
     return float(total)
 
 
-def test_points(kl, ku):
-    hb = kl + ku
+def tests_per_lane(hb, tests=0):
+    """Tests per lane and bisection pass: the library's test-count modes (ps_opts.tests)."""
+    if tests == 1:
+        return 1
+    if tests == 3:
+        return 2 if hb <= 6 else 1
     return 3 if hb <= 2 else 2 if hb <= 4 else 1
 
 
-def bisection_flops(n, kl, ku, info):
-    """Floating-point operations of the bisection passes of one launch (every pass covers
-    all n rows): F_row * n * total passes, F_row as in the module docstring."""
-    hb, kt = kl + ku, test_points(kl, ku)
-    per_row = 4 * (hb + 1) + 8 * hb * (hb + 1) // 2 + kt * (8 * hb * (hb - 1) // 2 + 6 * hb + 10)
+def row_flops(hb, tests_per_pass):
+    """FP64 operations of one row of a bisection pass (adds, multiplies, FMAs as executed, an FMA
+    counting 2): forming the row of (zI-A)^H(zI-A) from the Gram band, 8 hb + 5, once per pass;
+    per test the row of L D L^H (4 hb (hb - 1)), the scaled multipliers and the pivot update
+    (6 hb), the shift and 1/pivot by the hardware reciprocal with two Newton steps (10)."""
+    return 8 * hb + 5 + tests_per_pass * (4 * hb * (hb - 1) + 6 * hb + 10)
+
+
+def bisection_flops(n, hb, info, lanes=1, tests=0):
+    """Algorithmic floating-point operations of the bisection passes of one call: every pass
+    covers all n rows; a pass of lanes * tests_per_lane tests forms the row of H once."""
     info = np.asarray(info, dtype=np.int64)
     passes = np.where((info & 8) != 0, info >> 8, 0).astype(np.float64)
-    return float(np.sum(passes) * n * per_row)
+    return float(np.sum(passes) * n * row_flops(hb, lanes * tests_per_lane(hb, tests)))
 
 
 def _grid_points(grid):
@@ -381,8 +391,13 @@ def mask_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["batch64", "toeplitz2000"], default="batch64",
+                    help="batch64 (default): the 64-matrix batch, the largest single-GPU configuration; "
+                         "toeplitz2000: the n = 2000 full grid plus its annulus list")
+    ap.add_argument("--plain-shifts", type=int, default=64,
+                    help="batch64: seeded shifts timed one per launch for the plain per-shift path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=1)
     ap.add_argument("--progress", action="store_true", help="synchronise and report after every timed step")
@@ -401,7 +416,10 @@ def main():
                          "matrices of the Sec. 3.3 setting, one JSON line")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters)
+        if args.workload == "batch64":
+            summarize_batch_counters(*args.summarize_counters)
+        else:
+            summarize_counters(*args.summarize_counters)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -425,6 +443,286 @@ def main():
     if args.mask:
         mask_bench(args)
         return
+    if args.workload == "batch64":
+        batch_bench(args, dev)
+        return
+    toeplitz_bench(args, dev)
+
+
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch64_traffic.json")
+BATCH_SOURCES = ("ps_bisect.hpp", "ps_bisect.hip", "ps_internal.h", "ps_api.cpp") + tuple(
+    "ps_bis_h%d.hip" % h for h in range(1, 9))
+
+
+def batch_source_hash():
+    """Hash of what decides the batch bisection kernel's traffic: its sources and the inputs."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_04550_amd", "csrc")
+    for f in BATCH_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "workloads", "gen.py"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def batch_stored_traffic():
+    if not os.path.exists(BATCH_TRAFFIC_FILE):
+        return None
+    try:
+        doc = json.load(open(BATCH_TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if doc.get("source_hash") != batch_source_hash():
+        return None        # kernel or workload changed since the counters were taken
+    return doc.get("traffic_bytes_per_launch")
+
+
+def summarize_batch_counters(fetch_csv, write_csv):
+    """HBM bytes of the bisection kernel's two launches in one batch call, from two rocprofv3
+    --pmc runs of ``--counter-pass``, each counter scaled by its reading for the calibration
+    copy of known size."""
+    import csv
+
+    def rows(path, counter):
+        out = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        return sorted(out)
+
+    res = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rs = rows(path, counter)
+        cid, calib = [(d, v) for d, k, v in rs if "copyBuffer" in k and v > 1000.0][0]
+        parts = [v for d, k, v in rs if d > cid and "k_bis<" in k]
+        factor = (CALIB_BYTES / 1024.0) / calib
+        res[counter] = dict(kib=sum(parts), launches=len(parts), calib_kib=calib, factor=factor,
+                            bytes=sum(parts) * 1024.0 * factor)
+    traffic = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
+    doc = dict(kernel="ps::bis::k_bis<1, 8, 1, 1>, both launches of one batch64 call",
+               source_hash=batch_source_hash(), traffic_bytes_per_launch=traffic,
+               fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
+               commands=["timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch "
+                         "-o fetch -- python3 bench.py --counter-pass",
+                         "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write "
+                         "-o write -- python3 bench.py --counter-pass",
+                         "python bench.py --summarize-counters <out>/pmc_fetch/fetch_counter_collection.csv "
+                         "<out>/pmc_write/write_counter_collection.csv"])
+    with open(BATCH_TRAFFIC_FILE, "w") as f:
+        json.dump(doc, f, indent=1)
+        f.write("\n")
+    print(json.dumps(doc, indent=1))
+
+
+def batch_bench(args, dev):
+    """The headline: the 64-matrix batch (n ~ U{500..20000}, kl, ku ~ U{1..4}, CN(0,1) entries,
+    128 x 128 grid on each matrix's Gershgorin box, 4915 masked points each: 314,560 shifts)
+    through one ps_eval_batch call per step, captured once in a HIP graph and replayed."""
+    import torch
+    import workloads as W
+    from paper_2605_04550_amd import api, ps_set_timing_events, ps_batch_workspace_size
+
+    w = W.batch_workload()
+    bands = [m["band"] for m in w["mats"]]
+    mats = [api.BandedMatrix.from_band(b) for b in bands]
+    batch = api.BandedBatch(mats, [m["grid"] for m in w["mats"]])
+    masks = [torch.tensor(m["mask"], dtype=torch.uint8, device=dev).contiguous() for m in w["mats"]]
+    mtab = batch.mask_table(masks, device=dev)
+    o = api.make_opts()
+    ws = torch.empty(ps_batch_workspace_size(batch.handle, o), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    nshift = int(sum(int(m["mask"].sum()) for m in w["mats"]))
+
+    if args.counter_pass:
+        x = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print("bench: calibration copy done (%d bytes each way)" % CALIB_BYTES, file=sys.stderr, flush=True)
+        del x, y
+        batch.eval(mtab, workspace=ws, device=dev)
+        torch.cuda.synchronize()
+        print("bench: batch call done", file=sys.stderr, flush=True)
+        return
+
+    stream = torch.cuda.Stream(device=dev)
+    ev_s = torch.cuda.Event(enable_timing=True)
+    ev_e = torch.cuda.Event(enable_timing=True)
+    ev_s.record(stream)
+    ev_e.record(stream)
+    torch.cuda.synchronize()
+    # eager warm-up (first-call set-up outside any timing), then one capture
+    with torch.cuda.stream(stream):
+        batch.eval(mtab, workspace=ws, device=dev, stream=stream)
+    torch.cuda.synchronize()
+    print("bench: eager call done", file=sys.stderr, flush=True)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        out = batch.eval(mtab, workspace=ws, device=dev, stream=stream)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        graph.replay()
+        torch.cuda.synchronize()
+        print("bench: warmup replay %d done" % (i + 1), file=sys.stderr, flush=True)
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        step_ms.append(1000.0 * (time.perf_counter() - ts))
+        if args.progress:
+            print("bench: replay %d done (%.1f s)" % (i + 1, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1000.0 * elapsed / args.steps
+    value = nshift * args.steps / elapsed
+    # the dominant kernel's duration: HIP events that the library records on the caller's
+    # stream around its two bisection launches, on eager calls right after the timed replays
+    bis_ms = []
+    ps_set_timing_events(ev_s.cuda_event, ev_e.cuda_event)
+    try:
+        for i in range(3):
+            with torch.cuda.stream(stream):
+                batch.eval(mtab, workspace=ws, device=dev, stream=stream)
+            torch.cuda.synchronize()
+            bis_ms.append(ev_s.elapsed_time(ev_e))
+    finally:
+        ps_set_timing_events(0, 0)
+
+    # per-shift outcomes of the last replay
+    counts = out["counts"].cpu().numpy()
+    info = out["info"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    sig = out["sigma"].cpu().numpy()
+    offs = out["offsets"]
+    flops = 0.0
+    gk_bytes = 0.0
+    n_bis = n_gk = 0
+    passes_all = []
+    for m, b in enumerate(bands):
+        sl = slice(offs[m], offs[m] + int(counts[m]))
+        inf, it = info[sl], iters[sl]
+        hb = b.kl + b.ku
+        flops += bisection_flops(b.n, hb, inf)
+        bis = (inf & 8) != 0
+        n_bis += int(bis.sum())
+        n_gk += int((~bis).sum())
+        passes_all.append(inf[bis] >> 8)
+        gk_bytes += algorithmic_bytes(b.n, b.kl, b.ku, it, inf) - (b.kl + b.ku + 1) * 16 * b.n
+    passes_all = np.concatenate(passes_all)
+    dur_bis = float(np.median(bis_ms)) / 1000.0
+    achieved = flops / dur_bis / 1e12
+    traffic = batch_stored_traffic()
+
+    # plain per-shift GPU path: one wavefront per shift (lanes = 64: a pass tests 64 points of
+    # the bracket), one call per shift driven from the host, no batching, no graph; timed on a
+    # seeded sample of one masked shift per matrix, extrapolated matrix by matrix
+    rng = np.random.default_rng(2605_04550 + 11)
+    from paper_2605_04550_amd import ps_eval_points, ps_workspace_size
+    op = api.make_opts(lanes=64)
+    plain_total = 0.0
+    plain_time = 0.0
+    nplain = 0
+    order = rng.permutation(len(bands))[:max(1, min(args.plain_shifts, len(bands)))]
+    for m in order:
+        b, mat = bands[m], mats[m]
+        zs = _grid_points(w["mats"][m]["grid"])[rng.choice(np.flatnonzero(w["mats"][m]["mask"].ravel()))]
+        z1 = torch.tensor([zs], dtype=torch.complex128, device=dev)
+        ws1 = torch.empty(ps_workspace_size(mat.handle, 1, op), dtype=torch.uint8, device=dev)
+        sig1 = torch.empty(1, dtype=torch.float64, device=dev)
+        handle = torch.cuda.current_stream().cuda_stream
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        ps_eval_points(mat.handle, z1.data_ptr(), 1, op, ws1.data_ptr(), ws1.numel(), sig1.data_ptr(), 0, 0, 0, 0,
+                       handle)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tp
+        plain_time += dt
+        plain_total += dt * int(w["mats"][m]["mask"].sum())
+        nplain += 1
+    scale = nshift / sum(int(w["mats"][m]["mask"].sum()) for m in order)
+    plain_total *= scale
+    plain_value = nshift / plain_total
+
+    out_line = {
+        "metric": "shifts/sec sigma_min(zI-A) FP64 (|dsigma|<=1e-10||A||_F+1e-8 sigma)",
+        "value": value,
+        "unit": "shifts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch64: 64 banded matrices, n ~ U{500..20000}, kl, ku ~ U{1..4}, CN(0,1) entries, "
+                        "128x128 grid on each Gershgorin box, 4915-point seeded mask each; one ps_eval_batch call "
+                        "per step, replayed from a captured HIP graph",
+            "matrices": len(bands), "shifts_per_step": nshift,
+            "n_total": int(sum(b.n for b in bands)),
+            "replay_ms_median": float(np.median(step_ms)), "replay_ms_min": float(np.min(step_ms)),
+            "bisection_shifts": n_bis, "golub_kahan_shifts": n_gk,
+            "bisection_passes_mean": float(passes_all.mean()) if passes_all.size else 0.0,
+            "maxiter_shifts": int(np.sum((info[np.concatenate([np.arange(offs[m], offs[m] + counts[m]) for m in range(len(bands))])] & 2) != 0)),
+            "plan": {"lanes": 1, "tests": "default (3 for kl+ku<=2, 2 for <=4, 1 above)"},
+        },
+        "plain": {"value": plain_value, "unit": "shifts/s",
+                  "sample": "%d seeded masked shifts, one per matrix, each one ps_eval_points call with "
+                            "lanes = 64 (one wavefront per shift), host-driven, no graph; %.2f s measured, "
+                            "extrapolated by each matrix's shift count" % (nplain, plain_time)},
+        "speedup_vs_plain": value / plain_value,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": "ps::bis::k_bis<1, 8, 1, 1> (inertia bisection, both launches of a call)",
+            "algorithmic_flops_per_launch": flops,
+            "launch_ms_median": dur_bis * 1000.0,
+            # the Golub-Kahan shifts run on side streams beside the bisection
+            "golub_kahan_algorithmic_bytes": gk_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample: 16 seeded masked points of the smallest matrix,
+        # one point per thread (dense one-sided Jacobi, cyclic pairs)
+        k = int(np.argmin([b.n for b in bands]))
+        rng2 = np.random.default_rng(2605_04550 + 12)
+        cand = np.flatnonzero(w["mats"][k]["mask"].ravel())
+        zs = _grid_points(w["mats"][k]["grid"])[rng2.choice(cand, size=16, replace=False)]
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        print("bench: timing the CPU oracle on %d points (n=%d)" % (len(zs), bands[k].n), file=sys.stderr,
+              flush=True)
+        import oracle
+        oracle.build(force=False)
+        tc = time.time()
+        oracle.sigma_min(bands[k], zs, nthreads=threads, parallel_pairs=False)
+        dtc = time.time() - tc
+        ncube = np.array([b.n for b in bands], dtype=np.float64) ** 3
+        per_shift = dtc / len(zs) / bands[k].n ** 3 * np.sum(ncube * 4915) / nshift
+        out_line["cpu_baseline"] = dict(
+            value=len(zs) / dtc, unit="shifts/s", cores=threads, kind="oracle",
+            sample="16 seeded masked shifts of the smallest matrix of the batch (n=%d), dense one-sided Jacobi "
+                   "to convergence, one shift per thread over %d threads; %.1f s" % (bands[k].n, threads, dtc),
+            extrapolated_full_workload=dict(value=1.0 / per_shift if per_shift > 0 else None,
+                                            unit="shifts/s", note="cost per shift scaled by n^3 to the batch's "
+                                                                  "matrices; extrapolated, not measured"))
+    print(json.dumps(out_line), flush=True)
+
+
+def toeplitz_bench(args, dev):
+    """The toeplitz2000 line: full grid + annulus mask per step (see the module docstring)."""
+    import torch
+    import workloads as W
+    from paper_2605_04550_amd import api
     w = W.workload("toeplitz2000")
     band, grid = w["band"], w["grid"]
     mat = api.BandedMatrix.from_band(band)
@@ -503,8 +801,8 @@ def main():
     achieved = bytes_full / dur_full / 1e9
     bytes_mask = algorithmic_bytes(band.n, band.kl, band.ku, it_mask, info_mask)
     si_full = (info_full & 8) != 0
-    flops_full = bisection_flops(band.n, band.kl, band.ku, info_full)
-    flops_mask = bisection_flops(band.n, band.kl, band.ku, info_mask)
+    flops_full = bisection_flops(band.n, band.kl + band.ku, info_full)
+    flops_mask = bisection_flops(band.n, band.kl + band.ku, info_mask)
 
     # plain per-shift GPU path (the speedup denominator): the same numerics and tolerance,
     # one launch per shift, no batching, on a seeded sample of the full grid

@@ -503,6 +503,20 @@ ps_status ps_mask_calibrate(int32_t nval, const ps_grid *g, const float *prob_de
                             double median_min, double p10_min, void *ws_dev, size_t ws_bytes, int32_t *index_dev,
                             double *recall_dev, double *median_dev, double *p10_dev, void *stream);
 
+/*
+ * ps_set_timing_events -- measurement hook (no passage of the paper: it serves benchmarks).
+ *   start, end   hipEvent_t (as void *) created by the caller, or both NULL to switch the hook off.
+ * While set, every sigma-only evaluation on the calling thread that bisects (ps_eval_points,
+ * ps_eval_grid, ps_eval_batch and the calls built on them) records start on the caller's
+ * stream just before its bisection launches and end right after them, so that
+ * hipEventElapsedTime(start, end) is the duration of the bisection kernel's launches (the
+ * Golub-Kahan launches on the handle's side streams run beside them and are not included).
+ * Meant for eager calls (under stream capture the records become capture-internal
+ * dependencies, not timed nodes).  Thread-local; the caller keeps the events alive while the
+ * hook is set.  Errors: PS_ERR_INVALID (one NULL).
+ */
+ps_status ps_set_timing_events(void *start, void *end);
+
 /* Thread-local description of the last error on the calling thread ("" if none). */
 const char *ps_last_error(void);
 

@@ -65,6 +65,7 @@ _SIGNATURES = {
     "ps_opts_default": (None, [ctypes.POINTER(ps_opts)]),
     "ps_last_error": (ctypes.c_char_p, []),
     "ps_version": (ctypes.c_char_p, []),
+    "ps_set_timing_events": (ctypes.c_int, [_P, _P]),
     "ps_create_banded": (ctypes.c_int, [_P, _I64, _I64, _I32, _I32, ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
     "ps_destroy": (ctypes.c_int, [_P]),
     "ps_matrix_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
@@ -144,6 +145,11 @@ def _check(status):
 
 def ps_last_error() -> str:
     return lib().ps_last_error().decode(errors="replace")
+
+
+def ps_set_timing_events(start: int, end: int) -> None:
+    """Measurement hook: hipEvent_t handles (ints, 0 = off) recorded around the bisection launches."""
+    _check(lib().ps_set_timing_events(_P(start or None), _P(end or None)))
 
 
 def ps_version() -> str:

@@ -102,14 +102,20 @@ class BandedBatch:
 
     def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
              device=None, stream=None, workspace: torch.Tensor | None = None, lanes=0, tests=0):
-        """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None.  Returns dict with
-        the concatenated idx, sigma, info, iters, and counts [nmat]; matrix m owns offsets[m] onward."""
+        """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None, or the device
+        table of their addresses (an int64 CUDA tensor from ``mask_table``, which a captured graph needs:
+        building the table copies from the host).  Returns dict with the concatenated idx, sigma, info,
+        iters, and counts [nmat]; matrix m owns offsets[m] onward."""
         dev = device or torch.device("cuda")
         nmat = len(self.mats)
         o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect, lanes=lanes, tests=tests)
         keep = []
         mptr = 0
-        if masks is not None:
+        if isinstance(masks, torch.Tensor):
+            assert masks.is_cuda and masks.dtype == torch.int64 and masks.numel() == nmat
+            keep.append(masks)
+            mptr = masks.data_ptr()
+        elif masks is not None:
             ptrs = []
             for m, mk in enumerate(masks):
                 if mk is None:
@@ -134,6 +140,19 @@ class BandedBatch:
                       out["sigma"].data_ptr(), out["info"].data_ptr(), out["iters"].data_ptr(), _stream_handle(stream))
         out["_keep"] = keep
         return out
+
+    def mask_table(self, masks, device=None):
+        """The device table of mask addresses for ``eval`` (keep the masks alive while it is used)."""
+        dev = device or torch.device("cuda")
+        ptrs = []
+        for m, mk in enumerate(masks):
+            if mk is None:
+                ptrs.append(0)
+            else:
+                assert mk.is_cuda and mk.dtype == torch.uint8 and mk.is_contiguous()
+                assert mk.numel() == self.grids[m].nx * self.grids[m].ny
+                ptrs.append(mk.data_ptr())
+        return torch.tensor(ptrs, dtype=torch.int64, device=dev)
 
     def label(self, eps: float, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
               device=None, stream=None):

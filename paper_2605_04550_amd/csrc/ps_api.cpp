@@ -464,6 +464,13 @@ ps_status ps_mask_calibrate(int32_t nval, const ps_grid *g, const float *prob_de
 
 const char *ps_last_error(void) { return g_err; }
 
+ps_status ps_set_timing_events(void *start, void *end) {
+    if ((start == nullptr) != (end == nullptr)) return fail(PS_ERR_INVALID, "start and end must both be set or NULL");
+    ps::timing_events().start = (hipEvent_t)start;
+    ps::timing_events().end = (hipEvent_t)end;
+    return ok();
+}
+
 const char *ps_version(void) { return "ps-mi355x 0.1 (gfx950, fp64)"; }
 
 ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t kl, int32_t ku, uint32_t flags,
@@ -696,7 +703,7 @@ struct ps_batch_s {
     ps::MatDesc *desc_caller = nullptr;   // device, caller order
     ps::MatDesc *desc_class = nullptr;    // device, grouped by (kl, ku), larger n first
     ps::MatDesc *desc_lpt = nullptr;      // device, longest-first by predicted bisection cost
-    static constexpr int kSides = 4;      // streams for the per-class Golub-Kahan launches
+    static constexpr int kSides = 1;      // the stream of the Golub-Kahan launch
     ps::SideStream side[kSides];
     int max_hb = 0;                       // largest kl + ku
     int64_t lpt_chunks[3] = {0, 0, 0};    // chunks of 64, 32, 16 shifts over the full grids
@@ -1242,6 +1249,7 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
                                  int32_t *iters_dev, hipStream_t s) {
     const BatchScratch bs = batch_scratch(b, base);
     const int lanes = lanes_of(r);
+    if (lanes == 64) return fail(PS_ERR_INVALID, "lanes = 64 (a wavefront per shift) is not a batch plan: use 1, 2 or 4");
     const bool bis = bisect_of(r) && b->max_hb >= 1;
     const size_t ncls = b->classes.size();
     HIP_TRY(ps::launch_batch_compact(b->desc_caller, b->nmat, b->max_npts, masks_dev, idx_dev, counts_dev,
@@ -1270,76 +1278,59 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
         ba.st_hi = bs.st_hi;
         ba.st_np = bs.st_np;
         ba.phase = 1;
+        if (ps::timing_events().start)
+            HIP_TRY(hipEventRecord(ps::timing_events().start, s));
         HIP_TRY(ps::launch_bis(ba, b->max_hb, ktm_of(r), lanes, chunks, s));
     }
-    // the class launches: largest predicted Golub-Kahan time first, each on the side stream
-    // that has the least predicted work so far
-    std::vector<size_t> order(ncls);
-    std::vector<double> est(ncls);
-    for (size_t ci = 0; ci < ncls; ++ci) {
-        const auto &c = b->classes[ci];
-        order[ci] = ci;
-        est[ci] = (double)c.nmax * (double)((c.kl + 1) * (c.kl + c.ku + 1)) * (double)c.count;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return est[x] > est[y]; });
-    double load[ps_batch_s::kSides] = {0.0, 0.0, 0.0, 0.0};
-    bool used[ps_batch_s::kSides] = {false, false, false, false};
-    HIP_TRY(hipEventRecord(b->side[0].fork, s));
-    std::vector<size_t> wsoff(ncls);
+    // one Golub-Kahan launch for all classes on a side stream, beside the resumed bisection
+    ps::GkBatchArgs g;
+    g.base.mode = ps::kShiftGrid;
+    g.base.idx = idx_dev;
+    g.base.tol_norm = r.tol_norm;
+    g.base.tol_rel = r.tol_rel;
+    g.base.max_iter = r.max_iter;
+    g.base.check_shift = check_shift_of(r);
+    g.base.bisect = 0;
+    g.base.want_vectors = 0;
+    g.base.sigma = sigma_dev;
+    g.base.info = info_dev;
+    g.base.iters = iters_dev;
+    g.ws = base;
+    g.ncls = (int32_t)ncls;
     size_t off = bs.bytes;
+    int64_t blocks = 0;
     for (size_t ci = 0; ci < ncls; ++ci) {
-        wsoff[ci] = off;
-        off += class_ws_bytes(b->classes[ci], r, bis, ncls);
-    }
-    for (size_t oi = 0; oi < ncls; ++oi) {
-        const size_t ci = order[oi];
         const auto &c = b->classes[ci];
-        int q = 0;
-        for (int k = 1; k < ps_batch_s::kSides; ++k)
-            if (load[k] < load[q]) q = k;
-        load[q] += est[ci];
-        hipStream_t sq = b->side[q].stream;
-        if (!used[q]) {
-            HIP_TRY(hipStreamWaitEvent(sq, b->side[0].fork, 0));
-            used[q] = true;
-        }
-        ps::Workspace w;
-        ps::carve_workspace(base + wsoff[ci], c.nmax, c.kl, c.ku, class_slots(c, r, bis, ncls), r.max_iter, 0, 0,
-                            &w);
-        ps::EvalArgs a;
-        a.n = c.nmax;
-        a.kl = c.kl;
-        a.ku = c.ku;
-        a.arow = nullptr;
-        a.normA = 0.0;
-        a.mode = ps::kShiftGrid;
-        a.idx = idx_dev;
         const bool handed = bis && c.kl + c.ku >= 1;
-        a.perm = handed ? bs.gk_list + c.gkbase : nullptr;
-        a.count_dev = handed ? bs.gk_count + ci : bs.ctotal + ci;
-        a.tol_norm = r.tol_norm;
-        a.tol_rel = r.tol_rel;
-        a.max_iter = r.max_iter;
-        a.check_shift = check_shift_of(r);
-        a.bisect = 0;
-        a.want_vectors = 0;
-        a.sigma = sigma_dev;
-        a.info = info_dev;
-        a.iters = iters_dev;
-        a.mats = b->desc_class + c.begin;
-        a.nmat = c.count;
-        a.mfirst = bs.mfirst + c.begin;
-        HIP_TRY(ps::launch_eval_batch_gk(a, w, c.kl, c.ku, sq));
+        ps::GkClass &q = g.cls[ci];
+        q.kl = c.kl;
+        q.ku = c.ku;
+        q.nmat = c.count;
+        q.pad = 0;
+        q.first_block = blocks;
+        q.nmax = c.nmax;
+        q.slots = class_slots(c, r, bis, ncls);
+        q.ws_off = (int64_t)off;
+        q.mats = b->desc_class + c.begin;
+        q.mfirst = bs.mfirst + c.begin;
+        q.perm = handed ? bs.gk_list + c.gkbase : nullptr;
+        q.count = handed ? bs.gk_count + ci : bs.ctotal + ci;
+        HIP_TRY(ps::launch_zero(base + off, sizeof(unsigned long long), s));   // the class's queue counter
+        blocks += q.slots / 64;
+        off += class_ws_bytes(c, r, bis, ncls);
     }
+    ps::SideStream &sd = b->side[0];
+    HIP_TRY(hipEventRecord(sd.fork, s));
+    HIP_TRY(hipStreamWaitEvent(sd.stream, sd.fork, 0));
+    HIP_TRY(ps::launch_gk_batch(g, blocks, sd.stream));
+    HIP_TRY(hipEventRecord(sd.join, sd.stream));
     if (bis) {
         ba.phase = 2;
         HIP_TRY(ps::launch_bis(ba, b->max_hb, ktm_of(r), lanes, chunks, s));
+        if (ps::timing_events().end)
+            HIP_TRY(hipEventRecord(ps::timing_events().end, s));
     }
-    for (int q = 0; q < ps_batch_s::kSides; ++q) {
-        if (!used[q]) continue;
-        HIP_TRY(hipEventRecord(b->side[q].join, b->side[q].stream));
-        HIP_TRY(hipStreamWaitEvent(s, b->side[q].join, 0));
-    }
+    HIP_TRY(hipStreamWaitEvent(s, sd.join, 0));
     return ok();
 }
 

@@ -157,7 +157,8 @@ hipError_t launch_gram_band(const double2 *arow, int64_t n, int kl, int ku, doub
 }
 
 hipError_t launch_bis(const BisArgs &a, int hb, int ktm, int lanes, int64_t chunks, hipStream_t st) {
-    BisKernel k = pick_bis(a.batch != 0, hb, ktm, lanes);
+    // a wavefront per shift already tests 64 points per pass: one test per lane
+    BisKernel k = pick_bis(a.batch != 0, hb, lanes == 64 ? 0 : ktm, lanes);
     if (!k) return hipErrorInvalidValue;
     if (chunks < 1) return hipSuccess;
     hipLaunchKernelGGL(k, dim3((unsigned)chunks), dim3(64), 0, st, a);

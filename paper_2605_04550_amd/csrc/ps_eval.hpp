@@ -1620,8 +1620,8 @@ struct Kern {
         return w;
     }
 
-    static __device__ void run(const EvalArgs a, const Workspace wg) {
-        const int64_t sg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // sg: the lane's slot in the workspace (its global thread index in a one-class launch)
+    static __device__ void run(const EvalArgs a, const Workspace wg, int64_t sg) {
         const Workspace w = lane_view(wg, sg);
         const int64_t s = 0;
         const int64_t npts = *a.count_dev;
@@ -1750,18 +1750,17 @@ constexpr int kEvalBlock = 64;
 
 template <int KL, int KU, bool VEC, bool BATCH>
 __global__ void __launch_bounds__(kEvalBlock) k_eval(EvalArgs a, Workspace w) {
-    Kern<KL, KU, VEC, BATCH>::run(a, w);
+    Kern<KL, KU, VEC, BATCH>::run(a, w, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 typedef void (*EvalKernel)(EvalArgs, Workspace);
 
-// mode 0: one matrix, sigma only; 1: one matrix with vectors; 2: batch, sigma only
+// mode 0: one matrix, sigma only; 1: one matrix with vectors (batches: ps_eval_batch.hip)
 template <int KL, int KU>
 EvalKernel pick_mode(int mode) {
     switch (mode) {
     case 0: return k_eval<KL, KU, false, false>;
     case 1: return k_eval<KL, KU, true, false>;
-    case 2: return k_eval<KL, KU, false, true>;
     }
     return nullptr;
 }

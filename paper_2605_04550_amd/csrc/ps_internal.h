@@ -16,7 +16,7 @@ constexpr int kMaxIterCap = 4096;
 // Rows per chunk of the triangular sweeps.  Per-row arrays are allocated with
 // round_up(n, kChunk) + kChunk rows; rows past n hold zeros and make no contribution.
 constexpr int kChunk = 8;
-inline int64_t padded_rows(int64_t n) { return ((n + kChunk - 1) / kChunk) * kChunk + kChunk; }
+__host__ __device__ inline int64_t padded_rows(int64_t n) { return ((n + kChunk - 1) / kChunk) * kChunk + kChunk; }
 // Zero rows stored before and after the row band of A (so that blocked reads near the ends
 // of the matrix need no bounds checks): rows -kBandPadTop .. n + kBandPadBottom - 1 exist.
 constexpr int kBandPadTop = 8;
@@ -160,13 +160,85 @@ hipError_t launch_bis(const BisArgs &a, int hb, int ktm, int lanes, int64_t chun
 hipError_t launch_bis_plan(const MatDesc *cls_order, const MatDesc *lpt_order, int nmat, int nclass,
                            const int64_t *counts, int spw, int64_t *pfx, int64_t *mfirst, int64_t *ctotal,
                            int64_t *chunkfirst, int64_t *total, int64_t *gk_count, hipStream_t st);
-// Golub-Kahan launch of one class of a batch over count_dev queue positions, taken from perm
-// when it is not NULL.
-hipError_t launch_eval_batch_gk(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st);
+// The batch's Golub-Kahan launch: every (kl, ku) class at once, each on its own wavefronts
+// and its own part of the workspace; a class takes count queue positions, from perm when it
+// is not NULL.
+struct GkClass {
+    int32_t kl, ku;
+    int32_t nmat;
+    int32_t pad;
+    int64_t first_block;   // first wavefront of the class in the launch
+    int64_t nmax;          // largest n of the class
+    int64_t slots;
+    int64_t ws_off;        // its workspace, from the base
+    const MatDesc *mats;   // its matrices (class-sorted order)
+    const int64_t *mfirst;
+    const int64_t *perm;
+    const int64_t *count;
+};
+constexpr int kMaxClasses = (kMaxKL + 1) * (kMaxKU + 1);
+struct GkBatchArgs {
+    EvalArgs base;         // the fields every class shares (outputs, tolerances, shift source)
+    char *ws;
+    int32_t ncls;
+    GkClass cls[kMaxClasses];
+};
+hipError_t launch_gk_batch(const GkBatchArgs &g, int64_t blocks, hipStream_t st);
 
 size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max);
-void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max,
-                     Workspace *ws);
+// The carve-up of one evaluation workspace (host and device: the batch's Golub-Kahan kernel
+// carves each class's part itself).
+__host__ __device__ inline void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax,
+                                                int vec, int64_t npts_max, Workspace *w) {
+    size_t off = 0;
+    char *b = (char *)base;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = (void *)(b + off);
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const int64_t nrow = padded_rows(n);
+    const size_t ns = (size_t)nrow * (size_t)slots;
+    const int wu = kl + ku + 1;
+    w->slots = slots;
+    w->nrow = nrow;
+    w->kmax = kmax;
+    w->vec = vec;
+    w->queue = (unsigned long long *)take(sizeof(unsigned long long));
+    w->count = (int64_t *)take(sizeof(int64_t));
+    w->L = (double2 *)take(sizeof(double2) * ns * (size_t)(kl > 0 ? kl : 1));
+    w->U = (double2 *)take(sizeof(double2) * ns * (size_t)wu);
+    w->piv = (uint8_t *)take(ns);
+    w->vu = (double2 *)take(sizeof(double2) * ns);
+    w->vv = (double2 *)take(sizeof(double2) * ns);
+    w->vy = (double2 *)take(sizeof(double2) * ns);
+    w->eu = (int16_t *)take(sizeof(int16_t) * ns);
+    w->ev = (int16_t *)take(sizeof(int16_t) * ns);
+    w->ey = (int16_t *)take(sizeof(int16_t) * ns);
+    w->hist = (double *)take(sizeof(double) * (size_t)kmax * 2 * (size_t)slots);
+    if (vec) {
+        w->vacc = (double2 *)take(sizeof(double2) * ns);
+        w->vmeta = (double *)take(sizeof(double) * (size_t)kmax * 4 * (size_t)slots);
+    } else {
+        w->vacc = nullptr;
+        w->vmeta = nullptr;
+    }
+    if (!vec && npts_max > 0) {
+        w->gk_list = (int64_t *)take(sizeof(int64_t) * (size_t)npts_max);
+        w->gk_count = (int64_t *)take(sizeof(int64_t));
+        w->st_lo = (double *)take(sizeof(double) * (size_t)npts_max);
+        w->st_hi = (double *)take(sizeof(double) * (size_t)npts_max);
+        w->st_np = (int32_t *)take(sizeof(int32_t) * (size_t)npts_max);
+    } else {
+        w->gk_list = nullptr;
+        w->gk_count = nullptr;
+        w->st_lo = w->st_hi = nullptr;
+        w->st_np = nullptr;
+    }
+    w->npts_max = npts_max;
+    w->blocksums = (int64_t *)take(8);   // extends to the end (sized by workspace_bytes)
+}
+
 
 // Kernel launchers (enqueue on stream; return hipError_t of the launch).
 hipError_t launch_iota(int64_t *idx, int64_t npts, hipStream_t st);
@@ -178,6 +250,11 @@ struct SideStream {
     hipStream_t stream = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
+// The measurement hook of ps_set_timing_events (thread-local; NULL when off).
+struct TimingEvents {
+    hipEvent_t start = nullptr, end = nullptr;
+};
+TimingEvents &timing_events();
 // side: if not NULL (and the call bisects), the Golub-Kahan launch runs on side->stream beside
 // the bisection's second launch.
 hipError_t launch_eval(const EvalArgs &a, const Workspace &ws, hipStream_t st, const SideStream *side);

@@ -476,57 +476,6 @@ size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int v
     return (size_t)(uintptr_t)w.blocksums + align256(sizeof(int64_t) * (size_t)((npts_max + kScanTile - 1) / kScanTile + 1));
 }
 
-void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max,
-                     Workspace *w) {
-    size_t off = 0;
-    char *b = (char *)base;
-    auto take = [&](size_t bytes) -> void * {
-        void *p = (void *)(b + off);
-        off += align256(bytes);
-        return p;
-    };
-    const int64_t nrow = padded_rows(n);
-    const size_t ns = (size_t)nrow * (size_t)slots;
-    const int wu = kl + ku + 1;
-    w->slots = slots;
-    w->nrow = nrow;
-    w->kmax = kmax;
-    w->vec = vec;
-    w->queue = (unsigned long long *)take(sizeof(unsigned long long));
-    w->count = (int64_t *)take(sizeof(int64_t));
-    w->L = (double2 *)take(sizeof(double2) * ns * (size_t)(kl > 0 ? kl : 1));
-    w->U = (double2 *)take(sizeof(double2) * ns * (size_t)wu);
-    w->piv = (uint8_t *)take(ns);
-    w->vu = (double2 *)take(sizeof(double2) * ns);
-    w->vv = (double2 *)take(sizeof(double2) * ns);
-    w->vy = (double2 *)take(sizeof(double2) * ns);
-    w->eu = (int16_t *)take(sizeof(int16_t) * ns);
-    w->ev = (int16_t *)take(sizeof(int16_t) * ns);
-    w->ey = (int16_t *)take(sizeof(int16_t) * ns);
-    w->hist = (double *)take(sizeof(double) * (size_t)kmax * 2 * (size_t)slots);
-    if (vec) {
-        w->vacc = (double2 *)take(sizeof(double2) * ns);
-        w->vmeta = (double *)take(sizeof(double) * (size_t)kmax * 4 * (size_t)slots);
-    } else {
-        w->vacc = nullptr;
-        w->vmeta = nullptr;
-    }
-    if (!vec && npts_max > 0) {
-        w->gk_list = (int64_t *)take(sizeof(int64_t) * (size_t)npts_max);
-        w->gk_count = (int64_t *)take(sizeof(int64_t));
-        w->st_lo = (double *)take(sizeof(double) * (size_t)npts_max);
-        w->st_hi = (double *)take(sizeof(double) * (size_t)npts_max);
-        w->st_np = (int32_t *)take(sizeof(int32_t) * (size_t)npts_max);
-    } else {
-        w->gk_list = nullptr;
-        w->gk_count = nullptr;
-        w->st_lo = w->st_hi = nullptr;
-        w->st_np = nullptr;
-    }
-    w->npts_max = npts_max;
-    w->blocksums = (int64_t *)take(8);   // extends to the end (sized by workspace_bytes)
-}
-
 hipError_t launch_set_count(int64_t *count, int64_t value, unsigned long long *queue, hipStream_t st) {
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, st, count, value, queue);
     return hipGetLastError();
@@ -607,14 +556,22 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
         a.perm = ws.gk_list;
         a.count_dev = ws.gk_count;
         if (!side || !side->stream) {
+            const TimingEvents &tv = timing_events();
+            if (tv.start && (e = hipEventRecord(tv.start, st)) != hipSuccess)
+                return e;
             b.phase = 0;
             e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st);
             if (e != hipSuccess) return e;
+            if (tv.end && (e = hipEventRecord(tv.end, st)) != hipSuccess)
+                return e;
             hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
             return hipGetLastError();
         }
         // first pass of every shift; then the Golub-Kahan launch over the shifts it handed
         // over runs on the side stream while the bisection resumes on this one
+        const TimingEvents &tev = timing_events();
+        if (tev.start && (e = hipEventRecord(tev.start, st)) != hipSuccess)
+            return e;
         b.phase = 1;
         if ((e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st)) != hipSuccess) return e;
         if ((e = hipEventRecord(side->fork, st)) != hipSuccess) return e;
@@ -624,21 +581,18 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
         if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess) return e;
         b.phase = 2;
         if ((e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st)) != hipSuccess) return e;
+        if (tev.end && (e = hipEventRecord(tev.end, st)) != hipSuccess) return e;
         return hipStreamWaitEvent(st, side->join, 0);
     }
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_eval_batch_gk(const EvalArgs &a, const Workspace &ws, int kl, int ku, hipStream_t st) {
-    EvalKernel k = pick(kl, ku, 2);
-    if (!k) return hipErrorInvalidValue;
-    hipError_t e = launch_zero(ws.queue, sizeof(unsigned long long), st);
-    if (e != hipSuccess) return e;
-    int64_t blocks = ws.slots / kEvalBlock;
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
-    return hipGetLastError();
+TimingEvents &timing_events() {
+    static thread_local TimingEvents t;
+    return t;
 }
+
 
 int64_t batch_tiles(int64_t max_npts) { return (max_npts + kScanTile - 1) / kScanTile; }
 
