@@ -504,6 +504,29 @@ ps_status ps_mask_calibrate(int32_t nval, const ps_grid *g, const float *prob_de
                             double *recall_dev, double *median_dev, double *p10_dev, void *stream);
 
 /*
+ * ps_eval_points_noalloc -- ps_eval_points for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): sigma only, and the
+ * workspace is a fixed device array of PS_NOALLOC_SCRATCH_BYTES inside the library instead
+ * of a caller buffer.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); it uses the matrix's own side stream as ps_eval_points does.
+ *   z_dev, npts, o, sigma_dev, info_dev, iters_dev, stream   as in ps_eval_points
+ *              (o->want_vectors must be 0).
+ * Limit: the call needs the room ps_workspace_size would ask for npts shifts with at least one
+ * wavefront (64) of Golub-Kahan slots: about 28 bytes per shift plus, per slot, about
+ * (32 kl + 16 ku + 71) (n + 16) + 16 max_iter bytes (under 1 MiB per slot at n <= 4000 with
+ * kl = ku = 4 and the default max_iter).  Requests that do not fit are refused with
+ * PS_ERR_WORKSPACE and a message giving the bytes needed and the scratch size.
+ * Each GPU holds one such array for the life of the process, shared by every call on that
+ * GPU, and the array keeps the last call's contents: calls that overlap on one GPU (from
+ * different streams or threads) race on it and must be serialised by the caller.  Everything
+ * a call needs zeroed is cleared by its own kernels.
+ * Errors: PS_ERR_INVALID, PS_ERR_UNSUPPORTED (vectors), PS_ERR_WORKSPACE (too large), PS_ERR_HIP.
+ */
+#define PS_NOALLOC_SCRATCH_BYTES (128u << 20)
+ps_status ps_eval_points_noalloc(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const ps_opts *o,
+                                 double *sigma_dev, int32_t *info_dev, int32_t *iters_dev, void *stream);
+
+/*
  * ps_set_timing_events -- measurement hook (no passage of the paper: it serves benchmarks).
  *   start, end   hipEvent_t (as void *) created by the caller, or both NULL to switch the hook off.
  * While set, every sigma-only evaluation on the calling thread that bisects (ps_eval_points,

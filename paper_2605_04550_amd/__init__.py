@@ -73,6 +73,7 @@ _SIGNATURES = {
     "ps_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ps_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "ps_eval_points": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t, _P, _P, _P, _P,
                                       _P, _P]),
+    "ps_eval_points_noalloc": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ps_opts), _P, _P, _P, _P]),
     "ps_eval_grid": (ctypes.c_int, [_P, ctypes.POINTER(ps_grid), _P, ctypes.POINTER(ps_opts), _P, ctypes.c_size_t,
                                     _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P]),
     "ps_backward_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(ctypes.c_size_t)]),
@@ -145,6 +146,13 @@ def _check(status):
 
 def ps_last_error() -> str:
     return lib().ps_last_error().decode(errors="replace")
+
+
+def ps_eval_points_noalloc(handle: int, z_ptr: int, npts: int, opts, sigma_ptr: int, info_ptr: int = 0,
+                           iters_ptr: int = 0, stream: int = 0) -> None:
+    """ps_eval_points with the library's fixed device scratch instead of a workspace (sigma only)."""
+    _check(lib().ps_eval_points_noalloc(_P(handle), _P(z_ptr), npts, ctypes.byref(opts) if opts is not None else None,
+                                        _P(sigma_ptr), _P(info_ptr or None), _P(iters_ptr or None), _P(stream)))
 
 
 def ps_set_timing_events(start: int, end: int) -> None:

@@ -615,6 +615,64 @@ ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const 
     return ok();
 }
 
+ps_status ps_eval_points_noalloc(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const ps_opts *o,
+                                 double *sigma_dev, int32_t *info_dev, int32_t *iters_dev, void *stream) {
+    ps_status st = check_handle(m);
+    if (st) return st;
+    if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    ps_opts r = resolve(o);
+    if ((st = check_opts(r))) return st;
+    if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "the allocation-free call computes sigma only");
+    if (npts == 0) return ok();
+    if (!z_dev) return fail(PS_ERR_INVALID, "z is NULL");
+    void *scratch = nullptr;
+    HIP_TRY(ps::noalloc_scratch(&scratch));
+    // the largest slot count (a multiple of one wavefront, at most the default plan's) whose
+    // workspace fits the fixed scratch
+    const int64_t quantum = 64;
+    int64_t slots = default_slots(m, npts, r);
+    slots -= slots % quantum;
+    while (slots >= quantum && ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, 0, npts) >
+                                   ps::kNoallocScratchBytes)
+        slots -= quantum;
+    if (slots < quantum)
+        return fail(PS_ERR_WORKSPACE,
+                    "%lld shifts at n=%lld need %zu bytes with one wavefront of slots; the fixed scratch holds %zu",
+                    (long long)npts, (long long)m->n,
+                    ps::workspace_bytes(m->n, m->kl, m->ku, quantum, r.max_iter, 0, npts),
+                    ps::kNoallocScratchBytes);
+    r.slots = (int32_t)slots;
+    ps::Workspace w;
+    ps::EvalArgs a;
+    ps::carve_workspace(scratch, m->n, m->kl, m->ku, slots, r.max_iter, 0, npts, &w);
+    if (!sigma_dev) return fail(PS_ERR_INVALID, "sigma output is NULL");
+    a.n = m->n;
+    a.kl = m->kl;
+    a.ku = m->ku;
+    a.arow = m->arow;
+    a.normA = m->fro;
+    a.norm2A = m->norm2;
+    a.bisect = bisect_of(r);
+    a.gram = m->gram;
+    a.lanes = lanes_of(r);
+    a.ktm = ktm_of(r);
+    a.tol_norm = r.tol_norm;
+    a.tol_rel = r.tol_rel;
+    a.max_iter = r.max_iter;
+    a.check_shift = check_shift_of(r);
+    a.want_vectors = 0;
+    a.sigma = sigma_dev;
+    a.count_dev = w.count;
+    a.mode = ps::kShiftList;
+    a.z = (const double2 *)z_dev;
+    a.info = info_dev;
+    a.iters = iters_dev;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
+    HIP_TRY(ps::launch_eval(a, w, s, &m->side));
+    return ok();
+}
+
 ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, const ps_opts *o, void *ws_dev,
                        size_t ws_bytes, int64_t *idx_dev, int64_t *count_dev, double *sigma_dev, ps_c128 *u_dev,
                        ps_c128 *v_dev, int32_t *info_dev, int32_t *iters_dev, double eps, uint8_t *sens_dev,

@@ -22,6 +22,11 @@ __host__ __device__ inline int64_t padded_rows(int64_t n) { return ((n + kChunk 
 constexpr int kBandPadTop = 8;
 constexpr int kBandPadBottom = 32;
 
+// Size of the fixed device scratch of ps_eval_points_noalloc (see include/ps.h) and the
+// lookup of its address on the current device.
+constexpr size_t kNoallocScratchBytes = (size_t)PS_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch(void **ptr);
+
 // Where the shifts of one evaluation come from.
 enum ShiftMode : int {
     kShiftList = 0,   // z[p] from a device array
