@@ -62,7 +62,8 @@ enum {
     PS_PT_CONVERGED = 0,
     PS_PT_SINGULAR = 1,   /* the LU met an exactly zero (or negligible) pivot: sigma_min = 0 */
     PS_PT_MAXITER = 2,    /* iteration cap reached: sigma is the best (upper) estimate        */
-    PS_PT_UNDERFLOW = 4,  /* sigma_min below the smallest double: reported as 0               */
+    PS_PT_UNDERFLOW = 4,  /* sigma_min below the smallest normal double: reported as 0, with
+                             -floor(log2 sigma_min) in bits 8..31 of info                   */
     PS_PT_BISECT = 8      /* sigma came from the inertia bisection (sigma only, kl + ku >= 1):
                              sigma_min^2 is the smallest eigenvalue of (zI-A)^H (zI-A), so
                              t < sigma_min exactly when (zI-A)^H (zI-A) - t^2 I has a Cholesky

@@ -1351,8 +1351,17 @@ struct Kern {
             sigma = 0.0;
             flags |= 1;
         } else {
-            sigma = ldexp(1.0 / sqrt(ln.theta), -ln.E0);
-            if (!(sigma >= 0x1p-1022)) flags |= 4;
+            const double m = 1.0 / sqrt(ln.theta);      // sigma = m 2^-E0
+            sigma = ldexp(m, -ln.E0);
+            if (!(sigma >= 0x1p-1022) && m > 0.0 && m < INFINITY) {
+                // below the normal range: reported as 0, with -floor(log2 sigma) in bits 8..31
+                const int e2 = ilogb(m) - ln.E0;
+                flags |= PS_PT_UNDERFLOW | ((-e2 < 0x7fffff ? -e2 : 0x7fffff) << 8);
+                sigma = 0.0;
+            } else if (!(sigma >= 0x1p-1022)) {
+                flags |= PS_PT_UNDERFLOW;
+                sigma = 0.0;
+            }
         }
         a.sigma[ln.pid] = sigma;
         if (a.info) a.info[ln.pid] = flags;

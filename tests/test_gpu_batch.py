@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import golden, need_gpu, report, tol
+from gpu_util import certify, column_norm_bound, golden, johnson_bound, need_gpu, report, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -59,16 +59,24 @@ def test_small_mixed_batch_matches_single_matrix_path_and_oracle():
         assert np.all(np.abs(sb[pick] - ref) <= bnd)
 
 
-def test_batch64_workload_runs_and_matches_stored_oracle_points():
-    """The 64-matrix workload (n in [500, 20000], kl, ku in 1..4, 128x128 grids, 4915-point
-    masks) through one ps_eval_batch call; stored oracle values for the matrices with n <= 1200."""
-    api = _api()
-    import time
-    import torch
+def _batch64(api, torch):
     w = W.batch_workload()
     mats = [api.BandedMatrix.from_band(m["band"]) for m in w["mats"]]
     batch = api.BandedBatch(mats, [m["grid"] for m in w["mats"]])
-    masks = [torch.tensor(m["mask"], device="cuda") for m in w["mats"]]
+    masks = [torch.tensor(m["mask"], device="cuda").contiguous() for m in w["mats"]]
+    return w, mats, batch, masks
+
+
+def test_batch64_full_workload_certified():
+    """The 64-matrix workload (n in [500, 20000], kl, ku in 1..4, 128x128 grids, 4915-point
+    masks) in one ps_eval_batch call, as the benchmark makes it.  Every shift: finite, no
+    MAXITER, 1-Lipschitz between masked grid neighbours; stored oracle values (two per matrix
+    with n <= 5000); per matrix an inertia certificate on 8 shifts stratified by sigma and
+    Johnson's lower bound and the column-norm upper bound on 64 seeded shifts."""
+    api = _api()
+    import time
+    import torch
+    w, mats, batch, masks = _batch64(api, torch)
     print("batch64: launching %d matrices, %d shifts" % (len(mats), 64 * 4915), flush=True)
     t = time.perf_counter()
     r = batch.eval(masks)
@@ -78,17 +86,80 @@ def test_batch64_workload_runs_and_matches_stored_oracle_points():
     assert np.all(counts == 4915)
     sig = r["sigma"].cpu().numpy()
     info = r["info"].cpu().numpy()
-    it = r["iters"].cpu().numpy()
+    idx = r["idx"].cpu().numpy()
     sel = np.concatenate([np.arange(o, o + 4915) for o in r["offsets"]])
     assert np.all(np.isfinite(sig[sel])) and np.all(sig[sel] >= 0)
-    print("batch64: %d shifts in %.3f s = %.0f shifts/s (first call, with set-up); Golub-Kahan steps mean %.1f "
-          "max %d; bisection at %d shifts; MAXITER %d"
-          % (len(sel), dt, len(sel) / dt, it[sel].mean(), it[sel].max(), np.sum((info[sel] & 8) != 0),
-             np.sum((info[sel] & 2) != 0)), flush=True)
+    assert np.all((info[sel] & 2) == 0), "MAXITER at %d shifts" % np.sum((info[sel] & 2) != 0)
+    print("batch64: %d shifts in %.3f s (first call, with set-up); bisection at %d shifts"
+          % (len(sel), dt, np.sum((info[sel] & 8) != 0)), flush=True)
+    rng = np.random.default_rng(2605)
+    for m, mm in enumerate(w["mats"]):
+        b, g = mm["band"], mm["grid"]
+        off = r["offsets"][m]
+        im = idx[off:off + 4915]
+        assert np.array_equal(im, oracle.compact_mask(mm["mask"]))
+        sm = sig[off:off + 4915]
+        zs = oracle.grid_points(g)[im]
+        bnd = tol(b.fro, sm)
+        # 1-Lipschitz between masked neighbours (full grid of sigma with NaN outside the mask)
+        S = np.full(g.npts, np.nan)
+        S[im] = sm
+        S = S.reshape(g.ny, g.nx)
+        B = np.full(g.npts, np.nan)
+        B[im] = bnd
+        B = B.reshape(g.ny, g.nx)
+        hx = (g.b - g.a) / (g.nx - 1)
+        hy = (g.d - g.c) / (g.ny - 1)
+        for dS, dB, h in [(S[:, 1:] - S[:, :-1], B[:, 1:] + B[:, :-1], hx), (S[1:] - S[:-1], B[1:] + B[:-1], hy)]:
+            ok = np.isnan(dS) | (np.abs(dS) <= h * (1 + 1e-12) + dB)
+            assert ok.all(), (m, np.nanmax(np.abs(dS) - h - dB))
+        pick = rng.choice(4915, 64, replace=False)
+        assert np.all(sm[pick] >= johnson_bound(b, zs[pick]) - bnd[pick]), m
+        assert np.all(sm[pick] <= column_norm_bound(b, zs[pick]) * (1 + 1e-12) + bnd[pick]), m
+        order = np.argsort(sm)
+        strat = order[np.linspace(0, 4914, 8).astype(int)]
+        strat = strat[sm[strat] >= 1e-3]
+        certify(b, zs[strat], sm[strat], bnd[strat], "batch64 matrix %d (n=%d kl=%d ku=%d)" % (m, b.n, b.kl, b.ku))
     g = golden("batch_pts")
     for mi, k, zz, s_or in zip(g["mat"], g["idx"], g["z"], g["sigma"]):
         off = r["offsets"][mi]
-        pos = np.searchsorted(r["idx"][off:off + 4915].cpu().numpy(), k)
+        pos = np.searchsorted(idx[off:off + 4915], k)
+        assert idx[off + pos] == k
         got = sig[off + pos]
         b = tol(w["mats"][mi]["band"].fro, s_or)
         assert abs(got - s_or) <= b, (mi, k, got, s_or)
+    print("batch64: %d stored oracle points within the bar" % len(g["sigma"]), flush=True)
+
+
+def test_batch64_graph_replays_match_eager():
+    """The full 64-matrix call captured in a HIP graph: three replays, each with eager work and
+    synchronisation between them, equal to the eager result bit for bit."""
+    api = _api()
+    import torch
+    w, mats, batch, masks = _batch64(api, torch)
+    mtab = batch.mask_table(masks)
+    eager = batch.eval(mtab)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.eval(mtab, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        got = batch.eval(mtab)
+    # the masked positions of every matrix (the others are never written)
+    sel = torch.tensor(np.concatenate([np.arange(o, o + 4915) for o in eager["offsets"]]), device="cuda")
+    for rep in range(3):
+        got["sigma"].fill_(-1.0)
+        got["info"].fill_(-1)
+        x = torch.ones(1 << 20, device="cuda").sum()          # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert float(x) == float(1 << 20)
+        assert torch.equal(got["counts"], eager["counts"]), rep
+        assert torch.equal(got["sigma"][sel], eager["sigma"][sel]), rep
+        assert torch.equal(got["info"][sel], eager["info"][sel]), rep
+    print("batch64: 3 graph replays identical to the eager call", flush=True)

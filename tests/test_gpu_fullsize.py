@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import golden, need_gpu, tol
+from gpu_util import certify, golden, need_gpu, tol
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -64,14 +64,7 @@ def _band_rmatvec(band, z, x):
 
 
 def _certify(band, z, sigma, delta, name):
-    """Both sides by inertia.  Callers keep sigma well above zero: the count factorises
-    [[-t I, M], [M^H, -t I]] without pivoting, which is reliable only while t is not tiny
-    against the other singular values of M."""
-    lo = oracle.count_below(band, z, sigma - delta)
-    hi = oracle.count_below(band, z, sigma + delta)
-    bad = np.flatnonzero((lo != 0) | (hi < 1))
-    print("%s: inertia certificate on %d points, %d failures" % (name, len(z), len(bad)), flush=True)
-    assert len(bad) == 0, [(int(p), z[p], sigma[p], int(lo[p]), int(hi[p])) for p in bad[:5]]
+    certify(band, z, sigma, delta, name)
 
 
 def test_random10k_full_grid_certified():
