@@ -150,7 +150,7 @@ def tests_per_lane(hb, tests=0):
         return 1
     if tests == 3:
         return 2 if hb <= 6 else 1
-    return 3 if hb <= 2 else 2 if hb <= 4 else 1
+    return 3 if hb <= 2 else 2 if hb <= 6 else 1
 
 
 def row_flops(hb, tests_per_pass):
@@ -670,7 +670,7 @@ def batch_bench(args, dev):
             "bisection_shifts": n_bis, "golub_kahan_shifts": n_gk,
             "bisection_passes_mean": float(passes_all.mean()) if passes_all.size else 0.0,
             "maxiter_shifts": int(np.sum((info[np.concatenate([np.arange(offs[m], offs[m] + counts[m]) for m in range(len(bands))])] & 2) != 0)),
-            "plan": {"lanes": 1, "tests": "default (3 for kl+ku<=2, 2 for <=4, 1 above)"},
+            "plan": {"lanes": 1, "tests": "default (3 for kl+ku<=2, 2 for <=6, 1 above)"},
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded masked shifts, one per matrix, each one ps_eval_points call with "

@@ -87,7 +87,7 @@ ps_status check_opts(const ps_opts &o) {
 int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
 
 // Lanes per shift of the bisection kernel (default 1) and its test-count mode: tests 1 -> one
-// test per lane and pass; 0 and 2 -> three for kl + ku <= 2, two for <= 4, one above; 3 -> two
+// test per lane and pass; 0 and 2 -> three for kl + ku <= 2, two for <= 6, one above; 3 -> two
 // for kl + ku <= 6, one above.
 int lanes_of(const ps_opts &o) { return o.lanes > 0 ? o.lanes : 1; }
 int ktm_of(const ps_opts &o) { return o.tests == 1 ? 0 : o.tests == 3 ? 2 : 1; }
@@ -1376,6 +1376,11 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
         HIP_TRY(ps::launch_zero(base + off, sizeof(unsigned long long), s));   // the class's queue counter
         blocks += q.slots / 64;
         off += class_ws_bytes(c, r, bis, ncls);
+    }
+    if (bis) {
+        ps::ListBases lb = {};
+        for (size_t ci = 0; ci < ncls; ++ci) lb.base[ci] = b->classes[ci].gkbase;
+        HIP_TRY(ps::launch_sort_lists(bs.gk_list, lb, bs.gk_count, (int)ncls, s));
     }
     ps::SideStream &sd = b->side[0];
     HIP_TRY(hipEventRecord(sd.fork, s));

@@ -126,7 +126,47 @@ __global__ void __launch_bounds__(kPlanBlock) k_bis_plan(const MatDesc *cls_orde
     if (threadIdx.x == 0) *total = carry;
 }
 
+// Sorts each list of shifts handed to the Golub-Kahan kernel (one workgroup per list; the
+// first pass appends to them in no particular order) into increasing queue position, so that
+// the lanes of a Golub-Kahan wavefront take neighbouring shifts of one matrix: their band
+// reads coincide and their step counts are alike.  Lists longer than kSortMax stay as they are.
+constexpr int kSortMax = 8192;
+
+__global__ void __launch_bounds__(kPlanBlock) k_sort_lists(int64_t *lists, ListBases bases, const int64_t *counts) {
+    __shared__ int64_t v[kSortMax];
+    int64_t *list = lists + bases.base[blockIdx.x];
+    const int64_t cnt = counts[blockIdx.x];
+    if (cnt < 2 || cnt > kSortMax) return;
+    int m = 1;
+    while (m < cnt) m <<= 1;
+    for (int i = (int)threadIdx.x; i < m; i += kPlanBlock) v[i] = i < cnt ? list[i] : INT64_MAX;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = (int)threadIdx.x; i < m; i += kPlanBlock) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const bool up = (i & k) == 0;
+                    const int64_t a = v[i], b = v[p];
+                    if ((a > b) == up) {
+                        v[i] = b;
+                        v[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = (int)threadIdx.x; i < cnt; i += kPlanBlock) list[i] = v[i];
+}
+
 }  // namespace
+
+hipError_t launch_sort_lists(int64_t *lists, const ListBases &bases, const int64_t *counts, int nlists,
+                             hipStream_t st) {
+    if (nlists < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)nlists), dim3(kPlanBlock), 0, st, lists, bases, counts);
+    return hipGetLastError();
+}
 
 // Batch kernels exist for even largest half-bandwidths (they compile in every smaller one).
 BisKernel pick_bis(bool batch, int hb, int ktm, int lanes) {

@@ -44,9 +44,11 @@ typedef double2 cd;
 __host__ __device__ constexpr int gram_stride(int hb) { return 4 + 6 * hb; }
 
 // Tests per lane and pass for half-bandwidth HB under test-count mode KTM:
-// 0: one test; 1: three for hb <= 2, two for hb <= 4, one above; 2: two for hb <= 6, else one.
+// 0: one test; 1: three for hb <= 2, two for hb <= 6, one above; 2: two for hb <= 6, else one.
+// (Measured: at hb <= 2 three tests share the row formation best; at hb = 5, 6 two tests beat
+// one by 13-15 %; at hb = 7, 8 a second test's registers cost more than it saves.)
 __host__ __device__ constexpr int tests_per_lane(int hb, int ktm) {
-    return ktm == 0 ? 1 : ktm == 1 ? (hb <= 2 ? 3 : hb <= 4 ? 2 : 1) : (hb <= 6 ? 2 : 1);
+    return ktm == 0 ? 1 : ktm == 1 ? (hb <= 2 ? 3 : hb <= 6 ? 2 : 1) : (hb <= 6 ? 2 : 1);
 }
 
 constexpr int kMaxPasses = 128;   // far above the ~30 passes a shift needs with one test per pass

@@ -1527,13 +1527,14 @@ struct Kern {
         }
     }
 
-    // In the kernels with kl = 4 the four sweeps are compiled as functions of their own.
-    // Inlined there, they put the kernel into heavy register spilling, and some of those
-    // builds returned wrong values for ku <= 2 on the Golub-Kahan path, although the same
-    // source is correct when its lane code runs on the CPU and when the sweeps are compiled
-    // separately: a code-generation problem, guarded by the all-band-shapes GPU test.  The
-    // other kernels keep the sweeps inline (separate sweeps cost about 2x in time there).
-    static constexpr bool kSplitSweeps = KL >= 4;
+    // In the kernels with kl = 4 and singular vectors the four sweeps are compiled as
+    // functions of their own: inlined there (beside the bisection, which those kernels keep),
+    // builds once returned wrong values for ku <= 2 on the Golub-Kahan path although the same
+    // lane code is correct on the CPU and with the sweeps compiled separately.  The sigma-only
+    // kernels no longer hold the bisection and inline the sweeps at every kl (the separate
+    // functions' calls save registers to scratch: twice the time per row at kl = 4).  Every
+    // mode of all 25 band shapes is checked against the oracle by the all-band-shapes test.
+    static constexpr bool kSplitSweeps = KL >= 4 && VEC;
     static __device__ __noinline__ void f1_sep(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
         f1(a, w, s, ln);
     }

@@ -189,6 +189,12 @@ struct GkBatchArgs {
     GkClass cls[kMaxClasses];
 };
 hipError_t launch_gk_batch(const GkBatchArgs &g, int64_t blocks, hipStream_t st);
+// Sorting of the hand-off lists (list k starts at lists + base[k] and holds counts[k] entries).
+struct ListBases {
+    int64_t base[kMaxClasses];
+};
+hipError_t launch_sort_lists(int64_t *lists, const ListBases &bases, const int64_t *counts, int nlists,
+                             hipStream_t st);
 
 size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max);
 // The carve-up of one evaluation workspace (host and device: the batch's Golub-Kahan kernel

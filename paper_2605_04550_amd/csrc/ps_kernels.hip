@@ -564,6 +564,8 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
             if (e != hipSuccess) return e;
             if (tv.end && (e = hipEventRecord(tv.end, st)) != hipSuccess)
                 return e;
+            ListBases lb = {};
+            if ((e = launch_sort_lists(ws.gk_list, lb, ws.gk_count, 1, st)) != hipSuccess) return e;
             hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
             return hipGetLastError();
         }
@@ -574,6 +576,8 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
             return e;
         b.phase = 1;
         if ((e = launch_bis(b, b.hb, a.ktm, a.lanes, chunks, st)) != hipSuccess) return e;
+        ListBases lb = {};
+        if ((e = launch_sort_lists(ws.gk_list, lb, ws.gk_count, 1, st)) != hipSuccess) return e;
         if ((e = hipEventRecord(side->fork, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, side->stream, a, ws);
