@@ -240,10 +240,11 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
 /*
  * ps_label_batch -- ps_label_grid for every matrix of a batch at once (the label generation
  * of Sec. 3.3 runs over many matrices): each level builds the masks of all matrices, evaluates
- * them with one persistent launch per (kl, ku) class as ps_eval_batch does, then marks and
- * excludes for all matrices together.  Matrix m's labels (and sigma) occupy
+ * them as ps_eval_batch does (one bisection launch and one Golub-Kahan launch for all
+ * matrices), then marks and excludes for all matrices together.  Matrix m's labels (and sigma) occupy
  * [offsets[m], offsets[m] + nx ny) of the concatenated outputs (offsets from ps_batch_info).
- *   label_dev  device uint8[total] (required).   sigma_dev: device double[total] or NULL.
+ *   label_dev  device uint8[total] (required; values as in ps_label_grid).
+ *   sigma_dev  device double[total] or NULL.
  *   evals_dev  device int64[1] or NULL: shifts evaluated over all matrices.
  *   ws_dev / ws_bytes >= ps_label_batch_workspace_size(b, o).  Calls on one batch must not
  *   overlap.
@@ -331,7 +332,11 @@ ps_status ps_trace_contour(ps_matrix m, const ps_c128 *seeds_dev, int64_t nseed,
  * unknown points of the lattices of stride 8, 4, 2 and 1 (coarser strides are skipped on
  * small grids) are evaluated in turn, each level followed by the exclusion disks of its
  * points.  All steps run on the stream without host synchronisation.
- *   label_dev  device uint8[ny][nx] (required): 1 where sigma_min <= eps, else 0.
+ *   label_dev  device uint8[ny][nx] (required): 1 where sigma_min <= eps, 0 where it is
+ *              above, 2 where neither is certified: the evaluation stopped at o->max_iter
+ *              (PS_PT_MAXITER) with an estimate above eps.  A capped evaluation sizes no
+ *              exclusion disk; it is labelled 1 when its estimate (an upper bound of sigma_min
+ *              on the Golub-Kahan path) is <= eps.
  *   sigma_dev  device double[ny][nx] or NULL: sigma_min where it was evaluated, -1 where the
  *              point was excluded.
  *   evals_dev  device int64[1] or NULL: the number of shifts evaluated.

@@ -60,6 +60,8 @@ class BandedMatrix:
         if real:
             flags |= PS_REAL_A
         self.handle = ps_create_banded(ptr, kl + ku + 1, n, kl, ku, flags, _stream_handle() if flags & 1 else 0)
+        # the band the handle holds, kept for SigmaMin's check that its band argument still is it
+        self.band = keep.clone() if isinstance(keep, torch.Tensor) else torch.from_numpy(keep.copy())
         del keep
         self.n, self.kl, self.ku, self.fro = ps_matrix_info(self.handle)
         self.real = real
@@ -248,12 +250,21 @@ def backward(mat: BandedMatrix, grad_sigma: torch.Tensor, u: torch.Tensor, v: to
 
 
 class SigmaMin(torch.autograd.Function):
-    """sigma = SigmaMin.apply(band, z, mat): band is the complex128 GB tensor the handle was built from
-    (only its gradient slot is used), z the shifts.  Gradients follow the conjugate-Wirtinger
-    convention torch uses for complex tensors."""
+    """sigma = SigmaMin.apply(band, z, mat): band is a complex128 GB tensor [n, kl + ku + 1] of the
+    matrix (kl, ku and the real flag come from the handle mat), z the shifts.  sigma and both
+    gradients belong to the values band holds at the call: when they differ from the band mat
+    was built from (an in-place edit, another tensor), a handle is built from band for the call.
+    Gradients follow the conjugate-Wirtinger convention torch uses for complex tensors."""
 
     @staticmethod
     def forward(ctx, band, z, mat, tol_norm=1e-10, tol_rel=1e-8):
+        b = band.detach()
+        if tuple(b.shape) != (mat.n, mat.kl + mat.ku + 1):
+            raise ValueError("band has shape %s; the handle's matrix needs (%d, %d)"
+                             % (tuple(b.shape), mat.n, mat.kl + mat.ku + 1))
+        if not torch.equal(b.to(mat.band.device, torch.complex128), mat.band):
+            real = mat.real and not bool(torch.any(b.imag != 0))   # an edit may leave A complex
+            mat = BandedMatrix(b, mat.n, mat.kl, mat.ku, real=real)
         r = sigma_min(mat, z.detach(), want_vectors=True, tol_norm=tol_norm, tol_rel=tol_rel)
         ctx.mat = mat
         ctx.save_for_backward(r["u"], r["v"])

@@ -844,7 +844,7 @@ extern "C" {
 // compacted indices, compacted sigma and the evaluation counter.
 static size_t label_aux_bytes(int64_t npts) {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return 2 * al((size_t)npts) + 2 * al(sizeof(int64_t) * (size_t)npts) + 256;
+    return 2 * al((size_t)npts) + 2 * al(sizeof(int64_t) * (size_t)npts) + al(sizeof(int32_t) * (size_t)npts) + 256;
 }
 
 ps_status ps_label_workspace_size(ps_matrix m, const ps_grid *g, const ps_opts *o, size_t *bytes) {
@@ -884,11 +884,13 @@ ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts
     uint8_t *mask = status + al((size_t)npts);
     int64_t *idx = (int64_t *)(mask + al((size_t)npts));
     double *sig_c = (double *)((char *)idx + al(sizeof(int64_t) * (size_t)npts));
-    int64_t *evals = (int64_t *)((char *)sig_c + al(sizeof(double) * (size_t)npts));
+    int32_t *info_c = (int32_t *)((char *)sig_c + al(sizeof(double) * (size_t)npts));
+    int64_t *evals = (int64_t *)((char *)info_c + al(sizeof(int32_t) * (size_t)npts));
     if (evals_dev) evals = evals_dev;
     ps::Workspace w;
     ps::EvalArgs a;
     if ((st = prepare_eval(m, npts, r, ws_dev, evb, sig_c, nullptr, nullptr, &w, &a))) return st;
+    a.info = info_c;
     a.mode = ps::kShiftGrid;
     a.ga = g->a;
     a.gb = g->b;
@@ -907,7 +909,7 @@ ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts
         HIP_TRY(ps::launch_label_mask(status, g->nx, npts, stride, mask, s));
         HIP_TRY(ps::launch_compact_mask(mask, npts, idx, w.count, w.blocksums, w.queue, s));
         HIP_TRY(ps::launch_eval(a, w, s, &m->side));
-        HIP_TRY(ps::launch_label_update(g->a, g->b, g->c, g->d, g->nx, g->ny, idx, w.count, lattice, sig_c, eps,
+        HIP_TRY(ps::launch_label_update(g->a, g->b, g->c, g->d, g->nx, g->ny, idx, w.count, lattice, sig_c, info_c, eps,
                                         r.tol_norm * m->fro, r.tol_rel, status, sigma_dev, evals, s));
     }
     HIP_TRY(ps::launch_label_finish(status, label_dev, npts, s));
@@ -1420,7 +1422,7 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
 static size_t blabel_aux_bytes(ps_batch b) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t tot = (size_t)b->total;
-    return 2 * al(tot) + al(sizeof(void *) * (size_t)b->nmat) + 2 * al(8 * tot) + al(8 * (size_t)b->nmat) + 256;
+    return 2 * al(tot) + al(sizeof(void *) * (size_t)b->nmat) + 2 * al(8 * tot) + al(4 * tot) + al(8 * (size_t)b->nmat) + 256;
 }
 
 ps_status ps_label_batch_workspace_size(ps_batch b, const ps_opts *o, size_t *bytes) {
@@ -1454,7 +1456,8 @@ ps_status ps_label_batch(ps_batch b, double eps, const ps_opts *o, void *ws_dev,
     uint8_t **mptr = (uint8_t **)(mask + al(tot));
     int64_t *idx = (int64_t *)((char *)mptr + al(sizeof(void *) * (size_t)b->nmat));
     double *sig_c = (double *)((char *)idx + al(8 * tot));
-    int64_t *counts = (int64_t *)((char *)sig_c + al(8 * tot));
+    int32_t *info_c = (int32_t *)((char *)sig_c + al(8 * tot));
+    int64_t *counts = (int64_t *)((char *)info_c + al(4 * tot));
     int64_t *evals = (int64_t *)((char *)counts + al(8 * (size_t)b->nmat));
     if (evals_dev) evals = evals_dev;
     hipStream_t s = (hipStream_t)stream;
@@ -1469,11 +1472,11 @@ ps_status ps_label_batch(ps_batch b, double eps, const ps_opts *o, void *ws_dev,
     for (; stride >= 1; stride /= 2) {
         const int64_t lattice = ((nymax + stride - 1) / stride) * ((nxmax + stride - 1) / stride);
         HIP_TRY(ps::launch_blabel_mask(b->desc_caller, b->nmat, b->max_npts, status, stride, mask, s));
-        if ((st = batch_eval_core(b, (const uint8_t *const *)mptr, r, (char *)ws_dev, idx, counts, sig_c, nullptr,
+        if ((st = batch_eval_core(b, (const uint8_t *const *)mptr, r, (char *)ws_dev, idx, counts, sig_c, info_c,
                                   nullptr, s)))
             return st;
-        HIP_TRY(ps::launch_blabel_update(b->desc_caller, b->nmat, lattice, idx, counts, sig_c, eps, r.tol_norm,
-                                         r.tol_rel, status, sigma_dev, evals, s));
+        HIP_TRY(ps::launch_blabel_update(b->desc_caller, b->nmat, lattice, idx, counts, sig_c, info_c, eps,
+                                         r.tol_norm, r.tol_rel, status, sigma_dev, evals, s));
     }
     HIP_TRY(ps::launch_label_finish(status, label_dev, b->total, s));
     return ok();

@@ -295,17 +295,18 @@ hipError_t launch_label_init(uint8_t *status, double *sig_out, int64_t npts, int
 hipError_t launch_label_mask(const uint8_t *status, int64_t nx, int64_t npts, int stride, uint8_t *mask,
                              hipStream_t st);
 hipError_t launch_label_update(double a, double b, double c, double d, int64_t nx, int64_t ny, const int64_t *idx,
-                               const int64_t *count, int64_t max_count, const double *sigma, double eps,
-                               double tol_abs, double tol_rel, uint8_t *status, double *sig_out, int64_t *evals,
-                               hipStream_t st);
+                               const int64_t *count, int64_t max_count, const double *sigma, const int32_t *info,
+                               double eps, double tol_abs, double tol_rel, uint8_t *status, double *sig_out,
+                               int64_t *evals, hipStream_t st);
 hipError_t launch_label_finish(const uint8_t *status, uint8_t *label, int64_t npts, hipStream_t st);
 hipError_t launch_blabel_init(const MatDesc *mats, int nmat, int64_t max_npts, uint8_t *status, double *sig_out,
                               uint8_t *mask_base, uint8_t **mask_ptrs, int64_t *evals, hipStream_t st);
 hipError_t launch_blabel_mask(const MatDesc *mats, int nmat, int64_t max_npts, const uint8_t *status, int stride,
                               uint8_t *mask, hipStream_t st);
 hipError_t launch_blabel_update(const MatDesc *mats, int nmat, int64_t max_count, const int64_t *idx,
-                                const int64_t *counts, const double *sigma, double eps, double tol_norm,
-                                double tol_rel, uint8_t *status, double *sig_out, int64_t *evals, hipStream_t st);
+                                const int64_t *counts, const double *sigma, const int32_t *info, double eps,
+                                double tol_norm, double tol_rel, uint8_t *status, double *sig_out, int64_t *evals,
+                                hipStream_t st);
 hipError_t launch_contour_seeds(double a, double b, double c, double d, int64_t nx, int64_t ny, const double *sigma,
                                 double eps, double2 *seeds, int64_t max_seeds, int64_t *count, int64_t *blocksums,
                                 unsigned long long *scratch_queue, hipStream_t st);

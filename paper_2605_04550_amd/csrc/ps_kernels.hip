@@ -190,7 +190,17 @@ hipError_t launch_contour_seeds(double a, double b, double c, double d, int64_t 
 
 // ------------------------------------------------------------------------ exclusion-region labels
 // Status of a grid point: 0 unknown, 1 sigma <= eps (evaluated), 2 sigma > eps (evaluated, or
-// inside the exclusion disk of an evaluated point).
+// inside the exclusion disk of an evaluated point), 3 undecided: the evaluation stopped at its
+// iteration cap (PS_PT_MAXITER) with an estimate above eps.  A capped estimate is not the
+// certified value: such a point gets no exclusion disk, and it is labelled 1 only when the
+// estimate, an upper bound of sigma_min on the Golub-Kahan path, is <= eps.
+
+// The outcome of an evaluated point from its sigma and info word.
+__device__ __forceinline__ uint8_t label_status(double sg, int32_t info, double eps) {
+    const bool capped = (info & PS_PT_MAXITER) != 0;
+    if (sg <= eps && !(capped && (info & PS_PT_BISECT))) return 1;
+    return capped ? 3 : 2;
+}
 
 __global__ void k_label_init(uint8_t *status, double *sig_out, int64_t npts, int64_t *evals) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,14 +219,14 @@ __global__ void k_label_mask(const uint8_t *status, int64_t nx, int64_t npts, in
     mask[t] = (uint8_t)(status[t] == 0 && i % stride == 0 && j % stride == 0);
 }
 
-__global__ void k_label_mark(const int64_t *idx, const int64_t *count, const double *sigma, double eps,
-                             uint8_t *status, double *sig_out, int64_t *evals) {
+__global__ void k_label_mark(const int64_t *idx, const int64_t *count, const double *sigma, const int32_t *info,
+                             double eps, uint8_t *status, double *sig_out, int64_t *evals) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = *count;
     if (p == 0 && evals) *evals += c;
     if (p >= c) return;
     const int64_t f = idx[p];
-    status[f] = sigma[p] <= eps ? 1 : 2;
+    status[f] = label_status(sigma[p], info[p], eps);
     if (sig_out) sig_out[f] = sigma[p];
 }
 
@@ -225,10 +235,11 @@ __global__ void k_label_mark(const int64_t *idx, const int64_t *count, const dou
 // |z - z0| < sigma(z0) - eps - margin has sigma(z) > eps, where margin (twice the evaluation
 // tolerance) covers the error of the computed sigma(z0).
 __global__ void __launch_bounds__(256) k_label_exclude(EdgeGrid g, const int64_t *idx, const int64_t *count,
-                                                       const double *sigma, double eps, double tol_abs,
-                                                       double tol_rel, uint8_t *status) {
+                                                       const double *sigma, const int32_t *info, double eps,
+                                                       double tol_abs, double tol_rel, uint8_t *status) {
     const int64_t p = blockIdx.x;
     if (p >= *count) return;
+    if (info[p] & PS_PT_MAXITER) return;       // not certified: no exclusion disk
     const double sg = sigma[p];
     const double rho = sg - eps - 2.0 * (tol_abs + tol_rel * sg);
     if (!(rho > 0.0)) return;
@@ -253,7 +264,7 @@ __global__ void __launch_bounds__(256) k_label_exclude(EdgeGrid g, const int64_t
 
 __global__ void k_label_finish(const uint8_t *status, uint8_t *label, int64_t npts) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < npts) label[t] = (uint8_t)(status[t] == 1);
+    if (t < npts) label[t] = status[t] == 1 ? 1 : status[t] == 3 ? 2 : 0;
 }
 
 static EdgeGrid make_edge_grid(double a, double b, double c, double d, int64_t nx, int64_t ny) {
@@ -283,15 +294,15 @@ hipError_t launch_label_mask(const uint8_t *status, int64_t nx, int64_t npts, in
 }
 
 hipError_t launch_label_update(double a, double b, double c, double d, int64_t nx, int64_t ny, const int64_t *idx,
-                               const int64_t *count, int64_t max_count, const double *sigma, double eps,
-                               double tol_abs, double tol_rel, uint8_t *status, double *sig_out, int64_t *evals,
-                               hipStream_t st) {
+                               const int64_t *count, int64_t max_count, const double *sigma, const int32_t *info,
+                               double eps, double tol_abs, double tol_rel, uint8_t *status, double *sig_out,
+                               int64_t *evals, hipStream_t st) {
     if (max_count < 1) return hipSuccess;
     hipLaunchKernelGGL(k_label_mark, dim3((unsigned)((max_count + 255) / 256)), dim3(256), 0, st, idx, count, sigma,
-                       eps, status, sig_out, evals);
+                       info, eps, status, sig_out, evals);
     const EdgeGrid g = make_edge_grid(a, b, c, d, nx, ny);
-    hipLaunchKernelGGL(k_label_exclude, dim3((unsigned)max_count), dim3(256), 0, st, g, idx, count, sigma, eps, tol_abs,
-                       tol_rel, status);
+    hipLaunchKernelGGL(k_label_exclude, dim3((unsigned)max_count), dim3(256), 0, st, g, idx, count, sigma, info, eps,
+                       tol_abs, tol_rel, status);
     return hipGetLastError();
 }
 
@@ -326,7 +337,7 @@ __global__ void k_blabel_mask(const MatDesc *mats, const uint8_t *status, int st
 }
 
 __global__ void k_blabel_mark(const MatDesc *mats, const int64_t *idx, const int64_t *counts, const double *sigma,
-                              double eps, uint8_t *status, double *sig_out, int64_t *evals) {
+                              const int32_t *info, double eps, uint8_t *status, double *sig_out, int64_t *evals) {
     const int m = blockIdx.y;
     const MatDesc d = mats[m];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -335,17 +346,19 @@ __global__ void k_blabel_mark(const MatDesc *mats, const int64_t *idx, const int
     if (p >= c) return;
     const int64_t f = idx[d.out_off + p];
     const double sg = sigma[d.out_off + p];
-    status[d.out_off + f] = sg <= eps ? 1 : 2;
+    status[d.out_off + f] = label_status(sg, info[d.out_off + p], eps);
     if (sig_out) sig_out[d.out_off + f] = sg;
 }
 
 __global__ void __launch_bounds__(256) k_blabel_exclude(const MatDesc *mats, const int64_t *idx,
-                                                        const int64_t *counts, const double *sigma, double eps,
-                                                        double tol_norm, double tol_rel, uint8_t *status) {
+                                                        const int64_t *counts, const double *sigma,
+                                                        const int32_t *info, double eps, double tol_norm,
+                                                        double tol_rel, uint8_t *status) {
     const int m = blockIdx.y;
     const MatDesc d = mats[m];
     const int64_t p = blockIdx.x;
     if (p >= counts[m]) return;
+    if (info[d.out_off + p] & PS_PT_MAXITER) return;   // not certified: no exclusion disk
     const double sg = sigma[d.out_off + p];
     const double rho = sg - eps - 2.0 * (tol_norm * d.normA + tol_rel * sg);
     if (!(rho > 0.0)) return;
@@ -392,13 +405,14 @@ hipError_t launch_blabel_mask(const MatDesc *mats, int nmat, int64_t max_npts, c
 }
 
 hipError_t launch_blabel_update(const MatDesc *mats, int nmat, int64_t max_count, const int64_t *idx,
-                                const int64_t *counts, const double *sigma, double eps, double tol_norm,
-                                double tol_rel, uint8_t *status, double *sig_out, int64_t *evals, hipStream_t st) {
+                                const int64_t *counts, const double *sigma, const int32_t *info, double eps,
+                                double tol_norm, double tol_rel, uint8_t *status, double *sig_out, int64_t *evals,
+                                hipStream_t st) {
     if (max_count < 1) return hipSuccess;
     hipLaunchKernelGGL(k_blabel_mark, dim3((unsigned)((max_count + 255) / 256), (unsigned)nmat), dim3(256), 0, st,
-                       mats, idx, counts, sigma, eps, status, sig_out, evals);
+                       mats, idx, counts, sigma, info, eps, status, sig_out, evals);
     hipLaunchKernelGGL(k_blabel_exclude, dim3((unsigned)max_count, (unsigned)nmat), dim3(256), 0, st, mats, idx,
-                       counts, sigma, eps, tol_norm, tol_rel, status);
+                       counts, sigma, info, eps, tol_norm, tol_rel, status);
     return hipGetLastError();
 }
 

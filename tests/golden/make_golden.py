@@ -15,7 +15,8 @@ Sets (file ``tests/golden/<set>.npz``):
                      Gershgorin box, all 256 points.
   grcar400_vec       Grcar n=400, 32 seeded points of the 256x256 grid on [-1.5,3]x[-3.5,3.5],
                      with singular vectors and the two smallest singular values.
-  batch_pts          One seeded point for each matrix of the 64-matrix batch with n <= 1200.
+  batch_pts          Two seeded masked points for each matrix of the 64-matrix batch with
+                     n <= 5000 (14 matrices).
   paper_labels       The first three matrices of the label workload of Sec. 3.3 (n = 64,
                      100x100 grid on [-4,4]^2): sigma at all 10^4 points and the labels
                      sigma <= 0.01 (keys sigma0.., label0..).
@@ -105,15 +106,16 @@ def batch_pts(threads):
     rng = np.random.default_rng(W.SEED_BASE + 104)
     rows = []
     for m, mat in enumerate(w["mats"]):
-        if mat["band"].n > 1200:
+        if mat["band"].n > 5000:
             continue
         cand = oracle.compact_mask(mat["mask"])
-        k = int(rng.choice(cand))
-        zz = oracle.grid_points(mat["grid"])[k]
-        r = oracle.sigma_min(mat["band"], [zz], all_sv=True, nthreads=threads, parallel_pairs=True)
-        s1, s2 = _two_smallest(r["sall"])
-        rows.append((m, k, zz, r["sigma"][0], s2[0]))
-        print("batch matrix", m, "n", mat["band"].n, flush=True)
+        for k in np.sort(rng.choice(cand, size=2, replace=False)):
+            zz = oracle.grid_points(mat["grid"])[int(k)]
+            t = time.time()
+            r = oracle.sigma_min(mat["band"], [zz], all_sv=True, nthreads=threads, parallel_pairs=True)
+            s1, s2 = _two_smallest(r["sall"])
+            rows.append((m, int(k), zz, r["sigma"][0], s2[0]))
+            print("batch matrix", m, "n", mat["band"].n, "point", int(k), "%.0f s" % (time.time() - t), flush=True)
     m, k, zz, s, s2 = map(np.array, zip(*rows))
     _save("batch_pts", mat=m.astype(np.int64), idx=k.astype(np.int64), z=zz.astype(complex), sigma=s, s2=s2)
 

@@ -71,6 +71,50 @@ def test_labels_edge_cases():
             assert lab.all() and ev == grid.npts        # no exclusion possible
 
 
+def test_labels_with_capped_evaluations():
+    """Labels when evaluations stop at a low iteration cap (Golub-Kahan only, max_iter = 2): on
+    the Toeplitz (0.25, 0, 1) matrix outside the symbol curve the process needs hundreds of
+    steps, so many points end with PS_PT_MAXITER and an estimate above eps.  Those points are
+    reported as undecided (2) and size no exclusion disk: every 1 and every 0 still agrees with
+    the plain method at the default cap (away from sigma = eps within the tolerance), for one
+    matrix and for a batch."""
+    api = _api()
+    import torch
+    band = W.toeplitz(400, 0.25, 0.0, 1.0)
+    grid = W.Grid(-2.0, 2.0, -2.0, 2.0, 64, 64)
+    eps = 1e-2
+    mat = api.BandedMatrix.from_band(band)
+    full = api.eval_grid(mat, grid, eps=eps)
+    s = full["sigma"].cpu().numpy()
+    assert np.all((full["info"].cpu().numpy() & 2) == 0)
+    sure = np.abs(s - eps) > 2 * tol(band.fro, s)
+    ref = full["sens"].cpu().numpy()
+    r = api.label_grid(mat, grid, eps, max_iter=2, bisect=False)
+    lab = r["label"].cpu().numpy().ravel()
+    und = lab == 2
+    print("capped labels: %d undecided of %d" % (und.sum(), lab.size), flush=True)
+    assert und.sum() > 0 and set(np.unique(lab)) <= {0, 1, 2}
+    dec = ~und & sure
+    assert np.array_equal(lab[dec], ref[dec])
+    # batch: the same matrix twice, plus a normal matrix whose labels are known exactly
+    b2 = W.diagonal(np.linspace(-1, 1, 50) + 0.3j)
+    g2 = W.Grid(-1.5, 1.5, -1.0, 1.0, 33, 21)
+    mats = [api.BandedMatrix.from_band(b) for b in (band, band, b2)]
+    batch = api.BandedBatch(mats, [grid, grid, g2])
+    rb = batch.label(eps, max_iter=2, bisect=False)
+    lb = rb["label"].cpu().numpy()
+    for m in range(2):
+        lm = lb[rb["offsets"][m]:rb["offsets"][m] + grid.npts]
+        assert np.array_equal(lm == 2, und)
+        assert np.array_equal(lm[dec], ref[dec])
+    l3 = lb[rb["offsets"][2]:rb["offsets"][2] + g2.npts]
+    z3 = oracle.grid_points(g2)
+    d3 = np.min(np.abs(z3[:, None] - (np.linspace(-1, 1, 50) + 0.3j)[None]), axis=1)   # normal: exact
+    dec3 = (l3 != 2) & (np.abs(d3 - eps) > 2 * tol(b2.fro, d3))
+    print("capped labels, normal matrix: %d decided of %d" % (dec3.sum(), l3.size), flush=True)
+    assert dec3.any() and np.array_equal(l3[dec3] == 1, (d3 <= eps)[dec3])
+
+
 def test_batched_labels_match_single_matrix_and_oracle():
     """ps_label_batch over matrices of the label workload (plus one matrix on a small ragged
     grid of its own): per matrix the labels of ps_label_grid and, for the three with stored

@@ -160,6 +160,33 @@ def test_sigmamin_autograd_function():
     np.testing.assert_allclose(ab.grad.cpu().numpy(), gb.cpu().numpy(), atol=1e-8)
 
 
+def test_sigmamin_follows_an_edited_band():
+    """SigmaMin with a band tensor whose values differ from the handle's (edited in place after
+    the handle was built): sigma and both gradients are those of the edited matrix, equal to a
+    fresh handle's; with the band unchanged the handle is used as it is."""
+    api = _api()
+    import torch
+    band = W.grcar(40)
+    mat = api.BandedMatrix.from_band(band)
+    ab = torch.tensor(band.ab, dtype=torch.complex128, device="cuda")
+    ab[5, band.ku] += 0.75                  # A[5][5] += 0.75, after mat was built
+    ab.requires_grad_(True)
+    z = torch.tensor([0.5 + 1.5j, 2.0 - 1.0j, 1.2 + 0.1j], dtype=torch.complex128, device="cuda", requires_grad=True)
+    w = torch.tensor([1.0, -2.0, 0.5], device="cuda", dtype=torch.float64)
+    s = api.SigmaMin.apply(ab, z, mat)
+    (s * w).sum().backward()
+    fresh = api.BandedMatrix(ab.detach(), band.n, band.kl, band.ku, real=mat.real)   # the edit keeps A real
+    r = api.sigma_min(fresh, z.detach(), want_vectors=True)
+    gz, gb = api.backward(fresh, w, r["u"], r["v"])
+    old = api.sigma_min(mat, z.detach())["sigma"]
+    assert not torch.allclose(old, r["sigma"])            # the edit changes sigma
+    np.testing.assert_array_equal(s.detach().cpu().numpy(), r["sigma"].cpu().numpy())
+    np.testing.assert_allclose(z.grad.cpu().numpy(), gz.cpu().numpy(), atol=1e-8)
+    np.testing.assert_allclose(ab.grad.cpu().numpy(), gb.cpu().numpy(), atol=1e-8)
+    with pytest.raises(ValueError):
+        api.SigmaMin.apply(ab.detach()[:-1], z.detach(), mat)
+
+
 def test_contour_seeds_vs_oracle():
     """ps_contour_seeds on the grcar100 grid (the GPU's own sigma values feed both sides, so
     the sign decisions are the same): same edges in the same order, same points."""
