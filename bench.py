@@ -150,14 +150,15 @@ def tests_per_lane(hb, tests=0):
         return 1
     if tests == 3:
         return 2 if hb <= 6 else 1
-    return 3 if hb <= 2 else 2 if hb <= 6 else 1
+    return 3 if hb <= 2 else 2 if hb <= 5 else 1
 
 
 def row_flops(hb, tests_per_pass):
     """FP64 operations of one row of a bisection pass (adds, multiplies, FMAs as executed, an FMA
     counting 2): forming the row of (zI-A)^H(zI-A) from the Gram band, 8 hb + 5, once per pass;
-    per test the row of L D L^H (4 hb (hb - 1)), the scaled multipliers and the pivot update
-    (6 hb), the shift and 1/pivot by the hardware reciprocal with two Newton steps (10)."""
+    per test the rank-one update of the trailing window (4 hb (hb - 1) off the diagonal), the
+    scaled pivot column and the diagonal updates (6 hb), the shift and 1/pivot by the hardware
+    reciprocal with two Newton steps (10)."""
     return 8 * hb + 5 + tests_per_pass * (4 * hb * (hb - 1) + 6 * hb + 10)
 
 
@@ -670,7 +671,7 @@ def batch_bench(args, dev):
             "bisection_shifts": n_bis, "golub_kahan_shifts": n_gk,
             "bisection_passes_mean": float(passes_all.mean()) if passes_all.size else 0.0,
             "maxiter_shifts": int(np.sum((info[np.concatenate([np.arange(offs[m], offs[m] + counts[m]) for m in range(len(bands))])] & 2) != 0)),
-            "plan": {"lanes": 1, "tests": "default (3 for kl+ku<=2, 2 for <=6, 1 above)"},
+            "plan": {"lanes": 1, "tests": "default (3 for kl+ku<=2, 2 for <=5, 1 above)"},
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded masked shifts, one per matrix, each one ps_eval_points call with "

@@ -106,7 +106,7 @@ typedef struct {
                              bisection (0 = default 1; 1, 2, 4, or 64 = one wavefront per
                              shift, the plain per-shift form; 64 is refused in batch mode) */
     int32_t tests;        /* sigma only: tests per lane and bisection pass (0 = default 2;
-                             1: one; 2: three for kl + ku <= 2, two for <= 6, one above;
+                             1: one; 2: three for kl + ku <= 2, two for <= 5, one above;
                              3: two for kl + ku <= 6, one above).  A pass splits the bracket
                              into lanes * tests + 1 parts.  Set by ps_autotune.            */
 } ps_opts;

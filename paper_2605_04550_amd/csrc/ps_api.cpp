@@ -1322,6 +1322,8 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
         ba.batch = 1;
         ba.mats = b->desc_lpt;
         ba.nmat = b->nmat;
+        ba.mlo = 0;
+        ba.mhi = b->nmat - 1;
         ba.chunkfirst = bs.chunkfirst;
         ba.total_chunks = bs.total_chunks;
         ba.counts = counts_dev;

@@ -44,11 +44,12 @@ typedef double2 cd;
 __host__ __device__ constexpr int gram_stride(int hb) { return 4 + 6 * hb; }
 
 // Tests per lane and pass for half-bandwidth HB under test-count mode KTM:
-// 0: one test; 1: three for hb <= 2, two for hb <= 6, one above; 2: two for hb <= 6, else one.
-// (Measured: at hb <= 2 three tests share the row formation best; at hb = 5, 6 two tests beat
-// one by 13-15 %; at hb = 7, 8 a second test's registers cost more than it saves.)
+// 0: one test; 1: three for hb <= 2, two for hb <= 5, one above; 2: two for hb <= 6, else one.
+// (Measured: at hb <= 2 three tests share the row formation best; at hb = 5 two tests beat one
+// by about 10 %; at hb = 6 two tests take the registers of a second wavefront per SIMD and
+// gain nothing; at hb = 7, 8 a second test does not fit.)
 __host__ __device__ constexpr int tests_per_lane(int hb, int ktm) {
-    return ktm == 0 ? 1 : ktm == 1 ? (hb <= 2 ? 3 : hb <= 6 ? 2 : 1) : (hb <= 6 ? 2 : 1);
+    return ktm == 0 ? 1 : ktm == 1 ? (hb <= 2 ? 3 : hb <= 5 ? 2 : 1) : (hb <= 6 ? 2 : 1);
 }
 
 constexpr int kMaxPasses = 128;   // far above the ~30 passes a shift needs with one test per pass
@@ -87,136 +88,148 @@ __device__ __forceinline__ double2 kload2(const double *p) {
 // on with meaningless values): every pass then costs the same known work, and the lanes of a
 // wavefront run in step anyway.  hmin = min_i H[i][i] = min_i |M e_i|^2 >= sigma_min^2.
 //
-// Row i, m = i - e (e = hb .. 1):  w_e = H[i][m] - sum_{e2 > e} w_e2 conj(L[m][i - e2]),
-// L[i][m] = w_e / d_m,  d_i = H[i][i] - t^2 - sum_e Re(w_e conj(L[i][m])).
-// Registers: the hb previous rows of the factor sit in hb slots, row r in slot r mod hb:
-// Ls[k][f] = L[r][r-1-f] (f = 0 .. hb-2) and Qs[k] = 1 / d_r; rows before the first are zero.
-// The row loop is unrolled by hb, so that every slot index is a compile-time constant and a
-// new row simply takes the registers of the row hb back (whose last use is this row's e = hb
-// term): nothing is shifted from register to register.
+// Right-looking elimination over a sliding window.  Before step i the registers hold the
+// trailing matrix S (H with the updates of pivots 0 .. i-1 applied) on rows i .. i+hb-1,
+// columns from i on; step i
+//   brings in row i+hb of H (no earlier pivot reaches it),
+//   takes the pivot d_i = S[i][i] (the test fails if it is not positive), and
+//   updates S[i+k][i+k'] -= S[i+k][i] conj(S[i+k'][i]) / d_i for 1 <= k' <= k <= hb.
+// The hb^2 / 2 updates of a step are independent of each other; only the next pivot
+// (row i+1's diagonal, updated first) and its reciprocal lie on the path from step to step.
+// Row r sits in slot r mod (hb+1), its entry (r, r-e) at position e of the slot: a row keeps
+// its registers while the window slides, and the row loop is unrolled by hb+1 so that every
+// slot index is a compile-time constant.
 template <int HB, int KT>
 __device__ __forceinline__ unsigned pass(const double *gb, int64_t n, double x, double y, const double (&sh)[KT],
                                          double &hmin) {
     constexpr int RS = gram_stride(HB);
-    constexpr int HA = HB > 1 ? HB - 1 : 1;
-    cd Ls[KT][HB][HA];
-    double Qs[KT][HB];
+    constexpr int NS = HB + 1;
+    cd S[KT][NS][NS];
+    double dcur[KT], rcur[KT];
     bool ok[KT];
-#pragma unroll
-    for (int j = 0; j < KT; ++j) {
-        ok[j] = true;
-#pragma unroll
-        for (int k = 0; k < HB; ++k) {
-            Qs[j][k] = 0.0;
-#pragma unroll
-            for (int f = 0; f < HA; ++f) Ls[j][k][f] = make_double2(0.0, 0.0);
-        }
-    }
-    // The Gram band is the same for every lane of the wavefront and does not change during
-    // the launch: read through the constant address space, its rows come in by scalar loads
-    // into scalar registers (one copy per wavefront, used directly as operands), instead of
-    // vector loads that would copy every value into all 64 lanes.
     const double zz = fma(x, x, y * y);
     double hm = 0x1p1000;
-    // Row data of the Gram band (RS doubles).  The part a row needs first (the diagonal entry
-    // and the PFB outermost e blocks, all of it at narrow bands) is loaded one row ahead, so
-    // that those scalar loads are in flight while the previous row is computed; the rest of
-    // the row is loaded when the row starts and arrives while its first blocks are computed.
-    // (Loading every row completely ahead would not fit the scalar register file at wider
-    // bands.)  The band has zero rows past n, so the load ahead of the last row stays inside.
-    constexpr int PFB = HB <= 2 ? HB : HB <= 4 ? 2 : 1;
+    // Row r of H - sh[j] I (the diagonal shifted per test) into slot F.  The Gram band is the
+    // same for every lane of the wavefront and does not change during the launch: read through
+    // the constant address space, it comes in by scalar loads into scalar registers (one copy
+    // per wavefront, used directly as operands).  Each formula has one scalar operand per
+    // instruction (the limit of the instruction set); with contraction off the compiler does
+    // not fuse them into a form with two.  The band has zero rows past n (read by the last hb
+    // steps, never pivoted).
     struct Row {
         double v[RS];
     };
-    auto load_part = [&](Row &rw, int64_t i, bool ahead) {
-        const double *r = uniform_ptr(gb + i * RS);
-        if (ahead) {
-            const double2 a = kload2(r), b = kload2(r + 2);
-            rw.v[0] = a.x;
-            rw.v[1] = a.y;
-            rw.v[2] = b.x;
-            rw.v[3] = b.y;
+    auto load_row = [&](int64_t r) {
+        Row rw;
+        const double *p = uniform_ptr(gb + r * RS);
+#pragma unroll
+        for (int q = 0; q < RS; q += 2) {
+            const double2 t = kload2(p + q);
+            rw.v[q] = t.x;
+            rw.v[q + 1] = t.y;
         }
+        return rw;
+    };
+    auto form = [&](const Row &rw, int64_t r, cd (&h)[HB + 1]) {
+#pragma clang fp contract(off)
+        const double hd = fma(-x, rw.v[1], rw.v[0] + fma(-y, rw.v[2], zz));
+        hm = r < n ? fmin(hm, hd) : hm;
+        h[0] = make_double2(hd, 0.0);
 #pragma unroll
         for (int e = 1; e <= HB; ++e) {
-            if ((e > HB - PFB) != ahead) continue;
-#pragma unroll
-            for (int q = 4 + 6 * (e - 1); q < 10 + 6 * (e - 1); q += 2) {
-                const double2 t = kload2(r + q);
-                rw.v[q] = t.x;
-                rw.v[q + 1] = t.y;
-            }
+            const double *q = rw.v + 4 + 6 * (e - 1);   // G, s, d of entry (r, r - e)
+            h[e] = make_double2(fma(-x, q[2], q[0] - y * q[5]), fma(-x, q[3], q[1] + y * q[4]));
         }
     };
-    // row i of the factorisations, held in slot K = i mod hb.  H[i][i-e] is formed just before
-    // its e step (for all tests), with one scalar operand per instruction (the limit of the
-    // instruction set): t = y d_y, t = g_x - t, H_x = t - x s_x (and likewise for H_y); with
-    // contraction off the compiler does not fuse them into a form with two.
-    auto step = [&](int64_t i, Row &rw, auto kc) {
-        constexpr int K = decltype(kc)::value;
-        load_part(rw, i, false);
-        double h0;
-        {
-#pragma clang fp contract(off)
-            h0 = fma(-x, rw.v[1], rw.v[0] + fma(-y, rw.v[2], zz));
-        }
-        hm = fmin(hm, h0);
-        double dd[KT];
-        cd wv[KT][HB + 1], lv[KT][HB + 1];
-#pragma unroll
-        for (int j = 0; j < KT; ++j) dd[j] = h0 - sh[j];
-#pragma unroll
-        for (int e = HB; e >= 1; --e) {
-            const double *q = rw.v + 4 + 6 * (e - 1);   // G, s, d of entry e
-            cd he;
-            {
-#pragma clang fp contract(off)
-                he = make_double2(fma(-x, q[2], q[0] - y * q[5]), fma(-x, q[3], q[1] + y * q[4]));
-            }
-            const int se = (K - e + HB) % HB;   // slot of row i - e (a constant)
+    // s -= c conj(p), and its real part alone on the diagonal
+    auto upd = [](cd &s, const cd c, const cd p) {
+        s.x = fma(-c.x, p.x, fma(-c.y, p.y, s.x));
+        s.y = fma(-c.y, p.x, fma(c.x, p.y, s.y));
+    };
+    auto upd_diag = [](cd &s, const cd c, const cd p) { s.x = fma(-c.x, p.x, fma(-c.y, p.y, s.x)); };
+    // rows 0 .. hb-1 (entries left of column 0 are never read)
+    [&]<int... U>(std::integer_sequence<int, U...>) {
+        auto one = [&](auto uc) {
+            constexpr int R = decltype(uc)::value;
+            cd h[HB + 1];
+            form(load_row(R), R, h);
 #pragma unroll
             for (int j = 0; j < KT; ++j) {
-                cd acc = he;
+                S[j][R][0] = make_double2(h[0].x - sh[j], 0.0);
 #pragma unroll
-                for (int e2 = HB; e2 > e; --e2) {
-                    // acc -= wv[e2] * conj(L[i-e][i-e2]),  L[i-e][i-e2] = Ls[se][e2-e-1]
-                    const cd p = Ls[j][se][e2 - e - 1];
-                    acc.x = fma(-wv[j][e2].x, p.x, fma(-wv[j][e2].y, p.y, acc.x));
-                    acc.y = fma(-wv[j][e2].y, p.x, fma(wv[j][e2].x, p.y, acc.y));
-                }
-                wv[j][e] = acc;
-                lv[j][e] = make_double2(acc.x * Qs[j][se], acc.y * Qs[j][se]);
-                dd[j] = fma(-acc.x, lv[j][e].x, fma(-acc.y, lv[j][e].y, dd[j]));
+                for (int e = 1; e <= HB; ++e) S[j][R][e] = h[e];
             }
-        }
+        };
+        (one(std::integral_constant<int, U>{}), ...);
+    }(std::make_integer_sequence<int, HB>{});
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        ok[j] = true;
+        dcur[j] = S[j][0][0].x;
+        rcur[j] = recip(dcur[j]);
+    }
+    auto step = [&](int64_t i, auto kc) {
+        constexpr int K = decltype(kc)::value;   // slot of row i
+        constexpr int F = (K + HB) % NS;         // slot of the incoming row i + hb
+        const Row rw = load_row(i + HB);         // arrives while the window rows are updated
+        cd cp[KT][HB + 1];                       // S[i+k][i] / d_i
+        double ri[KT];
 #pragma unroll
         for (int j = 0; j < KT; ++j) {
-            ok[j] = ok[j] && dd[j] > 0.0;
-            Qs[j][K] = recip(dd[j]);
+            ok[j] = ok[j] && dcur[j] > 0.0;
+            ri[j] = rcur[j];
 #pragma unroll
-            for (int f = 0; f + 1 < HB; ++f) Ls[j][K][f] = lv[j][f + 1];
+            for (int k = 1; k < HB; ++k) {
+                const cd c = S[j][(K + k) % NS][k];
+                cp[j][k] = make_double2(c.x * ri[j], c.y * ri[j]);
+            }
         }
-    };
-    // one row: the loads of the next row are issued first, then the row is computed; rows are
-    // scheduled one by one (interleaving them would only lengthen register lifetimes)
-    Row cur;
-    load_part(cur, 0, true);
-    auto advance = [&](int64_t i, auto kc) {
-        Row nxt;
-        load_part(nxt, i + 1, true);
-        step(i, cur, kc);
-        cur = nxt;
+        // window rows i+1 .. i+hb-1, row i+1 first: its diagonal is the next pivot
+#pragma unroll
+        for (int k = 1; k < HB; ++k) {
+#pragma unroll
+            for (int j = 0; j < KT; ++j) {
+                cd *row = S[j][(K + k) % NS];
+                const cd c = row[k];
+#pragma unroll
+                for (int k2 = 1; k2 < k; ++k2) upd(row[k - k2], c, cp[j][k2]);
+                upd_diag(row[0], c, cp[j][k]);
+                if (k == 1) {
+                    dcur[j] = row[0].x;
+                    rcur[j] = recip(dcur[j]);
+                }
+            }
+        }
+        // the incoming row
+        cd h[HB + 1];
+        form(rw, i + HB, h);
+#pragma unroll
+        for (int j = 0; j < KT; ++j) {
+            cd *row = S[j][F];
+            const cd c = h[HB];
+            cp[j][HB] = make_double2(c.x * ri[j], c.y * ri[j]);
+            row[0] = make_double2(h[0].x - sh[j], 0.0);
+#pragma unroll
+            for (int e = 1; e < HB; ++e) row[e] = h[e];
+#pragma unroll
+            for (int k2 = 1; k2 < HB; ++k2) upd(row[HB - k2], c, cp[j][k2]);
+            upd_diag(row[0], c, cp[j][HB]);
+            if (HB == 1) {
+                dcur[j] = row[0].x;
+                rcur[j] = recip(dcur[j]);
+            }
+        }
         __builtin_amdgcn_sched_barrier(0);
     };
     int64_t i0 = 0;
-    for (; i0 + HB <= n; i0 += HB) {
+    for (; i0 + NS <= n; i0 += NS) {
         [&]<int... U>(std::integer_sequence<int, U...>) {
-            (advance(i0 + U, std::integral_constant<int, U>{}), ...);
-        }(std::make_integer_sequence<int, HB>{});
+            (step(i0 + U, std::integral_constant<int, U>{}), ...);
+        }(std::make_integer_sequence<int, NS>{});
     }
     [&]<int... U>(std::integer_sequence<int, U...>) {
-        ((i0 + U < n ? advance(i0 + U, std::integral_constant<int, U>{}) : void()), ...);
-    }(std::make_integer_sequence<int, HB>{});
+        ((i0 + U < n ? step(i0 + U, std::integral_constant<int, U>{}) : void()), ...);
+    }(std::make_integer_sequence<int, NS>{});
     hmin = hm;
     unsigned bits = 0;
 #pragma unroll
@@ -379,21 +392,31 @@ __device__ __forceinline__ void run_hb(const BisArgs &a, const MatView &mv, cons
     bisect<HB, tests_per_lane(HB, KTM), L>(a, mv, sf);
 }
 
+// Wavefronts per SIMD the register allocation aims at: two where a single test per lane
+// leaves the window of the widest bands just over half the register file (the allocator then
+// keeps it within half), no demand otherwise.
+__host__ __device__ constexpr int bis_waves(int hb, int kt) { return hb >= 7 && kt == 1 ? 2 : 1; }
+
 // One wavefront per workgroup, one chunk of 64 / L shifts per wavefront.  Half-bandwidths
 // HBLO .. HBHI are compiled in; the chunk's matrix picks one (the same for the whole
 // wavefront).
 template <int HBLO, int HBHI, int KTM, int L>
-__global__ void __launch_bounds__(64) k_bis(BisArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(bis_waves(HBHI, tests_per_lane(HBHI, KTM)))))
+k_bis(BisArgs a) {
     constexpr int SPW = 64 / L;
-    const int64_t b = blockIdx.x;
+    int64_t b = blockIdx.x;
     const int lane = (int)threadIdx.x;
     MatView mv;
     Shift sf;
     int hb;
     if (a.batch) {
-        if (b >= *a.total_chunks) return;
-        // matrix of chunk b: the last k with chunkfirst[k] <= b (longest-first order)
-        int lo = 0, hi = a.nmat - 1;
+        // the launch covers the chunks of mats[mlo .. mhi], numbered on from chunkfirst[mlo]
+        const int64_t c0 = a.chunkfirst[a.mlo];
+        const int64_t c1 = a.mhi + 1 < a.nmat ? a.chunkfirst[a.mhi + 1] : *a.total_chunks;
+        b += c0;
+        if (b >= c1) return;
+        // matrix of chunk b: the last k with chunkfirst[k] <= b
+        int lo = a.mlo, hi = a.mhi;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (a.chunkfirst[mid] <= b) lo = mid;

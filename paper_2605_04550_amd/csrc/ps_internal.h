@@ -138,8 +138,9 @@ struct BisArgs {
     double ga = 0, gb = 0, gc = 0, gd = 0;
     int64_t nx = 1, ny = 1;
     const int64_t *count_dev = nullptr;
-    const MatDesc *mats = nullptr;          // batch: longest-first order
+    const MatDesc *mats = nullptr;          // batch: grouped by kl + ku, longest-first in a group
     int nmat = 0;
+    int mlo = 0, mhi = 0;                   // batch: the launch's matrices mats[mlo .. mhi]
     const int64_t *chunkfirst = nullptr;    // [nmat] first chunk of each matrix
     const int64_t *total_chunks = nullptr;
     const int64_t *counts = nullptr;        // [nmat] shifts per matrix (caller order)
