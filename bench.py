@@ -693,12 +693,12 @@ def batch_bench(args, dev):
         },
     }
     if not args.no_cpu_baseline:
-        # the oracle on a bounded sample: 16 seeded masked points of the smallest matrix,
-        # one point per thread (dense one-sided Jacobi, cyclic pairs)
+        # the oracle on a bounded sample: 32 seeded masked points of the smallest matrix,
+        # one point per thread (dense one-sided Jacobi, cyclic pairs; about 17 s)
         k = int(np.argmin([b.n for b in bands]))
         rng2 = np.random.default_rng(2605_04550 + 12)
         cand = np.flatnonzero(w["mats"][k]["mask"].ravel())
-        zs = _grid_points(w["mats"][k]["grid"])[rng2.choice(cand, size=16, replace=False)]
+        zs = _grid_points(w["mats"][k]["grid"])[rng2.choice(cand, size=32, replace=False)]
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         print("bench: timing the CPU oracle on %d points (n=%d)" % (len(zs), bands[k].n), file=sys.stderr,
               flush=True)
@@ -711,8 +711,9 @@ def batch_bench(args, dev):
         per_shift = dtc / len(zs) / bands[k].n ** 3 * np.sum(ncube * 4915) / nshift
         out_line["cpu_baseline"] = dict(
             value=len(zs) / dtc, unit="shifts/s", cores=threads, kind="oracle",
-            sample="16 seeded masked shifts of the smallest matrix of the batch (n=%d), dense one-sided Jacobi "
-                   "to convergence, one shift per thread over %d threads; %.1f s" % (bands[k].n, threads, dtc),
+            sample="%d seeded masked shifts of the smallest matrix of the batch (n=%d), dense one-sided Jacobi "
+                   "to convergence, one shift per thread over %d threads; %.1f s" % (len(zs), bands[k].n, threads,
+                                                                                      dtc),
             extrapolated_full_workload=dict(value=1.0 / per_shift if per_shift > 0 else None,
                                             unit="shifts/s", note="cost per shift scaled by n^3 to the batch's "
                                                                   "matrices; extrapolated, not measured"))

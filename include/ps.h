@@ -150,8 +150,12 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
  *   sigma_dev  device double[npts] (required).
  *   u_dev, v_dev  device ps_c128[npts][n] or NULL; required when o->want_vectors.
  *              Unit singular vectors with (zI - A) v = sigma u; the joint phase makes the
- *              first entry of v of largest modulus real and positive.  v is the Ritz vector
- *              of the converged Lanczos process (a second pass replays its steps exactly and
+ *              first entry of v of largest modulus real and positive.  For a shift that took
+ *              the inertia bisection (PS_PT_BISECT in info), v comes from four steps of
+ *              inverse iteration with the bisection's last factorisation, L D L^H of
+ *              (zI - A)^H (zI - A) - lo^2 I (lo the bracket's lower end), and
+ *              u = (zI - A) v / |(zI - A) v|.  For the other shifts v is the Ritz vector of
+ *              the converged Lanczos process (a second pass replays its steps exactly and
  *              accumulates it, so vectors cost about twice the steps of sigma alone) and u
  *              one inverse-iteration step from it, u = (zI - A)^{-H} v / |(zI - A)^{-H} v|.
  *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL:

@@ -8,6 +8,9 @@ meet only through the seeded inputs of the ``workloads`` package.
 Contents (each function names the passage of the paper it follows):
   * ``sigma_min``      -- dense one-sided Jacobi SVD per shift (``jacobi.c``), Sec. 2.1 and
                           the third form of the pseudospectrum definition (Sec. 2).
+  * ``smallest_pair_lapack`` -- the same sigma_min with its singular pair from LAPACK's dense
+                          SVD (numpy), for the n = 4000 gradient values; checked against
+                          ``sigma_min`` at small n.
   * ``grid_points``    -- the shift grid G of Sec. 2.1.
   * ``compact_mask``   -- the restricted set R of Sec. 4 as an index list.
   * ``sensitive``      -- the sensitive zone S_eps, Sec. 2.1 eq. (sensitive_zone).
@@ -127,6 +130,32 @@ def svd_dense(M):
     if st != 0:
         raise RuntimeError("oracle Jacobi failed (status %d)" % st)
     return s, U, V
+
+
+def smallest_pair_lapack(band, z):
+    """sigma_n, sigma_{n-1} and the singular pair (u, v) of sigma_n for each shift, from LAPACK's
+    dense SVD of zI - A (Sec. 2.1: sigma_min(z) is the smallest singular value, with M v = sigma u).
+
+    A second dense SVD beside the Jacobi one of ``sigma_min``, for sizes (n in the thousands)
+    where the Jacobi sweeps take too long; the two are checked against each other at small n.
+    Returns a dict with ``sigma``, ``s2`` [npts] and ``u``, ``v`` [npts, n]."""
+    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+    n, kl, ku = int(band.n), int(band.kl), int(band.ku)
+    A = np.zeros((n, n), dtype=np.complex128)
+    for j in range(n):                           # GB layout: ab[j, ku + i - j] = A[i, j]
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            A[i, j] = band.ab[j, ku + i - j]
+    sig = np.empty(z.size)
+    s2 = np.empty(z.size)
+    u = np.empty((z.size, n), dtype=np.complex128)
+    v = np.empty((z.size, n), dtype=np.complex128)
+    for p, zz in enumerate(z):
+        U, S, Vh = np.linalg.svd(zz * np.eye(n) - A)      # S descending
+        sig[p] = S[-1]
+        s2[p] = S[-2] if n > 1 else np.inf
+        u[p] = U[:, -1]
+        v[p] = np.conj(Vh[-1])
+    return dict(sigma=sig, s2=s2, u=u, v=v)
 
 
 def grid_points(grid) -> np.ndarray:

@@ -288,6 +288,40 @@ def test_singular_vectors_residual_and_phase():
         assert abs(v[kmax].imag) < 1e-15 and v[kmax].real > 0
 
 
+def test_lapack_pair_closed_form_and_jacobi():
+    """smallest_pair_lapack (used for the n = 4000 gradients): the distance to the nearest and
+    second-nearest eigenvalue of a diagonal matrix with the matching unit vectors; residuals
+    M v = sigma u, M^H u = sigma v; the Jacobi oracle's sigma_n, sigma_{n-1} and adjoint at n = 60."""
+    lam = np.array([0.5, -1.0 + 1.0j, 2.0j, 1.5 - 0.5j, -0.3])
+    z = np.array([0.4 + 0.1j, 1.0 - 0.2j, -0.5 + 1.7j])
+    r = oracle.smallest_pair_lapack(W.diagonal(lam), z)
+    d = np.abs(z[:, None] - lam[None, :])
+    np.testing.assert_allclose(r["sigma"], np.sort(d, axis=1)[:, 0], rtol=1e-15)
+    np.testing.assert_allclose(r["s2"], np.sort(d, axis=1)[:, 1], rtol=1e-15)
+    for p in range(3):
+        k = int(np.argmin(d[p]))
+        assert abs(abs(r["v"][p, k]) - 1) < 1e-15 and abs(abs(r["u"][p, k]) - 1) < 1e-15
+        np.testing.assert_allclose(r["u"][p, k], r["v"][p, k] * (z[p] - lam[k]) / d[p, k], atol=1e-15)
+    for band in (W.grcar(60), W.random_banded(60, 2, 1, seed=8)):
+        A = W.to_dense(band)
+        zz = np.array([0.7 + 1.2j, 2.1 - 0.4j, -0.2 + 0.1j])
+        a = oracle.smallest_pair_lapack(band, zz)
+        j = oracle.sigma_min(band, zz, want_vectors=True, all_sv=True)
+        s = np.sort(j["sall"], axis=1)
+        nm = np.linalg.norm(A) + 3
+        np.testing.assert_allclose(a["sigma"], s[:, 0], atol=1e-13 * nm)
+        np.testing.assert_allclose(a["s2"], s[:, 1], atol=1e-13 * nm)
+        for p in range(3):
+            M = zz[p] * np.eye(60) - A
+            assert np.linalg.norm(M @ a["v"][p] - a["sigma"][p] * a["u"][p]) <= 1e-13 * nm
+            assert np.linalg.norm(M.conj().T @ a["u"][p] - a["sigma"][p] * a["v"][p]) <= 1e-13 * nm
+        w = np.array([1.0, -0.5, 2.0])
+        ga = oracle.adjoint(band, a["u"], a["v"], w)
+        gj = oracle.adjoint(band, j["u"], j["v"], w)
+        np.testing.assert_allclose(ga[0], gj[0], atol=1e-10)
+        np.testing.assert_allclose(ga[1], gj[1], atol=1e-10)
+
+
 def test_grid_points_definition():
     g = W.Grid(-1.0, 3.0, -2.0, 2.0, 5, 3)
     z = oracle.grid_points(g).reshape(3, 5)
