@@ -407,6 +407,11 @@ def main():
     ap.add_argument("--counter-pass", action="store_true",
                     help="calibration copy + one full-grid launch, for rocprofv3 --pmc")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--lanes", type=int, choices=[1, 2, 4], default=None,
+                    help="batch64: lanes per shift (with --tests: a fixed plan instead of the autotuned one; the "
+                         "counter pass and its summary default to the library's default plan)")
+    ap.add_argument("--tests", type=int, choices=[1, 2, 3], default=None,
+                    help="batch64: tests-per-lane mode (see include/ps.h)")
     ap.add_argument("--trace", type=int, default=0, metavar="NSEED",
                     help="instead of the headline: trace the eps = 1e-2 contour of the workload from NSEED seeds")
     ap.add_argument("--labels", type=int, default=0, metavar="NMAT",
@@ -418,7 +423,7 @@ def main():
     args = ap.parse_args()
     if args.summarize_counters:
         if args.workload == "batch64":
-            summarize_batch_counters(*args.summarize_counters)
+            summarize_batch_counters(*args.summarize_counters, lanes=args.lanes or 1, tests=args.tests or 2)
         else:
             summarize_counters(*args.summarize_counters)
         return
@@ -466,7 +471,7 @@ def batch_source_hash():
     return h.hexdigest()[:16]
 
 
-def batch_stored_traffic():
+def batch_stored_traffic(lanes, tests):
     if not os.path.exists(BATCH_TRAFFIC_FILE):
         return None
     try:
@@ -475,10 +480,12 @@ def batch_stored_traffic():
         return None
     if doc.get("source_hash") != batch_source_hash():
         return None        # kernel or workload changed since the counters were taken
+    if doc.get("plan", {"lanes": 1, "tests_mode": 2}) != {"lanes": lanes, "tests_mode": tests}:
+        return None        # counters taken with another plan
     return doc.get("traffic_bytes_per_launch")
 
 
-def summarize_batch_counters(fetch_csv, write_csv):
+def summarize_batch_counters(fetch_csv, write_csv, lanes=1, tests=2):
     """HBM bytes of the bisection kernel's two launches in one batch call, from two rocprofv3
     --pmc runs of ``--counter-pass``, each counter scaled by its reading for the calibration
     copy of known size."""
@@ -500,15 +507,16 @@ def summarize_batch_counters(fetch_csv, write_csv):
         res[counter] = dict(kib=sum(parts), launches=len(parts), calib_kib=calib, factor=factor,
                             bytes=sum(parts) * 1024.0 * factor)
     traffic = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
-    doc = dict(kernel="ps::bis::k_bis<1, 8, 1, 1>, both launches of one batch64 call",
+    doc = dict(kernel="ps::bis::k_bis<1, 8, %d, %d>, both launches of one batch64 call"
+               % ({1: 0, 2: 1, 3: 2}[tests], lanes), plan={"lanes": lanes, "tests_mode": tests},
                source_hash=batch_source_hash(), traffic_bytes_per_launch=traffic,
                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
                commands=["timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch "
-                         "-o fetch -- python3 bench.py --counter-pass",
+                         "-o fetch -- python3 bench.py --counter-pass --lanes %d --tests %d" % (lanes, tests),
                          "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write "
-                         "-o write -- python3 bench.py --counter-pass",
+                         "-o write -- python3 bench.py --counter-pass --lanes %d --tests %d" % (lanes, tests),
                          "python bench.py --summarize-counters <out>/pmc_fetch/fetch_counter_collection.csv "
-                         "<out>/pmc_write/write_counter_collection.csv"])
+                         "<out>/pmc_write/write_counter_collection.csv --lanes %d --tests %d" % (lanes, tests)])
     with open(BATCH_TRAFFIC_FILE, "w") as f:
         json.dump(doc, f, indent=1)
         f.write("\n")
@@ -529,7 +537,17 @@ def batch_bench(args, dev):
     batch = api.BandedBatch(mats, [m["grid"] for m in w["mats"]])
     masks = [torch.tensor(m["mask"], dtype=torch.uint8, device=dev).contiguous() for m in w["mats"]]
     mtab = batch.mask_table(masks, device=dev)
-    o = api.make_opts()
+    if args.lanes is None and args.tests is None and not args.counter_pass:
+        # the plan: lanes per shift and tests per lane chosen by timing the whole call
+        # (ps_autotune_batch: one untimed call, then nine candidate plans, outside the timed region)
+        tt = time.perf_counter()
+        o = batch.autotune(mtab, device=dev)
+        print("bench: autotuned plan lanes %d tests %d (%.1f s)" % (o.lanes, o.tests, time.perf_counter() - tt),
+              file=sys.stderr, flush=True)
+        tuned = True
+    else:
+        o = api.make_opts(lanes=args.lanes or 0, tests=args.tests or 0)
+        tuned = False
     ws = torch.empty(ps_batch_workspace_size(batch.handle, o), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     nshift = int(sum(int(m["mask"].sum()) for m in w["mats"]))
@@ -542,7 +560,7 @@ def batch_bench(args, dev):
         torch.cuda.synchronize()
         print("bench: calibration copy done (%d bytes each way)" % CALIB_BYTES, file=sys.stderr, flush=True)
         del x, y
-        batch.eval(mtab, workspace=ws, device=dev)
+        batch.eval(mtab, workspace=ws, device=dev, opts=o)
         torch.cuda.synchronize()
         print("bench: batch call done", file=sys.stderr, flush=True)
         return
@@ -555,12 +573,12 @@ def batch_bench(args, dev):
     torch.cuda.synchronize()
     # eager warm-up (first-call set-up outside any timing), then one capture
     with torch.cuda.stream(stream):
-        batch.eval(mtab, workspace=ws, device=dev, stream=stream)
+        batch.eval(mtab, workspace=ws, device=dev, stream=stream, opts=o)
     torch.cuda.synchronize()
     print("bench: eager call done", file=sys.stderr, flush=True)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=stream):
-        out = batch.eval(mtab, workspace=ws, device=dev, stream=stream)
+        out = batch.eval(mtab, workspace=ws, device=dev, stream=stream, opts=o)
     torch.cuda.synchronize()
     for i in range(args.warmup):
         graph.replay()
@@ -587,7 +605,7 @@ def batch_bench(args, dev):
     try:
         for i in range(3):
             with torch.cuda.stream(stream):
-                batch.eval(mtab, workspace=ws, device=dev, stream=stream)
+                batch.eval(mtab, workspace=ws, device=dev, stream=stream, opts=o)
             torch.cuda.synchronize()
             bis_ms.append(ev_s.elapsed_time(ev_e))
     finally:
@@ -607,7 +625,7 @@ def batch_bench(args, dev):
         sl = slice(offs[m], offs[m] + int(counts[m]))
         inf, it = info[sl], iters[sl]
         hb = b.kl + b.ku
-        flops += bisection_flops(b.n, hb, inf)
+        flops += bisection_flops(b.n, hb, inf, int(o.lanes) or 1, int(o.tests))
         bis = (inf & 8) != 0
         n_bis += int(bis.sum())
         n_gk += int((~bis).sum())
@@ -616,7 +634,7 @@ def batch_bench(args, dev):
     passes_all = np.concatenate(passes_all)
     dur_bis = float(np.median(bis_ms)) / 1000.0
     achieved = flops / dur_bis / 1e12
-    traffic = batch_stored_traffic()
+    traffic = batch_stored_traffic(int(o.lanes) or 1, int(o.tests) or 2)
 
     # plain per-shift GPU path: one wavefront per shift (lanes = 64: a pass tests 64 points of
     # the bracket), one call per shift driven from the host, no batching, no graph; timed on a
@@ -671,7 +689,9 @@ def batch_bench(args, dev):
             "bisection_shifts": n_bis, "golub_kahan_shifts": n_gk,
             "bisection_passes_mean": float(passes_all.mean()) if passes_all.size else 0.0,
             "maxiter_shifts": int(np.sum((info[np.concatenate([np.arange(offs[m], offs[m] + counts[m]) for m in range(len(bands))])] & 2) != 0)),
-            "plan": {"lanes": 1, "tests": "default (3 for kl+ku<=2, 2 for <=5, 1 above)"},
+            "plan": {"lanes": int(o.lanes) or 1, "tests_mode": int(o.tests) or 2, "autotuned": tuned,
+                     "tests_modes": "1: one per lane; 2: 3 for kl+ku<=2, 2 for <=5, 1 above; "
+                                    "3: 2 for kl+ku<=6, 1 above"},
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded masked shifts, one per matrix, each one ps_eval_points call with "
@@ -685,7 +705,8 @@ def batch_bench(args, dev):
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "ps::bis::k_bis<1, 8, 1, 1> (inertia bisection, both launches of a call)",
+            "kernel": "ps::bis::k_bis<1, 8, %d, %d> (inertia bisection, both launches of a call)"
+                      % ({1: 0, 2: 1, 3: 2}[int(o.tests) or 2], int(o.lanes) or 1),
             "algorithmic_flops_per_launch": flops,
             "launch_ms_median": dur_bis * 1000.0,
             # the Golub-Kahan shifts run on side streams beside the bisection

@@ -96,6 +96,8 @@ _SIGNATURES = {
     "ps_contour_seeds": (ctypes.c_int, [ctypes.POINTER(ps_grid), _P, ctypes.c_double, _P, _I64, _P, _P,
                                         ctypes.c_size_t, _P]),
     "ps_autotune": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ps_opts), _P]),
+    "ps_autotune_batch": (ctypes.c_int, [_P, _P, ctypes.POINTER(ps_opts), _P]),
+    "ps_plan_cache_clear": (None, []),
     "ps_create_batch": (ctypes.c_int, [_I32, ctypes.POINTER(_P), ctypes.POINTER(ps_grid), ctypes.POINTER(_P)]),
     "ps_destroy_batch": (ctypes.c_int, [_P]),
     "ps_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -293,6 +295,15 @@ def ps_contour_seeds(grid: ps_grid, sigma_ptr, eps, seeds_ptr, max_seeds, count_
 def ps_autotune(handle, z_ptr, npts, opts: ps_opts, stream=0) -> ps_opts:
     _check(lib().ps_autotune(_P(handle), _P(z_ptr), npts, ctypes.byref(opts), _P(stream)))
     return opts
+
+
+def ps_autotune_batch(batch, masks_ptr, opts: ps_opts, stream=0) -> ps_opts:
+    _check(lib().ps_autotune_batch(_P(batch), _P(masks_ptr), ctypes.byref(opts), _P(stream)))
+    return opts
+
+
+def ps_plan_cache_clear() -> None:
+    lib().ps_plan_cache_clear()
 
 
 def ps_create_batch(handles, grids) -> int:

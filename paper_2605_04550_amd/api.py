@@ -18,7 +18,7 @@ import math
 import numpy as np
 import torch
 
-from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_backward, ps_backward_workspace_size, ps_batch_info,
+from . import (PS_DEVICE_PTR, PS_REAL_A, ps_autotune, ps_autotune_batch, ps_backward, ps_backward_workspace_size, ps_batch_info,
                ps_batch_workspace_size, ps_create_banded, ps_create_batch, ps_destroy, ps_destroy_batch,
                ps_eval_batch, ps_eval_grid, ps_eval_points, ps_grid, ps_matrix_info, ps_newton_contour,
                ps_newton_workspace_size, ps_opts_default, ps_workspace_size, ps_contour_seeds,
@@ -102,34 +102,52 @@ class BandedBatch:
         except Exception:
             pass
 
-    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
-             device=None, stream=None, workspace: torch.Tensor | None = None, lanes=0, tests=0):
-        """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None, or the device
-        table of their addresses (an int64 CUDA tensor from ``mask_table``, which a captured graph needs:
-        building the table copies from the host).  Returns dict with the concatenated idx, sigma, info,
-        iters, and counts [nmat]; matrix m owns offsets[m] onward."""
-        dev = device or torch.device("cuda")
+    def _mask_ptr(self, masks, dev, keep):
+        """Device address of the mask table (0 for none); tensors it refers to go into keep."""
         nmat = len(self.mats)
-        o = make_opts(tol_norm, tol_rel, max_iter, False, slots, bisect=bisect, lanes=lanes, tests=tests)
-        keep = []
-        mptr = 0
         if isinstance(masks, torch.Tensor):
             assert masks.is_cuda and masks.dtype == torch.int64 and masks.numel() == nmat
             keep.append(masks)
-            mptr = masks.data_ptr()
-        elif masks is not None:
-            ptrs = []
-            for m, mk in enumerate(masks):
-                if mk is None:
-                    ptrs.append(0)
-                else:
-                    assert mk.is_cuda and mk.dtype == torch.uint8 and mk.numel() == self.grids[m].nx * self.grids[m].ny
-                    mk = mk.contiguous()
-                    keep.append(mk)
-                    ptrs.append(mk.data_ptr())
-            parr = torch.tensor(ptrs, dtype=torch.int64, device=dev)
-            keep.append(parr)
-            mptr = parr.data_ptr()
+            return masks.data_ptr()
+        if masks is None:
+            return 0
+        ptrs = []
+        for m, mk in enumerate(masks):
+            if mk is None:
+                ptrs.append(0)
+            else:
+                assert mk.is_cuda and mk.dtype == torch.uint8 and mk.numel() == self.grids[m].nx * self.grids[m].ny
+                mk = mk.contiguous()
+                keep.append(mk)
+                ptrs.append(mk.data_ptr())
+        parr = torch.tensor(ptrs, dtype=torch.int64, device=dev)
+        keep.append(parr)
+        return parr.data_ptr()
+
+    def autotune(self, masks=None, *, device=None, stream=None, **kw):
+        """ps_autotune_batch with these masks: returns the options (lanes, tests or check_shift set,
+        the rest as given by kw) that ran fastest; cached per process."""
+        dev = device or torch.device("cuda")
+        o = make_opts(**kw)
+        keep = []
+        mptr = self._mask_ptr(masks, dev, keep)
+        ps_autotune_batch(self.handle, mptr, o, _stream_handle(stream))
+        return o
+
+    def eval(self, masks=None, *, tol_norm=1e-10, tol_rel=1e-8, max_iter=3000, slots=0, bisect=True,
+             device=None, stream=None, workspace: torch.Tensor | None = None, lanes=0, tests=0, check_shift=0,
+             opts=None):
+        """masks: list of uint8 CUDA tensors [ny, nx] (None entries = full grid) or None, or the device
+        table of their addresses (an int64 CUDA tensor from ``mask_table``, which a captured graph needs:
+        building the table copies from the host).  opts: a ps_opts (e.g. from ``autotune``) used
+        instead of the keyword options.  Returns dict with the concatenated idx, sigma, info, iters,
+        and counts [nmat]; matrix m owns offsets[m] onward."""
+        dev = device or torch.device("cuda")
+        nmat = len(self.mats)
+        o = opts if opts is not None else make_opts(tol_norm, tol_rel, max_iter, False, slots, check_shift,
+                                                      bisect=bisect, lanes=lanes, tests=tests)
+        keep = []
+        mptr = self._mask_ptr(masks, dev, keep)
         out = dict(idx=torch.empty(self.total, dtype=torch.int64, device=dev),
                    counts=torch.zeros(nmat, dtype=torch.int64, device=dev),
                    sigma=torch.full((self.total,), float("nan"), dtype=torch.float64, device=dev),
@@ -351,7 +369,8 @@ def label_grid(mat: BandedMatrix, grid, eps: float, *, tol_norm=1e-10, tol_rel=1
 
 
 def autotune(mat: BandedMatrix, z: torch.Tensor, **kw):
-    """ps_autotune on the shifts z: returns the options (slots, check_shift; bisect as given) that ran fastest."""
+    """ps_autotune on the shifts z: returns the options that ran fastest (lanes and tests for sigma-only
+    calls that bisect, else slots and check_shift; the rest as given by kw); cached per process."""
     o = make_opts(**kw)
     ps_autotune(mat.handle, z.contiguous().data_ptr(), z.numel(), o, _stream_handle())
     return o

@@ -12,6 +12,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 struct ps_mlp_s {
@@ -87,7 +90,7 @@ ps_status check_opts(const ps_opts &o) {
 int check_shift_of(const ps_opts &o) { return o.check_shift > 0 ? o.check_shift : 5; }
 
 // Lanes per shift of the bisection kernel (default 1) and its test-count mode: tests 1 -> one
-// test per lane and pass; 0 and 2 -> three for kl + ku <= 2, two for <= 6, one above; 3 -> two
+// test per lane and pass; 0 and 2 -> three for kl + ku <= 2, two for <= 5, one above; 3 -> two
 // for kl + ku <= 6, one above.
 int lanes_of(const ps_opts &o) { return o.lanes > 0 ? o.lanes : 1; }
 int ktm_of(const ps_opts &o) { return o.tests == 1 ? 0 : o.tests == 3 ? 2 : 1; }
@@ -756,6 +759,8 @@ struct ps_batch_s {
     std::vector<ps_grid> grids;
     std::vector<int64_t> off;
     std::vector<int64_t> npts;
+    std::vector<int64_t> mat_n;           // per matrix, caller order (plan-cache key)
+    std::vector<int32_t> mat_kl, mat_ku;
     int64_t total = 0;
     int64_t max_npts = 0;
     ps::MatDesc *desc_caller = nullptr;   // device, caller order
@@ -835,6 +840,46 @@ BatchScratch batch_scratch(const ps_batch_s *b, char *base) {
 }
 
 size_t batch_scratch_bytes(const ps_batch_s *b) { return batch_scratch(b, nullptr).bytes; }
+
+// Plans chosen by ps_autotune / ps_autotune_batch, by device and problem shape.
+std::mutex &plan_mutex() {
+    static std::mutex mu;
+    return mu;
+}
+std::map<std::string, ps_opts> &plan_cache() {
+    static std::map<std::string, ps_opts> c;
+    return c;
+}
+std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    return std::string(p.gcnArchName) + "/" + std::to_string(p.multiProcessorCount);
+}
+int log2_bucket(int64_t v) {
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < v) ++b;
+    return b;
+}
+// the fields a plan sets
+void copy_plan(const ps_opts &from, ps_opts *to) {
+    to->slots = from.slots;
+    to->check_shift = from.check_shift;
+    to->lanes = from.lanes;
+    to->tests = from.tests;
+}
+bool plan_lookup(const std::string &key, ps_opts *o) {
+    std::lock_guard<std::mutex> g(plan_mutex());
+    auto it = plan_cache().find(key);
+    if (it == plan_cache().end()) return false;
+    copy_plan(it->second, o);
+    return true;
+}
+void plan_store(const std::string &key, const ps_opts &o) {
+    std::lock_guard<std::mutex> g(plan_mutex());
+    plan_cache()[key] = o;
+}
+
 
 }  // namespace
 
@@ -1099,16 +1144,41 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     if (st) return st;
     if (!o || !z_dev || npts < 1) return fail(PS_ERR_INVALID, "need options, shifts and npts >= 1");
     if ((st = check_opts(*o))) return st;
+    const bool bis = !o->want_vectors && bisect_of(*o) && m->kl + m->ku >= 1;
+    char key[160];
+    snprintf(key, sizeof key, "m|%s|n%d|kl%d|ku%d|p%d|v%d|b%d", device_tag().c_str(), log2_bucket(m->n), m->kl,
+             m->ku, log2_bucket(npts), o->want_vectors ? 1 : 0, bisect_of(*o));
+    if (plan_lookup(key, o)) return ok();
     hipStream_t s = (hipStream_t)stream;
     ps_opts base = *o;
     base.slots = 0;
-    const int64_t s0 = default_slots(m, npts, base);
-    std::vector<int64_t> slot_cands;
-    for (int64_t sl = s0; sl >= kSlotQuantum && slot_cands.size() < 3; sl = round_slots(sl / 2))
-        slot_cands.push_back(sl);
-    const int shift_cands[3] = {3, 4, 5};
+    // candidates: the bisection's lanes per shift and tests per lane (sigma-only calls that
+    // bisect), otherwise the Golub-Kahan kernel's slot count and Ritz-check interval
+    std::vector<ps_opts> cands;
+    if (bis) {
+        for (int lanes : {1, 2, 4})
+            for (int tests : {2, 1, 3}) {
+                ps_opts t = base;
+                t.lanes = lanes;
+                t.tests = tests;
+                cands.push_back(t);
+            }
+    } else {
+        const int64_t s0 = default_slots(m, npts, base);
+        for (int64_t sl = s0; sl >= kSlotQuantum && cands.size() < 9; sl = round_slots(sl / 2))
+            for (int c : {5, 4, 3}) {
+                ps_opts t = base;
+                t.slots = (int32_t)sl;
+                t.check_shift = c;
+                cands.push_back(t);
+            }
+    }
     size_t wsb = 0;
-    if ((st = ps_workspace_size(m, npts, &base, &wsb))) return st;
+    for (const auto &t : cands) {
+        size_t b = 0;
+        if ((st = ps_workspace_size(m, npts, &t, &b))) return st;
+        wsb = std::max(wsb, b);
+    }
     void *ws = nullptr;
     double *sig = nullptr;
     HIP_TRY(hipMalloc(&ws, wsb));
@@ -1117,29 +1187,26 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = INFINITY;
-    ps_opts pick = base;
-    for (size_t i = 0; e == hipSuccess && i < slot_cands.size(); ++i) {
-        for (int c = 0; e == hipSuccess && c < 3; ++c) {
-            ps_opts t = base;
-            t.slots = (int32_t)slot_cands[i];
-            t.check_shift = shift_cands[c];
-            t.want_vectors = 0;
-            if ((st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr, nullptr, stream)))
-                break;
-            e = hipEventRecord(e0, s);
-            if (e == hipSuccess && (st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr,
-                                                        nullptr, stream)))
-                break;
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && ms < best) {
-                best = ms;
-                pick = t;
-            }
+    ps_opts pick = cands[0];
+    // sigma only while timing: the plan fields do not change what vectors cost per step
+    for (size_t i = 0; e == hipSuccess && !st && i < cands.size(); ++i) {
+        ps_opts t = cands[i];
+        const int32_t vec = t.want_vectors;
+        if (!bis) t.want_vectors = 0;
+        float ms = INFINITY;
+        for (int rep = 0; rep < 2 && e == hipSuccess && !st; ++rep) {   // the first call is untimed
+            if (rep == 1) e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+                st = ps_eval_points(m, z_dev, npts, &t, ws, wsb, sig, nullptr, nullptr, nullptr, nullptr, stream);
+            if (rep == 1 && e == hipSuccess && !st) e = hipEventRecord(e1, s);
+            if (rep == 1 && e == hipSuccess && !st) e = hipEventSynchronize(e1);
+            if (rep == 1 && e == hipSuccess && !st) e = hipEventElapsedTime(&ms, e0, e1);
         }
-        if (st) break;
+        t.want_vectors = vec;
+        if (e == hipSuccess && !st && ms < best) {
+            best = ms;
+            pick = t;
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -1147,9 +1214,14 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     (void)hipFree(ws);
     if (st) return st;
     if (e != hipSuccess) return fail(PS_ERR_HIP, "autotune: %s", hipGetErrorString(e));
-    o->slots = pick.slots;
-    o->check_shift = pick.check_shift;
+    copy_plan(pick, o);
+    plan_store(key, *o);
     return ok();
+}
+
+void ps_plan_cache_clear(void) {
+    std::lock_guard<std::mutex> g(plan_mutex());
+    plan_cache().clear();
 }
 
 ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *grids, ps_batch *out) {
@@ -1196,6 +1268,9 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         b->grids.push_back(g);
         b->off.push_back(b->total);
         b->npts.push_back(g.nx * g.ny);
+        b->mat_n.push_back(a->n);
+        b->mat_kl.push_back(a->kl);
+        b->mat_ku.push_back(a->ku);
         b->total += g.nx * g.ny;
         b->max_npts = std::max(b->max_npts, g.nx * g.ny);
     }
@@ -1417,6 +1492,84 @@ ps_status ps_eval_batch(ps_batch b, const uint8_t *const *masks_dev, const ps_op
     if (ws_bytes < need) return fail(PS_ERR_WORKSPACE, "batch workspace needs %zu bytes (got %zu)", need, ws_bytes);
     return batch_eval_core(b, masks_dev, r, (char *)ws_dev, idx_dev, counts_dev, sigma_dev, info_dev, iters_dev,
                            (hipStream_t)stream);
+}
+
+ps_status ps_autotune_batch(ps_batch b, const uint8_t *const *masks_dev, ps_opts *o, void *stream) {
+    if (!b) return fail(PS_ERR_INVALID, "batch is NULL");
+    if (!o) return fail(PS_ERR_INVALID, "options are NULL");
+    ps_status st;
+    if ((st = check_opts(*o))) return st;
+    if (o->want_vectors) return fail(PS_ERR_UNSUPPORTED, "vectors are not produced in batch mode");
+    if (o->lanes == 64) return fail(PS_ERR_INVALID, "lanes = 64 is not a batch plan");
+    const bool bis = bisect_of(*o) && b->max_hb >= 1;
+    std::string key = "b|" + device_tag() + "|b" + std::to_string(bisect_of(*o)) + "|m" + std::to_string(b->nmat);
+    for (int32_t m = 0; m < b->nmat; ++m) {
+        key += "|" + std::to_string(log2_bucket(b->mat_n[(size_t)m])) + "," + std::to_string(b->mat_kl[(size_t)m]) +
+               "," + std::to_string(b->mat_ku[(size_t)m]) + "," + std::to_string(log2_bucket(b->npts[(size_t)m]));
+    }
+    if (plan_lookup(key, o)) return ok();
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ps_opts> cands;
+    if (bis) {
+        for (int lanes : {1, 2, 4})
+            for (int tests : {2, 1, 3}) {
+                ps_opts t = *o;
+                t.lanes = lanes;
+                t.tests = tests;
+                cands.push_back(t);
+            }
+    } else {
+        for (int c : {5, 4, 3}) {
+            ps_opts t = *o;
+            t.check_shift = c;
+            cands.push_back(t);
+        }
+    }
+    size_t wsb = 0;
+    for (const auto &t : cands) {
+        size_t x = 0;
+        if ((st = ps_batch_workspace_size(b, &t, &x))) return st;
+        wsb = std::max(wsb, x);
+    }
+    void *ws = nullptr;
+    int64_t *idx = nullptr, *counts = nullptr;
+    double *sig = nullptr;
+    HIP_TRY(hipMalloc(&ws, wsb));
+    hipError_t e = hipMalloc((void **)&idx, sizeof(int64_t) * (size_t)b->total);
+    if (e == hipSuccess) e = hipMalloc((void **)&counts, sizeof(int64_t) * (size_t)b->nmat);
+    if (e == hipSuccess) e = hipMalloc((void **)&sig, sizeof(double) * (size_t)b->total);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = INFINITY;
+    ps_opts pick = cands[0];
+    // one untimed call first (set-up), then each candidate once
+    if (e == hipSuccess)
+        st = ps_eval_batch(b, masks_dev, &cands[0], ws, wsb, idx, counts, sig, nullptr, nullptr, stream);
+    for (size_t i = 0; e == hipSuccess && !st && i < cands.size(); ++i) {
+        float ms = INFINITY;
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+            st = ps_eval_batch(b, masks_dev, &cands[i], ws, wsb, idx, counts, sig, nullptr, nullptr, stream);
+        if (e == hipSuccess && !st) e = hipEventRecord(e1, s);
+        if (e == hipSuccess && !st) e = hipEventSynchronize(e1);
+        if (e == hipSuccess && !st) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && !st && ms < best) {
+            best = ms;
+            pick = cands[i];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sig);
+    (void)hipFree(counts);
+    (void)hipFree(idx);
+    (void)hipFree(ws);
+    if (st) return st;
+    if (e != hipSuccess) return fail(PS_ERR_HIP, "batch autotune: %s", hipGetErrorString(e));
+    copy_plan(pick, o);
+    plan_store(key, *o);
+    return ok();
 }
 
 // Batched labelling workspace past the batch evaluation workspace: status and mask bytes for

@@ -81,22 +81,110 @@ def test_graph_capture_of_batch_and_newton():
         assert torch.equal(got["counts"], eager["counts"])
 
 
-def test_autotune_returns_a_valid_plan():
+def test_autotune_returns_a_valid_plan_and_caches_it():
+    """ps_autotune on grcar100: a sigma-only call that bisects gets lanes per shift and tests per
+    lane (slots and the Ritz-check interval left at their defaults), and its sigma stays within
+    the bar of the oracle's; the same key returns the cached plan without timing; without the
+    bisection the plan is a slot count and a Ritz-check interval."""
+    import time
     api = _api()
     import torch
+    import paper_2605_04550_amd as P
+    P.ps_plan_cache_clear()
     w = W.workload("grcar100")
     mat = api.BandedMatrix.from_band(w["band"])
     z = torch.tensor(oracle.grid_points(w["grid"]), dtype=torch.complex128, device="cuda")
+    t0 = time.perf_counter()
     o = api.autotune(mat, z)
-    assert o.slots >= 256 and o.slots % 256 == 0 and o.check_shift in (3, 4, 5)
+    t1 = time.perf_counter()
+    assert o.lanes in (1, 2, 4) and o.tests in (1, 2, 3) and o.slots == 0 and o.check_shift == 0
     assert o.bisect == 0
-    r = api.sigma_min(mat, z, slots=o.slots, bisect=o.bisect == 0)
+    r = api.sigma_min(mat, z, lanes=o.lanes, tests=o.tests)
     gold = golden("grcar100_all")
     sig = r["sigma"].cpu().numpy()
     assert np.all(np.abs(sig - gold["sigma"]) <= tol(w["band"].fro, gold["sigma"]))
-    print("autotuned plan: slots %d, check_shift %d" % (o.slots, o.check_shift))
+    o2 = api.autotune(mat, z)
+    t2 = time.perf_counter()
+    print("autotuned plan: lanes %d, tests %d (%.3f s; cached %.4f s)" % (o.lanes, o.tests, t1 - t0, t2 - t1))
+    assert (o2.lanes, o2.tests) == (o.lanes, o.tests) and t2 - t1 < 0.25 * (t1 - t0)
     off = api.autotune(mat, z, bisect=False)
     assert off.bisect == -1
+    assert off.slots >= 256 and off.slots % 256 == 0 and off.check_shift in (3, 4, 5)
+    print("autotuned Golub-Kahan plan: slots %d, check_shift %d" % (off.slots, off.check_shift))
+
+
+def _best_ms(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def test_tuned_plan_not_slower_than_default_toeplitz2000():
+    """The full grid of toeplitz2000 (65 536 shifts): the autotuned plan takes at most the
+    default plan's time (5 % allowed for timing noise), and its sigma meets the bar at the stored
+    oracle points."""
+    api = _api()
+    import torch
+    import paper_2605_04550_amd as P
+    P.ps_plan_cache_clear()
+    w = W.workload("toeplitz2000")
+    band, grid = w["band"], w["grid"]
+    mat = api.BandedMatrix.from_band(band)
+    z = torch.tensor(oracle.grid_points(grid), dtype=torch.complex128, device="cuda")
+    o = api.autotune(mat, z)
+    t_def = _best_ms(lambda: api.eval_grid(mat, grid))
+    t_tun = _best_ms(lambda: api.eval_grid(mat, grid, lanes=o.lanes, tests=o.tests))
+    print("toeplitz2000 full grid: default %.2f ms, tuned (lanes %d, tests %d) %.2f ms"
+          % (t_def, o.lanes, o.tests, t_tun), flush=True)
+    assert t_tun <= 1.05 * t_def
+    r = api.eval_grid(mat, grid, lanes=o.lanes, tests=o.tests)
+    g = golden("toeplitz2000_pts")
+    full = g["idx"] >= 0
+    sig = torch.empty(grid.npts, dtype=torch.float64, device="cuda")
+    sig[r["idx"][:int(r["count"])]] = r["sigma"][:int(r["count"])]
+    got = sig.cpu().numpy()[g["idx"][full]]
+    assert np.all(np.abs(got - g["sigma"][full]) <= tol(band.fro, g["sigma"][full]))
+
+
+def test_batch_tuned_plan_not_slower_than_default():
+    """One (kl, ku) class of the 64-matrix batch (its matrices with their grids and masks):
+    ps_autotune_batch's plan takes at most the default plan's time (5 % for noise), and both
+    plans' sigma agree within twice the bar."""
+    api = _api()
+    import torch
+    import paper_2605_04550_amd as P
+    P.ps_plan_cache_clear()
+    w = W.batch_workload()
+    from collections import Counter
+    cls = Counter((m["band"].kl, m["band"].ku) for m in w["mats"]).most_common(1)[0][0]
+    sel = [m for m in w["mats"] if (m["band"].kl, m["band"].ku) == cls]
+    mats = [api.BandedMatrix.from_band(m["band"]) for m in sel]
+    batch = api.BandedBatch(mats, [m["grid"] for m in sel])
+    masks = [torch.tensor(m["mask"], dtype=torch.uint8, device="cuda").contiguous() for m in sel]
+    mtab = batch.mask_table(masks)
+    o = batch.autotune(mtab)
+    d = api.make_opts()
+    t_def = _best_ms(lambda: batch.eval(mtab, opts=d), reps=2)
+    t_tun = _best_ms(lambda: batch.eval(mtab, opts=o), reps=2)
+    print("batch class (kl, ku) = %s, %d matrices: default %.1f ms, tuned (lanes %d, tests %d) %.1f ms"
+          % (cls, len(sel), t_def, o.lanes, o.tests, t_tun), flush=True)
+    assert t_tun <= 1.05 * t_def
+    a = batch.eval(mtab, opts=d)
+    b = batch.eval(mtab, opts=o)
+    for m, band in enumerate(m["band"] for m in sel):
+        off, cnt = a["offsets"][m], int(a["counts"][m])
+        sa = a["sigma"][off:off + cnt].cpu().numpy()
+        sb = b["sigma"][off:off + cnt].cpu().numpy()
+        assert np.all(np.abs(sa - sb) <= 2 * tol(band.fro, np.minimum(sa, sb)))
 
 
 def test_graph_capture_of_mask_predict():
