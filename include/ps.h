@@ -120,11 +120,17 @@ void ps_opts_default(ps_opts *o);
  *   ab    LAPACK general-band storage, column-major: A[i][j] = ab[(ku + i - j) + j * ldab]
  *         for max(0, j - ku) <= i <= min(n - 1, j + kl); other entries are ignored.
  *         Host pointer unless flags has PS_DEVICE_PTR.
- *   ldab  >= kl + ku + 1.   n >= 1.   0 <= kl, ku <= n - 1; kl, ku <= 4 are supported.
+ *   ldab  >= kl + ku + 1.   n >= 1.   0 <= kl, ku <= n - 1.
+ *         kl, ku <= 4: the banded kernels (every entry point).  kl or ku > 4 with n <= 64:
+ *         the matrix is taken as dense (as the Jordan example of Sec. 2, a Jordan block with a
+ *         corner entry): ps_eval_points and ps_eval_grid compute sigma only, one wavefront
+ *         per shift (Householder bidiagonalisation in LDS, then bisection by Sturm counts on
+ *         the Golub-Kahan tridiagonal; info 0, iters = bisection rounds); vectors, the adjoint,
+ *         labels, contours, batches and the allocation-free call return PS_ERR_UNSUPPORTED.
  *   flags PS_DEVICE_PTR | PS_REAL_A.   stream: used for the upload (the call waits for it).
  *   out   receives a handle that owns a device copy of the band (plus ||A||_F).
  * Errors: PS_ERR_INVALID (sizes, NULL), PS_ERR_NONFINITE (NaN/Inf in the band),
- *         PS_ERR_UNSUPPORTED (kl or ku > 4), PS_ERR_HIP.
+ *         PS_ERR_UNSUPPORTED (kl or ku > 4 with n > 64), PS_ERR_HIP.
  */
 ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t kl, int32_t ku,
                            uint32_t flags, void *stream, ps_matrix *out);

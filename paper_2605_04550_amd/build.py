@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libps.so")
-SOURCES = (["ps_kernels.hip", "ps_mask.hip", "ps_api.cpp", "ps_bisect.hip", "ps_eval_batch.hip", "ps_noalloc.hip"] + ["ps_eval_kl%d.hip" % k for k in range(5)]
+SOURCES = (["ps_kernels.hip", "ps_mask.hip", "ps_api.cpp", "ps_bisect.hip", "ps_eval_batch.hip", "ps_noalloc.hip", "ps_dense.hip"] + ["ps_eval_kl%d.hip" % k for k in range(5)]
            + ["ps_bis_h%d.hip" % h for h in range(1, 9)])
 ARCH = "gfx950"
 

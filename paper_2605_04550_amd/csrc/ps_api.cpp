@@ -34,6 +34,7 @@ struct ps_matrix_s {
     double *gram;    // device, the Gram band read by the bisection kernel (kl + ku >= 1)
     ps::SideStream side;   // second stream for the Golub-Kahan launch beside the bisection
     int device;
+    bool dense;      // kl or ku above the banded kernels' limit: sigma only, n <= kDenseMaxN
 };
 
 namespace {
@@ -161,12 +162,46 @@ ps_status check_handle(ps_matrix m) {
     return PS_OK;
 }
 
+// Entry points that need the banded kernels (vectors, labels, batches, ...); called after
+// their argument checks, where the handle is first used.
+ps_status check_banded(ps_matrix m, const char *what) {
+    if (m->dense)
+        return fail(PS_ERR_UNSUPPORTED, "%s needs kl, ku <= %d (this matrix has kl=%d ku=%d and takes the dense "
+                    "sigma-only path)", what, ps::kMaxKL, m->kl, m->ku);
+    return PS_OK;
+}
+
+// Workspace of a dense-path evaluation: the shift counter and the mask compaction only.
+size_t dense_ws_bytes(const ps_matrix_s *m, int64_t npts) {
+    return ps::workspace_bytes(m->n, 0, 0, kSlotQuantum, 1, 0, npts);
+}
+
 ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws, size_t ws_bytes, double *sigma,
                        ps_c128 *u, ps_c128 *v, ps::Workspace *w, ps::EvalArgs *a) {
     if (!sigma) return fail(PS_ERR_INVALID, "sigma output is NULL");
     if (o.want_vectors && (!u || !v)) return fail(PS_ERR_INVALID, "want_vectors needs u and v outputs");
     if (!ws) return fail(PS_ERR_WORKSPACE, "workspace is NULL");
     if (!aligned(ws, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (m->dense) {
+        if (o.want_vectors)
+            return fail(PS_ERR_UNSUPPORTED, "singular vectors need kl, ku <= %d (kl=%d ku=%d)", ps::kMaxKL, m->kl,
+                        m->ku);
+        const size_t need = dense_ws_bytes(m, npts_max);
+        if (ws_bytes < need) return fail(PS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", need, ws_bytes);
+        ps::carve_workspace(ws, m->n, 0, 0, kSlotQuantum, 1, 0, npts_max, w);
+        a->n = m->n;
+        a->kl = m->kl;
+        a->ku = m->ku;
+        a->arow = m->arow;
+        a->normA = m->fro;
+        a->norm2A = m->norm2;
+        a->tol_norm = o.tol_norm;
+        a->tol_rel = o.tol_rel;
+        a->sigma = sigma;
+        a->count_dev = w->count;
+        a->dense = 1;
+        return PS_OK;
+    }
     int64_t slots = slots_for(m, npts_max, o, ws_bytes);
     if (slots == 0)
         return fail(PS_ERR_WORKSPACE, "workspace of %zu bytes is below the minimum %zu", ws_bytes,
@@ -486,8 +521,10 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
         return fail(PS_ERR_INVALID, "need 0 <= kl, ku <= n - 1 (kl=%d ku=%d n=%lld)", kl, ku, (long long)n);
     if (ldab < (int64_t)kl + ku + 1) return fail(PS_ERR_INVALID, "ldab must be >= kl + ku + 1");
     if (flags & ~(uint32_t)(PS_DEVICE_PTR | PS_REAL_A)) return fail(PS_ERR_INVALID, "unknown flags");
-    if (kl > ps::kMaxKL || ku > ps::kMaxKU)
-        return fail(PS_ERR_UNSUPPORTED, "kl and ku must be <= %d (got kl=%d ku=%d)", ps::kMaxKL, kl, ku);
+    const bool dense = kl > ps::kMaxKL || ku > ps::kMaxKU;
+    if (dense && n > ps::kDenseMaxN)
+        return fail(PS_ERR_UNSUPPORTED, "kl and ku must be <= %d, or n <= %d for wider bands (got n=%lld kl=%d ku=%d)",
+                    ps::kMaxKL, ps::kDenseMaxN, (long long)n, kl, ku);
     hipStream_t st = (hipStream_t)stream;
     const int64_t w = (int64_t)kl + ku + 1;
     std::vector<ps_c128> gb((size_t)(ldab * n));
@@ -534,6 +571,7 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
     m->abase = nullptr;
     m->gram = nullptr;
     m->side = ps::SideStream();
+    m->dense = dense;
     (void)hipGetDevice(&m->device);
     // zero rows around the band: kernels may read rows -kBandPadTop .. n + kBandPadBottom - 1
     const size_t padded = (size_t)(ps::kBandPadTop + n + ps::kBandPadBottom) * (size_t)w;
@@ -547,7 +585,7 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
     m->arow = m->abase + (size_t)ps::kBandPadTop * (size_t)w;
     e = hipMemcpyAsync(m->abase, store.data(), sizeof(double2) * padded, hipMemcpyHostToDevice, st);
     // the Gram band of the bisection kernel (computed on the device from the uploaded band)
-    if (e == hipSuccess && kl + ku >= 1) {
+    if (e == hipSuccess && kl + ku >= 1 && !dense) {
         e = hipMalloc((void **)&m->gram, ps::gram_bytes(n, kl, ku));
         if (e == hipSuccess) e = ps::launch_gram_band(m->arow, n, kl, ku, m->gram, st);
     }
@@ -590,6 +628,11 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
     if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
     ps_opts r = resolve(o);
     if ((st = check_opts(r))) return st;
+    if (m->dense) {
+        if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "singular vectors need kl, ku <= %d", ps::kMaxKL);
+        *bytes = dense_ws_bytes(m, npts);
+        return ok();
+    }
     int64_t slots = default_slots(m, npts, r);
     *bytes = ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, vec_of(r), npts);
     return ok();
@@ -628,6 +671,7 @@ ps_status ps_eval_points_noalloc(ps_matrix m, const ps_c128 *z_dev, int64_t npts
     if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "the allocation-free call computes sigma only");
     if (npts == 0) return ok();
     if (!z_dev) return fail(PS_ERR_INVALID, "z is NULL");
+    if ((st = check_banded(m, "the allocation-free call"))) return st;
     void *scratch = nullptr;
     HIP_TRY(ps::noalloc_scratch(&scratch));
     // the largest slot count (a multiple of one wavefront, at most the default plan's) whose
@@ -722,6 +766,7 @@ ps_status ps_backward_workspace_size(ps_matrix m, int64_t npts, size_t *bytes) {
     if (st) return st;
     if (!bytes) return fail(PS_ERR_INVALID, "bytes is NULL");
     if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
+    if ((st = check_banded(m, "the adjoint"))) return st;
     int64_t rows = ps::backward_partial_rows(npts);
     *bytes = sizeof(double2) * (size_t)(rows > 0 ? rows : 1) * (size_t)m->n * (size_t)(m->kl + m->ku + 1);
     return ok();
@@ -736,6 +781,7 @@ ps_status ps_backward(ps_matrix m, int64_t npts, const double *grad_sigma_dev, c
     if (!grad_z_dev && !grad_band_dev) return ok();
     if (npts > 0 && (!grad_sigma_dev || !u_dev || !v_dev))
         return fail(PS_ERR_INVALID, "grad_sigma, u and v are required");
+    if ((st = check_banded(m, "the adjoint"))) return st;
     hipStream_t s = (hipStream_t)stream;
     if (npts == 0) {
         if (grad_band_dev)
@@ -900,6 +946,7 @@ ps_status ps_label_workspace_size(ps_matrix m, const ps_grid *g, const ps_opts *
     ps_opts r = resolve(o);
     if ((st = check_opts(r))) return st;
     if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "labelling does not produce vectors");
+    if ((st = check_banded(m, "labelling"))) return st;
     const int64_t npts = g->nx * g->ny;
     size_t ev = 0;
     if ((st = ps_workspace_size(m, npts, &r, &ev))) return st;
@@ -918,7 +965,7 @@ ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts
     if ((st = check_opts(r))) return st;
     if (r.want_vectors) return fail(PS_ERR_UNSUPPORTED, "labelling does not produce vectors");
     size_t need = 0;
-    ps_label_workspace_size(m, g, &r, &need);
+    if ((st = ps_label_workspace_size(m, g, &r, &need))) return st;
     if (!ws_dev || ws_bytes < need) return fail(PS_ERR_WORKSPACE, "label workspace needs %zu bytes", need);
     if (!aligned(ws_dev, 256)) return fail(PS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     const int64_t npts = g->nx * g->ny;
@@ -1144,6 +1191,7 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
     if (st) return st;
     if (!o || !z_dev || npts < 1) return fail(PS_ERR_INVALID, "need options, shifts and npts >= 1");
     if ((st = check_opts(*o))) return st;
+    if (m->dense) return ok();   // the dense path has no plan to choose
     const bool bis = !o->want_vectors && bisect_of(*o) && m->kl + m->ku >= 1;
     char key[160];
     snprintf(key, sizeof key, "m|%s|n%d|kl%d|ku%d|p%d|v%d|b%d", device_tag().c_str(), log2_bucket(m->n), m->kl,
@@ -1235,6 +1283,11 @@ ps_status ps_create_batch(int32_t nmat, const ps_matrix *mats, const ps_grid *gr
         const ps_matrix a = mats[m];
         const ps_grid &g = grids[m];
         if (!a) { delete b; return fail(PS_ERR_INVALID, "matrix %d is NULL", m); }
+        if (a->dense) {
+            delete b;
+            return fail(PS_ERR_UNSUPPORTED, "matrix %d has kl=%d ku=%d: batches need kl, ku <= %d", m, a->kl, a->ku,
+                        ps::kMaxKL);
+        }
         if (g.nx < 1 || g.ny < 1 || g.nx * g.ny > ((int64_t)1 << 40)) {
             delete b;
             return fail(PS_ERR_INVALID, "bad grid size for matrix %d", m);

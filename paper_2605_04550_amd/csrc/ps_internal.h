@@ -12,6 +12,8 @@ namespace ps {
 // Maximum supported bandwidths of the compiled kernels.
 constexpr int kMaxKL = 4;
 constexpr int kMaxKU = 4;
+// Wider bands (kl or ku above these) are taken as dense matrices, up to this order.
+constexpr int kDenseMaxN = 64;
 constexpr int kMaxIterCap = 4096;
 // Rows per chunk of the triangular sweeps.  Per-row arrays are allocated with
 // round_up(n, kChunk) + kChunk rows; rows past n hold zeros and make no contribution.
@@ -122,7 +124,11 @@ struct EvalArgs {
     const MatDesc *mats = nullptr;
     int nmat = 0;
     const int64_t *mfirst = nullptr;   // device: first queue position of each matrix
+    int dense = 0;                     // 1: kl or ku above the banded kernels' limit, n <= kDenseMaxN
 };
+
+// sigma only for a matrix taken as dense (one wavefront per shift; at most npts_max shifts)
+hipError_t launch_dense(const EvalArgs &a, int64_t npts_max, hipStream_t st);
 
 // Arguments of the inertia-bisection kernel (sigma only): one matrix (batch == 0) or the
 // chunks of a batch in longest-first order.

@@ -530,6 +530,7 @@ static bool bisects(const EvalArgs &a, const Workspace &ws) {
 }
 
 hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, const SideStream *side) {
+    if (a0.dense) return launch_dense(a0, ws.npts_max, st);
     EvalArgs a = a0;
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;

@@ -60,10 +60,15 @@ def test_create_rejects_bad_arguments_before_any_device_call():
     with pytest.raises(P.PsError) as e:
         P.ps_create_banded(0, 3, 8, 1, 1)
     assert e.value.status == P.PS_ERR_INVALID
-    big = _gb(16, 5, 1)
+    big = _gb(65, 5, 1)               # kl > 4 is taken as dense, up to n = 64
     with pytest.raises(P.PsError) as e:
-        P.ps_create_banded(big.ctypes.data, 7, 16, 5, 1)
+        P.ps_create_banded(big.ctypes.data, 7, 65, 5, 1)
     assert e.value.status == P.PS_ERR_UNSUPPORTED
+    wide = _gb(64, 5, 1)              # accepted: fails later only for lack of a GPU
+    try:
+        P.ps_create_banded(wide.ctypes.data, 7, 64, 5, 1)
+    except P.PsError as e:
+        assert e.status == P.PS_ERR_HIP
     bad = _gb(8, 1, 1)
     bad[3, 1] = np.nan
     with pytest.raises(P.PsError) as e:
