@@ -17,6 +17,11 @@ Sets (file ``tests/golden/<set>.npz``):
                      with singular vectors and the two smallest singular values.
   batch_pts          Two seeded masked points for each matrix of the 64-matrix batch with
                      n <= 5000 (14 matrices).
+  grcar4000_grad     Grcar n=4000 (the vectors-and-adjoint workload): 32 seeded grid points with
+                     1e-8 <= sigma < 1 and sigma_{n-1} >= 1.05 sigma_n, their singular pairs from
+                     LAPACK's dense SVD, and the gradients of L = sum_p w_p sigma_p (w the
+                     workload's weights at those points): grad_z [32] and the band gradient
+                     [n, kl+ku+1] (GB layout, complex: no real projection).
   paper_labels       The first three matrices of the label workload of Sec. 3.3 (n = 64,
                      100x100 grid on [-4,4]^2): sigma at all 10^4 points and the labels
                      sigma <= 0.01 (keys sigma0.., label0..).
@@ -132,8 +137,47 @@ def paper_labels(threads):
     _save("paper_labels", **out)
 
 
+def grcar4000_grad(threads):
+    w = W.workload("grcar4000")
+    band = w["band"]
+    z = oracle.grid_points(w["grid"])
+    rng = np.random.default_rng(W.SEED_BASE + 107)
+    rows = []
+    for k in rng.permutation(z.size):
+        zz = z[k:k + 1]
+        # Before the dense SVD (which decides): sigma_min in [1e-8, 1) and sigma_{n-1} >= 1.05
+        # sigma_min by inertia counts (sigma_min bracketed by bisection on the count, then one
+        # count at 1.05 times its upper end).  The counts are not trusted where sigma_min is
+        # far below 1e-8 (deep inside the pseudospectrum of this matrix), hence the SVD check.
+        cnt = lambda t: oracle.count_below(band, zz, t, threads)[0]
+        if cnt(1.0) < 1 or cnt(1e-8) != 0:
+            continue
+        lo, hi = 1e-8, 1.0
+        for _ in range(30):
+            mid = math.sqrt(lo * hi)
+            lo, hi = (lo, mid) if cnt(mid) >= 1 else (mid, hi)
+        if hi < 1e-7 or cnt(1.05 * hi) != 1:
+            continue
+        t = time.time()
+        r = oracle.smallest_pair_lapack(band, zz)
+        ok = r["s2"][0] >= 1.05 * r["sigma"][0] and 1e-8 <= r["sigma"][0] < 1.0
+        print("grcar4000 point", int(k), "sigma %.3e gap %.3f" % (r["sigma"][0], r["s2"][0] / r["sigma"][0]),
+              "kept" if ok else "skipped", "%.0f s" % (time.time() - t), flush=True)
+        if ok:
+            rows.append((int(k), r))
+        if len(rows) == 32:
+            break
+    idx = np.array([k for k, _ in rows], dtype=np.int64)
+    u = np.concatenate([r["u"] for _, r in rows])
+    v = np.concatenate([r["v"] for _, r in rows])
+    wts = w["weights"][idx]
+    gz, gb = oracle.adjoint(band, u, v, wts)
+    _save("grcar4000_grad", idx=idx, z=z[idx], sigma=np.array([r["sigma"][0] for _, r in rows]),
+          s2=np.array([r["s2"][0] for _, r in rows]), grad_z=gz, grad_band=gb)
+
+
 SETS = dict(grcar100_all=grcar100_all, toeplitz2000_pts=toeplitz2000_pts, random1000_grid=random1000_grid,
-            grcar400_vec=grcar400_vec, batch_pts=batch_pts, paper_labels=paper_labels)
+            grcar400_vec=grcar400_vec, batch_pts=batch_pts, paper_labels=paper_labels, grcar4000_grad=grcar4000_grad)
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()

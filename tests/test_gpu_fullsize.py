@@ -212,6 +212,54 @@ def test_grcar4000_vectors_adjoint_newton():
     assert np.sum(e6 <= bar) >= 0.99 * count
 
 
+def test_grcar4000_gradients_against_dense_svd():
+    """Grcar n = 4000, the 32 stored points (1e-8 <= sigma < 1, sigma_{n-1} >= 1.05 sigma_n):
+    sigma, grad_z = w_p conj(u_p^H v_p) and the band gradient of L = sum_p w_p sigma_p against
+    the oracle's values from LAPACK's dense SVD.  Bar for the gradients (Wedin's theorem): a
+    singular pair with residuals r1 = |M v - sigma u|, r2 = |M^H u - sigma v| is within angle
+    sqrt(r1^2 + r2^2) / delta of the exact one, delta the distance of sigma to the rest of the
+    spectrum; each gradient term moves by at most twice the angle of each side, times |w_p|.
+    The oracle's own pairs are backward stable (residual ~ n eps |A|_2)."""
+    api = _api()
+    import torch
+    g = golden("grcar4000_grad")
+    w = W.workload("grcar4000")
+    band = w["band"]
+    band.real = False                      # complex band gradient, as the stored one
+    mat = api.BandedMatrix.from_band(band)
+    z = np.asarray(g["z"])
+    zt = torch.tensor(z, dtype=torch.complex128, device="cuda")
+    print("grcar4000 gradients: %d stored points" % len(z), flush=True)
+    r = api.sigma_min(mat, zt, want_vectors=True)
+    sig = r["sigma"].cpu().numpy()
+    bar = tol(band.fro, g["sigma"])
+    err = np.abs(sig - g["sigma"])
+    print("grcar4000 gradients: sigma max err/bound %.3e" % (err / bar).max(), flush=True)
+    assert np.all(err <= bar)
+    U = r["u"].cpu().numpy()
+    V = r["v"].cpu().numpy()
+    r1 = np.linalg.norm(_band_matvec(band, z, V) - sig[:, None] * U, axis=1)
+    r2 = np.linalg.norm(_band_rmatvec(band, z, U) - sig[:, None] * V, axis=1)
+    norm2 = 5.0                              # |A|_2 <= sqrt(|A|_1 |A|_inf) = 5 for Grcar (5 entries of modulus 1 per row and column)
+    ref_res = 4000 * 2.0 ** -52 * (np.abs(z) + norm2)
+    delta = g["s2"] - np.maximum(sig, g["sigma"]) - bar
+    assert np.all(delta > 0)
+    angle = (np.hypot(r1, r2) + ref_res) / delta
+    wts = w["weights"][g["idx"]]
+    gz, gb = api.backward(mat, torch.tensor(wts, device="cuda"), r["u"], r["v"])
+    gz = gz.cpu().numpy()
+    gb = gb.cpu().numpy()
+    zbar = 4 * np.abs(wts) * angle + 1e-14
+    zerr = np.abs(gz - g["grad_z"])
+    print("grcar4000 gradients: grad_z max err %.3e, max err/bound %.3e; angle bound max %.3e"
+          % (zerr.max(), (zerr / zbar).max(), angle.max()), flush=True)
+    assert np.all(zerr <= zbar)
+    bbar = 4 * np.sum(np.abs(wts) * angle) + 1e-14
+    berr = np.abs(gb - g["grad_band"]).max()
+    print("grcar4000 gradients: band gradient max err %.3e (bound %.3e)" % (berr, bbar), flush=True)
+    assert berr <= bbar
+
+
 def _fd_grad_z(api, mat, z, h=1e-6):
     import torch
     tight = dict(tol_rel=1e-15, tol_norm=1e-17, max_iter=3000)
