@@ -116,9 +116,11 @@ def test_batch64_full_workload_certified():
         pick = rng.choice(4915, 64, replace=False)
         assert np.all(sm[pick] >= johnson_bound(b, zs[pick]) - bnd[pick]), m
         assert np.all(sm[pick] <= column_norm_bound(b, zs[pick]) * (1 + 1e-12) + bnd[pick]), m
+        # 8 shifts stratified by sigma among those the count can certify (sigma >= 1e-3)
         order = np.argsort(sm)
-        strat = order[np.linspace(0, 4914, 8).astype(int)]
-        strat = strat[sm[strat] >= 1e-3]
+        order = order[sm[order] >= 1e-3]
+        strat = order[np.unique(np.linspace(0, len(order) - 1, 8).astype(int))]
+        assert len(strat) == 8, m
         certify(b, zs[strat], sm[strat], bnd[strat], "batch64 matrix %d (n=%d kl=%d ku=%d)" % (m, b.n, b.kl, b.ku))
     g = golden("batch_pts")
     for mi, k, zz, s_or in zip(g["mat"], g["idx"], g["z"], g["sigma"]):

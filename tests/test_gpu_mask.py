@@ -260,3 +260,50 @@ def test_mask_batch_at_the_benchmarked_size():
     r = {k: v[311].cpu().numpy() for k, v in rb.items()}
     r["evals"] = np.array([r["evals"]])
     _check_mask(grid, params, gfs[311], eig_np[311], 0.05, 4, 5, r, what="benchmarked batch, matrix 311")
+
+
+def test_trained_network_on_held_out_matrices():
+    """The trained classifier (paper_2605_04550_amd/data/mask_net.npz, written by the training
+    script): ps_mlp_prob equals the oracle's float64 network within its float32 error bound on the
+    real features of a held-out matrix (plus float32 underflow); on 20 held-out matrices of the Sec. 3.3 class the region R
+    at the calibrated tau* (hierarchical prediction, 5 x 5 dilation) covers the exact labels
+    (dilated 3 x 3, as in the calibration of Sec. 3.6) with median recall >= 0.90 and 10th
+    percentile >= 0.75, the bounds tau* was calibrated to."""
+    need_gpu()
+    import os
+    import scipy.ndimage as nd
+    import torch
+    from paper_2605_04550_amd import api
+    from paper_2605_04550_amd.features import band_features
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2605_04550_amd", "data",
+                        "mask_net.npz")
+    if not os.path.exists(path):
+        pytest.skip("no trained weights")
+    tw = np.load(path, allow_pickle=False)
+    params, tau = tw["params"], float(tw["tau"])
+    net = api.MaskNet(params)
+    w = W.paper_label_workload(20)
+    grid = w["grid"]
+    fe = [band_features(b, 3_000_000 + m) for m, b in enumerate(w["mats"])]
+    rng = np.random.default_rng(41)
+    z = rng.uniform(-4, 4, 512) + 1j * rng.uniform(-4, 4, 512)
+    eig0 = torch.tensor(fe[0][1], dtype=torch.complex128, device="cuda")
+    p = net.prob(list(fe[0][0]), eig0, torch.tensor(z, dtype=torch.complex128, device="cuda")).double().cpu().numpy()
+    ref, bnd = OM.mlp_prob(params, fe[0][0], fe[0][1], z, bound=True)
+    # the trained logits reach -90 far from the spectrum: probabilities below float32's normal
+    # range (2^-126) may be flushed to zero, which the rounding bound does not model
+    assert np.all(np.abs(p - ref) <= bnd + 2.0 ** -126)
+    eigs = [torch.tensor(lam, dtype=torch.complex128, device="cuda") for _, lam in fe]
+    rs = net.predict_batch(grid, [list(f) for f, _ in fe], eigs, tau=tau)
+    mats = [api.BandedMatrix.from_band(b) for b in w["mats"]]
+    lab = api.BandedBatch(mats, [grid] * len(mats)).label(w["eps"])["label"].reshape(20, grid.ny, grid.nx)
+    lab = lab.cpu().numpy().astype(bool)
+    rmask = rs["mask"].cpu().numpy().astype(bool)
+    rec = []
+    for m in range(20):
+        dl = nd.binary_dilation(lab[m], structure=np.ones((3, 3), dtype=bool))
+        rec.append(1.0 if dl.sum() == 0 else float((dl & rmask[m]).sum()) / float(dl.sum()))
+    print("trained network, tau* %.2f: recall median %.3f, P10 %.3f, region fraction %.3f"
+          % (tau, np.median(rec), np.percentile(rec, 10), rmask.mean()), flush=True)
+    assert np.median(rec) >= 0.90 and np.percentile(rec, 10) >= 0.75
+    assert rmask.mean() < 0.5
