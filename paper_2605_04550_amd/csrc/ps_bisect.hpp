@@ -350,6 +350,12 @@ __device__ void bisect(const BisArgs &a, const MatView &mv, const Shift &sf) {
         }
     }
     if (!sf.valid || gl != 0) return;
+    if (a.phase == 3) {
+        a.st_np[sf.sid] = gk ? -1 : passes;
+        a.st_lo[sf.sid] = lo;
+        a.st_hi[sf.sid] = hi;
+        return;
+    }
     if (a.phase == 1) {
         a.st_np[sf.sid] = pending ? passes : -1;
         a.st_lo[sf.sid] = lo;

@@ -1041,6 +1041,17 @@ struct Kern {
         ln.phase = 0;
         ln.nbis = 0;
         if (!BIS || !a.bisect) return;
+        if (a.brk_np) {               // the bracket is known: straight to the singular pair
+            const int np = a.brk_np[ln.pid];
+            if (np < 0) return;       // sigma below the bisection's limit: the Golub-Kahan path
+            ln.phase = 1;
+            ln.nbis = np;
+            ln.blo = a.brk_lo[ln.pid];
+            ln.bhi = a.brk_hi[ln.pid];
+            const double target = a.tol_norm * fro(a, ln) + a.tol_rel * ln.blo;
+            finish_bis(a, ln, 0.5 * (ln.blo + ln.bhi), ln.bhi - ln.blo <= target ? 0 : 2);
+            return;
+        }
         const double mn = hypot(ln.z.x, ln.z.y) + nrm2(a, ln);
         if (!(mn < 1e100 && mn > 1e-100)) return;   // H and its pivots stay far from over/underflow
         const double b = a.tol_norm * fro(a, ln), c = 256.0 * 0x1p-52 * mn * mn;

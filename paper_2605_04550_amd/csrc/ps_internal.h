@@ -125,6 +125,10 @@ struct EvalArgs {
     int nmat = 0;
     const int64_t *mfirst = nullptr;   // device: first queue position of each matrix
     int dense = 0;                     // 1: kl or ku above the banded kernels' limit, n <= kDenseMaxN
+    // with vectors: brackets found beforehand by the bisection kernel (per shift position;
+    // brk_np < 0: sigma below the bisection's limit, the Golub-Kahan path), or NULL
+    const double *brk_lo = nullptr, *brk_hi = nullptr;
+    const int32_t *brk_np = nullptr;
 };
 
 // sigma only for a matrix taken as dense (one wavefront per shift; at most npts_max shifts)
@@ -160,7 +164,9 @@ struct BisArgs {
     int64_t *gk_list = nullptr;             // batch: base of all class lists
     int64_t *gk_count = nullptr;            // batch: one per class
     // 0: every pass in one launch; 1: first pass only, saving the bracket of every shift that
-    // goes on (and handing over or finishing the others); 2: resume from the saved brackets
+    // goes on (and handing over or finishing the others); 2: resume from the saved brackets;
+    // 3: every pass, then save each final bracket (passes; -1 below the bisection's limit)
+    // instead of writing sigma, for the singular vectors that follow
     int phase = 0;
     double *st_lo = nullptr, *st_hi = nullptr;   // saved brackets (queue position, or output
     int32_t *st_np = nullptr;                    // position in a batch); passes, -1 = settled
@@ -241,7 +247,7 @@ __host__ __device__ inline void carve_workspace(void *base, int64_t n, int kl, i
         w->vacc = nullptr;
         w->vmeta = nullptr;
     }
-    if (!vec && npts_max > 0) {
+    if (npts_max > 0) {
         w->gk_list = (int64_t *)take(sizeof(int64_t) * (size_t)npts_max);
         w->gk_count = (int64_t *)take(sizeof(int64_t));
         w->st_lo = (double *)take(sizeof(double) * (size_t)npts_max);

@@ -529,12 +529,48 @@ static bool bisects(const EvalArgs &a, const Workspace &ws) {
     return !a.want_vectors && a.bisect && a.kl + a.ku >= 1 && a.gram && ws.gk_list && ws.npts_max > 0;
 }
 
+// Calls with vectors on a short list of shifts (contour refinement and tracing evaluate one shift
+// per contour point): the Golub-Kahan kernel's own bisection runs one test per lane and pass on
+// one lane per shift, so such a call is a few wavefronts doing some thirty passes each.  Instead
+// the bisection kernel first finds every bracket with a whole wavefront per shift (64 tests per
+// pass, a handful of passes), and the vector kernel starts from those brackets.
+constexpr int64_t kWaveBracketMax = 2048;
+
+static bool wave_brackets(const EvalArgs &a, const Workspace &ws) {
+    return a.want_vectors && a.bisect && a.kl + a.ku >= 1 && a.gram && a.mode == kShiftList && ws.st_np &&
+           ws.npts_max > 0 && ws.npts_max <= kWaveBracketMax;
+}
+
 hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, const SideStream *side) {
     if (a0.dense) return launch_dense(a0, ws.npts_max, st);
     EvalArgs a = a0;
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
     const int64_t blocks = ws.slots / kEvalBlock;
+    if (wave_brackets(a, ws)) {
+        BisArgs b;
+        b.gram = a.gram;
+        b.n = a.n;
+        b.hb = a.kl + a.ku;
+        b.normA = a.normA;
+        b.norm2A = a.norm2A;
+        b.mode = kShiftList;
+        b.z = a.z;
+        b.count_dev = a.count_dev;
+        b.tol_norm = a.tol_norm;
+        b.tol_rel = a.tol_rel;
+        b.st_lo = ws.st_lo;
+        b.st_hi = ws.st_hi;
+        b.st_np = ws.st_np;
+        b.phase = 3;
+        hipError_t e = launch_bis(b, b.hb, 0, 64, ws.npts_max, st);
+        if (e != hipSuccess) return e;
+        a.brk_lo = ws.st_lo;
+        a.brk_hi = ws.st_hi;
+        a.brk_np = ws.st_np;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kEvalBlock), 0, st, a, ws);
+        return hipGetLastError();
+    }
     if (bisects(a, ws)) {
         BisArgs b;
         b.gram = a.gram;
