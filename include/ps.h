@@ -369,10 +369,12 @@ ps_status ps_contour_seeds(const ps_grid *g, const double *sigma_dev, double eps
  *   Sigma-only calls that bisect (want_vectors = 0, bisect = 0, kl + ku >= 1): lanes per shift
  *   (1, 2, 4) times tests per lane (modes 2, 1, 3), nine plans.  Otherwise: the Golub-Kahan
  *   kernel's slot count (the default, a half and a quarter of it) times the Ritz-check
- *   interval (check_shift 5, 4, 3).  Each candidate runs once untimed and once timed with HIP
+ *   interval (check_shift 5, 4, 3).  Each candidate runs once untimed and twice timed with HIP
  *   events on z_dev[0 .. npts) (a representative sample of the shifts to be evaluated, on the
  *   device; with vectors the timing runs sigma only); the fastest plan's fields (slots,
- *   check_shift, lanes, tests) are written into *o, everything else in *o is kept.
+ *   check_shift, lanes, tests) are written into *o, everything else in *o is kept.  The first
+ *   candidate is the default plan; another replaces it only when it takes under 98 % of its
+ *   time (the faster of its timed runs).
  *   Plans are cached per process by (device architecture and compute-unit count, ceil(log2 n),
  *   kl, ku, ceil(log2 npts), want_vectors, bisect): a later call with the same key returns the
  *   cached plan without timing (ps_plan_cache_clear empties the cache).
@@ -386,7 +388,9 @@ ps_status ps_autotune(ps_matrix m, const ps_c128 *z_dev, int64_t npts, ps_opts *
  * ps_autotune_batch -- the same for ps_eval_batch on this batch with these masks (masks_dev as
  * for ps_eval_batch): lanes per shift times tests per lane when the batch bisects (the plan
  * applies to all its matrices), else the Ritz-check interval.  One untimed call, then each
- * candidate timed once over the whole batch call.  Cached by (device, bisect, and per matrix
+ * candidate timed twice over the whole batch call (the faster run counts; the default plan,
+ * the first candidate, is kept unless another takes under 98 % of its time).  Cached by
+ * (device, bisect, and per matrix
  * ceil(log2 n), kl, ku, ceil(log2 grid points)).  Synchronous; allocates and frees its own
  * workspace and outputs.
  * Errors: PS_ERR_INVALID, PS_ERR_UNSUPPORTED (vectors), PS_ERR_HIP.
