@@ -1194,40 +1194,75 @@ struct Kern {
     // One step x <- (H - sh I)^{-1} (x / |x|) (forward L solve and the 1/d scaling into vy, then
     // the backward L^H solve into vv); returns the new |x|^2 and records in vamax / vph the first
     // entry of largest modulus.
+    // The two solves run in chunks of VC rows: a chunk's workspace loads are all issued before
+    // its rows are computed, so a lane waits for memory once per chunk rather than once per row
+    // (the recurrence itself is short; one lane per shift has nothing else to hide the wait).
+    // The workspace holds rows up to round_up(n, 8) + 8, so a chunk may read past row n - 1
+    // (values unused); going backward, rows below 0 are clamped to row 0 (values unused).
+    static constexpr int VC = HB <= 2 ? 8 : HB <= 4 ? 4 : 2;
+
     static __device__ double vec_step(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln, double scale) {
         const int64_t n = nn(a, ln), T = w.slots;
         constexpr int HA = HB > 0 ? HB : 1;
         cd y[HA];
 #pragma unroll
         for (int e = 0; e < HA; ++e) y[e] = czero();   // y[e-1] = y_{i-e}
-        for (int64_t i = 0; i < n; ++i) {
-            cd acc = cscale(w.vv[i * T + s], scale);
+        for (int64_t i0 = 0; i0 < n; i0 += VC) {
+            cd vin[VC], uu[VC][HB + 1];
 #pragma unroll
-            for (int e = 1; e <= HB; ++e) acc = cfnma(w.U[(i * W + e) * T + s], y[e - 1], acc);
+            for (int r = 0; r < VC; ++r) {
+                const int64_t i = i0 + r;
+                vin[r] = w.vv[i * T + s];
 #pragma unroll
-            for (int e = HB - 1; e >= 1; --e) y[e] = y[e - 1];
-            y[0] = acc;
-            w.vy[i * T + s] = cscale(acc, w.U[(i * W + 0) * T + s].x);
+                for (int e = 0; e <= HB; ++e) uu[r][e] = w.U[(i * W + e) * T + s];
+            }
+#pragma unroll
+            for (int r = 0; r < VC; ++r) {
+                const int64_t i = i0 + r;
+                if (i < n) {
+                    cd acc = cscale(vin[r], scale);
+#pragma unroll
+                    for (int e = 1; e <= HB; ++e) acc = cfnma(uu[r][e], y[e - 1], acc);
+#pragma unroll
+                    for (int e = HB - 1; e >= 1; --e) y[e] = y[e - 1];
+                    y[0] = acc;
+                    w.vy[i * T + s] = cscale(acc, uu[r][0].x);
+                }
+            }
         }
         cd x[HA];
 #pragma unroll
         for (int e = 0; e < HA; ++e) x[e] = czero();   // x[e-1] = x_{i+e}
         double x2 = 0.0, am = -1.0;
         cd ph = C(1.0, 0.0);
-        for (int64_t i = n - 1; i >= 0; --i) {
-            cd acc = w.vy[i * T + s];
+        for (int64_t i0 = n - 1; i0 >= 0; i0 -= VC) {
+            cd yin[VC], uu[VC][HB + 1];
 #pragma unroll
-            for (int e = 1; e <= HB; ++e)
-                if (i + e < n) acc = cfnmac(w.U[((i + e) * W + e) * T + s], x[e - 1], acc);
+            for (int r = 0; r < VC; ++r) {
+                const int64_t i = i0 - r >= 0 ? i0 - r : 0;
+                yin[r] = w.vy[i * T + s];
 #pragma unroll
-            for (int e = HB - 1; e >= 1; --e) x[e] = x[e - 1];
-            x[0] = acc;
-            w.vv[i * T + s] = acc;
-            const double m = cabs2(acc);
-            x2 += m;
-            if (m >= am) {             // going backward, >= keeps the first index on ties
-                am = m;
-                ph = acc;
+                for (int e = 1; e <= HB; ++e) uu[r][e] = w.U[((i + e) * W + e) * T + s];
+            }
+#pragma unroll
+            for (int r = 0; r < VC; ++r) {
+                const int64_t i = i0 - r;
+                if (i >= 0) {
+                    cd acc = yin[r];
+#pragma unroll
+                    for (int e = 1; e <= HB; ++e)
+                        if (i + e < n) acc = cfnmac(uu[r][e], x[e - 1], acc);
+#pragma unroll
+                    for (int e = HB - 1; e >= 1; --e) x[e] = x[e - 1];
+                    x[0] = acc;
+                    w.vv[i * T + s] = acc;
+                    const double m = cabs2(acc);
+                    x2 += m;
+                    if (m >= am) {     // going backward, >= keeps the first index on ties
+                        am = m;
+                        ph = acc;
+                    }
+                }
             }
         }
         ln.vamax = am;
