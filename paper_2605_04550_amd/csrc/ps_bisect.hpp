@@ -350,10 +350,10 @@ __device__ void bisect(const BisArgs &a, const MatView &mv, const Shift &sf) {
         }
     }
     if (!sf.valid || gl != 0) return;
-    if (a.phase == 3) {
-        a.st_np[sf.sid] = gk ? -1 : passes;
-        a.st_lo[sf.sid] = lo;
-        a.st_hi[sf.sid] = hi;
+    if (a.phase == 3) {                  // brackets for a call with vectors, at output positions
+        a.st_np[sf.pid] = gk ? -1 : passes;
+        a.st_lo[sf.pid] = lo;
+        a.st_hi[sf.pid] = hi;
         return;
     }
     if (a.phase == 1) {

@@ -237,9 +237,10 @@ struct Lane {
     double vnorm2;    // |v|^2 of the accumulated vector (known after its last step)
     double vamax;     // largest |v_i|^2 so far (first index on ties)
     cd vph;           // the entry that attains it
-    // Inertia bisection (sigma only): phase 1 while a lane bisects, 0 on the Golub-Kahan path.
+    // Shifts bisected beforehand (calls with vectors): phase 2 while the lane computes the
+    // singular pair from its bracket, 0 on the Golub-Kahan path.
     int phase;
-    int nbis;         // bisection passes so far
+    int nbis;         // bisection passes the bracket took
     double blo, bhi;  // bracket: blo < sigma_min (tested), sigma_min <= bhi
     // vectors after the bisection (phase 2): the step, sigma and flags to report, |x|^2
     int vit, vflags;
@@ -266,8 +267,7 @@ struct Kern {
         return BATCH ? ln.norm2A : a.norm2A;
     }
 
-    // The bisection is compiled for sigma-only kernels with kl + ku >= 1 (its constants are
-    // defined with it, below); a lane is on the Golub-Kahan path unless it is in phase 1.
+    // A lane is on the Golub-Kahan path unless it is computing a bisected shift's vectors.
     static __device__ __forceinline__ bool gk(const Lane &ln) { return ln.phase == 0; }
 
     // M[r][c] of M = zI - A from the row band (zero outside the matrix).
@@ -873,42 +873,14 @@ struct Kern {
         eacc_out = Eacc;
     }
 
-    // ---------------------------------------------------------------- inertia bisection
-    // sigma_min^2 is the smallest eigenvalue of H = M^H M, so for t >= 0, t < sigma_min exactly
-    // when H - t^2 I is positive definite, that is when its Cholesky factorisation meets no
-    // non-positive pivot (Sylvester's law of inertia).  One such test is one pass over the rows
-    // that reads only the band of A: H (half-bandwidth HB = kl + ku) is formed row by row from
-    // M = zI - A, and the HB previous rows of the factor stay in registers, so a pass moves no
-    // per-shift data through memory.  Bisection on t between a bound known to lie below
-    // sigma_min and one above it then gives sigma_min to any width above the rounding of the
-    // test, in about log2(sigma / target) passes.
-    //
-    // Rounding: forming H and factorising it perturb H by about eps |M|^2 (backward error),
-    // which moves the decision point sigma_min^2 by as much and sigma_min by eps |M|^2 /
-    // (2 sigma).  A shift uses the bisection only where 32 eps mn^2 (mn = |z| + sqrt(||A||_1
-    // ||A||_inf), at least the 2-norm of |M|) stays below an eighth of sigma * target(sigma),
-    // target(s) = tol_norm ||A||_F + tol_rel s: for sigma >= sigma_adm, the positive root of
-    // tol_rel s^2 + tol_norm ||A||_F s = 256 eps mn^2.  The first test, at t = sigma_adm, decides
-    // whether the shift qualifies; if H - sigma_adm^2 I is not positive definite the shift takes
-    // the Golub-Kahan path instead, which has no such limit (it never forms H).  With sigma_min
-    // above sigma_adm nothing overflows or underflows, so the passes use plain doubles.
-    // Sigma-only calls bisect in their own kernel (ps_bisect.hpp); this one keeps the
-    // bisection for calls with singular vectors, which need its factor afterwards.
+    // ---------------------------------------------------------------- shifts bisected beforehand
+    // Calls with singular vectors first run the bisection kernel over every shift (ps_bisect.hpp:
+    // the inertia bisection on H = M^H M, sigma_min^2 its smallest eigenvalue), which saves each
+    // final bracket lo < sigma_min <= hi, or -1 for a shift below the bisection's rounding limit.
+    // This kernel starts from those brackets: the singular pair of a bisected shift comes from
+    // inverse iteration on H - lo^2 I (below); the others take the Golub-Kahan path.
     static constexpr bool BIS = VEC && (KL + KU) >= 1;
     static constexpr int HB = KL + KU;          // half-bandwidth of H
-    static constexpr int kBisMaxPass = 128;     // far above the ~30-40 passes a shift needs
-
-    // Rows per block of the pass.  The M rows a block needs (PB + HB band rows) sit in
-    // registers; the PB rows the next block adds are loaded while the current block is
-    // computed, so the pass does not wait for memory.  Narrower bands take longer blocks.
-    // Reads past the ends of the matrix land in the zero rows stored around the band.
-    static constexpr int PB = W <= 3 ? 4 : W <= 4 ? 2 : 1;
-
-    // Test points per pass: one pass factorises H - sh_j I for KT shifts sh_1 < .. < sh_KT at
-    // once.  H is formed once per row for all of them, and the KT independent recurrences
-    // overlap one another's latency; the bracket shrinks by KT + 1 per pass instead of 2.
-    // Wider bands keep fewer (each recurrence holds HB (HB - 1) / 2 factor entries).
-    static constexpr int KT = HB <= 2 ? 3 : HB <= 4 ? 2 : 1;
 
     // 1 / d to full precision: the hardware reciprocal (about 24 correct bits) and two
     // Newton steps (each doubles the correct bits), without the library's special-case paths
@@ -919,180 +891,20 @@ struct Kern {
         return fma(r, fma(-d, r, 1.0), r);
     }
 
-    // One pass: the number c of leading tests (sh_1 .. sh_c) for which every pivot of the
-    // factorisation H - sh_j I = L D L^H (L unit lower triangular) is positive.  A pass always
-    // runs over all n rows (a test that has failed computes on with meaningless values): the
-    // lanes of a wavefront run in step anyway, and every pass then costs the same known work.
-    // The pass also returns hmin = min_i H[i][i] = min_i |M e_i|^2, an upper bound on
-    // sigma_min^2.
-    static __device__ int pd_pass(const EvalArgs &a, const Lane &ln, const double (&sh)[KT], double &hmin) {
-        const int64_t n = nn(a, ln);
-        const double2 *ab = band(a, ln);
-        // The band address is the same in every lane; held in vector registers it is read by
-        // vector loads into vector registers, instead of scalar loads whose values would
-        // overflow the scalar register file.
-        asm volatile("" : "+v"(ab));
-        const cd z = ln.z;
-        // Per test j, the factor rows i-1 .. i-HB: P[j][e-1][f-1] = L[i-e][i-e-f] (f = 1 ..
-        // HB-e, the entries later rows still need) and Q[j][e-1] = 1 / d[i-e]; rows before the
-        // first are zero.
-        constexpr int HA = HB > 0 ? HB : 1;   // (the pass is not compiled in for HB = 0)
-        cd P[KT][HA][HA];
-        double Q[KT][HA];
-        bool ok[KT];
-#pragma unroll
-        for (int j = 0; j < KT; ++j) {
-            ok[j] = true;
-#pragma unroll
-            for (int e = 0; e < HA; ++e) {
-                Q[j][e] = 0.0;
-#pragma unroll
-                for (int f = 0; f < HA; ++f) P[j][e][f] = czero();
-            }
-        }
-        // M[r][r + d - kl] of band row r (zero outside the matrix)
-        auto mrow = [&](int64_t r, int d) -> cd {
-            const cd v = ab[r * W + d];
-            const bool diag = d == KL && r >= 0 && r < n;
-            return C(diag ? z.x - v.x : -v.x, diag ? z.y - v.y : -v.y);
-        };
-        // Mb[q][d] = M[r][r + d - kl] for the rows r = i0 - ku + q of the current block
-        cd Mb[PB + HB][W];
-#pragma unroll
-        for (int q = 0; q < PB + HB; ++q)
-#pragma unroll
-            for (int d = 0; d < W; ++d) Mb[q][d] = mrow(q - KU, d);
-        double hm = 0x1p1000;
-        // one row of the factorisations (row = false: a row past n, which acts as an identity row)
-        auto do_row = [&](int p, bool row) {
-            // H[i][i-e] = sum_t conj(M[r][i]) M[r][i-e], r = i - ku + t, t = 0 .. HB - e
-            cd h[HB + 1];
-#pragma unroll
-            for (int e = 0; e <= HB; ++e) {
-                double hx = 0.0, hy = 0.0;
-#pragma unroll
-                for (int t = 0; t <= HB - e; ++t) {
-                    const cd mi = Mb[p + t][HB - t], mj = Mb[p + t][HB - t - e];
-                    hx = fma(mi.x, mj.x, fma(mi.y, mj.y, hx));
-                    if (e > 0) hy = fma(mi.x, mj.y, fma(-mi.y, mj.x, hy));
-                }
-                h[e] = row ? C(hx, hy) : czero();
-            }
-            if (row) hm = fmin(hm, h[0].x);
-#pragma unroll
-            for (int j = 0; j < KT; ++j) {
-                // row i, m = i - e:  w_m = L[i][m] d[m] = H[i][m] - sum_{l < m} w_l conj(L[m][l]),
-                // L[i][m] = w_m / d[m],  d[i] = H[i][i] - sh - sum_m Re(w_m conj(L[i][m]))
-                double d = row ? h[0].x - sh[j] : 1.0;
-                cd wv[HB + 1], lv[HB + 1];
-#pragma unroll
-                for (int e = HB; e >= 1; --e) {
-                    cd acc = h[e];
-#pragma unroll
-                    for (int e2 = HB; e2 > e; --e2) acc = cfnmac(P[j][e - 1][e2 - e - 1], wv[e2], acc);
-                    wv[e] = acc;
-                    lv[e] = cscale(acc, Q[j][e - 1]);
-                    d = fma(-acc.x, lv[e].x, fma(-acc.y, lv[e].y, d));
-                }
-                ok[j] = ok[j] && d > 0.0;
-#pragma unroll
-                for (int e = HB - 1; e >= 1; --e) {
-                    Q[j][e] = Q[j][e - 1];
-#pragma unroll
-                    for (int f = 0; f + e + 1 < HB; ++f) P[j][e][f] = P[j][e - 1][f];
-                }
-                Q[j][0] = recip(d);            // not used once ok[j] is false
-#pragma unroll
-                for (int f = 1; f < HB; ++f) P[j][0][f - 1] = lv[f];
-            }
-        };
-        for (int64_t i0 = 0; i0 < n; i0 += PB) {
-            // the rows the next block adds: i0 + PB + kl .. i0 + 2 PB - 1 + kl
-            cd Nb[PB][W];
-#pragma unroll
-            for (int q = 0; q < PB; ++q)
-#pragma unroll
-                for (int d = 0; d < W; ++d) Nb[q][d] = mrow(i0 + PB + KL + q, d);
-            if (i0 + PB <= n) {
-#pragma unroll
-                for (int p = 0; p < PB; ++p) do_row(p, true);
-            } else {
-#pragma unroll
-                for (int p = 0; p < PB; ++p) do_row(p, i0 + p < n);
-            }
-#pragma unroll
-            for (int q = 0; q < HB; ++q)
-#pragma unroll
-                for (int d = 0; d < W; ++d) Mb[q][d] = Mb[q + PB][d];
-#pragma unroll
-            for (int q = 0; q < PB; ++q)
-#pragma unroll
-                for (int d = 0; d < W; ++d) Mb[HB + q][d] = Nb[q][d];
-        }
-        hmin = hm;
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < KT; ++j) c += (c == j && ok[j]) ? 1 : 0;
-        return c;
-    }
-
-    // A fresh shift: phase 1 (bisection) if it may qualify, with the bracket [sigma_adm, mn].
+    // A fresh shift: straight to its singular pair if the bisection kernel settled its bracket;
+    // the Golub-Kahan path otherwise (below the bisection's limit, or no brackets given).
     static __device__ void bis_begin(const EvalArgs &a, Lane &ln) {
         ln.phase = 0;
         ln.nbis = 0;
-        if (!BIS || !a.bisect) return;
-        if (a.brk_np) {               // the bracket is known: straight to the singular pair
-            const int np = a.brk_np[ln.pid];
-            if (np < 0) return;       // sigma below the bisection's limit: the Golub-Kahan path
-            ln.phase = 1;
-            ln.nbis = np;
-            ln.blo = a.brk_lo[ln.pid];
-            ln.bhi = a.brk_hi[ln.pid];
-            const double target = a.tol_norm * fro(a, ln) + a.tol_rel * ln.blo;
-            finish_bis(a, ln, 0.5 * (ln.blo + ln.bhi), ln.bhi - ln.blo <= target ? 0 : 2);
-            return;
-        }
-        const double mn = hypot(ln.z.x, ln.z.y) + nrm2(a, ln);
-        if (!(mn < 1e100 && mn > 1e-100)) return;   // H and its pivots stay far from over/underflow
-        const double b = a.tol_norm * fro(a, ln), c = 256.0 * 0x1p-52 * mn * mn;
-        const double adm = 2.0 * c / (b + sqrt(b * b + 4.0 * a.tol_rel * c));   // inf if the target is 0
-        if (!(adm < mn)) return;
+        if (!BIS || !a.bisect || !a.brk_np) return;
+        const int np = a.brk_np[ln.pid];
+        if (np < 0) return;
         ln.phase = 1;
-        ln.blo = adm;
-        ln.bhi = mn;
-    }
-
-    // One pass of a lane in phase 1.  The first pass tests sigma_adm and KT - 1 points
-    // spread geometrically up to mn; later passes split the bracket into KT + 1 parts,
-    // geometrically while hi > 2 lo, then evenly.  The result is the midpoint of the final
-    // bracket, whose width is at most target(lo).
-    static __device__ void bis_cycle(const EvalArgs &a, Lane &ln) {
-        const bool first = ln.nbis == 0;
-        const double lo = ln.blo, hi = ln.bhi;
-        double t[KT], sh[KT];
-        const bool geo = first || hi > 2.0 * lo;
-        const double lr = geo ? log2(hi / lo) : 0.0;
-#pragma unroll
-        for (int j = 0; j < KT; ++j) {
-            const double f = first ? (double)j / KT : (double)(j + 1) / (KT + 1);
-            t[j] = geo ? (j == 0 && first ? lo : lo * exp2(f * lr)) : lo + (hi - lo) * f;
-            sh[j] = t[j] * t[j];
-        }
-        double hmin = 0.0;
-        const int c = pd_pass(a, ln, sh, hmin);
-        ln.nbis += 1;
-        if (first && c == 0) {        // sigma_min < sigma_adm: the Golub-Kahan path
-            ln.phase = 0;
-            return;
-        }
-        // tests are monotone in t: t_c < sigma_min <= t_{c+1}
-        if (c > 0) ln.blo = fmax(lo, t[c - 1]);
-        if (c < KT) ln.bhi = fmin(hi, t[c]);
-        if (first) ln.bhi = fmin(ln.bhi, sqrt(hmin));
+        ln.nbis = np;
+        ln.blo = a.brk_lo[ln.pid];
+        ln.bhi = a.brk_hi[ln.pid];
         const double target = a.tol_norm * fro(a, ln) + a.tol_rel * ln.blo;
-        const double mid = 0.5 * (ln.blo + ln.bhi);
-        const bool done = ln.bhi - ln.blo <= target || !(mid > ln.blo && mid < ln.bhi);
-        if (done || ln.nbis >= kBisMaxPass) finish_bis(a, ln, mid, done ? 0 : 2);
+        finish_bis(a, ln, 0.5 * (ln.blo + ln.bhi), ln.bhi - ln.blo <= target ? 0 : 2);
     }
 
     static __device__ void finish_bis(const EvalArgs &a, Lane &ln, double sigma, int flags) {
@@ -1758,11 +1570,10 @@ struct Kern {
                 }
                 continue;
             }
-            // Lanes in the bisection, or computing their vectors after it, take one unit of
-            // that work per cycle.
+            // Lanes computing their vectors after the bisection take one unit of that work per
+            // cycle.
             if (BIS && __any(ln.active && !gk(ln))) {
-                if (ln.active && ln.phase == 1) bis_cycle(a, ln);
-                else if (ln.active && ln.phase == 2) vec_cycle(a, w, s, ln);
+                if (ln.active && ln.phase == 2) vec_cycle(a, w, s, ln);
             }
             if (!__any(ln.active && gk(ln))) continue;
             // With vectors a cycle serves lanes in all three stages; lanes sit out the sweeps

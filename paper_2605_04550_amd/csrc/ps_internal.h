@@ -168,8 +168,8 @@ struct BisArgs {
     // 3: every pass, then save each final bracket (passes; -1 below the bisection's limit)
     // instead of writing sigma, for the singular vectors that follow
     int phase = 0;
-    double *st_lo = nullptr, *st_hi = nullptr;   // saved brackets (queue position, or output
-    int32_t *st_np = nullptr;                    // position in a batch); passes, -1 = settled
+    double *st_lo = nullptr, *st_hi = nullptr;   // saved brackets (queue position; output position
+    int32_t *st_np = nullptr;                    // in phase 3 and in a batch); passes, -1 = settled
 };
 
 size_t gram_bytes(int64_t n, int kl, int ku);

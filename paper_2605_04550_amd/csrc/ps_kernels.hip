@@ -529,16 +529,17 @@ static bool bisects(const EvalArgs &a, const Workspace &ws) {
     return !a.want_vectors && a.bisect && a.kl + a.ku >= 1 && a.gram && ws.gk_list && ws.npts_max > 0;
 }
 
-// Calls with vectors on a short list of shifts (contour refinement and tracing evaluate one shift
-// per contour point): the Golub-Kahan kernel's own bisection runs one test per lane and pass on
-// one lane per shift, so such a call is a few wavefronts doing some thirty passes each.  Instead
-// the bisection kernel first finds every bracket with a whole wavefront per shift (64 tests per
-// pass, a handful of passes), and the vector kernel starts from those brackets.
+// Calls with vectors and the bisection on: the Golub-Kahan kernel's own bisection runs at one
+// wavefront per SIMD (its registers hold the Lanczos state as well), so the bisection kernel
+// first finds every shift's final bracket (phase 3: saved at the shift's output position)
+// and the vector kernel starts from those brackets: inverse iteration for the shifts that
+// qualified, the Golub-Kahan process for the others.  Short shift sets (contour refinement
+// and tracing evaluate one shift per contour point) take a whole wavefront per shift, 64
+// tests per pass; larger ones the call's lanes per shift.
 constexpr int64_t kWaveBracketMax = 2048;
 
-static bool wave_brackets(const EvalArgs &a, const Workspace &ws) {
-    return a.want_vectors && a.bisect && a.kl + a.ku >= 1 && a.gram && a.mode == kShiftList && ws.st_np &&
-           ws.npts_max > 0 && ws.npts_max <= kWaveBracketMax;
+static bool brackets_first(const EvalArgs &a, const Workspace &ws) {
+    return a.want_vectors && a.bisect && a.kl + a.ku >= 1 && a.gram && ws.st_np && ws.npts_max > 0;
 }
 
 hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, const SideStream *side) {
@@ -547,15 +548,22 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
     EvalKernel k = pick(a.kl, a.ku, a.want_vectors != 0 ? 1 : 0);
     if (!k) return hipErrorInvalidValue;
     const int64_t blocks = ws.slots / kEvalBlock;
-    if (wave_brackets(a, ws)) {
+    if (brackets_first(a, ws)) {
         BisArgs b;
         b.gram = a.gram;
         b.n = a.n;
         b.hb = a.kl + a.ku;
         b.normA = a.normA;
         b.norm2A = a.norm2A;
-        b.mode = kShiftList;
+        b.mode = a.mode;
         b.z = a.z;
+        b.idx = a.idx;
+        b.ga = a.ga;
+        b.gb = a.gb;
+        b.gc = a.gc;
+        b.gd = a.gd;
+        b.nx = a.nx;
+        b.ny = a.ny;
         b.count_dev = a.count_dev;
         b.tol_norm = a.tol_norm;
         b.tol_rel = a.tol_rel;
@@ -563,7 +571,9 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
         b.st_hi = ws.st_hi;
         b.st_np = ws.st_np;
         b.phase = 3;
-        hipError_t e = launch_bis(b, b.hb, 0, 64, ws.npts_max, st);
+        const int lanes = ws.npts_max <= kWaveBracketMax ? 64 : a.lanes;
+        const int64_t spw = 64 / lanes;
+        hipError_t e = launch_bis(b, b.hb, a.ktm, lanes, (ws.npts_max + spw - 1) / spw, st);
         if (e != hipSuccess) return e;
         a.brk_lo = ws.st_lo;
         a.brk_hi = ws.st_hi;
