@@ -534,9 +534,11 @@ struct Kern {
                 const double fu = bm * rd_old * p2(eu - E_old + be - es);
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
+                    // the previous row's x (xw[1]) enters last: the row-to-row chain is one
+                    // complex multiply-add and the scaling by 1/u_ii
                     cd rhs = cscale(yr[c], fy);
 #pragma unroll
-                    for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                    for (int d = W - 1; d >= 1; --d) rhs = cfnma(Ur[c][d], xw[d], rhs);
                     const cd t = cmul(rhs, Ur[c][0]);
                     flag = flag || unsafe(t);
                     const cd o = C(fma(-fu, ur[c].x, ft * t.x), fma(-fu, ur[c].y, ft * t.y));
@@ -557,7 +559,7 @@ struct Kern {
                 for (int c = 0; c < CH; ++c) {
                     cd rhs = cldexp(yr[c], ey - R);
 #pragma unroll
-                    for (int d = 1; d < W; ++d) rhs = cfnma(Ur[c][d], xw[d], rhs);
+                    for (int d = W - 1; d >= 1; --d) rhs = cfnma(Ur[c][d], xw[d], rhs);
                     const cd inv = Ur[c][0];
                     cd t = cmul(rhs, inv);
                     if (unsafe(t)) {
@@ -1034,7 +1036,7 @@ struct Kern {
                 if (i < n) {
                     cd acc = cscale(vin[r], scale);
 #pragma unroll
-                    for (int e = 1; e <= HB; ++e) acc = cfnma(uu[r][e], y[e - 1], acc);
+                    for (int e = HB; e >= 1; --e) acc = cfnma(uu[r][e], y[e - 1], acc);   // y[0] last
 #pragma unroll
                     for (int e = HB - 1; e >= 1; --e) y[e] = y[e - 1];
                     y[0] = acc;
@@ -1062,7 +1064,7 @@ struct Kern {
                 if (i >= 0) {
                     cd acc = yin[r];
 #pragma unroll
-                    for (int e = 1; e <= HB; ++e)
+                    for (int e = HB; e >= 1; --e)     // x[0] (the previous row's) last
                         if (i + e < n) acc = cfnmac(uu[r][e], x[e - 1], acc);
 #pragma unroll
                     for (int e = HB - 1; e >= 1; --e) x[e] = x[e - 1];
