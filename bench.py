@@ -437,10 +437,10 @@ def main():
                     help="calibration copy + one full-grid launch, for rocprofv3 --pmc")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--lanes", type=int, choices=[1, 2, 4], default=None,
-                    help="batch64: lanes per shift (with --tests: a fixed plan instead of the autotuned one; the "
+                    help="batch64, toeplitz2000: lanes per shift (with --tests: a fixed plan instead of the autotuned one; the "
                          "counter pass and its summary default to the library's default plan)")
     ap.add_argument("--tests", type=int, choices=[1, 2, 3], default=None,
-                    help="batch64: tests-per-lane mode (see include/ps.h)")
+                    help="batch64, toeplitz2000: tests-per-lane mode (see include/ps.h)")
     ap.add_argument("--trace", type=int, default=0, metavar="NSEED",
                     help="instead of the headline: trace the eps = 1e-2 contour of the workload from NSEED seeds")
     ap.add_argument("--labels", type=int, default=0, metavar="NMAT",
@@ -916,9 +916,16 @@ def toeplitz_bench(args, dev):
               file=sys.stderr, flush=True)
         return
 
+    # the plan: the library's default (one lane per shift, tests mode 2) unless --lanes / --tests
+    # fix it.  Not autotuned: the tuner times a call alone, and the plans it picks for each call
+    # of a step (two lanes for the full grid, four for the mask) make the step slower when the
+    # two calls run together (13.1 against 12.1 ms)
+    o = om = api.make_opts(lanes=args.lanes or 0, tests=args.tests or 0)
+    tuned = False
+    lanes, tests = int(o.lanes) or 1, int(o.tests) or 2
+    lanes_m, tests_m = lanes, tests
     # workspaces allocated once, outside the timed region
     from paper_2605_04550_amd import ps_workspace_size
-    o = api.make_opts()
     ws = torch.empty(ps_workspace_size(mat.handle, npts_full, o), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -932,12 +939,14 @@ def toeplitz_bench(args, dev):
     def step():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
-        rf = api.eval_grid(mat, grid, eps=EPS_ZONE, workspace=ws, device=dev, stream=stream)
+        rf = api.eval_grid(mat, grid, eps=EPS_ZONE, workspace=ws, device=dev, stream=stream, lanes=lanes,
+                           tests=tests)
         ev[1].record(stream)
         with torch.cuda.stream(stream_mask):
             stream_mask.wait_event(ev[0])
             ev[2].record(stream_mask)
-            rm = api.eval_grid(mat, grid, mask, eps=EPS_ZONE, workspace=ws_mask, stream=stream_mask)
+            rm = api.eval_grid(mat, grid, mask, eps=EPS_ZONE, workspace=ws_mask, stream=stream_mask, lanes=lanes_m,
+                               tests=tests_m)
             ev[3].record(stream_mask)
         stream.wait_event(ev[3])
         return rf, rm, ev
@@ -1023,6 +1032,7 @@ def toeplitz_bench(args, dev):
             "maxiter_points_full": int(np.sum((info_full & 2) != 0)),
             "bisection_points_full": int(si_full.sum()),
             "bisection_passes_mean": float((info_full[si_full] >> 8).mean()) if si_full.any() else 0.0,
+            "plan": {"lanes": lanes, "tests_mode": tests, "autotuned": tuned},
         },
         "plain": {"value": plain_value, "unit": "shifts/s",
                   "sample": "%d seeded points of the full grid, one launch per shift (same kernel numerics and "
@@ -1035,7 +1045,8 @@ def toeplitz_bench(args, dev):
             "unit": "TFLOP/s",
             "frac": flops_full / dur_full / 1e12 / FP64_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "full-grid call: ps::k_classify, partition kernels, ps::k_eval<1,1,false,false>",
+            "kernel": "full-grid call: the bisection kernel ps::bis::k_bis (first pass, then resumed) and the "
+                      "Golub-Kahan kernel ps::k_eval<1,1,false,false> beside it on a side stream",
             "algorithmic_flops_per_launch": flops_full,
             # bytes of the Golub-Kahan shifts and of the outputs, and the HBM rate they make
             "algorithmic_bytes_per_launch": bytes_full,

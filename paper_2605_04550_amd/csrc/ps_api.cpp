@@ -32,7 +32,17 @@ struct ps_matrix_s {
     double2 *arow;   // device, [n][kl+ku+1] rows 0 .. n-1 of the band
     double2 *abase;  // the allocation: kBandPadTop zero rows, the band, kBandPadBottom zero rows
     double *gram;    // device, the Gram band read by the bisection kernel (kl + ku >= 1)
-    ps::SideStream side;   // second stream for the Golub-Kahan launch beside the bisection
+    // Second streams for the Golub-Kahan launch beside the bisection, one per caller stream
+    // seen (so that concurrent calls on different streams do not queue their Golub-Kahan
+    // launches behind one another): side[0] is created with the handle, the others on first use
+    // by another stream (never while that stream is capturing a graph: such a call shares
+    // side[0]); beyond kMatSides callers, side[0] is shared.
+    static constexpr int kMatSides = 4;
+    ps::SideStream side[kMatSides];
+    hipStream_t side_key[kMatSides];
+    bool side_bound[kMatSides];
+    int nside;
+    std::mutex side_mu;
     int device;
     bool dense;      // kl or ku above the banded kernels' limit: sigma only, n <= kDenseMaxN
 };
@@ -145,6 +155,32 @@ void destroy_side(ps::SideStream *s) {
     if (s->join) (void)hipEventDestroy(s->join);
     s->stream = nullptr;
     s->fork = s->join = nullptr;
+}
+
+// The side stream of a call on `caller` (see ps_matrix_s::side).
+const ps::SideStream *side_for(ps_matrix m, hipStream_t caller) {
+    std::lock_guard<std::mutex> g(m->side_mu);
+    for (int i = 0; i < m->nside; ++i)
+        if (m->side_bound[i] && m->side_key[i] == caller) return &m->side[i];
+    if (!m->side_bound[0]) {
+        m->side_bound[0] = true;
+        m->side_key[0] = caller;
+        return &m->side[0];
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (m->nside < ps_matrix_s::kMatSides && hipStreamIsCapturing(caller, &cs) == hipSuccess &&
+        cs == hipStreamCaptureStatusNone) {
+        ps::SideStream sd;
+        if (create_side(&sd) == hipSuccess) {
+            const int i = m->nside++;
+            m->side[i] = sd;
+            m->side_key[i] = caller;
+            m->side_bound[i] = true;
+            return &m->side[i];
+        }
+        destroy_side(&sd);
+    }
+    return &m->side[0];
 }
 
 ps_status check_grid(const ps_grid *g) {
@@ -570,7 +606,12 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
     m->arow = nullptr;
     m->abase = nullptr;
     m->gram = nullptr;
-    m->side = ps::SideStream();
+    for (int i = 0; i < ps_matrix_s::kMatSides; ++i) {
+        m->side[i] = ps::SideStream();
+        m->side_key[i] = nullptr;
+        m->side_bound[i] = false;
+    }
+    m->nside = 1;
     m->dense = dense;
     (void)hipGetDevice(&m->device);
     // zero rows around the band: kernels may read rows -kBandPadTop .. n + kBandPadBottom - 1
@@ -590,11 +631,11 @@ ps_status ps_create_banded(const ps_c128 *ab, int64_t ldab, int64_t n, int32_t k
         if (e == hipSuccess) e = ps::launch_gram_band(m->arow, n, kl, ku, m->gram, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = create_side(&m->side);
+    if (e == hipSuccess) e = create_side(&m->side[0]);
     if (e != hipSuccess) {
         (void)hipFree(m->abase);
         if (m->gram) (void)hipFree(m->gram);
-        destroy_side(&m->side);
+        destroy_side(&m->side[0]);
         delete m;
         return fail(PS_ERR_HIP, "band upload: %s", hipGetErrorString(e));
     }
@@ -606,7 +647,7 @@ ps_status ps_destroy(ps_matrix m) {
     if (!m) return ok();
     if (m->abase) (void)hipFree(m->abase);
     if (m->gram) (void)hipFree(m->gram);
-    destroy_side(&m->side);
+    for (int i = 0; i < m->nside; ++i) destroy_side(&m->side[i]);
     delete m;
     return ok();
 }
@@ -657,7 +698,7 @@ ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const 
     a.iters = iters_dev;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
-    HIP_TRY(ps::launch_eval(a, w, s, &m->side));
+    HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
     return ok();
 }
 
@@ -716,7 +757,7 @@ ps_status ps_eval_points_noalloc(ps_matrix m, const ps_c128 *z_dev, int64_t npts
     a.iters = iters_dev;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
-    HIP_TRY(ps::launch_eval(a, w, s, &m->side));
+    HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
     return ok();
 }
 
@@ -757,7 +798,7 @@ ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, c
     }
     a.count_dev = w.count;
     HIP_TRY(hipMemcpyAsync(count_dev, w.count, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(ps::launch_eval(a, w, s, &m->side));
+    HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
     return ok();
 }
 
@@ -1004,7 +1045,7 @@ ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts
         const int64_t lattice = ((g->ny + stride - 1) / stride) * ((g->nx + stride - 1) / stride);
         HIP_TRY(ps::launch_label_mask(status, g->nx, npts, stride, mask, s));
         HIP_TRY(ps::launch_compact_mask(mask, npts, idx, w.count, w.blocksums, w.queue, s));
-        HIP_TRY(ps::launch_eval(a, w, s, &m->side));
+        HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
         HIP_TRY(ps::launch_label_update(g->a, g->b, g->c, g->d, g->nx, g->ny, idx, w.count, lattice, sig_c, info_c, eps,
                                         r.tol_norm * m->fro, r.tol_rel, status, sigma_dev, evals, s));
     }
