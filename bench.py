@@ -54,13 +54,13 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector peak
 EPS_ZONE = 1e-2
 CALIB_BYTES = 1 << 30          # the calibration copy: 1 GiB read, 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "toeplitz2000_traffic.json")
-KERNEL_TAG = "k_eval<1, 1, false, false>"
 
 
-# The sources of the measured launch: the kernels (classification, partition, k_eval at
-# kl = ku = 1), their workspace carving and launchers, and the constants they share.  The
-# host-side plan for this workload (one slot per shift) lives in ps_api.cpp.
-EVAL_SOURCES = ("ps_eval.hpp", "ps_eval_kl1.hip", "ps_kernels.hip", "ps_internal.h")
+# The sources of the measured call: the bisection kernel (half-bandwidth 2) and the
+# Golub-Kahan kernel at kl = ku = 1, their workspace carving and launchers, the constants they
+# share, and the host side that plans the call.
+EVAL_SOURCES = ("ps_bisect.hpp", "ps_bisect.hip", "ps_bis_h2.hip", "ps_eval.hpp", "ps_eval_kl1.hip", "ps_kernels.hip",
+                "ps_internal.h", "ps_api.cpp")
 
 
 def source_hash():
@@ -93,7 +93,8 @@ def summarize_counters(fetch_csv, write_csv):
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         rs = rows(path, counter)
         cid, calib = [(d, v) for d, k, v in rs if "copyBuffer" in k and v > 1000.0][0]
-        # every library kernel of the full-grid call (classification, partition, k_eval)
+        # every library kernel of the full-grid call (the bisection kernel's two launches, the
+        # list sort, the Golub-Kahan kernel)
         parts = {}
         for d, k, v in rs:
             if d > cid and "ps::" in k:
@@ -104,15 +105,16 @@ def summarize_counters(fetch_csv, write_csv):
         res[counter] = dict(kib=kern, calib_kib=calib, factor=factor, bytes=kern * 1024.0 * factor,
                             per_kernel_kib=parts)
     traffic = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
-    doc = dict(kernel="full-grid call of toeplitz2000 (ps::k_classify, partition kernels, ps::" + KERNEL_TAG + ")",
+    doc = dict(kernel="full-grid call of toeplitz2000 (the bisection kernel ps::bis::k_bis<2, 2, 1, 1>, "
+                      "ps::k_sort_lists, the Golub-Kahan kernel ps::k_eval<1, 1, false, false>)",
                source_hash=source_hash(), traffic_bytes_per_launch=traffic,
                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
                commands=["timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch "
-                         "-o fetch -- python3 bench.py --counter-pass",
+                         "-o fetch -- python3 bench.py --workload toeplitz2000 --counter-pass",
                          "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write "
-                         "-o write -- python3 bench.py --counter-pass",
-                         "python bench.py --summarize-counters <out>/pmc_fetch/fetch_counter_collection.csv "
-                         "<out>/pmc_write/write_counter_collection.csv"])
+                         "-o write -- python3 bench.py --workload toeplitz2000 --counter-pass",
+                         "python bench.py --workload toeplitz2000 --summarize-counters "
+                         "<out>/pmc_fetch/fetch_counter_collection.csv <out>/pmc_write/write_counter_collection.csv"])
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(doc, f, indent=1)
         f.write("\n")
