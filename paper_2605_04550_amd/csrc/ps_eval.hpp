@@ -231,7 +231,9 @@ struct Lane {
     // Singular vectors (VEC): stage 0 runs the Lanczos process to convergence; stage 1
     // replays its first kfinal steps bit for bit from the same start vector, accumulating
     // v = sum_j p_j u_j (p = top left singular vector of B_kfinal) in vacc; stage 2 applies
-    // one inverse-iteration step u = M^{-H} v / |M^{-H} v| and writes the pair.
+    // one inverse-iteration step u = M^{-H} v / |M^{-H} v| and writes the pair.  With a
+    // Lanczos-vector store (calls on few slots) stage 0 keeps every normalised u_j and v is
+    // formed from them in one pass: no replay.  kfinal counts the kept vectors during stage 0.
     int stage;
     int kfinal;
     double vnorm2;    // |v|^2 of the accumulated vector (known after its last step)
@@ -608,6 +610,10 @@ struct Kern {
         const bool act = ln.active && gk(ln);
         const bool fin = VEC && ln.stage == 2;
         const bool rep = VEC && ln.stage == 1;
+        // first pass with a Lanczos-vector store: keep the normalised u_k (the values a replay
+        // would accumulate) in ustore[k - 1]
+        const bool sto = VEC && ln.stage == 0 && act && w.ustore != nullptr && ln.k >= 1 && ln.k <= w.kstore;
+        double2 *const ust = sto ? w.ustore + (int64_t)(ln.k - 1) * w.nrow * w.slots : nullptr;
         const double2 *uin = fin ? w.vacc : w.vu;
         const int16_t *euin = w.eu;
         const double rdu = fin ? 1.0 / sqrt(ln.vnorm2) : ln.rdu;
@@ -645,6 +651,7 @@ struct Kern {
             for (int d = 0; d < W - 1; ++d) {
                 acc[d] = cscale(uin[d * T + s], f0);
                 if (rep) accum(d, acc[d]);
+                if (sto) ust[d * T + s] = acc[d];
             }
         }
         for (int64_t i0 = 0; i0 < npad; i0 += CH) {
@@ -662,11 +669,15 @@ struct Kern {
             const int ea = ex(q);
             const bool last = i0 + CH >= npad;                 // rows at or past npad were never written
             const int eb = (W > 1 && !last) ? ex(q + 1) : ea;
-            if (rep) {
+            if (rep || sto) {
                 const double ga = rdu * p2(ea - Eu), gb = rdu * p2(eb - Eu);
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
-                    if (c + W - 1 < CH || !last) accum(i0 + c + W - 1, cscale(pin[c], c + W - 1 < CH ? ga : gb));
+                    if (c + W - 1 < CH || !last) {
+                        const cd un = cscale(pin[c], c + W - 1 < CH ? ga : gb);
+                        if (rep) accum(i0 + c + W - 1, un);
+                        if (sto) ust[(i0 + c + W - 1) * T + s] = un;
+                    }
             }
             cd as[W];
 #pragma unroll
@@ -723,6 +734,7 @@ struct Kern {
             w.ey[q * T + s] = (int16_t)R;
         }
         if (act) ln.Ey = R;
+        if (sto) ln.kfinal = ln.k;      // Lanczos vectors kept so far (until the first pass ends)
         if (act && lastk) {
             ln.vnorm2 = vn;
             ln.vamax = vam;
@@ -739,6 +751,8 @@ struct Kern {
                               int &eacc_out) {
         const int64_t n = nn(a, ln), T = w.slots;
         const bool act = ln.active && gk(ln);
+        // the final solve of the singular vectors (stage 2) has no -alpha v term: v is not read
+        const bool fin = VEC && ln.stage == 2;
         int R = ln.Ey;
         cd b[KL + 1];
 #pragma unroll
@@ -796,7 +810,7 @@ struct Kern {
                 } else {
                     pv[c] = 0;
                 }
-                vr[c] = w.vv[(j + KL) * T + s];
+                vr[c] = fin ? czero() : w.vv[(j + KL) * T + s];
             }
             const int eyh = (int)w.ey[pq * T + s];                  // rows >= 8 pq
             const int eyl = pq > 0 ? (int)w.ey[(pq - 1) * T + s] : eyh;   // rows < 8 pq
@@ -812,7 +826,7 @@ struct Kern {
                 const int es = R > ae ? R : ae;
                 eo = es;
                 const double fh = p2(eyh - R), fl = p2(eyl - R), fbv = p2(R - es);
-                const double fv = am * rdv * p2(evp - Ev + ae - es);
+                const double fv = fin ? 0.0 : am * rdv * p2(evp - Ev + ae - es);
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     // row j = jtop - c lies in chunk pq iff c + kl < 8
@@ -851,7 +865,7 @@ struct Kern {
                     for (int r = 1; r <= KL; ++r) cswap_if(pv[c] == r, b[0], b[r]);
                     const int es = R > ae ? R : ae;
                     const cd val = cldexp(b[KL], R - es);
-                    const cd vo = cscale(cldexp(vr[c], evp - Ev + ae - es), am * rdv);
+                    const cd vo = fin ? czero() : cscale(cldexp(vr[c], evp - Ev + ae - es), am * rdv);
                     ob[c] = csub(val, vo);
                     Ec[c] = es;
 #pragma unroll
@@ -1186,6 +1200,61 @@ struct Kern {
         for (int j = 0; j < k; ++j) vm(j, 3) *= rpn;
     }
 
+    // Ritz vector v = sum_j p_j u_j (j = 1 .. kfinal) from the Lanczos vectors kept by the first
+    // pass, into vacc, with |v|^2 and the first entry of largest modulus (as the replay's last
+    // step gives them; same terms, same order).  A block of RB rows reads JB kept vectors per
+    // memory wait.
+    static __device__ __forceinline__ void ritz_from_store(const Workspace &w, int64_t s, Lane &ln, int64_t n) {
+        const int64_t T = w.slots, nr = w.nrow;
+        const int k = ln.kfinal;
+        const int64_t npad = ((n + CH - 1) / CH) * CH;
+        constexpr int RB = 4, JB = 8;
+        double vn = 0.0, vam = -1.0;
+        cd vph = C(1.0, 0.0);
+        for (int64_t r0 = 0; r0 < npad; r0 += RB) {
+            cd v[RB];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) v[b] = czero();
+            for (int j0 = 0; j0 < k; j0 += JB) {
+                cd u[JB][RB];
+                double c[JB];
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb) {
+                    const int j = j0 + jb < k ? j0 + jb : k - 1;     // past k: a valid row, unused
+                    c[jb] = w.vmeta[((int64_t)j * 4 + 3) * T + s];
+#pragma unroll
+                    for (int b = 0; b < RB; ++b) u[jb][b] = w.ustore[((int64_t)j * nr + r0 + b) * T + s];
+                }
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb) {
+                    if (j0 + jb < k) {
+#pragma unroll
+                        for (int b = 0; b < RB; ++b) {
+                            const cd t = C(c[jb] * u[jb][b].x, c[jb] * u[jb][b].y);
+                            v[b] = j0 + jb == 0 ? t : C(v[b].x + t.x, v[b].y + t.y);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                const int64_t r = r0 + b;
+                w.vacc[r * T + s] = v[b];
+                if (r < n) {
+                    const double m = cabs2(v[b]);
+                    vn += m;
+                    if (m > vam) {
+                        vam = m;
+                        vph = v[b];
+                    }
+                }
+            }
+        }
+        ln.vnorm2 = vn;
+        ln.vamax = vam;
+        ln.vph = vph;
+    }
+
     // Stage 2 output, after the inverse-iteration step left M^{-H} v in vv (|.|^2 = acc 2^(2 eacc)):
     // v = vacc / |vacc|, u = that direction normalised, both rotated by the unit scalar that
     // makes the first entry of v of largest modulus real and positive.
@@ -1236,9 +1305,16 @@ struct Kern {
                     a.v[ln.pid * nn(a, ln) + i] = czero();
                 }
             } else {
-                // replay the same kfinal steps from the same start vector (the factors stay)
                 ritz_coeffs(w, s, ln);
+                const int kept = ln.kfinal;      // Lanczos vectors the first pass kept
                 ln.kfinal = ln.k;
+                if (w.ustore && ln.k >= 1 && kept == ln.k) {
+                    // the Ritz vector from the kept vectors; the final solve follows (stage 2)
+                    ritz_from_store(w, s, ln, nn(a, ln));
+                    ln.stage = 2;
+                    return;  // the lane stays active
+                }
+                // replay the same kfinal steps from the same start vector (the factors stay)
                 ln.stage = 1;
                 ln.fresh = true;
                 ln.k = 0;
@@ -1486,6 +1562,7 @@ struct Kern {
         if (VEC) {
             w.vacc = g.vacc + wv * nr * 64 + l;
             w.vmeta = g.vmeta + wv * (int64_t)g.kmax * 4 * 64 + l;
+            if (g.ustore) w.ustore = g.ustore + wv * (int64_t)g.kstore * nr * 64 + l;
         }
         return w;
     }
@@ -1545,6 +1622,7 @@ struct Kern {
                     ln.exhausted = qid < 0;
                     ln.fresh = true;
                     ln.stage = 0;
+                    ln.kfinal = 0;
                     ln.phase = 0;
                     ln.sing = false;
                     ln.k = 0;

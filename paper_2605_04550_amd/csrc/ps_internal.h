@@ -56,6 +56,11 @@ struct Workspace {
     double *hist = nullptr;        // [kmax][2][slots] Lanczos tridiagonal: diag, offdiag^2
     double2 *vacc = nullptr;       // [n][slots]       singular-vector accumulator (vectors only)
     double *vmeta = nullptr;       // [kmax][4][slots] alpha', beta', Ritz work, coefficients (vectors only)
+    // Calls with vectors on few slots: the normalised Lanczos vectors u_1 .. u_kstore, kept so
+    // that the Ritz vector is one pass over them instead of a replay of the Lanczos steps
+    // (see kstore_for); NULL and 0 otherwise.
+    double2 *ustore = nullptr;     // [kstore][n][slots]
+    int kstore = 0;
     unsigned long long *queue = nullptr;   // shift counter of the persistent launch
     int64_t *count = nullptr;      // number of shifts (device)
     int64_t *blocksums = nullptr;  // mask compaction scratch
@@ -212,6 +217,21 @@ hipError_t launch_sort_lists(int64_t *lists, const ListBases &bases, const int64
 size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max);
 // The carve-up of one evaluation workspace (host and device: the batch's Golub-Kahan kernel
 // carves each class's part itself).
+// Lanczos vectors kept per slot in a call with vectors: up to 64 (and up to kmax) while the
+// store stays within 4 GiB, for calls of at most 4096 slots (contour refinement, tracing and
+// other short shift lists; a full grid replays the Lanczos steps instead).
+constexpr int64_t kStoreMaxSlots = 4096;
+constexpr int kStoreMaxK = 64;
+constexpr double kStoreBudget = 4.0 * (1ull << 30);
+__host__ __device__ inline int kstore_for(int64_t slots, int64_t nrow, int kmax, int vec) {
+    if (!vec || slots > kStoreMaxSlots || slots < 1) return 0;
+    const double per_k = 16.0 * (double)slots * (double)nrow;
+    double k = kStoreBudget / per_k;
+    if (k > kStoreMaxK) k = kStoreMaxK;
+    if (k > kmax) k = kmax;
+    return k >= 1.0 ? (int)k : 0;
+}
+
 __host__ __device__ inline void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax,
                                                 int vec, int64_t npts_max, Workspace *w) {
     size_t off = 0;
@@ -247,6 +267,8 @@ __host__ __device__ inline void carve_workspace(void *base, int64_t n, int kl, i
         w->vacc = nullptr;
         w->vmeta = nullptr;
     }
+    w->kstore = kstore_for(slots, nrow, kmax, vec);
+    w->ustore = w->kstore > 0 ? (double2 *)take(sizeof(double2) * ns * (size_t)w->kstore) : nullptr;
     if (npts_max > 0) {
         w->gk_list = (int64_t *)take(sizeof(int64_t) * (size_t)npts_max);
         w->gk_count = (int64_t *)take(sizeof(int64_t));
