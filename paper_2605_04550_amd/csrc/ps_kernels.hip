@@ -89,6 +89,53 @@ __global__ void __launch_bounds__(kScanBlock) k_mask_scatter(const uint8_t *mask
         if (base + q < npts && mask[base + q]) idx[pos++] = base + q;
 }
 
+// Queue order of a call with vectors: the shifts the bisection settled (saved passes >= 0)
+// first, then those on the Golub-Kahan path, each in queue order.  A wavefront then holds
+// shifts of one kind: a lane computing its vectors by inverse iteration and a lane on the
+// Golub-Kahan path would otherwise pay for each other's work every cycle.  np is indexed by
+// output position: the flat index of the tile order for a full grid, the queue position
+// otherwise (as the bisection kernel saved it).
+__device__ __forceinline__ int64_t part_out_pos(int mode, const int64_t *idx, int64_t q, int64_t nx, int64_t ny) {
+    return (mode != kShiftList && !idx) ? tile_flat(q, nx, ny) : q;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_part_count(const int32_t *np, const int64_t *count, int mode,
+                                                           const int64_t *idx, int64_t nx, int64_t ny,
+                                                           int64_t *blocksums) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t cnt = *count;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < cnt && np[part_out_pos(mode, idx, base + q, nx, ny)] >= 0) ++c;
+    int64_t total;
+    block_scan(c, sh, total);
+    if (threadIdx.x == 0) blocksums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_part_scatter(const int32_t *np, const int64_t *count, int mode,
+                                                             const int64_t *idx, int64_t nx, int64_t ny,
+                                                             const int64_t *blocksums, const int64_t *nbis,
+                                                             int64_t *perm) {
+    __shared__ int64_t sh[kScanBlock];
+    const int64_t cnt = *count, nb = *nbis;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    bool bis[kScanItems];
+    int64_t c = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        bis[q] = base + q < cnt && np[part_out_pos(mode, idx, base + q, nx, ny)] >= 0;
+        c += bis[q] ? 1 : 0;
+    }
+    int64_t total;
+    int64_t pos = blocksums[blockIdx.x] + block_scan(c, sh, total);   // settled shifts before base
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + q;
+        if (i >= cnt) break;
+        if (bis[q]) perm[pos++] = i;
+        else perm[nb + (i - pos)] = i;      // i - pos: Golub-Kahan shifts before i
+    }
+}
+
 // ------------------------------------------------------------------------ contour seeds
 // Edge e of an nx x ny grid: the first ny (nx - 1) edges are horizontal, (i, j)-(i, j+1) in
 // row-major order; the next (ny - 1) nx are vertical, (i, j)-(i+1, j).  An edge seeds the
@@ -575,6 +622,18 @@ hipError_t launch_eval(const EvalArgs &a0, const Workspace &ws, hipStream_t st, 
         const int64_t spw = 64 / lanes;
         hipError_t e = launch_bis(b, b.hb, a.ktm, lanes, (ws.npts_max + spw - 1) / spw, st);
         if (e != hipSuccess) return e;
+        if (ws.gk_list && ws.gk_count && ws.blocksums) {   // settled shifts first (k_part_*)
+            const int64_t nb = ws.npts_max > kScanTile ? (ws.npts_max + kScanTile - 1) / kScanTile : 1;
+            hipLaunchKernelGGL(k_part_count, dim3((unsigned)nb), dim3(kScanBlock), 0, st, (const int32_t *)ws.st_np,
+                               a.count_dev, a.mode, a.idx, a.nx, a.ny, ws.blocksums);
+            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ws.blocksums, nb, ws.gk_count,
+                               ws.queue);
+            hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(kScanBlock), 0, st,
+                               (const int32_t *)ws.st_np, a.count_dev, a.mode, a.idx, a.nx, a.ny,
+                               (const int64_t *)ws.blocksums, (const int64_t *)ws.gk_count, ws.gk_list);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            a.perm = ws.gk_list;
+        }
         a.brk_lo = ws.st_lo;
         a.brk_hi = ws.st_hi;
         a.brk_np = ws.st_np;
