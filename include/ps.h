@@ -144,7 +144,10 @@ ps_status ps_matrix_info(ps_matrix m, int64_t *n, int32_t *kl, int32_t *ku, doub
 /*
  * ps_workspace_size -- bytes of device workspace needed by ps_eval_points / ps_eval_grid
  * for npts shifts with options o (NULL = defaults).  The result depends on n, kl, ku, the
- * number of slots and whether vectors are wanted, not on the shift values.
+ * number of slots and whether vectors are wanted, not on the shift values.  With vectors on
+ * at most 4096 slots it includes room for the Lanczos vectors of each slot (up to 64 of them,
+ * at most 4 GiB in all), from which the Ritz vector is formed instead of replaying the
+ * Lanczos steps.  A smaller workspace is accepted: the call then runs on fewer slots.
  */
 ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes);
 
@@ -157,13 +160,16 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
  *   u_dev, v_dev  device ps_c128[npts][n] or NULL; required when o->want_vectors.
  *              Unit singular vectors with (zI - A) v = sigma u; the joint phase makes the
  *              first entry of v of largest modulus real and positive.  For a shift that took
- *              the inertia bisection (PS_PT_BISECT in info), v comes from four steps of
- *              inverse iteration with the bisection's last factorisation, L D L^H of
- *              (zI - A)^H (zI - A) - lo^2 I (lo the bracket's lower end), and
- *              u = (zI - A) v / |(zI - A) v|.  For the other shifts v is the Ritz vector of
- *              the converged Lanczos process (a second pass replays its steps exactly and
- *              accumulates it, so vectors cost about twice the steps of sigma alone) and u
- *              one inverse-iteration step from it, u = (zI - A)^{-H} v / |(zI - A)^{-H} v|.
+ *              the inertia bisection (PS_PT_BISECT in info; the bisection kernel runs first
+ *              over all shifts of a call with vectors and saves each bracket), v comes from
+ *              four steps of inverse iteration with L D L^H of (zI - A)^H (zI - A) - lo^2 I
+ *              (lo the bracket's lower end, where the bisection found it positive definite),
+ *              and u = (zI - A) v / |(zI - A) v|.  For the other shifts v is the Ritz vector
+ *              of the converged Lanczos process, formed from the Lanczos vectors the first
+ *              pass kept (see ps_workspace_size) or, where they were not kept, by a second pass
+ *              that replays its steps exactly (then vectors cost about twice the steps of
+ *              sigma alone), and u one inverse-iteration step from it,
+ *              u = (zI - A)^{-H} v / |(zI - A)^{-H} v|.
  *   info_dev   device int32[npts] or NULL (PS_PT_* bits).  iters_dev: int32[npts] or NULL:
  *              Golub-Kahan (inverse Lanczos) steps (0 for a shift flagged PS_PT_BISECT,
  *              whose number of Cholesky tests is in info).
