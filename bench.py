@@ -436,7 +436,7 @@ def main():
     ap.add_argument("--plain-points", type=int, default=32)
     ap.add_argument("--serial", action="store_true", help="run the full-grid and mask evaluations back to back")
     ap.add_argument("--counter-pass", action="store_true",
-                    help="calibration copy + one full-grid launch, for rocprofv3 --pmc")
+                    help="calibration copy + one full-grid call of the workload (with vectors for grcar4000), for rocprofv3 --pmc")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--lanes", type=int, choices=[1, 2, 4], default=None,
                     help="batch64, toeplitz2000: lanes per shift (with --tests: a fixed plan instead of the autotuned one; the "
@@ -849,6 +849,20 @@ def grcar4000_bench(args, dev):
     band.real = False
     mat = api.BandedMatrix.from_band(band)
     wts = torch.tensor(w["weights"], device=dev)
+
+    if args.counter_pass:
+        # for rocprofv3 --pmc: a calibration copy of known size, then one grid call with vectors
+        x = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print("bench: calibration copy done (%d bytes each way)" % CALIB_BYTES, file=sys.stderr, flush=True)
+        del x, y
+        api.eval_grid(mat, grid, eps=eps, want_vectors=True, device=dev)
+        torch.cuda.synchronize()
+        print("bench: grid call with vectors done", file=sys.stderr, flush=True)
+        return
 
     def step():
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
