@@ -34,15 +34,18 @@ struct ps_matrix_s {
     double *gram;    // device, the Gram band read by the bisection kernel (kl + ku >= 1)
     // Second streams for the Golub-Kahan launch beside the bisection, one per caller stream
     // seen (so that concurrent calls on different streams do not queue their Golub-Kahan
-    // launches behind one another): side[0] is created with the handle, the others on first use
-    // by another stream (never while that stream is capturing a graph: such a call shares
-    // side[0]); beyond kMatSides callers, side[0] is shared.
+    // launches behind one another): side[0] is created with the handle, the others on the
+    // handle's device on first use by another stream (never while that stream is capturing a
+    // graph: such a call shares side[0]); beyond kMatSides callers, side[0] is shared.  A call
+    // holds its side stream's mutex while it enqueues the fork, the launch and the join, so
+    // that calls sharing a side stream from several threads do not interleave its events.
     static constexpr int kMatSides = 4;
     ps::SideStream side[kMatSides];
     hipStream_t side_key[kMatSides];
     bool side_bound[kMatSides];
     int nside;
-    std::mutex side_mu;
+    std::mutex side_mu;                   // the table above
+    std::mutex side_call_mu[kMatSides];   // one enqueue sequence at a time per side stream
     int device;
     bool dense;      // kl or ku above the banded kernels' limit: sigma only, n <= kDenseMaxN
 };
@@ -157,31 +160,47 @@ void destroy_side(ps::SideStream *s) {
     s->fork = s->join = nullptr;
 }
 
-// The side stream of a call on `caller` (see ps_matrix_s::side).
-const ps::SideStream *side_for(ps_matrix m, hipStream_t caller) {
+// Index of the side stream of a call on `caller` (see ps_matrix_s::side).
+int side_index(ps_matrix m, hipStream_t caller) {
     std::lock_guard<std::mutex> g(m->side_mu);
     for (int i = 0; i < m->nside; ++i)
-        if (m->side_bound[i] && m->side_key[i] == caller) return &m->side[i];
+        if (m->side_bound[i] && m->side_key[i] == caller) return i;
     if (!m->side_bound[0]) {
         m->side_bound[0] = true;
         m->side_key[0] = caller;
-        return &m->side[0];
+        return 0;
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (m->nside < ps_matrix_s::kMatSides && hipStreamIsCapturing(caller, &cs) == hipSuccess &&
         cs == hipStreamCaptureStatusNone) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != m->device) (void)hipSetDevice(m->device);
         ps::SideStream sd;
-        if (create_side(&sd) == hipSuccess) {
+        const hipError_t e = create_side(&sd);
+        if (cur != m->device) (void)hipSetDevice(cur);
+        if (e == hipSuccess) {
             const int i = m->nside++;
             m->side[i] = sd;
             m->side_key[i] = caller;
             m->side_bound[i] = true;
-            return &m->side[i];
+            return i;
         }
         destroy_side(&sd);
     }
-    return &m->side[0];
+    return 0;
 }
+
+// The side stream of a call on `caller`, held for the call's enqueue sequence.
+struct SideLock {
+    const ps::SideStream *side;
+    std::unique_lock<std::mutex> lk;
+    SideLock(ps_matrix m, hipStream_t caller) {
+        const int i = side_index(m, caller);
+        side = &m->side[i];
+        lk = std::unique_lock<std::mutex>(m->side_call_mu[i]);
+    }
+};
 
 ps_status check_grid(const ps_grid *g) {
     if (!g) return fail(PS_ERR_INVALID, "grid is NULL");
@@ -698,7 +717,10 @@ ps_status ps_eval_points(ps_matrix m, const ps_c128 *z_dev, int64_t npts, const 
     a.iters = iters_dev;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
-    HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
+    {
+        SideLock sl(m, s);
+        HIP_TRY(ps::launch_eval(a, w, s, sl.side));
+    }
     return ok();
 }
 
@@ -757,7 +779,10 @@ ps_status ps_eval_points_noalloc(ps_matrix m, const ps_c128 *z_dev, int64_t npts
     a.iters = iters_dev;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ps::launch_set_count(w.count, npts, w.queue, s));
-    HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
+    {
+        SideLock sl(m, s);
+        HIP_TRY(ps::launch_eval(a, w, s, sl.side));
+    }
     return ok();
 }
 
@@ -798,7 +823,10 @@ ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, c
     }
     a.count_dev = w.count;
     HIP_TRY(hipMemcpyAsync(count_dev, w.count, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
+    {
+        SideLock sl(m, s);
+        HIP_TRY(ps::launch_eval(a, w, s, sl.side));
+    }
     return ok();
 }
 
@@ -855,6 +883,7 @@ struct ps_batch_s {
     ps::MatDesc *desc_lpt = nullptr;      // device, longest-first by predicted bisection cost
     static constexpr int kSides = 1;      // the stream of the Golub-Kahan launch
     ps::SideStream side[kSides];
+    std::mutex side_mu;                   // held while a call enqueues its fork, launch and join
     int max_hb = 0;                       // largest kl + ku
     int64_t lpt_chunks[3] = {0, 0, 0};    // chunks of 64, 32, 16 shifts over the full grids
     struct Cls {
@@ -1045,7 +1074,10 @@ ps_status ps_label_grid(ps_matrix m, const ps_grid *g, double eps, const ps_opts
         const int64_t lattice = ((g->ny + stride - 1) / stride) * ((g->nx + stride - 1) / stride);
         HIP_TRY(ps::launch_label_mask(status, g->nx, npts, stride, mask, s));
         HIP_TRY(ps::launch_compact_mask(mask, npts, idx, w.count, w.blocksums, w.queue, s));
-        HIP_TRY(ps::launch_eval(a, w, s, side_for(m, s)));
+        {
+            SideLock sl(m, s);
+            HIP_TRY(ps::launch_eval(a, w, s, sl.side));
+        }
         HIP_TRY(ps::launch_label_update(g->a, g->b, g->c, g->d, g->nx, g->ny, idx, w.count, lattice, sig_c, info_c, eps,
                                         r.tol_norm * m->fro, r.tol_rel, status, sigma_dev, evals, s));
     }
@@ -1563,6 +1595,7 @@ static ps_status batch_eval_core(ps_batch b, const uint8_t *const *masks_dev, co
         HIP_TRY(ps::launch_sort_lists(bs.gk_list, lb, bs.gk_count, (int)ncls, s));
     }
     ps::SideStream &sd = b->side[0];
+    std::lock_guard<std::mutex> side_lock(b->side_mu);
     HIP_TRY(hipEventRecord(sd.fork, s));
     HIP_TRY(hipStreamWaitEvent(sd.stream, sd.fork, 0));
     HIP_TRY(ps::launch_gk_batch(g, blocks, sd.stream));

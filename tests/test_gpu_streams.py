@@ -48,3 +48,26 @@ def test_concurrent_calls_on_one_handle_equal_serial_calls():
             for key in ("idx", "sigma", "info", "iters", "sens"):
                 assert torch.equal(a[key][:cnt], b[key][:cnt]), (rep, k, key)
     print("3 rounds of %d concurrent calls equal the serial ones" % len(work), flush=True)
+    # the same calls from two host threads at once (ctypes calls release the interpreter lock,
+    # so the enqueue sequences of calls sharing a side stream can interleave)
+    import threading
+    for rep in range(3):
+        out = [None] * len(work)
+
+        def run(ks):
+            for k in ks:
+                with torch.cuda.stream(streams[k]):
+                    out[k] = call(work[k], stream=streams[k])
+
+        th = [threading.Thread(target=run, args=(range(j, len(work), 2),)) for j in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(ref, out)):
+            cnt = int(a["count"].item())
+            assert int(b["count"].item()) == cnt, (rep, k)
+            for key in ("idx", "sigma", "info", "iters", "sens"):
+                assert torch.equal(a[key][:cnt], b[key][:cnt]), (rep, k, key)
+    print("3 rounds of the calls from two threads equal the serial ones", flush=True)
