@@ -210,8 +210,10 @@ ps_status ps_eval_grid(ps_matrix m, const ps_grid *g, const uint8_t *mask_dev, c
  *   grad_sigma_dev device double[npts];  u_dev, v_dev device ps_c128[npts][n] as returned by
  *   the eval calls.  grad_z_dev: device ps_c128[npts] or NULL.  grad_band_dev: device
  *   ps_c128 in the GB layout of ps_create_banded with ldab = kl + ku + 1 (n columns), or
- *   NULL; overwritten (not accumulated).  The band sum uses a fixed order (deterministic).
- *   ws_dev / ws_bytes >= ps_backward_workspace_size(m, npts).
+ *   NULL; overwritten (not accumulated).  Both sums use a fixed order (deterministic).  With
+ *   both outputs asked for, one pass reads u and v once for both gradients (partial sums per
+ *   256 rows and per 64 shifts in the workspace, then reduced).
+ *   ws_dev / ws_bytes >= ps_backward_workspace_size(m, npts) (needed when grad_band_dev is set).
  * Errors: PS_ERR_INVALID, PS_ERR_WORKSPACE, PS_ERR_HIP.
  */
 ps_status ps_backward_workspace_size(ps_matrix m, int64_t npts, size_t *bytes);

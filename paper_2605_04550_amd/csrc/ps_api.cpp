@@ -837,7 +837,8 @@ ps_status ps_backward_workspace_size(ps_matrix m, int64_t npts, size_t *bytes) {
     if (npts < 0) return fail(PS_ERR_INVALID, "npts must be >= 0");
     if ((st = check_banded(m, "the adjoint"))) return st;
     int64_t rows = ps::backward_partial_rows(npts);
-    *bytes = sizeof(double2) * (size_t)(rows > 0 ? rows : 1) * (size_t)m->n * (size_t)(m->kl + m->ku + 1);
+    *bytes = sizeof(double2) * ((size_t)(rows > 0 ? rows : 1) * (size_t)m->n * (size_t)(m->kl + m->ku + 1) +
+                                (size_t)npts * (size_t)ps::backward_zpart_cols(m->n));
     return ok();
 }
 

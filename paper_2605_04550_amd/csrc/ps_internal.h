@@ -313,6 +313,9 @@ hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double
                            const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,
                            hipStream_t st);
 int64_t backward_partial_rows(int64_t npts);
+// Columns per shift of the z-gradient partials of the one-pass adjoint (after the band partials
+// in its workspace: backward_partial_rows(npts) * n * (kl + ku + 1) + npts * cols complex values).
+int64_t backward_zpart_cols(int64_t n);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 int64_t contour_edge_tiles(int64_t nx, int64_t ny);
 hipError_t launch_trace_init(int64_t m, const double2 *seeds, double2 *zt, int32_t *active, int32_t *count,

@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(256) k_grad_z(int64_t n, int64_t npts, const d
     if (lane == 0) grad_z[p] = make_double2(gp * re, -gp * im);
 }
 
-constexpr int kBwdRows = 64;   // shifts summed per partial row (fixed order)
+constexpr int kBwdRows = 256;  // shifts summed per partial row (fixed order)
 
 // Partial band gradient: partial[r][t] = -sum_{p in block r} g_p u_p[i] conj(v_p[j]) for
 // band entry t = (j, d) of the GB layout, i = j + d - ku.  Threads stride over entries.
@@ -512,6 +512,101 @@ __global__ void __launch_bounds__(256) k_grad_band_partial(int64_t n, int kl, in
         }
     }
     partial[r * n * w + t] = make_double2(-re, -im);
+}
+
+// Both gradients in one pass over u and v (each element read once from memory): workgroup
+// (x, y) takes rows 256 x .. 256 x + 255 of the kBwdRows shifts of block y, one row per thread.
+// A thread adds g_p u_p[i] conj(v_p[j]) of its row j to its band entries (i = j + d - ku, the
+// neighbouring rows of u coming from the cache) and each wavefront sums conj(u_p) v_p over its
+// 64 rows into LDS; the next shift's rows are loaded while a shift is summed.  After the block
+// the wavefront sums go to zpart[p][4 x + wave] and the band sums to partial[y][j][d] (the
+// layout of k_grad_band_partial).
+constexpr int kBwdRowBlock = 256;
+int64_t backward_zpart_cols(int64_t n) { return ((n + kBwdRowBlock - 1) / kBwdRowBlock) * (kBwdRowBlock / 64); }
+
+template <int W>
+__global__ void __launch_bounds__(kBwdRowBlock) k_grad_fused(int64_t n, int ku, int64_t npts, const double *g,
+                                                             const double2 *u, const double2 *v, double2 *partial,
+                                                             double2 *zpart) {
+    __shared__ double2 zsh[kBwdRowBlock / 64][kBwdRows];   // 16 KiB
+    const int64_t j = (int64_t)blockIdx.x * kBwdRowBlock + threadIdx.x;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t p0 = (int64_t)blockIdx.y * kBwdRows;
+    const int np = (int)(npts - p0 < kBwdRows ? npts - p0 : kBwdRows);
+    const bool in = j < n;
+    bool ok[W];                       // row i = j + d - ku inside the matrix
+#pragma unroll
+    for (int d = 0; d < W; ++d) ok[d] = in && j + d - ku >= 0 && j + d - ku < n;
+    double re[W], im[W];
+#pragma unroll
+    for (int d = 0; d < W; ++d) re[d] = im[d] = 0.0;
+    // rows of shift p0 + q: v_p[j] and u_p[j + d - ku]
+    double2 bn = make_double2(0.0, 0.0), an[W];
+    auto fetch = [&](int q) {
+        const int64_t off = (p0 + q) * n;
+        bn = in ? v[off + j] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int d = 0; d < W; ++d) an[d] = ok[d] ? u[off + j + d - ku] : make_double2(0.0, 0.0);
+    };
+    if (np > 0) fetch(0);
+    for (int q = 0; q < np; ++q) {
+        const double2 b = bn;
+        double2 a[W];
+#pragma unroll
+        for (int d = 0; d < W; ++d) a[d] = an[d];
+        if (q + 1 < np) fetch(q + 1);
+        const double gp = g ? g[p0 + q] : 1.0;
+        double zr = 0.0, zi = 0.0;
+#pragma unroll
+        for (int d = 0; d < W; ++d) {          // a conj(b), weighted (zero outside the matrix)
+            re[d] = fma(gp, fma(a[d].x, b.x, a[d].y * b.y), re[d]);
+            im[d] = fma(gp, fma(a[d].y, b.x, -a[d].x * b.y), im[d]);
+            if (d == ku) {                     // row i = j: conj(u_p[j]) v_p[j]
+                zr = fma(a[d].x, b.x, a[d].y * b.y);
+                zi = fma(a[d].x, b.y, -a[d].y * b.x);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            zr += __shfl_xor(zr, off);
+            zi += __shfl_xor(zi, off);
+        }
+        if (lane == 0) zsh[wave][q] = make_double2(zr, zi);
+    }
+    __syncthreads();
+    const int64_t zcols = (int64_t)gridDim.x * (kBwdRowBlock / 64);
+    for (int t = (int)threadIdx.x; t < np * (kBwdRowBlock / 64); t += kBwdRowBlock) {
+        const int q = t / (kBwdRowBlock / 64), wv = t % (kBwdRowBlock / 64);
+        zpart[(p0 + q) * zcols + (int64_t)blockIdx.x * (kBwdRowBlock / 64) + wv] = zsh[wv][q];
+    }
+    if (in) {
+        double2 *pr = partial + (int64_t)blockIdx.y * n * W + j * W;
+#pragma unroll
+        for (int d = 0; d < W; ++d) pr[d] = make_double2(-re[d], -im[d]);
+    }
+}
+
+// grad_z[p] = g_p conj(sum of the row-block partials of p): one wavefront per shift, lane l
+// summing columns l, l + 64, ... (coalesced), then a fixed butterfly over the lanes.
+__global__ void __launch_bounds__(256) k_grad_zsum(int64_t npts, int64_t zcols, const double *g,
+                                                   const double2 *zpart, double2 *grad_z) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= npts) return;                       // whole wavefronts
+    double re = 0.0, im = 0.0;
+    for (int64_t c = lane; c < zcols; c += 64) {
+        const double2 x = zpart[p * zcols + c];
+        re += x.x;
+        im += x.y;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+    }
+    const double gp = g ? g[p] : 1.0;
+    if (lane == 0) grad_z[p] = make_double2(gp * re, -gp * im);
 }
 
 __global__ void __launch_bounds__(256) k_grad_band_sum(int64_t n, int w, int64_t rows, const double2 *partial,
@@ -943,6 +1038,28 @@ hipError_t launch_newton_update(int64_t npts, double2 *z, const double *sigma, c
 hipError_t launch_backward(int64_t n, int kl, int ku, int64_t npts, const double *g, const double2 *u,
                            const double2 *v, double2 *grad_z, double2 *grad_band, double2 *partial, int real_a,
                            hipStream_t st) {
+    if (grad_z && grad_band && partial) {
+        // both gradients: one pass over u and v, then the two fixed-order reductions
+        const int w = kl + ku + 1;
+        const int64_t rows = backward_partial_rows(npts);
+        const int64_t rb = (n + kBwdRowBlock - 1) / kBwdRowBlock;
+        double2 *zpart = partial + rows * n * w;
+        const dim3 grid((unsigned)rb, (unsigned)rows);
+        switch (w) {
+#define PS_FUSED_CASE(WW) \
+    case WW: hipLaunchKernelGGL(k_grad_fused<WW>, grid, dim3(kBwdRowBlock), 0, st, n, ku, npts, g, u, v, partial, zpart); \
+        break;
+            PS_FUSED_CASE(1) PS_FUSED_CASE(2) PS_FUSED_CASE(3) PS_FUSED_CASE(4) PS_FUSED_CASE(5)
+            PS_FUSED_CASE(6) PS_FUSED_CASE(7) PS_FUSED_CASE(8) PS_FUSED_CASE(9)
+#undef PS_FUSED_CASE
+        default: return hipErrorInvalidValue;
+        }
+        hipLaunchKernelGGL(k_grad_zsum, dim3((unsigned)((npts * 64 + 255) / 256)), dim3(256), 0, st, npts,
+                           backward_zpart_cols(n), g, (const double2 *)zpart, grad_z);
+        hipLaunchKernelGGL(k_grad_band_sum, dim3((unsigned)((n * w + 255) / 256)), dim3(256), 0, st, n, w, rows,
+                           (const double2 *)partial, grad_band, real_a);
+        return hipGetLastError();
+    }
     if (grad_z) {
         int64_t threads = npts * 64;
         hipLaunchKernelGGL(k_grad_z, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, n, npts, g, u, v,
