@@ -144,10 +144,11 @@ ps_status ps_matrix_info(ps_matrix m, int64_t *n, int32_t *kl, int32_t *ku, doub
 /*
  * ps_workspace_size -- bytes of device workspace needed by ps_eval_points / ps_eval_grid
  * for npts shifts with options o (NULL = defaults).  The result depends on n, kl, ku, the
- * number of slots and whether vectors are wanted, not on the shift values.  With vectors on
- * at most 4096 slots it includes room for the Lanczos vectors of each slot (up to 64 of them,
- * at most 4 GiB in all), from which the Ritz vector is formed instead of replaying the
- * Lanczos steps.  A smaller workspace is accepted: the call then runs on fewer slots.
+ * number of slots and whether vectors are wanted, not on the shift values.  With vectors it
+ * includes room for Lanczos vectors of each slot (up to 64 of them, at most 16 GiB in all),
+ * from which the Ritz vector is formed instead of replaying the Lanczos steps.  A smaller
+ * workspace is accepted: the call keeps fewer Lanczos vectors (a shift that needs more steps
+ * than are kept replays them), and below what the slots themselves need it runs on fewer slots.
  */
 ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t *bytes);
 

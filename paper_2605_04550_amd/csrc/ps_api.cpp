@@ -261,7 +261,13 @@ ps_status prepare_eval(ps_matrix m, int64_t npts_max, const ps_opts &o, void *ws
     if (slots == 0)
         return fail(PS_ERR_WORKSPACE, "workspace of %zu bytes is below the minimum %zu", ws_bytes,
                     ps::workspace_bytes(m->n, m->kl, m->ku, kSlotQuantum, o.max_iter, vec_of(o), npts_max));
-    ps::carve_workspace(ws, m->n, m->kl, m->ku, slots, o.max_iter, vec_of(o), npts_max, w);
+    // kept Lanczos vectors (calls with vectors): the default number where the workspace holds
+    // them beyond the slots' own needs, else as many as it does hold (0: the replay)
+    int kst = ps::kstore_for(slots, ps::padded_rows(m->n), o.max_iter, vec_of(o));
+    while (kst > 0 &&
+           ps::workspace_bytes(m->n, m->kl, m->ku, slots, o.max_iter, vec_of(o), npts_max, kst) > ws_bytes)
+        --kst;
+    ps::carve_workspace(ws, m->n, m->kl, m->ku, slots, o.max_iter, vec_of(o), npts_max, w, kst);
     a->n = m->n;
     a->kl = m->kl;
     a->ku = m->ku;
@@ -694,7 +700,9 @@ ps_status ps_workspace_size(ps_matrix m, int64_t npts, const ps_opts *o, size_t 
         return ok();
     }
     int64_t slots = default_slots(m, npts, r);
-    *bytes = ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, vec_of(r), npts);
+    const int vec = vec_of(r);
+    *bytes = ps::workspace_bytes(m->n, m->kl, m->ku, slots, r.max_iter, vec, npts,
+                                 ps::kstore_for(slots, ps::padded_rows(m->n), r.max_iter, vec));
     return ok();
 }
 

@@ -56,7 +56,7 @@ struct Workspace {
     double *hist = nullptr;        // [kmax][2][slots] Lanczos tridiagonal: diag, offdiag^2
     double2 *vacc = nullptr;       // [n][slots]       singular-vector accumulator (vectors only)
     double *vmeta = nullptr;       // [kmax][4][slots] alpha', beta', Ritz work, coefficients (vectors only)
-    // Calls with vectors on few slots: the normalised Lanczos vectors u_1 .. u_kstore, kept so
+    // Calls with vectors: the normalised Lanczos vectors u_1 .. u_kstore of each slot, kept so
     // that the Ritz vector is one pass over them instead of a replay of the Lanczos steps
     // (see kstore_for); NULL and 0 otherwise.
     double2 *ustore = nullptr;     // [kstore][n][slots]
@@ -214,17 +214,18 @@ struct ListBases {
 hipError_t launch_sort_lists(int64_t *lists, const ListBases &bases, const int64_t *counts, int nlists,
                              hipStream_t st);
 
-size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max);
+size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max,
+                       int kstore = 0);
 // The carve-up of one evaluation workspace (host and device: the batch's Golub-Kahan kernel
 // carves each class's part itself).
-// Lanczos vectors kept per slot in a call with vectors: up to 64 (and up to kmax) while the
-// store stays within 4 GiB, for calls of at most 4096 slots (contour refinement, tracing and
-// other short shift lists; a full grid replays the Lanczos steps instead).
-constexpr int64_t kStoreMaxSlots = 4096;
+// Lanczos vectors kept per slot in a call with vectors, by default: up to 64 (and up to kmax)
+// while the store stays within 16 GiB (a short shift list keeps 64; a 65536-shift grid at
+// n = 4000 keeps 3, all its Golub-Kahan shifts need there).  A call given less workspace keeps
+// fewer (see prepare_eval).
 constexpr int kStoreMaxK = 64;
-constexpr double kStoreBudget = 4.0 * (1ull << 30);
+constexpr double kStoreBudget = 16.0 * (1ull << 30);
 __host__ __device__ inline int kstore_for(int64_t slots, int64_t nrow, int kmax, int vec) {
-    if (!vec || slots > kStoreMaxSlots || slots < 1) return 0;
+    if (!vec || slots < 1) return 0;
     const double per_k = 16.0 * (double)slots * (double)nrow;
     double k = kStoreBudget / per_k;
     if (k > kStoreMaxK) k = kStoreMaxK;
@@ -233,7 +234,7 @@ __host__ __device__ inline int kstore_for(int64_t slots, int64_t nrow, int kmax,
 }
 
 __host__ __device__ inline void carve_workspace(void *base, int64_t n, int kl, int ku, int64_t slots, int kmax,
-                                                int vec, int64_t npts_max, Workspace *w) {
+                                                int vec, int64_t npts_max, Workspace *w, int kstore = 0) {
     size_t off = 0;
     char *b = (char *)base;
     auto take = [&](size_t bytes) -> void * {
@@ -267,7 +268,7 @@ __host__ __device__ inline void carve_workspace(void *base, int64_t n, int kl, i
         w->vacc = nullptr;
         w->vmeta = nullptr;
     }
-    w->kstore = kstore_for(slots, nrow, kmax, vec);
+    w->kstore = vec ? kstore : 0;
     w->ustore = w->kstore > 0 ? (double2 *)take(sizeof(double2) * ns * (size_t)w->kstore) : nullptr;
     if (npts_max > 0) {
         w->gk_list = (int64_t *)take(sizeof(int64_t) * (size_t)npts_max);

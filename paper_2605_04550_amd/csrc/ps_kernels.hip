@@ -626,9 +626,9 @@ __global__ void __launch_bounds__(256) k_grad_band_sum(int64_t n, int w, int64_t
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max) {
+size_t workspace_bytes(int64_t n, int kl, int ku, int64_t slots, int kmax, int vec, int64_t npts_max, int kstore) {
     Workspace w;
-    carve_workspace(nullptr, n, kl, ku, slots, kmax, vec, npts_max, &w);
+    carve_workspace(nullptr, n, kl, ku, slots, kmax, vec, npts_max, &w, kstore);
     return (size_t)(uintptr_t)w.blocksums + align256(sizeof(int64_t) * (size_t)((npts_max + kScanTile - 1) / kScanTile + 1));
 }
 

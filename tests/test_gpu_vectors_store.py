@@ -1,10 +1,11 @@
 """GPU test of the two ways the Golub-Kahan path forms the Ritz vector of a call with singular
-vectors: from the Lanczos vectors kept by the first pass (calls on at most 4096 slots, up to 64
-steps) or by replaying the Lanczos steps (larger calls, or a shift that needed more steps than
-were kept).  The same shifts are evaluated both ways (an explicit slot count above 4096 forces
-the replay) and must give the same sigma and the same singular pair; the residuals of the pair
-are checked against the matrix itself (the σ of this path against the oracle: the vector
-tests at n = 400 and the all-band-shapes test)."""
+vectors: from the Lanczos vectors kept by the first pass, or by replaying the Lanczos steps (a
+shift that needed more steps than were kept).  A call keeps as many vectors per slot as its
+workspace holds beyond the slots' own needs, up to the default that ps_workspace_size asks
+room for; the same shifts are evaluated with that workspace (64 kept), with room for 2 and with
+none (every shift replays), and must give the same sigma and the same singular pair; the
+residuals of the pair are checked against the matrix itself (the sigma of this path against the
+oracle: the vector tests at n = 400 and the all-band-shapes test)."""
 import numpy as np
 import pytest
 
@@ -17,7 +18,7 @@ pytestmark = pytest.mark.gpu
 def test_kept_vectors_equal_the_replay():
     need_gpu()
     import torch
-    from paper_2605_04550_amd import api
+    from paper_2605_04550_amd import api, ps_workspace_size
     n = 2000
     band = W.grcar(n)
     A = W.to_dense(band)
@@ -29,26 +30,36 @@ def test_kept_vectors_equal_the_replay():
                         0.8 + 1j * np.linspace(-2.0, 2.0, 16)])
     zt = torch.tensor(z, dtype=torch.complex128, device="cuda")
     kw = dict(want_vectors=True, bisect=False, tol_rel=1e-12, tol_norm=1e-14)
-    kept = api.sigma_min(mat, zt, **kw)
-    replay = api.sigma_min(mat, zt, slots=8192, **kw)
-    it = kept["iters"].cpu().numpy()
-    print("kept vs replay: %d shifts, Lanczos steps median %d max %d, %d above 64"
-          % (len(z), np.median(it), it.max(), np.sum(it > 64)), flush=True)
-    assert np.sum(it <= 64) >= 1 and np.sum(it > 64) >= 1       # both ways occur
-    assert np.array_equal(it, replay["iters"].cpu().numpy())
-    assert np.array_equal(kept["info"].cpu().numpy(), replay["info"].cpu().numpy())
-    s1, s2 = kept["sigma"].cpu().numpy(), replay["sigma"].cpu().numpy()
-    assert np.array_equal(s1, s2)
-    u1, v1 = kept["u"].cpu().numpy(), kept["v"].cpu().numpy()
-    u2, v2 = replay["u"].cpu().numpy(), replay["v"].cpu().numpy()
-    # the same terms in the same order; only the contraction of a multiply-add may differ
-    du = np.abs(u1 - u2).max()
-    dv = np.abs(v1 - v2).max()
-    print("kept vs replay: max |du| %.3e, max |dv| %.3e" % (du, dv), flush=True)
-    assert du < 1e-12 and dv < 1e-12
+    o = api.make_opts(1e-14, 1e-12, 3000, True, 0, bisect=False)
+    full = ps_workspace_size(mat.handle, len(z), o)
+    # one kept vector of every slot: 256 slots (one quantum for 40 shifts) x (round_up(n, 8) + 8)
+    # rows x 16 bytes; the default keeps 64
+    per_k = 256 * ((n + 7) // 8 * 8 + 8) * 16
+    runs = {}
+    for kept in (64, 2, 0):
+        ws = torch.empty(full - (64 - kept) * per_k, dtype=torch.uint8, device="cuda")
+        runs[kept] = api.sigma_min(mat, zt, workspace=ws, **kw)
+    it = runs[64]["iters"].cpu().numpy()
+    print("kept vectors 64 / 2 / 0: %d shifts, Lanczos steps median %d max %d, %d above 2, %d above 64"
+          % (len(z), np.median(it), it.max(), np.sum(it > 2), np.sum(it > 64)), flush=True)
+    assert np.sum(it <= 2) >= 1 and np.sum(it > 2) >= 1 and np.sum(it > 64) >= 1   # every way occurs
+    ref = runs[0]
+    s0 = ref["sigma"].cpu().numpy()
+    u0, v0 = ref["u"].cpu().numpy(), ref["v"].cpu().numpy()
+    for kept in (64, 2):
+        r = runs[kept]
+        assert np.array_equal(r["iters"].cpu().numpy(), ref["iters"].cpu().numpy())
+        assert np.array_equal(r["info"].cpu().numpy(), ref["info"].cpu().numpy())
+        assert np.array_equal(r["sigma"].cpu().numpy(), s0)
+        # the same terms in the same order; only the contraction of a multiply-add may differ
+        du = np.abs(r["u"].cpu().numpy() - u0).max()
+        dv = np.abs(r["v"].cpu().numpy() - v0).max()
+        print("kept %d vs replay: max |du| %.3e, max |dv| %.3e" % (kept, du, dv), flush=True)
+        assert du < 1e-12 and dv < 1e-12
     # each pair is a singular pair of zI - A to the working accuracy (backward error)
+    u1, v1 = runs[64]["u"].cpu().numpy(), runs[64]["v"].cpu().numpy()
     nA = np.linalg.norm(A)
     for p in range(len(z)):
         assert abs(np.linalg.norm(v1[p]) - 1) < 1e-10 and abs(np.linalg.norm(u1[p]) - 1) < 1e-10
-        res = np.linalg.norm(z[p] * v1[p] - A @ v1[p] - s1[p] * u1[p])
-        assert res <= 1e-8 * nA + 1e-6 * s1[p], (p, res)
+        res = np.linalg.norm(z[p] * v1[p] - A @ v1[p] - s0[p] * u1[p])
+        assert res <= 1e-8 * nA + 1e-6 * s0[p], (p, res)
