@@ -1106,27 +1106,98 @@ struct Kern {
         const double rv = 1.0 / sqrt(ln.vx2);
         double2 *vout = a.v + ln.pid * n;
         double2 *uout = a.u + ln.pid * n;
-        for (int64_t i = 0; i < n; ++i) {
-            const cd v = cscale(cmul(w.vv[i * T + s], ph), rv);
-            w.vv[i * T + s] = v;
-            vout[i] = v;
-        }
-        double u2 = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            cd acc = czero();
+        if constexpr (W <= 4) {
+            // Pass 1: v = x / |x| with the phase (into v) and y = M v (into vy, with |y|^2), row by
+            // row with the rows of v the product needs (v_{i-kl} .. v_{i+ku}) in a register window.
+            // The raw rows are loaded PD rows ahead of their use, into a ring indexed at compile time
+            // (the loop body is unrolled PD times), so a row's load is issued before the stores of the
+            // rows in between and its wait overlaps them.  The workspace holds rows up to
+            // round_up(n, 8) + 8 >= n + ku + 2 PD, so a prefetch may read past row n - 1 (unused).
+            constexpr int PD = 2;
+            cd win[W];
 #pragma unroll
-            for (int d = 0; d < W; ++d) {
-                const int64_t c = i - KL + d;
-                if (c >= 0 && c < n) {
-                    const cd m = mval(a, ln, i, c), v = w.vv[c * T + s];
-                    acc = C(fma(m.x, v.x, fma(-m.y, v.y, acc.x)), fma(m.x, v.y, fma(m.y, v.x, acc.y)));
+            for (int d = 0; d < W; ++d) win[d] = czero();
+            auto vnorm = [&](int64_t r, cd raw) -> cd {      // normalised row r of v (zero past n - 1)
+                const cd v = cscale(cmul(raw, ph), rv);
+                return r < n ? v : czero();
+            };
+            // the window before row 0 (that of row -1): win[d] = v_{d-1-kl}, so v_0 .. v_{ku-1} in
+            // win[kl+1] .. win[W-1] (rows below 0 are zero)
+#pragma unroll
+            for (int d = KL + 1; d < W; ++d) {
+                const int64_t r = d - 1 - KL;
+                win[d] = vnorm(r, w.vv[r * T + s]);
+                if (r < n) vout[r] = win[d];
+            }
+            cd ring[PD];
+#pragma unroll
+            for (int c = 0; c < PD; ++c) ring[c] = w.vv[(KU + c) * T + s];
+            double u2 = 0.0;
+            for (int64_t i0 = 0; i0 < n; i0 += PD) {
+#pragma unroll
+                for (int c = 0; c < PD; ++c) {
+                    const int64_t i = i0 + c;
+                    const int64_t r = i + KU;              // the row the window gains
+                    const cd raw = ring[c];
+                    ring[c] = w.vv[(r + PD) * T + s];
+                    const cd vr = vnorm(r, raw);
+                    if (r < n) vout[r] = vr;
+#pragma unroll
+                    for (int d = 0; d < W - 1; ++d) win[d] = win[d + 1];
+                    win[W - 1] = vr;
+                    if (i < n) {
+                        cd acc = czero();
+#pragma unroll
+                        for (int d = 0; d < W; ++d) {
+                            const int64_t col = i - KL + d;
+                            if (col >= 0 && col < n) {
+                                const cd m = mval(a, ln, i, col), v = win[d];
+                                acc = C(fma(m.x, v.x, fma(-m.y, v.y, acc.x)), fma(m.x, v.y, fma(m.y, v.x, acc.y)));
+                            }
+                        }
+                        w.vy[i * T + s] = acc;
+                        u2 += cabs2(acc);
+                    }
                 }
             }
-            w.vy[i * T + s] = acc;
-            u2 += cabs2(acc);
+            // Pass 2: u = y / |y|, with the same prefetch
+            const double ru = 1.0 / sqrt(u2);
+#pragma unroll
+            for (int c = 0; c < PD; ++c) ring[c] = w.vy[c * T + s];
+            for (int64_t i0 = 0; i0 < n; i0 += PD) {
+#pragma unroll
+                for (int c = 0; c < PD; ++c) {
+                    const int64_t i = i0 + c;
+                    const cd y = ring[c];
+                    ring[c] = w.vy[(i + PD) * T + s];
+                    if (i < n) uout[i] = cscale(y, ru);
+                }
+            }
+        } else {
+            // wider bands: three passes, one memory wait per row (the window and the ring
+            // above make these kernels' register allocation spill)
+            for (int64_t i = 0; i < n; ++i) {
+                const cd v = cscale(cmul(w.vv[i * T + s], ph), rv);
+                w.vv[i * T + s] = v;
+                vout[i] = v;
+            }
+            double u2 = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                cd acc = czero();
+#pragma unroll
+                for (int d = 0; d < W; ++d) {
+                    const int64_t c = i - KL + d;
+                    if (c >= 0 && c < n) {
+                        const cd m = mval(a, ln, i, c), v = w.vv[c * T + s];
+                        acc = C(fma(m.x, v.x, fma(-m.y, v.y, acc.x)), fma(m.x, v.y, fma(m.y, v.x, acc.y)));
+                    }
+                }
+                w.vy[i * T + s] = acc;
+                u2 += cabs2(acc);
+            }
+            const double ru = 1.0 / sqrt(u2);
+            for (int64_t i = 0; i < n; ++i) uout[i] = cscale(w.vy[i * T + s], ru);
         }
-        const double ru = 1.0 / sqrt(u2);
-        for (int64_t i = 0; i < n; ++i) uout[i] = cscale(w.vy[i * T + s], ru);
         a.sigma[ln.pid] = ln.vsig;
         if (a.info) a.info[ln.pid] = ln.vflags;
         if (a.iters) a.iters[ln.pid] = 0;
