@@ -135,7 +135,7 @@ def stored_traffic():
 
 def algorithmic_bytes(n, kl, ku, iters, info=None):
     """Bytes the method must move for one launch: the band once, and per Golub-Kahan shift
-    the LU and its steps.  A shift that took the inertia bisection (info bit 8) moves only its
+    the LU and its steps.  A shift that took the inertia bisection (info & 8) moves only its
     result: its passes read the band (cached) and keep the factor rows in registers."""
     wl, wu = kl, kl + ku + 1
     b_lu = (wl + wu) * 16 * n + n

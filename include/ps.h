@@ -67,8 +67,9 @@ enum {
     PS_PT_BISECT = 8      /* sigma came from the inertia bisection (sigma only, kl + ku >= 1):
                              sigma_min^2 is the smallest eigenvalue of (zI-A)^H (zI-A), so
                              t < sigma_min exactly when (zI-A)^H (zI-A) - t^2 I has a Cholesky
-                             factor; bits 8..31 of info hold the number of such tests (one
-                             pass over the band each), and no Golub-Kahan step was taken   */
+                             factor; bits 8..31 of info hold the number of passes over
+                             the band (a pass makes one or more such tests: lanes per shift
+                             x tests per lane), and no Golub-Kahan step was taken          */
 };
 
 /* Flags of ps_create_banded. */
