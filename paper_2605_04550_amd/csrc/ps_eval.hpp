@@ -1535,12 +1535,14 @@ struct Kern {
     }
 
     // In the kernels with kl = 4 and singular vectors the four sweeps are compiled as
-    // functions of their own: inlined there (beside the bisection, which those kernels keep),
-    // builds once returned wrong values for ku <= 2 on the Golub-Kahan path although the same
-    // lane code is correct on the CPU and with the sweeps compiled separately.  The sigma-only
-    // kernels no longer hold the bisection and inline the sweeps at every kl (the separate
-    // functions' calls save registers to scratch: twice the time per row at kl = 4).  Every
-    // mode of all 25 band shapes is checked against the oracle by the all-band-shapes test.
+    // functions of their own: inlined there, the kl = 4, ku = 2 kernel returns wrong sigma on
+    // the Golub-Kahan path (about 1e-4 where sigma is below 1e-8), although the same lane code
+    // is correct on the CPU, with the sweeps compiled separately, and inlined in the sigma-only
+    // kernels at every kl.  It does so with or without the bisection that these kernels once
+    // held beside the sweeps.  Separate functions cost their calls' register saves to scratch,
+    // but inlined, these kernels spill as well (944 against 1204 bytes a lane at ku = 2).
+    // Every mode of all 25 band shapes is checked against the oracle by the all-band-shapes
+    // test.
     static constexpr bool kSplitSweeps = KL >= 4 && VEC;
     static __device__ __noinline__ void f1_sep(const EvalArgs &a, const Workspace &w, int64_t s, Lane &ln) {
         f1(a, w, s, ln);
@@ -1700,7 +1702,7 @@ struct Kern {
                     ln.b_m = 0.0;
                     ln.b_e = 0;
                     locate(a, qid >= 0 ? qid : 0, ln);
-                    if (ln.active) bis_begin(a, ln);   // (sigma only: the Golub-Kahan path)
+                    if (ln.active) bis_begin(a, ln);   // a settled bracket: on to the singular pair
                 }
             }
             if (__all(!ln.active && ln.exhausted)) break;
