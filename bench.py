@@ -460,7 +460,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(shifts are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(shifts are independent: several GPUs would each take their own share of them)", file=sys.stderr)
         sys.exit(2)
 
     import torch
